@@ -1,0 +1,204 @@
+/*
+ * hyperef.h -- C ABI of the MI355X (gfx950) HyperEF 2.0 hot path.
+ *
+ * The calls follow the paper's problem statement:
+ *   Alg. 1 ("Effective resistance estimation"): hypergraph H = (V, E, w) in,
+ *          the vector R of hyperedge effective resistances out;
+ *   Alg. 2 ("Resistance-Based Hypergraph Local Clustering"): H in, a
+ *          coarsened hypergraph and the vertex clusters C out.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Ownership.  The library never allocates or frees device memory.  Every
+ *   pointer marked DEVICE is caller-owned device memory on the current HIP
+ *   device; scratch memory comes from the caller's workspace `ws` of
+ *   `ws_bytes` bytes (256-byte aligned), sized by hef_workspace_size().
+ * Streams.  Calls enqueue their work on `stream` and return; device outputs
+ *   are valid once the stream is synchronised.  Calls with a HOST output
+ *   (n_clusters) synchronise `stream` before returning.
+ * Errors.  Every call returns an hef_status.  Argument checks run on the host
+ *   before any launch; when one fails nothing is written.  Unless
+ *   HEF_FLAG_ASSUME_VALID is set, the hypergraph is validated on the device
+ *   first (one stream synchronisation); an invalid hypergraph returns
+ *   HEF_ERR_INVALID_HYPERGRAPH with no output written.  HIP runtime failures
+ *   return HEF_ERR_DEVICE.  hef_last_error() gives a text for the last
+ *   non-OK status of the calling thread.
+ * Determinism.  Identical inputs, parameters and device give bitwise-
+ *   identical outputs: floating-point reductions use fixed orders and the
+ *   clustering stage uses integer atomics only.
+ * Concurrency.  Calls are reentrant; two calls may run concurrently if they
+ *   use different workspaces.
+ *
+ * Hypergraph layout (CSR over hyperedges)
+ * ---------------------------------------
+ *   eptr[m+1]  int32, eptr[0] = 0, non-decreasing, eptr[m] = nnz;
+ *   pins[nnz]  int32, 0 <= pin < n, strictly increasing within a hyperedge
+ *              (so pins of a hyperedge are distinct), every |e| >= 2;
+ *   w[m]       float32, finite and > 0 (NULL means all 1).
+ * Nodes of degree 0 are allowed.
+ */
+#ifndef HYPEREF_H
+#define HYPEREF_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HEF_OK = 0,
+  HEF_ERR_INVALID_ARGUMENT = 1,   /* bad scalar or NULL pointer            */
+  HEF_ERR_INVALID_HYPERGRAPH = 2, /* structure or weights violate layout   */
+  HEF_ERR_WORKSPACE_TOO_SMALL = 3,
+  HEF_ERR_DEVICE = 4,             /* a HIP runtime call failed             */
+  HEF_ERR_NUMERICAL = 5,          /* every quadratic form vanished / NaN   */
+  HEF_ERR_UNSUPPORTED = 6
+} hef_status;
+
+/* Storage type of the Krylov pool chi^(1..K). */
+typedef enum { HEF_BASIS_FP32 = 0, HEF_BASIS_BF16 = 1 } hef_basis;
+
+/* Which operation a workspace is sized for. */
+typedef enum {
+  HEF_OP_RESISTANCE = 0,
+  HEF_OP_COARSEN = 1,
+  HEF_OP_CLUSTER_LEVEL = 2,
+  HEF_OP_BACKWARD = 3,
+  HEF_OP_APPLY = 4
+} hef_op;
+
+/* Flags for hef_params.flags. */
+#define HEF_FLAG_ASSUME_VALID 1u  /* skip the device validation (no sync)  */
+#define HEF_FLAG_STAR_ONLY 2u     /* pool from the star expansion only     */
+#define HEF_FLAG_CLIQUE_ONLY 4u   /* pool from the clique expansion only   */
+
+typedef struct {
+  int32_t n, m;          /* nodes, hyperedges                               */
+  int64_t nnz;           /* pins; must equal eptr[m]                        */
+  const int32_t *eptr;   /* DEVICE [m+1]                                    */
+  const int32_t *pins;   /* DEVICE [nnz]                                    */
+  const float *w;        /* DEVICE [m], or NULL for unit weights            */
+} hef_hypergraph;
+
+typedef struct {
+  int32_t k;             /* Krylov steps per expansion (>= 1)               */
+  int32_t b;             /* start vectors per expansion, 1..16              */
+  int32_t levels;        /* coarsening levels for hef_coarsen (>= 1)        */
+  float percentile;      /* merge threshold delta as a percentile of R, (0,1] */
+  int32_t local_clustering; /* 0/1: attach isolated nodes (Alg. 2 steps 7-10) */
+  int32_t basis;         /* hef_basis of the pool                           */
+  uint64_t seed;         /* counter-generator seed for start blocks         */
+  float drop_tol;        /* tau: relative Gram-Schmidt residual below which
+                            a pool column is dropped (1e-3)                 */
+  int32_t orth_passes;   /* joint Cholesky-QR passes, 1 or 2                */
+  int32_t ckpt_every;    /* Krylov checkpoint interval of the adjoint (5)   */
+  uint32_t flags;        /* HEF_FLAG_*                                      */
+} hef_params;
+
+/* Fills *p with the defaults: k=10, b=1, levels=1, percentile=0.5,
+ * local_clustering=1, basis=FP32, seed=7, drop_tol=1e-3, orth_passes=1,
+ * ckpt_every=5, flags=0. */
+void hef_params_default(hef_params *p);
+
+/* Pool width K = 2*b*k (b*k with a single-expansion flag). */
+int32_t hef_pool_width(const hef_params *p);
+
+/* Bytes of workspace the operation `op` needs for this hypergraph and these
+ * parameters.  Host only; reads no device memory.  The bound covers every
+ * coarsening level, whose hypergraphs are never larger than level 0's. */
+hef_status hef_workspace_size(const hef_hypergraph *hg, const hef_params *p,
+                              int32_t op, size_t *bytes);
+
+/* Validates a hypergraph held in HOST arrays against the layout above
+ * (CPU only; no device needed).  Returns HEF_OK or
+ * HEF_ERR_INVALID_HYPERGRAPH / HEF_ERR_INVALID_ARGUMENT. */
+hef_status hef_validate_host(int32_t n, int32_t m, const int32_t *eptr,
+                             const int32_t *pins, const float *w);
+
+/* Alg. 1 (Section III-A, Eqs. (12)-(14)): per-hyperedge effective-resistance
+ * estimates.  Builds the b-column block Krylov sequences of the normalised
+ * star and clique adjacencies implicitly from the incidence, orthonormalises
+ * them into a pool chi^(1..K) (star columns first, star-node entries only),
+ * and returns R_e = max_i (max_{p in e} chi_p^(i) - min_{p in e} chi_p^(i))^2
+ * / Q_H(chi^(i)) with Q_H of Eq. (9).
+ *   start_star   DEVICE [(n+m) x b] float32 row-major start block of the star
+ *                expansion (node rows first, then hyperedge rows), or NULL to
+ *                draw it from the counter generator (seed, level 0, expansion 0);
+ *   start_clique DEVICE [n x b] float32, or NULL (expansion 1);
+ *   R            DEVICE [m] float32 output;
+ *   qh           DEVICE [K] float64 output Q_H(chi^(i)), or NULL; a dropped
+ *                column reports 0;
+ *   chi          DEVICE [n x K] row-major output pool (float32, or bfloat16
+ *                when basis = BF16), or NULL; dropped columns are zero.
+ * HEF_ERR_NUMERICAL if every Q_H vanished or a value is not finite. */
+hef_status hef_resistance(const hef_hypergraph *hg, const hef_params *p,
+                          const float *start_star, const float *start_clique,
+                          float *R, double *qh, void *chi,
+                          void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Alg. 2 (Section III-A "Multilevel Effective Resistance Clustering",
+ * Eq. (15); Section III-B, Eq. (16)): `levels` rounds of resistance
+ * estimation, Eq. (15) update, threshold contraction in ascending resistance
+ * order, resistance-based local clustering of isolated nodes and coarse
+ * rebuild.  Start blocks come from the counter generator.
+ *   cluster     DEVICE [n] int32 output: original node -> final cluster label
+ *               (labels are ranks of each cluster's smallest node id);
+ *   n_clusters  HOST int32 output;
+ *   R0          DEVICE [m] float32 output: level-0 resistances, or NULL;
+ *   eta         DEVICE [n] float32 output: eta of each final cluster in
+ *               entries [0, n_clusters), or NULL.
+ * Synchronises `stream`. */
+hef_status hef_coarsen(const hef_hypergraph *hg, const hef_params *p,
+                       int32_t *cluster, int32_t *n_clusters, float *R0,
+                       float *eta, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* One level of Alg. 2 (steps 4-10) from GIVEN inputs, so that a caller can
+ * feed the same resistances to two implementations:
+ *   R        DEVICE [m] float32 resistances of this level;
+ *   eta_in   DEVICE [n] float32 node weights eta (Eq. (15)), NULL = zeros;
+ *   chi      DEVICE [n x K] float32 pool, K = hef_pool_width(p);
+ *   qh       DEVICE [K] float64 quadratic forms (<= 0 marks an unusable column);
+ *   cluster  DEVICE [n] int32 output: node -> cluster label;
+ *   n_clusters HOST int32 output;
+ *   eta_out  DEVICE [n] float32 output, entries [0, n_clusters) valid.
+ * Synchronises `stream`. */
+hef_status hef_cluster_level(const hef_hypergraph *hg, const hef_params *p,
+                             const float *R, const float *eta_in,
+                             const float *chi, const double *qh,
+                             int32_t *cluster, int32_t *n_clusters,
+                             float *eta_out, void *ws, size_t ws_bytes,
+                             hipStream_t stream);
+
+/* Adjoint of hef_resistance with respect to the hyperedge weights: given
+ * dR = dL/dR (DEVICE [m] float32), writes dw = dL/dw (DEVICE [m] float32).
+ * Recomputes the forward pass with the same start blocks (which must be the
+ * ones the forward used; NULL = counter generator) and keeps Krylov
+ * checkpoints every p->ckpt_every steps.  Ties in a maximum take the lowest
+ * column index and the lowest CSR position.  FP32 pool only. */
+hef_status hef_resistance_backward(const hef_hypergraph *hg, const hef_params *p,
+                                   const float *start_star, const float *start_clique,
+                                   const float *dR, float *dw,
+                                   void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Test hook: y = A x for one normalised expansion adjacency
+ * (expansion 0 = star, x and y DEVICE [(n+m) x b]; 1 = clique, [n x b]),
+ * row-major float32, b in 1..16. */
+hef_status hef_debug_apply(const hef_hypergraph *hg, int32_t expansion, int32_t b,
+                           const float *x, float *y, void *ws, size_t ws_bytes,
+                           hipStream_t stream);
+
+/* The counter generator of the start blocks on the device: writes the
+ * rows x b float32 block for (seed, level, expansion) to DEVICE `out`. */
+hef_status hef_start_block(uint64_t seed, int32_t level, int32_t expansion,
+                           int64_t rows, int32_t b, float *out, hipStream_t stream);
+
+const char *hef_status_string(hef_status s);
+const char *hef_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HYPEREF_H */

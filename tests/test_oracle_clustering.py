@@ -1,0 +1,188 @@
+"""Pins of the oracle's Alg. 2 level: hand-worked examples, invariants of the
+greedy contraction, library union-find, brute-force nearest clusters, and
+structural invariants of the coarse hypergraph."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import connected_components
+
+from oracle import clustering as ocl
+from oracle import coarsen as oco
+from synth import generate, make_hypergraph, start_block
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "cluster_level_examples.json")
+
+
+def _csr(edges):
+    eptr = np.zeros(len(edges) + 1, dtype=np.int64)
+    eptr[1:] = np.cumsum([len(e) for e in edges])
+    pins = np.array([p for e in edges for p in e], dtype=np.int64)
+    return eptr, pins
+
+
+@pytest.mark.parametrize("ex", json.load(open(GOLD))["examples"], ids=lambda e: e["name"])
+def test_hand_worked_levels(ex):
+    n = ex["n"]
+    eptr, pins = _csr(ex["edges"])
+    m = len(ex["edges"])
+    R = np.array(ex["R"], dtype=np.float32)
+    eta = np.array(ex["eta"], dtype=np.float32)
+    chi = np.array(ex["chi"], dtype=np.float32)
+    qh = np.array(ex["qh"], dtype=np.float64)
+    res = ocl.cluster_level(n, m, eptr, pins, R, eta, chi, qh, ex["percentile"], True)
+    # Eq. (15) by the example's own arithmetic
+    R_upd = np.array([np.float32(sum(float(eta[v]) for v in e) + float(R[j]))
+                      for j, e in enumerate(ex["edges"])], dtype=np.float32)
+    assert np.array_equal(res.R_upd, R_upd)
+    assert res.delta == float(R_upd[ex["expect_delta_edge"]])
+    assert res.contracted == ex["expect_contracted"]
+    assert res.label.tolist() == ex["expect_label"]
+    assert res.n_clusters == ex["expect_n_clusters"]
+    for c, terms in enumerate(ex["expect_eta_terms"]):
+        acc = 0.0
+        for t in terms:
+            if isinstance(t, str) and t.startswith("eta"):
+                acc += float(eta[int(t[3:])])
+            elif isinstance(t, str) and t.startswith("R"):
+                acc += float(R_upd[int(t[1:])])
+            else:
+                acc += float(t)
+        assert res.eta[c] == np.float32(acc), (c, res.eta[c], acc)
+    m2, eptr2, pins2, w2, kept = ocl.rebuild(m, eptr, pins, np.array(ex["w"], np.float32), res.label)
+    got = [pins2[eptr2[j]:eptr2[j + 1]].tolist() for j in range(m2)]
+    assert got == ex["expect_coarse_edges"]
+    assert kept.tolist() == ex["expect_kept"]
+
+
+def _random_level(seed, n=3000, m=3200, K=6, local=True):
+    h = generate(n, m, 2, 30, 2.5, p_loc=0.5, win=200, seed=seed)
+    rng = np.random.default_rng(seed)
+    R = rng.random(h.m).astype(np.float32)
+    eta = (0.1 * rng.random(h.n)).astype(np.float32)
+    chi = rng.standard_normal((h.n, K)).astype(np.float32)
+    qh = rng.random(K) + 0.5
+    qh[1] = 0.0                                   # an unusable column
+    res = ocl.cluster_level(h.n, h.m, h.eptr, h.pins, R, eta, chi, qh, 0.5, local)
+    return h, R, eta, chi, qh, res
+
+
+def test_greedy_contraction_invariants():
+    h, R, eta, chi, qh, res = _random_level(1)
+    R_upd = res.R_upd
+    taken = np.full(h.n, -1)
+    for e in res.contracted:
+        mem = h.pins[h.eptr[e]:h.eptr[e + 1]]
+        assert R_upd[e] < res.delta
+        assert (taken[mem] < 0).all()            # pairwise disjoint
+        taken[mem] = e
+    cset = set(res.contracted)
+    key = lambda e: (R_upd[e], e)                # noqa: E731
+    for e in range(h.m):
+        if R_upd[e] < res.delta and e not in cset:
+            mem = h.pins[h.eptr[e]:h.eptr[e + 1]]
+            blockers = taken[mem][taken[mem] >= 0]
+            # maximal: blocked by a contracted hyperedge that comes earlier
+            assert blockers.size and min(key(b) for b in blockers) < key(e)
+    # the threshold admits at most ceil(pi m) - 1 hyperedges
+    assert (R_upd < res.delta).sum() <= int(np.ceil(0.5 * h.m)) - 1
+
+
+def test_local_clustering_matches_brute_force_and_union_find():
+    h, R, eta, chi, qh, res = _random_level(2)
+    n = h.n
+    # provisional labels from the contraction
+    prov = np.arange(n)
+    for e in res.contracted:
+        mem = h.pins[h.eptr[e]:h.eptr[e + 1]]
+        prov[mem] = mem.min()
+    single = np.ones(n, bool)
+    for e in res.contracted:
+        single[h.pins[h.eptr[e]:h.eptr[e + 1]]] = False
+    members = {}
+    for v in range(n):
+        members.setdefault(int(prov[v]), []).append(v)
+    use = qh > 0
+    chi64 = chi.astype(np.float64)
+    for p, c in list(res.best.items())[:400]:
+        assert single[p]
+        cands = set()
+        for e in range(h.m):
+            mem = h.pins[h.eptr[e]:h.eptr[e + 1]]
+            if p in mem:
+                cands |= {int(prov[v]) for v in mem if v != p}
+        dists = {}
+        for cl in cands:
+            cen = np.zeros(chi.shape[1])
+            for v in sorted(members[cl]):
+                cen = cen + chi64[v]
+            cen = cen / len(members[cl])
+            diffs = [chi64[p, i] - cen[i] for i in np.nonzero(use)[0]]
+            dists[cl] = max(d * d / qh[i] for d, i in zip(diffs, np.nonzero(use)[0]))
+        dmin = min(dists.values())
+        assert c == min(cl for cl, d in dists.items() if d == dmin)
+        assert res.dist[p] == dmin
+    # union-find equals the connected components of the attach graph
+    labs = np.unique(prov)
+    idx = {int(l): i for i, l in enumerate(labs)}
+    rows = [idx[p] for p in res.best]
+    cols = [idx[c] for c in res.best.values()]
+    G = sp.coo_matrix((np.ones(len(rows)), (rows, cols)), shape=(labs.size, labs.size))
+    ncomp, comp = connected_components(G, directed=False)
+    assert ncomp == res.n_clusters
+    lab_of_prov = res.label[labs]
+    for a in range(labs.size):
+        for bq in (a + 1, (a * 7) % labs.size):
+            if bq < labs.size:
+                assert (comp[a] == comp[bq]) == (lab_of_prov[a] == lab_of_prov[bq])
+
+
+def test_labels_are_canonical_and_total():
+    h, R, eta, chi, qh, res = _random_level(3)
+    lab = res.label
+    assert lab.min() == 0 and lab.max() == res.n_clusters - 1
+    assert np.unique(lab).size == res.n_clusters           # surjection onto [0, C)
+    first = np.array([np.nonzero(lab == c)[0].min() for c in range(res.n_clusters)])
+    assert (np.diff(first) > 0).all()                      # rank of smallest member id
+    assert res.eta.shape == (res.n_clusters,) and (res.eta >= 0).all()
+
+
+def test_no_local_clustering_leaves_singletons():
+    h, R, eta, chi, qh, res = _random_level(4, local=False)
+    assert not res.best
+    single = np.ones(h.n, bool)
+    for e in res.contracted:
+        single[h.pins[h.eptr[e]:h.eptr[e + 1]]] = False
+    assert res.n_clusters == single.sum() + len(res.contracted)
+    # singletons keep their eta
+    for v in np.nonzero(single)[0][:50]:
+        assert res.eta[res.label[v]] == eta[v]
+
+
+def test_rebuild_invariants():
+    h, R, eta, chi, qh, res = _random_level(5)
+    m2, eptr2, pins2, w2, kept = ocl.rebuild(h.m, h.eptr, h.pins, h.w, res.label)
+    assert (np.diff(eptr2) >= 2).all()
+    for j, e in enumerate(kept):
+        img = np.unique(res.label[h.pins[h.eptr[e]:h.eptr[e + 1]]])
+        assert np.array_equal(pins2[eptr2[j]:eptr2[j + 1]], img)
+        assert w2[j] == h.w[e]
+    dropped = np.setdiff1d(np.arange(h.m), kept)
+    for e in dropped[:200]:
+        assert np.unique(res.label[h.pins[h.eptr[e]:h.eptr[e + 1]]]).size < 2
+
+
+def test_multilevel_coarsening_shrinks_and_composes():
+    h = make_hypergraph("tiny2k")
+    start = lambda lev, x, rows, b: start_block(7, lev, x, rows, b)  # noqa: E731
+    out = oco.coarsen(h.n, h.m, h.eptr, h.pins, h.w, 6, 1, 3, start)
+    assert len(out.levels) == 3
+    ns = [lv[0] for lv in out.levels] + [out.n_clusters]
+    assert all(a > b for a, b in zip(ns, ns[1:]))
+    assert np.unique(out.cluster).size == out.n_clusters
+    assert out.cluster.min() == 0 and out.cluster.max() == out.n_clusters - 1
+    assert out.eta.shape == (out.n_clusters,)
+    assert (out.eta >= 0).all()
+    assert out.R0.shape == (h.m,)
