@@ -190,8 +190,17 @@ hef_status hef_debug_apply(const hef_hypergraph *hg, int32_t expansion, int32_t 
                            const float *x, float *y, void *ws, size_t ws_bytes,
                            hipStream_t stream);
 
+/* Test hook: G = X^T X (DEVICE [cols x cols] float64 output, row-major) of a
+ * DEVICE [rows x cols] row-major float32 matrix X (cols <= 512), through the
+ * matrix-core Gram kernels of the joint orthonormalisation.  The workspace
+ * must hold hef_debug_gram_ws(rows, cols) bytes. */
+hef_status hef_debug_gram(const float *X, int64_t rows, int32_t cols, double *G,
+                          void *ws, size_t ws_bytes, hipStream_t stream);
+size_t hef_debug_gram_ws(int64_t rows, int32_t cols);
+
 /* The counter generator of the start blocks on the device: writes the
- * rows x b float32 block for (seed, level, expansion) to DEVICE `out`. */
+ * rows x b float32 block for (seed, level, expansion) to DEVICE `out`
+ * (element (r, c) is element r*b + c of the stream). */
 hef_status hef_start_block(uint64_t seed, int32_t level, int32_t expansion,
                            int64_t rows, int32_t b, float *out, hipStream_t stream);
 

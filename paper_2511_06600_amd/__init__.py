@@ -1,0 +1,228 @@
+"""MI355X-native HyperEF 2.0 hot path: Python binding of libhyperef.so.
+
+Argument marshalling only: every stage runs in the library's HIP kernels;
+PyTorch provides device memory (tensors, the workspace) and the stream.
+There is no CPU fallback: if the library is missing, importing the
+functions below raises.
+
+    hg = DeviceHypergraph.from_arrays(n, m, eptr, pins, w)
+    R, qh, chi = resistance(hg, Params(k=30, b=8), return_pool=True)
+    cluster, n_clusters, R0, eta = coarsen(hg, Params(k=20, b=4, levels=3))
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import HefError, check, load  # noqa: F401
+
+
+@dataclass
+class Params:
+    """Mirror of hef_params (include/hyperef.h)."""
+    k: int = 10
+    b: int = 1
+    levels: int = 1
+    percentile: float = 0.5
+    local_clustering: bool = True
+    basis: str = "fp32"           # "fp32" or "bf16" pool storage
+    seed: int = 7
+    drop_tol: float = 1e-3
+    orth_passes: int = 1
+    ckpt_every: int = 5
+    assume_valid: bool = False
+    star_only: bool = False
+    clique_only: bool = False
+
+    def c(self) -> _lib.HefParams:
+        p = _lib.HefParams()
+        p.k, p.b, p.levels = self.k, self.b, self.levels
+        p.percentile = self.percentile
+        p.local_clustering = int(self.local_clustering)
+        p.basis = {"fp32": _lib.BASIS_FP32, "bf16": _lib.BASIS_BF16}[self.basis]
+        p.seed = self.seed
+        p.drop_tol = self.drop_tol
+        p.orth_passes = self.orth_passes
+        p.ckpt_every = self.ckpt_every
+        p.flags = ((_lib.FLAG_ASSUME_VALID if self.assume_valid else 0)
+                   | (_lib.FLAG_STAR_ONLY if self.star_only else 0)
+                   | (_lib.FLAG_CLIQUE_ONLY if self.clique_only else 0))
+        return p
+
+    @property
+    def K(self) -> int:
+        return load().hef_pool_width(C.byref(self.c()))
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class DeviceHypergraph:
+    """A CSR hypergraph resident on the GPU (int32 eptr / pins, float32 w)."""
+
+    def __init__(self, n: int, m: int, eptr: torch.Tensor, pins: torch.Tensor,
+                 w: torch.Tensor | None):
+        self.n, self.m = int(n), int(m)
+        self.eptr, self.pins, self.w = eptr, pins, w
+        self.nnz = int(pins.numel())
+        self.device = eptr.device
+
+    @classmethod
+    def from_arrays(cls, n, m, eptr, pins, w=None, device="cuda") -> "DeviceHypergraph":
+        e = torch.as_tensor(np.asarray(eptr, dtype=np.int32), device=device)
+        p = torch.as_tensor(np.asarray(pins, dtype=np.int32), device=device)
+        ww = None if w is None else torch.as_tensor(np.asarray(w, dtype=np.float32), device=device)
+        return cls(n, m, e, p, ww)
+
+    def c(self) -> _lib.HefHypergraph:
+        h = _lib.HefHypergraph()
+        h.n, h.m, h.nnz = self.n, self.m, self.nnz
+        h.eptr, h.pins, h.w = _ptr(self.eptr), _ptr(self.pins), _ptr(self.w)
+        return h
+
+
+def workspace_bytes(hg: DeviceHypergraph, params: Params, op: int) -> int:
+    out = C.c_size_t(0)
+    check(load().hef_workspace_size(C.byref(hg.c()), C.byref(params.c()), op, C.byref(out)),
+          "hef_workspace_size")
+    return int(out.value)
+
+
+def _workspace(hg, params, op):
+    nbytes = workspace_bytes(hg, params, op)
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=hg.device)
+
+
+def resistance(hg: DeviceHypergraph, params: Params, start_star: torch.Tensor | None = None,
+               start_clique: torch.Tensor | None = None, return_pool: bool = False):
+    """Alg. 1: returns (R [m] float32, qh [K] float64, chi [n, K] or None)."""
+    lib = load()
+    K = params.K
+    R = torch.empty(hg.m, dtype=torch.float32, device=hg.device)
+    qh = torch.empty(K, dtype=torch.float64, device=hg.device)
+    chi = None
+    if return_pool:
+        dt = torch.bfloat16 if params.basis == "bf16" else torch.float32
+        chi = torch.empty((hg.n, K), dtype=dt, device=hg.device)
+    ws = _workspace(hg, params, _lib.OP_RESISTANCE)
+    for t, rows in ((start_star, hg.n + hg.m), (start_clique, hg.n)):
+        if t is not None:
+            assert t.dtype == torch.float32 and t.is_contiguous() and t.shape == (rows, params.b)
+    check(lib.hef_resistance(C.byref(hg.c()), C.byref(params.c()), _ptr(start_star),
+                             _ptr(start_clique), _ptr(R), _ptr(qh), _ptr(chi), _ptr(ws),
+                             ws.numel(), _stream(hg.device)), "hef_resistance")
+    return R, qh, chi
+
+
+def coarsen(hg: DeviceHypergraph, params: Params):
+    """Alg. 2: returns (cluster [n] int32, n_clusters, R0 [m], eta [n_clusters])."""
+    lib = load()
+    cluster = torch.empty(hg.n, dtype=torch.int32, device=hg.device)
+    R0 = torch.empty(hg.m, dtype=torch.float32, device=hg.device)
+    eta = torch.empty(max(hg.n, 1), dtype=torch.float32, device=hg.device)
+    nc = C.c_int32(0)
+    ws = _workspace(hg, params, _lib.OP_COARSEN)
+    check(lib.hef_coarsen(C.byref(hg.c()), C.byref(params.c()), _ptr(cluster), C.byref(nc),
+                          _ptr(R0), _ptr(eta), _ptr(ws), ws.numel(), _stream(hg.device)),
+          "hef_coarsen")
+    return cluster, int(nc.value), R0, eta[:int(nc.value)]
+
+
+def cluster_level(hg: DeviceHypergraph, params: Params, R: torch.Tensor,
+                  eta: torch.Tensor | None, chi: torch.Tensor, qh: torch.Tensor):
+    """One level of Alg. 2 from given inputs: (cluster [n], n_clusters, eta_out)."""
+    lib = load()
+    cluster = torch.empty(hg.n, dtype=torch.int32, device=hg.device)
+    eta_out = torch.empty(max(hg.n, 1), dtype=torch.float32, device=hg.device)
+    nc = C.c_int32(0)
+    ws = _workspace(hg, params, _lib.OP_CLUSTER_LEVEL)
+    assert chi.dtype == torch.float32 and chi.shape == (hg.n, params.K) and chi.is_contiguous()
+    check(lib.hef_cluster_level(C.byref(hg.c()), C.byref(params.c()), _ptr(R), _ptr(eta),
+                                _ptr(chi), _ptr(qh), _ptr(cluster), C.byref(nc), _ptr(eta_out),
+                                _ptr(ws), ws.numel(), _stream(hg.device)), "hef_cluster_level")
+    return cluster, int(nc.value), eta_out[:int(nc.value)]
+
+
+def resistance_backward(hg: DeviceHypergraph, params: Params, dR: torch.Tensor,
+                        start_star: torch.Tensor | None = None,
+                        start_clique: torch.Tensor | None = None) -> torch.Tensor:
+    """dL/dw for dL/dR = dR (the adjoint of Alg. 1)."""
+    lib = load()
+    dw = torch.empty(hg.m, dtype=torch.float32, device=hg.device)
+    ws = _workspace(hg, params, _lib.OP_BACKWARD)
+    check(lib.hef_resistance_backward(C.byref(hg.c()), C.byref(params.c()), _ptr(start_star),
+                                      _ptr(start_clique), _ptr(dR.contiguous()), _ptr(dw),
+                                      _ptr(ws), ws.numel(), _stream(hg.device)),
+          "hef_resistance_backward")
+    return dw
+
+
+class HyperEFResistance(torch.autograd.Function):
+    """R = HyperEFResistance.apply(w, hg, params[, start_star, start_clique]):
+    resistances as a differentiable function of the hyperedge weights."""
+
+    @staticmethod
+    def forward(ctx, w, hg, params, start_star=None, start_clique=None):
+        h = DeviceHypergraph(hg.n, hg.m, hg.eptr, hg.pins, w.detach().contiguous())
+        R, _, _ = resistance(h, params, start_star, start_clique)
+        ctx.h, ctx.params = h, params
+        ctx.starts = (start_star, start_clique)
+        return R
+
+    @staticmethod
+    def backward(ctx, dR):
+        dw = resistance_backward(ctx.h, ctx.params, dR.float(), *ctx.starts)
+        return dw, None, None, None, None
+
+
+def debug_apply(hg: DeviceHypergraph, expansion: int, x: torch.Tensor) -> torch.Tensor:
+    """y = A x for the normalised star (0) or clique (1) adjacency."""
+    lib = load()
+    x = x.contiguous()
+    y = torch.empty_like(x)
+    ws = _workspace(hg, Params(), _lib.OP_APPLY)
+    check(lib.hef_debug_apply(C.byref(hg.c()), expansion, x.shape[1], _ptr(x), _ptr(y), _ptr(ws),
+                              ws.numel(), _stream(x.device)), "hef_debug_apply")
+    return y
+
+
+def debug_gram(X: torch.Tensor) -> torch.Tensor:
+    """X^T X (float64) through the matrix-core Gram kernels."""
+    lib = load()
+    X = X.contiguous()
+    rows, cols = X.shape
+    G = torch.empty((cols, cols), dtype=torch.float64, device=X.device)
+    nbytes = int(lib.hef_debug_gram_ws(rows, cols))
+    ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=X.device)
+    check(lib.hef_debug_gram(_ptr(X), rows, cols, _ptr(G), _ptr(ws), ws.numel(),
+                             _stream(X.device)), "hef_debug_gram")
+    return G
+
+
+def start_block(seed: int, level: int, expansion: int, rows: int, b: int,
+                device="cuda") -> torch.Tensor:
+    """The counter-generator start block on the device."""
+    lib = load()
+    out = torch.empty((rows, b), dtype=torch.float32, device=device)
+    check(lib.hef_start_block(seed, level, expansion, rows, b, _ptr(out), _stream(out.device)),
+          "hef_start_block")
+    return out
+
+
+def validate_host(n, m, eptr, pins, w=None) -> int:
+    """Host-side structural validation (no GPU needed); returns the status."""
+    lib = load()
+    e = np.ascontiguousarray(eptr, dtype=np.int32)
+    p = np.ascontiguousarray(pins, dtype=np.int32)
+    ww = None if w is None else np.ascontiguousarray(w, dtype=np.float32)
+    return int(lib.hef_validate_host(n, m, e.ctypes.data, p.ctypes.data,
+                                     None if ww is None else ww.ctypes.data))

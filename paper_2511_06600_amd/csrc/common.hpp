@@ -1,0 +1,88 @@
+// Internal helpers shared by the HIP translation units of libhyperef.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "hyperef.h"
+
+namespace hef {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char *fmt, ...);
+const char *last_error();
+
+#define HEF_HIP(call)                                                        \
+  do {                                                                       \
+    hipError_t _e = (call);                                                  \
+    if (_e != hipSuccess) {                                                  \
+      ::hef::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(_e), \
+                       __FILE__, __LINE__);                                  \
+      return HEF_ERR_DEVICE;                                                 \
+    }                                                                        \
+  } while (0)
+
+#define HEF_TRY(expr)                  \
+  do {                                 \
+    hef_status _s = (expr);            \
+    if (_s != HEF_OK) return _s;       \
+  } while (0)
+
+#define HEF_LAUNCH_CHECK() HEF_HIP(hipGetLastError())
+
+// ------------------------------------------------------------- workspace
+// Bump allocator over the caller's workspace.  With base == nullptr it only
+// measures, so the planner and the runtime carve the workspace identically.
+struct Arena {
+  char *base = nullptr;
+  size_t cap = 0;
+  size_t off = 0;
+  bool overflow = false;
+
+  template <class T>
+  T *take(size_t count) {
+    size_t bytes = count * sizeof(T);
+    size_t start = (off + 255) & ~size_t(255);
+    off = start + bytes;
+    if (base == nullptr) return nullptr;
+    if (off > cap) {
+      overflow = true;
+      return nullptr;
+    }
+    return reinterpret_cast<T *>(base + start);
+  }
+  size_t mark() const { return off; }
+  void reset(size_t m) { off = m; }
+};
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Map a launched block index to a logical one so that each of the 8 XCDs of
+// an MI355X (which receive blocks round-robin) walks a contiguous range of
+// logical blocks; neighbouring work then shares its XCD's L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblocks) {
+  constexpr int64_t kXcd = 8;
+  int64_t per = nblocks / kXcd;
+  int64_t rem = nblocks % kXcd;
+  int64_t x = bid % kXcd;
+  int64_t i = bid / kXcd;
+  // XCDs 0..rem-1 own per+1 blocks, the rest own per.
+  int64_t start = x * per + (x < rem ? x : rem);
+  int64_t cnt = per + (x < rem ? 1 : 0);
+  return i < cnt ? start + i : bid;  // i < cnt always holds for a full grid
+}
+
+// Level-independent sizes of one hypergraph level.
+struct Level {
+  int32_t n = 0, m = 0;
+  int64_t nnz = 0;
+  const int32_t *eptr = nullptr;
+  const int32_t *pins = nullptr;
+  const float *w = nullptr;  // nullptr = unit weights
+};
+
+}  // namespace hef

@@ -1,0 +1,54 @@
+// Block Krylov sequences of the normalised star and clique adjacencies.
+#pragma once
+
+#include "common.hpp"
+#include "structure.hpp"
+
+namespace hef {
+
+// Row-major blocks with row stride B (= b, a power of two, 1..16):
+//   star   block: (n+m) x B, node rows [0,n) then hyperedge rows [n, n+m)
+//   clique block: n x B
+struct Blocks {
+  float *star = nullptr;
+  float *clique = nullptr;
+};
+
+// One application of both normalised adjacencies (Section III-A: star
+// expansion with z_b(e,p) = w_e/|e|, clique expansion with
+// z_c(u,v) = sum_e w_e / C(|e|,2)), y = A x, implicit through CSR and CSC:
+//   star   y_E[e] = alpha_e sum_{p in e} s_p x_V[p]
+//          y_V[u] = s_u sum_{e ∋ u} alpha_e x_E[e]
+//   clique T_e    = beta_e sum_{p in e} s_p x_c[p]
+//          y_c[u] = s_u sum_{e ∋ u} T_e - gam_u x_c[u]
+// `tbuf` holds T (m x B).  Either expansion may be skipped (null pointers).
+hef_status spmm_apply(const Level &L, const Structure &st, int B, const float *xs,
+                      float *ys, const float *xc, float *yc, float *tbuf, hipStream_t s);
+
+// Pool column storage.
+enum PoolType { kPoolF32 = 0, kPoolBF16 = 1 };
+
+struct KrylovOut {
+  void *pool = nullptr;  // n x K row-major (fp32 or bf16)
+  int K = 0;
+  int pool_type = kPoolF32;
+};
+
+size_t krylov_ws_bytes(int64_t n, int64_t m, int B);
+
+// k steps of block Lanczos per expansion (three-term recurrence; each new
+// block is orthonormalised against the previous two in a float64 Gram
+// metric, with the drop rule for breakdowns); writes the pool columns
+// [star steps 1..k | clique steps 1..k], b columns per step, star node rows
+// only.  `start_star` ((n+m) x B) and `start_clique` (n x B) are consumed.
+// `use_star` / `use_clique` select the expansions (the pool then holds
+// b*k columns of the one selected).
+hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double tau,
+                       const float *start_star, const float *start_clique, bool use_star,
+                       bool use_clique, KrylovOut &out, Arena &ws, hipStream_t s);
+
+// Counter-based N(0,1) start block (splitmix64 + Box-Muller in float64).
+hef_status start_block(uint64_t seed, int level, int expansion, int64_t rows, int B,
+                       float *out, hipStream_t s);
+
+}  // namespace hef

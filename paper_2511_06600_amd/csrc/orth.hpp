@@ -1,0 +1,24 @@
+// Joint block orthonormalisation of the pool (Cholesky QR on matrix cores).
+#pragma once
+
+#include "common.hpp"
+
+namespace hef {
+
+size_t orth_ws_bytes(int64_t n, int K);
+
+// Orthonormalises the n x K row-major pool in place (Alg. 1 step 4, the
+// joint Gram-Schmidt of [star | clique]): G = V^T V (FP32 matrix-core tiles,
+// float64 across row chunks), Cholesky G = R^T R in float64 with the drop
+// rule (column j dropped when its Schur pivot <= tau^2 G_jj), V <- V R^-1.
+// `passes` = 1 or 2 repeats the factorisation (the second pass keeps the
+// first pass's drops).  `keep_out` (device int32 [K], may be null) receives
+// 1 for kept and 0 for dropped columns.
+hef_status orthonormalize_pool(void *pool, int pool_type, int64_t n, int K, double tau,
+                               int passes, int32_t *keep_out, Arena &ws, hipStream_t s);
+
+// Test hook: G = X^T X (float64, K x K) of a row-major n x K float32 matrix,
+// through the same matrix-core Gram kernels.
+hef_status gram_f32(const float *X, int64_t n, int K, double *G, Arena &ws, hipStream_t s);
+
+}  // namespace hef

@@ -1,0 +1,230 @@
+// Deterministic device primitives: exclusive scan, stable LSD radix sort,
+// stream compaction.
+#include "prims.hpp"
+
+namespace hef {
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_tiles(const int32_t *in, int32_t *out, int32_t *tile_sums, int64_t n) {
+  __shared__ int32_t sh[kScanThreads];
+  const int tid = threadIdx.x;
+  const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(tid) * kScanItems;
+  int32_t v[kScanItems];
+  int32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    int32_t t = (base + i < n) ? in[base + i] : 0;
+    v[i] = sum;
+    sum += t;
+  }
+  sh[tid] = sum;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    int32_t x = tid >= off ? sh[tid - off] : 0;
+    __syncthreads();
+    sh[tid] += x;
+    __syncthreads();
+  }
+  const int32_t excl = sh[tid] - sum;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n) out[base + i] = v[i] + excl;
+  if (tid == kScanThreads - 1) tile_sums[blockIdx.x] = sh[tid];
+}
+
+// One block scans the tile sums in place (exclusive) and writes the total.
+__global__ void __launch_bounds__(1024)
+k_scan_sums(int32_t *sums, int64_t ntiles, int32_t *total) {
+  __shared__ int32_t sh[1024];
+  __shared__ int32_t carry;
+  const int tid = threadIdx.x;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (int64_t c0 = 0; c0 < ntiles; c0 += 1024) {
+    int64_t i = c0 + tid;
+    int32_t v = i < ntiles ? sums[i] : 0;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      int32_t x = tid >= off ? sh[tid - off] : 0;
+      __syncthreads();
+      sh[tid] += x;
+      __syncthreads();
+    }
+    if (i < ntiles) sums[i] = carry + sh[tid] - v;
+    __syncthreads();
+    if (tid == 1023) carry += sh[1023];
+    __syncthreads();
+  }
+  if (tid == 0) *total = carry;
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_add(int32_t *out, const int32_t *tile_off, int64_t n) {
+  const int64_t base = int64_t(blockIdx.x) * kScanTile;
+  const int32_t add = tile_off[blockIdx.x];
+  for (int i = threadIdx.x; i < kScanTile; i += kScanThreads) {
+    int64_t j = base + i;
+    if (j < n) out[j] += add;
+  }
+}
+
+constexpr int kRadixBits = 8;
+constexpr int kBins = 1 << kRadixBits;
+constexpr int kRadixThreads = 256;
+constexpr int kRadixRounds = 16;
+constexpr int kRadixTile = kRadixThreads * kRadixRounds;
+
+__global__ void __launch_bounds__(kRadixThreads)
+k_radix_hist(const uint32_t *keys, int64_t n, int shift, int32_t *hist, int nblocks) {
+  __shared__ int32_t cnt[kBins];
+  const int tid = threadIdx.x;
+  cnt[tid] = 0;
+  __syncthreads();
+  const int64_t base = int64_t(blockIdx.x) * kRadixTile;
+  for (int r = 0; r < kRadixRounds; ++r) {
+    int64_t i = base + int64_t(r) * kRadixThreads + tid;
+    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (kBins - 1)], 1);
+  }
+  __syncthreads();
+  hist[int64_t(tid) * nblocks + blockIdx.x] = cnt[tid];
+}
+
+// Each block re-reads its tile and places every item at
+// offset[digit][block] + (items of the same digit earlier in the tile).
+__global__ void __launch_bounds__(kRadixThreads)
+k_radix_scatter(const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
+                uint32_t *vout, int64_t n, int shift, const int32_t *offs, int nblocks) {
+  __shared__ int32_t base_cnt[kBins];
+  __shared__ int32_t wcnt[kRadixThreads / 64][kBins];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  base_cnt[tid] = offs[int64_t(tid) * nblocks + blockIdx.x];
+  const int64_t base = int64_t(blockIdx.x) * kRadixTile;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < kRadixRounds; ++r) {
+#pragma unroll
+    for (int w = 0; w < kRadixThreads / 64; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const int64_t i = base + int64_t(r) * kRadixThreads + tid;
+    const bool valid = i < n;
+    const uint32_t k = valid ? kin[i] : 0u;
+    const uint32_t d = (k >> shift) & (kBins - 1);
+    uint64_t peer = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      peer &= bit ? bb : ~bb;
+    }
+    const int rank = __popcll(peer & lt);
+    if (valid && rank == 0) wcnt[wv][d] = __popcll(peer);
+    __syncthreads();
+    if (valid) {
+      int32_t pos = base_cnt[d] + rank;
+      for (int w = 0; w < wv; ++w) pos += wcnt[w][d];
+      kout[pos] = k;
+      vout[pos] = vin[i];
+    }
+    __syncthreads();
+    int32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < kRadixThreads / 64; ++w) add += wcnt[w][tid];
+    base_cnt[tid] += add;
+    __syncthreads();
+  }
+}
+
+__global__ void k_compact(const int32_t *flag, const int32_t *pos, int32_t *idx_out,
+                          int32_t *count_dev, int64_t n) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n && flag[i]) idx_out[pos[i]] = int32_t(i);
+  if (i == 0) *count_dev = pos[n];
+}
+
+__global__ void k_flag_copy(const int32_t *flag, int32_t *out, int64_t n) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = flag[i] ? 1 : 0;
+}
+
+}  // namespace
+
+size_t scan_ws_bytes(int64_t n) {
+  Arena a;
+  a.take<int32_t>(cdiv(n, kScanTile) + 1);
+  return a.mark();
+}
+
+hef_status exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, Arena &ws,
+                              hipStream_t s) {
+  const int64_t ntiles = cdiv(n, kScanTile);
+  const size_t mk = ws.mark();
+  int32_t *sums = ws.take<int32_t>(ntiles + 1);
+  if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+  if (n == 0) {
+    HEF_HIP(hipMemsetAsync(out, 0, sizeof(int32_t), s));
+    ws.reset(mk);
+    return HEF_OK;
+  }
+  k_scan_tiles<<<ntiles, kScanThreads, 0, s>>>(in, out, sums, n);
+  k_scan_sums<<<1, 1024, 0, s>>>(sums, ntiles, out + n);
+  k_scan_add<<<ntiles, kScanThreads, 0, s>>>(out, sums, n);
+  HEF_LAUNCH_CHECK();
+  ws.reset(mk);
+  return HEF_OK;
+}
+
+size_t radix_ws_bytes(int64_t n) {
+  const int64_t nb = cdiv(n, kRadixTile);
+  Arena a;
+  a.take<int32_t>(nb * kBins + 1);
+  return a.mark() + scan_ws_bytes(nb * kBins) + 512;
+}
+
+hef_status radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_out,
+                            uint32_t *vals_out, int64_t n, int bits, Arena &ws,
+                            hipStream_t s) {
+  if (n == 0) return HEF_OK;
+  const int64_t nb = cdiv(n, kRadixTile);
+  const size_t mk = ws.mark();
+  int32_t *hist = ws.take<int32_t>(nb * kBins + 1);
+  if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+  const int passes = (bits + kRadixBits - 1) / kRadixBits;
+  uint32_t *ka = keys, *va = vals, *kb = keys_out, *vb = vals_out;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * kRadixBits;
+    k_radix_hist<<<nb, kRadixThreads, 0, s>>>(ka, n, shift, hist, int(nb));
+    HEF_TRY(exclusive_scan_i32(hist, hist, nb * kBins, ws, s));
+    k_radix_scatter<<<nb, kRadixThreads, 0, s>>>(ka, va, kb, vb, n, shift, hist, int(nb));
+    HEF_LAUNCH_CHECK();
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  if (ka != keys_out) {
+    HEF_HIP(hipMemcpyAsync(keys_out, ka, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    HEF_HIP(hipMemcpyAsync(vals_out, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+  }
+  ws.reset(mk);
+  return HEF_OK;
+}
+
+hef_status compact_flags(const int32_t *flag, int32_t *scratch, int32_t *idx_out,
+                         int32_t *count_dev, int64_t n, Arena &ws, hipStream_t s) {
+  if (n == 0) {
+    HEF_HIP(hipMemsetAsync(count_dev, 0, sizeof(int32_t), s));
+    return HEF_OK;
+  }
+  k_flag_copy<<<cdiv(n, 256), 256, 0, s>>>(flag, scratch, n);
+  HEF_TRY(exclusive_scan_i32(scratch, scratch, n, ws, s));
+  k_compact<<<cdiv(n, 256), 256, 0, s>>>(flag, scratch, idx_out, count_dev, n);
+  HEF_LAUNCH_CHECK();
+  return HEF_OK;
+}
+
+}  // namespace hef

@@ -1,0 +1,202 @@
+// Resistance ratios (Eqs. (9), (13), (14); Alg. 1 steps 5-7).
+//
+// For every hyperedge e and pool column i the two most distant pins along
+// chi^(i) are its largest and smallest entries, so the numerator of Eq. (13)
+// is s_e^(i) = (max_{p in e} chi_p^(i) - min_{p in e} chi_p^(i))^2.
+// Pass 1 forms Q_H(chi^(i)) = sum_e w_e s_e^(i) (Eq. (9)); pass 2 forms
+// R_e = max_i s_e^(i) / Q_H(chi^(i)) (Eq. (14)).  The m x K ratio matrix is
+// never stored: both passes regather the pool rows of each hyperedge.
+//
+// A group of LPR lanes handles one hyperedge, each lane CPL consecutive
+// columns of the gathered rows; a workgroup walks a contiguous range of
+// hyperedges (XCD-contiguous), so neighbouring hyperedges share pool rows
+// in L2.  Sums are float64 in a fixed order.
+#include <cfloat>
+
+#include "krylov.hpp"
+#include "score.hpp"
+
+namespace hef {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kEdgesPerBlk = 256;
+
+template <int CPL, int PT>
+__device__ __forceinline__ void load_cols(const void *pool, int64_t p, int K, int c0,
+                                          float (&v)[CPL]) {
+  if (PT == kPoolF32) {
+    const float *row = reinterpret_cast<const float *>(pool) + p * K + c0;
+    if ((K & 3) == 0 && c0 + CPL <= K) {
+#pragma unroll
+      for (int q = 0; q < CPL; q += 4) {
+        const float4 t = *reinterpret_cast<const float4 *>(row + q);
+        v[q] = t.x; v[q + 1] = t.y; v[q + 2] = t.z; v[q + 3] = t.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) v[q] = (c0 + q < K) ? row[q] : 0.0f;
+    }
+  } else {
+    const uint16_t *row = reinterpret_cast<const uint16_t *>(pool) + p * K + c0;
+    if ((K & 3) == 0 && c0 + CPL <= K) {
+#pragma unroll
+      for (int q = 0; q < CPL; q += 4) {
+        const uint2 t = *reinterpret_cast<const uint2 *>(row + q);
+        v[q] = __uint_as_float(t.x << 16);
+        v[q + 1] = __uint_as_float(t.x & 0xFFFF0000u);
+        v[q + 2] = __uint_as_float(t.y << 16);
+        v[q + 3] = __uint_as_float(t.y & 0xFFFF0000u);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < CPL; ++q)
+        v[q] = (c0 + q < K) ? __uint_as_float(uint32_t(row[q]) << 16) : 0.0f;
+    }
+  }
+}
+
+template <int CPL, int PT>
+__device__ __forceinline__ void edge_spread(const int32_t *__restrict__ eptr,
+                                            const int32_t *__restrict__ pins, const void *pool,
+                                            int K, int c0, int64_t e, double (&s)[CPL]) {
+  float mx[CPL], mn[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) { mx[q] = -FLT_MAX; mn[q] = FLT_MAX; }
+  const int32_t a = eptr[e], b = eptr[e + 1];
+  for (int32_t j = a; j < b; ++j) {
+    float v[CPL];
+    load_cols<CPL, PT>(pool, pins[j], K, c0, v);
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) { mx[q] = fmaxf(mx[q], v[q]); mn[q] = fminf(mn[q], v[q]); }
+  }
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const double d = double(mx[q]) - double(mn[q]);
+    s[q] = d * d;
+  }
+}
+
+template <int CPL, int PT>
+__global__ void __launch_bounds__(kThreads)
+k_score_qh(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
+           const float *__restrict__ w, const void *__restrict__ pool, int K, int LPR,
+           int64_t m, double *__restrict__ partial) {
+  __shared__ double comb[512];
+  const int tid = threadIdx.x;
+  const int ngrp = kThreads / LPR;
+  const int grp = tid / LPR;
+  const int c0 = (tid % LPR) * CPL;
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t e0 = blk * kEdgesPerBlk;
+  const int64_t e1 = e0 + kEdgesPerBlk < m ? e0 + kEdgesPerBlk : m;
+  double acc[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) acc[q] = 0.0;
+  if (c0 < K) {
+    for (int64_t e = e0 + grp; e < e1; e += ngrp) {
+      double s[CPL];
+      edge_spread<CPL, PT>(eptr, pins, pool, K, c0, e, s);
+      const double we = w ? double(w[e]) : 1.0;
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) acc[q] = fma(we, s[q], acc[q]);
+    }
+  }
+  for (int g = 0; g < ngrp; ++g) {
+    if (grp == g && c0 < K) {
+#pragma unroll
+      for (int q = 0; q < CPL; ++q)
+        if (c0 + q < K) comb[c0 + q] = (g == 0) ? acc[q] : comb[c0 + q] + acc[q];
+    }
+    __syncthreads();
+  }
+  for (int c = tid; c < K; c += kThreads) partial[blk * K + c] = comb[c];
+}
+
+__global__ void k_score_qh_reduce(const double *__restrict__ partial, int64_t nblk, int K,
+                                  double *__restrict__ qh) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= K) return;
+  double s = 0.0;
+  for (int64_t b = 0; b < nblk; ++b) s += partial[b * K + c];
+  qh[c] = s;
+}
+
+template <int CPL, int PT>
+__global__ void __launch_bounds__(kThreads)
+k_score_r(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
+          const void *__restrict__ pool, int K, int LPR, int64_t m,
+          const double *__restrict__ qh, float *__restrict__ R) {
+  const int tid = threadIdx.x;
+  const int ngrp = kThreads / LPR;
+  const int grp = tid / LPR;
+  const int c0 = (tid % LPR) * CPL;
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t e0 = blk * kEdgesPerBlk;
+  const int64_t e1 = e0 + kEdgesPerBlk < m ? e0 + kEdgesPerBlk : m;
+  double inv[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const double qv = (c0 + q < K) ? qh[c0 + q] : 0.0;
+    inv[q] = qv > 0.0 ? 1.0 / qv : 0.0;
+  }
+  for (int64_t e = e0 + grp; e < e1; e += ngrp) {
+    double best = 0.0;
+    if (c0 < K) {
+      double s[CPL];
+      edge_spread<CPL, PT>(eptr, pins, pool, K, c0, e, s);
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) best = fmax(best, s[q] * inv[q]);
+    }
+    for (int off = LPR / 2; off > 0; off >>= 1) best = fmax(best, __shfl_xor(best, off, LPR));
+    if (tid % LPR == 0) R[e] = float(best);
+  }
+}
+
+int lanes_for(int K, int CPL) {
+  int need = (K + CPL - 1) / CPL;
+  int l = 1;
+  while (l < need) l <<= 1;
+  return l;
+}
+
+template <int CPL, int PT>
+hef_status score_t(const Level &L, const void *pool, int K, double *qh, float *R,
+                   double *partial, int64_t nblk, hipStream_t s) {
+  const int LPR = lanes_for(K, CPL);
+  k_score_qh<CPL, PT><<<nblk, kThreads, 0, s>>>(L.eptr, L.pins, L.w, pool, K, LPR, L.m, partial);
+  k_score_qh_reduce<<<cdiv(K, 256), 256, 0, s>>>(partial, nblk, K, qh);
+  k_score_r<CPL, PT><<<nblk, kThreads, 0, s>>>(L.eptr, L.pins, pool, K, LPR, L.m, qh, R);
+  HEF_LAUNCH_CHECK();
+  return HEF_OK;
+}
+
+}  // namespace
+
+size_t score_ws_bytes(int64_t m, int K) {
+  Arena a;
+  a.take<double>(cdiv(std::max<int64_t>(m, 1), kEdgesPerBlk) * K);
+  return a.mark();
+}
+
+hef_status score_pool(const Level &L, const void *pool, int pool_type, int K, double *qh,
+                      float *R, Arena &ws, hipStream_t s) {
+  if (K > 512) return HEF_ERR_UNSUPPORTED;
+  if (L.m == 0) return HEF_OK;
+  const int64_t nblk = cdiv(L.m, kEdgesPerBlk);
+  const size_t mk = ws.mark();
+  double *partial = ws.take<double>(nblk * K);
+  if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+  hef_status st;
+  const bool wide = K > 256;
+  if (pool_type == kPoolF32)
+    st = wide ? score_t<8, kPoolF32>(L, pool, K, qh, R, partial, nblk, s)
+              : score_t<4, kPoolF32>(L, pool, K, qh, R, partial, nblk, s);
+  else
+    st = wide ? score_t<8, kPoolBF16>(L, pool, K, qh, R, partial, nblk, s)
+              : score_t<4, kPoolBF16>(L, pool, K, qh, R, partial, nblk, s);
+  ws.reset(mk);
+  return st;
+}
+
+}  // namespace hef
