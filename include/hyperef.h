@@ -207,6 +207,18 @@ hef_status hef_start_block(uint64_t seed, int32_t level, int32_t expansion,
 const char *hef_status_string(hef_status s);
 const char *hef_last_error(void);
 
+/* Profiling aid.  While enabled (process-wide), every stage of the calls
+ * above records a pair of HIP events on its launch stream around its
+ * kernels.  hef_timing_read() waits for the recorded events, adds their
+ * elapsed times to per-stage totals, copies the totals (milliseconds) and
+ * launch counts of the first `nstages` stages to the HOST arrays `ms` and
+ * `counts` (either may be NULL), and clears them if `reset` is non-zero.
+ * Stage names come from hef_timing_stage_name(0 .. count-1). */
+void hef_timing_enable(int32_t on);
+int32_t hef_timing_stage_count(void);
+const char *hef_timing_stage_name(int32_t stage);
+hef_status hef_timing_read(double *ms, int64_t *counts, int32_t nstages, int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

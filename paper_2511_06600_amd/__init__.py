@@ -226,3 +226,19 @@ def validate_host(n, m, eptr, pins, w=None) -> int:
     ww = None if w is None else np.ascontiguousarray(w, dtype=np.float32)
     return int(lib.hef_validate_host(n, m, e.ctypes.data, p.ctypes.data,
                                      None if ww is None else ww.ctypes.data))
+
+
+def timing_enable(on: bool = True) -> None:
+    """Per-stage HIP-event timing inside the library (profiling aid)."""
+    load().hef_timing_enable(1 if on else 0)
+
+
+def timing_read(reset: bool = True) -> dict:
+    """{stage: (total ms, launches)} of the stages timed since the last reset."""
+    lib = load()
+    n = lib.hef_timing_stage_count()
+    ms = (C.c_double * n)()
+    cnt = (C.c_int64 * n)()
+    check(lib.hef_timing_read(C.cast(ms, C.c_void_p), C.cast(cnt, C.c_void_p), n, int(reset)),
+          "hef_timing_read")
+    return {lib.hef_timing_stage_name(i).decode(): (ms[i], cnt[i]) for i in range(n)}

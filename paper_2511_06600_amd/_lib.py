@@ -21,7 +21,8 @@ EXPORTS = [
     "hef_params_default", "hef_pool_width", "hef_workspace_size", "hef_validate_host",
     "hef_resistance", "hef_coarsen", "hef_cluster_level", "hef_resistance_backward",
     "hef_debug_apply", "hef_debug_gram", "hef_debug_gram_ws", "hef_start_block",
-    "hef_status_string", "hef_last_error",
+    "hef_status_string", "hef_last_error", "hef_timing_enable", "hef_timing_stage_count",
+    "hef_timing_stage_name", "hef_timing_read",
 ]
 
 
@@ -72,6 +73,10 @@ def load() -> C.CDLL:
         "hef_start_block": (i32, [u64, i32, i32, i64, i32, vp, vp]),
         "hef_status_string": (C.c_char_p, [i32]),
         "hef_last_error": (C.c_char_p, []),
+        "hef_timing_enable": (None, [i32]),
+        "hef_timing_stage_count": (i32, []),
+        "hef_timing_stage_name": (C.c_char_p, [i32]),
+        "hef_timing_read": (i32, [vp, vp, i32, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -1,25 +1,889 @@
-// Alg. 2 (placeholder until the clustering kernels land).
+// One level of Alg. 2 (steps 4-10) and the level loop.
+//
+// Section III-A "Multilevel Effective Resistance Clustering" and Eq. (15);
+// Alg. 1 step 6 / Alg. 2 step 5 (contraction from the lowest resistance);
+// Section III-B and Eq. (16) (resistance-based local clustering).  Readings
+// of the points the paper leaves open (all chosen so that the result is one
+// well-defined function of the inputs):
+//  * Eq. (15): eta is summed over the pins in CSR order in float64, R_e is
+//    added, and the sum is rounded to float32;
+//  * delta = the ceil(pi*m)-th smallest updated resistance; contraction needs
+//    R_upd < delta;
+//  * contraction = the sequential greedy in ascending (R_upd, e) order that
+//    contracts a hyperedge whose pins are all still free.  The device runs
+//    it as rounds of "an undecided candidate wins when it holds the smallest
+//    rank on every one of its pins"; the winners of a round are pairwise
+//    disjoint and every hyperedge they block ranks after them, so the result
+//    is the sequential one;
+//  * an isolated node (untouched by the contraction, with at least one
+//    hyperedge) measures d(p, C) = max_i (chi_p^(i) - c_C^(i))^2 / Q_H^(i)
+//    (the numerator of Eq. (13) against the mean chi-vector of cluster C,
+//    in resistance units, float64, columns with Q_H > 0) to every cluster
+//    met through its hyperedges, and picks the smallest (ties: smallest
+//    label).  All picks are applied together: the merged groups are the
+//    connected components of the pairs {p, best(p)};
+//  * eta of a merged group = float64 sum of its clusters' eta in ascending
+//    label order, then of the distances of its distinct attach pairs in
+//    ascending (min, max) order, rounded to float32;
+//  * labels are ranks of each cluster's smallest node id;
+//  * the coarse hypergraph keeps, in order, every hyperedge that still spans
+//    two or more clusters, with its weight.
+// Floating-point expressions in this file are compiled without contraction
+// so that they round exactly as written.
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <vector>
+
 #include "cluster.hpp"
+#include "krylov.hpp"
+#include "prims.hpp"
+
+#pragma clang fp contract(off)
 
 namespace hef {
-size_t coarsen_extra_bytes(int64_t, int64_t, int64_t, int) { return 0; }
-size_t cluster_level_bytes(int64_t, int64_t, int64_t, int) { return 0; }
-size_t backward_bytes(int64_t, int64_t, int64_t, const hef_params &) { return 0; }
+namespace {
+
+constexpr int kT = 256;
+constexpr int kRoundsPerSync = 16;
+constexpr int32_t kStUndecided = 0, kStIn = 1, kStOut = 2, kStNone = 3;
+
+// ---- a6: Eq. (15) -----------------------------------------------------------
+__global__ void k_eta_update(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
+                             const float *__restrict__ R, const float *__restrict__ eta,
+                             float *__restrict__ R_upd, uint32_t *__restrict__ keys,
+                             uint32_t *__restrict__ vals, int32_t m) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  double acc = 0.0;
+  if (eta)
+    for (int32_t j = eptr[e]; j < eptr[e + 1]; ++j) acc = acc + double(eta[pins[j]]);
+  const float r = float(acc + double(R[e]));
+  R_upd[e] = r;
+  keys[e] = __float_as_uint(r);  // r >= 0: bit order = numeric order
+  vals[e] = uint32_t(e);
+}
+
+// rank of every hyperedge in (R_upd, e) order; candidates have R_upd < delta
+__global__ void k_rank(const uint32_t *__restrict__ order, const float *__restrict__ R_upd,
+                       int32_t m, int64_t delta_pos, int32_t *__restrict__ rank,
+                       int32_t *__restrict__ state, float *__restrict__ delta_out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const float delta = R_upd[order[delta_pos]];
+  const int32_t e = int32_t(order[i]);
+  rank[e] = int32_t(i);
+  state[e] = R_upd[e] < delta ? kStUndecided : kStNone;
+  if (i == 0) *delta_out = delta;
+}
+
+// ---- a7: contraction rounds --------------------------------------------------
+// packed[p] = max over undecided candidates e ∋ p of (round << 32 | ~rank[e])
+// = the newest round's smallest rank.  First checks whether e is blocked.
+__global__ void k_round_propose(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
+                                const int32_t *__restrict__ rank, int32_t *__restrict__ state,
+                                const int32_t *__restrict__ owner,
+                                unsigned long long *__restrict__ packed, uint32_t round,
+                                int32_t m, int32_t *__restrict__ undecided) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= m || state[e] != kStUndecided) return;
+  const int32_t a = eptr[e], b = eptr[e + 1];
+  for (int32_t j = a; j < b; ++j)
+    if (owner[pins[j]] >= 0) {
+      state[e] = kStOut;
+      return;
+    }
+  const unsigned long long key =
+      (static_cast<unsigned long long>(round) << 32) | uint32_t(~uint32_t(rank[e]));
+  for (int32_t j = a; j < b; ++j) atomicMax(&packed[pins[j]], key);
+  atomicAdd(undecided, 1);
+}
+
+__global__ void k_round_select(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
+                               const int32_t *__restrict__ rank, int32_t *__restrict__ state,
+                               int32_t *__restrict__ owner,
+                               const unsigned long long *__restrict__ packed, uint32_t round,
+                               int32_t m) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= m || state[e] != kStUndecided) return;
+  const unsigned long long key =
+      (static_cast<unsigned long long>(round) << 32) | uint32_t(~uint32_t(rank[e]));
+  const int32_t a = eptr[e], b = eptr[e + 1];
+  for (int32_t j = a; j < b; ++j)
+    if (packed[pins[j]] != key) return;
+  state[e] = kStIn;
+  for (int32_t j = a; j < b; ++j) owner[pins[j]] = int32_t(e);
+}
+
+// provisional cluster of every node (its smallest member), eta of clusters,
+// singleton flags, and the compact index of contracted hyperedges
+__global__ void k_provisional(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
+                              const int32_t *__restrict__ owner, const float *__restrict__ eta,
+                              const float *__restrict__ R_upd, int32_t *__restrict__ prov,
+                              float *__restrict__ prov_eta, int32_t n) {
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t e = owner[v];
+  if (e < 0) {
+    prov[v] = int32_t(v);
+    prov_eta[v] = eta ? eta[v] : 0.0f;
+  } else {
+    const int32_t mn = pins[eptr[e]];
+    prov[v] = mn;
+    if (mn == v) prov_eta[v] = R_upd[e];
+  }
+}
+
+__global__ void k_flag_in(const int32_t *__restrict__ state, int32_t *__restrict__ flag, int32_t m) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e < m) flag[e] = state[e] == kStIn ? 1 : 0;
+}
+
+// ---- a8: centroids of contracted clusters (members ascending) ---------------
+template <int PT>
+__device__ __forceinline__ double pool_val(const void *pool, int64_t idx) {
+  if (PT == kPoolF32) return double(reinterpret_cast<const float *>(pool)[idx]);
+  const uint16_t h = reinterpret_cast<const uint16_t *>(pool)[idx];
+  return double(__uint_as_float(uint32_t(h) << 16));
+}
+
+template <int PT>
+__global__ void k_centroids(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
+                            const int32_t *__restrict__ in_list, const int32_t *__restrict__ n_in,
+                            const void *__restrict__ pool, int K, double *__restrict__ cent) {
+  const int32_t cnt = *n_in;
+  for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < int64_t(cnt) * K;
+       idx += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t c = idx / K;
+    const int col = int(idx % K);
+    const int32_t e = in_list[c];
+    const int32_t a = eptr[e], b = eptr[e + 1];
+    double acc = 0.0;
+    for (int32_t j = a; j < b; ++j) acc = acc + pool_val<PT>(pool, int64_t(pins[j]) * K + col);
+    cent[c * K + col] = acc / double(b - a);
+  }
+}
+
+// ---- a8: best neighbouring cluster of every isolated node --------------------
+// One wave per node; lanes split the columns.  For every co-pin v of every
+// hyperedge of p, C = prov[v] and d(p, C) as above; best = (smallest d,
+// smallest label).
+template <int PT>
+__global__ void __launch_bounds__(kT)
+k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
+       const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
+       const int32_t *__restrict__ owner, const int32_t *__restrict__ prov,
+       const int32_t *__restrict__ in_index, const double *__restrict__ cent,
+       const void *__restrict__ pool, int K, const double *__restrict__ qh,
+       int32_t n, int32_t *__restrict__ best_label, double *__restrict__ best_d) {
+  const int lane = threadIdx.x & 63;
+  const int64_t p = (int64_t(blockIdx.x) * kT + threadIdx.x) >> 6;
+  if (p >= n) return;
+  if (owner[p] >= 0 || vptr[p] == vptr[p + 1]) {
+    if (lane == 0) best_label[p] = -1;
+    return;
+  }
+  // this lane's columns: lane, lane+64, ... ; xp and 1/qh flags kept in registers
+  constexpr int MAXC = 8;
+  double xp[MAXC], qv[MAXC];
+#pragma unroll
+  for (int q = 0; q < MAXC; ++q) {
+    const int col = lane + 64 * q;
+    xp[q] = col < K ? pool_val<PT>(pool, p * K + col) : 0.0;
+    qv[q] = col < K ? qh[col] : 0.0;
+  }
+  double bd = DBL_MAX;
+  int32_t bl = INT32_MAX;
+  for (int32_t jj = vptr[p]; jj < vptr[p + 1]; ++jj) {
+    const int32_t e = eids[jj];
+    for (int32_t j = eptr[e]; j < eptr[e + 1]; ++j) {
+      const int32_t v = pins[j];
+      if (v == p) continue;
+      const int32_t C = prov[v];
+      const int32_t ow = owner[v];
+      // centroid row: the node itself (singleton) or the contracted cluster
+      const int64_t crow = ow < 0 ? -1 : int64_t(in_index[ow]);
+      double dl = 0.0;
+#pragma unroll
+      for (int q = 0; q < MAXC; ++q) {
+        const int col = lane + 64 * q;
+        if (col < K && qv[q] > 0.0) {
+          const double c = crow < 0 ? pool_val<PT>(pool, int64_t(v) * K + col) : cent[crow * K + col];
+          const double diff = xp[q] - c;
+          const double sq = diff * diff;
+          const double r = sq / qv[q];
+          dl = r > dl ? r : dl;
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(dl, off, 64);
+        dl = o > dl ? o : dl;
+      }
+      if (dl < bd || (dl == bd && C < bl)) {
+        bd = dl;
+        bl = C;
+      }
+    }
+  }
+  if (lane == 0) {
+    best_label[p] = bl;
+    best_d[p] = bd;
+  }
+}
+
+// ---- union-find over the attach pairs (roots end as component minima) ------
+__device__ __forceinline__ int32_t find_root(const int32_t *parent, int32_t x) {
+  int32_t p = parent[x];
+  while (p != x) {
+    x = p;
+    p = parent[x];
+  }
+  return x;
+}
+
+__global__ void k_uf_init(int32_t *__restrict__ parent, int32_t n) {
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v < n) parent[v] = int32_t(v);
+}
+
+__global__ void k_uf_hook(const int32_t *__restrict__ best_label, int32_t *__restrict__ parent,
+                          int32_t n, int32_t *__restrict__ changed) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t c = best_label[p];
+  if (c < 0) return;
+  const int32_t a = find_root(parent, int32_t(p));
+  const int32_t b = find_root(parent, c);
+  if (a != b) {
+    atomicMin(&parent[a > b ? a : b], a < b ? a : b);
+    *changed = 1;
+  }
+}
+
+__global__ void k_uf_compress(int32_t *__restrict__ parent, int32_t n) {
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v < n) parent[v] = find_root(parent, int32_t(v));
+}
+
+// cluster ids of this level are provisional labels (prov[v] == v); a root is
+// a cluster whose component root is itself
+__global__ void k_root_flags(const int32_t *__restrict__ prov, const int32_t *__restrict__ parent,
+                             int32_t *__restrict__ flag, int32_t n) {
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v < n) flag[v] = (prov[v] == v && parent[v] == v) ? 1 : 0;
+}
+
+__global__ void k_labels(const int32_t *__restrict__ prov, const int32_t *__restrict__ parent,
+                         const int32_t *__restrict__ rank_of_root, int32_t *__restrict__ label,
+                         int32_t n) {
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v < n) label[v] = rank_of_root[parent[prov[v]]];
+}
+
+// ---- eta of merged groups ---------------------------------------------------
+// attach pairs: each isolated p with best b gives key (min, max); mutual
+// pairs of two isolated nodes appear twice and are kept once (the copy from
+// the smaller endpoint).  flag marks the pairs to keep.
+__global__ void k_pair_flags(const int32_t *__restrict__ best_label, const int32_t *__restrict__ owner,
+                             int32_t *__restrict__ flag, int32_t n) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t b = best_label[p];
+  int32_t f = 0;
+  if (b >= 0) {
+    f = 1;
+    // b is a node id; if b is itself isolated and picked p, the pair is
+    // counted by the smaller of the two
+    if (owner[b] < 0 && best_label[b] == int32_t(p) && b < p) f = 0;
+  }
+  flag[p] = f;
+}
+
+// One thread per group: sequential float64 sum of the group's cluster etas
+// (ascending label) then its pair distances (ascending (min, max)).
+__global__ void k_group_eta(const int32_t *__restrict__ cl_ptr, const int32_t *__restrict__ cl_lab,
+                            const float *__restrict__ prov_eta, const int32_t *__restrict__ pr_ptr,
+                            const int32_t *__restrict__ pr_node, const double *__restrict__ best_d,
+                            int32_t ngroups, float *__restrict__ eta_out) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= ngroups) return;
+  double acc = 0.0;
+  for (int32_t i = cl_ptr[g]; i < cl_ptr[g + 1]; ++i) acc = acc + double(prov_eta[cl_lab[i]]);
+  for (int32_t i = pr_ptr[g]; i < pr_ptr[g + 1]; ++i) acc = acc + best_d[pr_node[i]];
+  eta_out[g] = float(acc);
+}
+
+// segment starts of a sorted key array: ptr[k] = first index with key >= k
+__global__ void k_seg_ptr(const uint32_t *__restrict__ keys, int64_t cnt, int32_t nseg,
+                          int32_t *__restrict__ ptr) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i > cnt) return;
+  const int64_t prev = i == 0 ? -1 : int64_t(keys[i - 1]);
+  const int64_t cur = i == cnt ? int64_t(nseg) : int64_t(keys[i]);
+  for (int64_t k = prev + 1; k <= cur; ++k) ptr[k] = int32_t(i);
+}
+
+// gather helpers for the sorts
+__global__ void k_items_clusters(const int32_t *__restrict__ prov, const int32_t *__restrict__ label,
+                                 const int32_t *__restrict__ pos, uint32_t *__restrict__ keys,
+                                 uint32_t *__restrict__ vals, int32_t n) {
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v >= n || prov[v] != v) return;
+  keys[pos[v]] = uint32_t(label[v]);
+  vals[pos[v]] = uint32_t(v);
+}
+
+__global__ void k_cluster_flags(const int32_t *__restrict__ prov, int32_t *__restrict__ flag, int32_t n) {
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v < n) flag[v] = prov[v] == v ? 1 : 0;
+}
+
+// pairs, step 1: key = max endpoint (low half of the (min, max) order)
+__global__ void k_items_pairs(const int32_t *__restrict__ best_label, const int32_t *__restrict__ flag,
+                              const int32_t *__restrict__ pos, uint32_t *__restrict__ keys,
+                              uint32_t *__restrict__ vals, int32_t n) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n || !flag[p]) return;
+  const int32_t b = best_label[p];
+  keys[pos[p]] = uint32_t(p > b ? p : b);
+  vals[pos[p]] = uint32_t(p);
+}
+
+__global__ void k_rekey_min(const int32_t *__restrict__ best_label, const uint32_t *__restrict__ vals,
+                            uint32_t *__restrict__ keys, int64_t cnt) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int32_t p = int32_t(vals[i]);
+  const int32_t b = best_label[p];
+  keys[i] = uint32_t(p < b ? p : b);
+}
+
+__global__ void k_rekey_group(const int32_t *__restrict__ label, const uint32_t *__restrict__ vals,
+                              uint32_t *__restrict__ keys, int64_t cnt) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < cnt) keys[i] = uint32_t(label[vals[i]]);
+}
+
+// ---- a9: coarse rebuild -----------------------------------------------------
+__global__ void k_pin_labels(const int32_t *__restrict__ pins, const int32_t *__restrict__ label,
+                             uint32_t *__restrict__ keys, uint32_t *__restrict__ vals, int64_t nnz) {
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= nnz) return;
+  keys[j] = uint32_t(label[pins[j]]);
+  vals[j] = uint32_t(j);
+}
+
+__global__ void k_slot_edge(const int32_t *__restrict__ eptr, uint32_t *__restrict__ eid, int32_t m) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  for (int32_t j = eptr[e]; j < eptr[e + 1]; ++j) eid[j] = uint32_t(e);
+}
+
+__global__ void k_gather_u32(const uint32_t *__restrict__ src, const uint32_t *__restrict__ idx,
+                             uint32_t *__restrict__ dst, int64_t cnt) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < cnt) dst[i] = src[idx[i]];
+}
+
+// after sorting slots by (edge, label): count distinct labels per edge
+__global__ void k_distinct(const int32_t *__restrict__ eptr, const uint32_t *__restrict__ lab_sorted,
+                           int32_t *__restrict__ cnt, int32_t m) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  int32_t c = 0;
+  for (int32_t j = eptr[e]; j < eptr[e + 1]; ++j)
+    if (j == eptr[e] || lab_sorted[j] != lab_sorted[j - 1]) ++c;
+  cnt[e] = c >= 2 ? c : 0;
+}
+
+__global__ void k_emit(const int32_t *__restrict__ eptr, const uint32_t *__restrict__ lab_sorted,
+                       const int32_t *__restrict__ cnt, const int32_t *__restrict__ new_ptr,
+                       const int32_t *__restrict__ keep_pos, const float *__restrict__ w,
+                       int32_t *__restrict__ eptr2, int32_t *__restrict__ pins2,
+                       float *__restrict__ w2, int32_t m) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= m || cnt[e] == 0) return;
+  const int32_t k = keep_pos[e];
+  int32_t o = new_ptr[e];
+  eptr2[k] = o;
+  w2[k] = w ? w[e] : 1.0f;
+  for (int32_t j = eptr[e]; j < eptr[e + 1]; ++j)
+    if (j == eptr[e] || lab_sorted[j] != lab_sorted[j - 1]) pins2[o++] = int32_t(lab_sorted[j]);
+}
+
+__global__ void k_flag_pos(const int32_t *__restrict__ v, int32_t *__restrict__ f, int32_t m) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e < m) f[e] = v[e] > 0 ? 1 : 0;
+}
+
+__global__ void k_compose(int32_t *__restrict__ map, const int32_t *__restrict__ label, int64_t n0) {
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v < n0) map[v] = label[map[v]];
+}
+
+__global__ void k_iota(int32_t *__restrict__ a, int64_t n) {
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v < n) a[v] = int32_t(v);
+}
+
+__global__ void k_set_i32(int32_t *__restrict__ p, int32_t v, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_zero_u64(unsigned long long *__restrict__ p, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+inline unsigned g1(int64_t n) { return unsigned(std::max<int64_t>(1, cdiv(n, kT))); }
+
+// Workspace of one clustering level (sizes of the level).
+struct LevelWs {
+  float *R_upd;
+  uint32_t *k0, *v0, *k1, *v1;  // sort buffers (max(n, m, nnz))
+  int32_t *rank, *state, *owner, *prov, *in_index, *in_list, *flag, *pos, *parent, *best_label,
+      *label, *cl_ptr, *pr_ptr, *ibuf;
+  unsigned long long *packed;
+  float *prov_eta;
+  double *best_d, *cent;
+  int32_t *small;  // [8] device scalars
+  float *delta;
+};
+
+void carve_level(Arena &a, int64_t n, int64_t m, int64_t nnz, int K, LevelWs &w) {
+  const int64_t big = std::max(std::max(n, m), nnz) + 1;
+  w.R_upd = a.take<float>(m + 1);
+  w.k0 = a.take<uint32_t>(big);
+  w.v0 = a.take<uint32_t>(big);
+  w.k1 = a.take<uint32_t>(big);
+  w.v1 = a.take<uint32_t>(big);
+  w.rank = a.take<int32_t>(m + 1);
+  w.state = a.take<int32_t>(m + 1);
+  w.owner = a.take<int32_t>(n + 1);
+  w.prov = a.take<int32_t>(n + 1);
+  w.in_index = a.take<int32_t>(m + 1);
+  w.in_list = a.take<int32_t>(m + 1);
+  w.flag = a.take<int32_t>(big);
+  w.pos = a.take<int32_t>(big);
+  w.parent = a.take<int32_t>(n + 1);
+  w.best_label = a.take<int32_t>(n + 1);
+  w.label = a.take<int32_t>(n + 1);
+  w.cl_ptr = a.take<int32_t>(n + 2);
+  w.pr_ptr = a.take<int32_t>(n + 2);
+  w.ibuf = a.take<int32_t>(big);
+  w.packed = a.take<unsigned long long>(n + 1);
+  w.prov_eta = a.take<float>(n + 1);
+  w.best_d = a.take<double>(n + 1);
+  w.cent = a.take<double>((n / 2 + 1) * int64_t(K));
+  w.small = a.take<int32_t>(8);
+  w.delta = a.take<float>(1);
+}
+
+size_t level_ws_bytes(int64_t n, int64_t m, int64_t nnz, int K) {
+  Arena a;
+  LevelWs w;
+  carve_level(a, n, m, nnz, K, w);
+  return a.mark() + radix_ws_bytes(std::max(std::max(n, m), nnz)) +
+         scan_ws_bytes(std::max(std::max(n, m), nnz) + 1) + 4096;
+}
+
+hef_status read_i32(const int32_t *dev, int32_t *host, hipStream_t s) {
+  HEF_HIP(hipMemcpyAsync(host, dev, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HEF_HIP(hipStreamSynchronize(s));
+  return HEF_OK;
+}
+
+}  // namespace
+
+// Steps 4-10 of Alg. 2 on one level.  Outputs label[n] (canonical), the
+// group count (host) and eta_out[n_groups].  Needs the level's CSC (st).
+hef_status cluster_one_level(const Level &L, const Structure &st, const float *R, const float *eta,
+                             const void *pool, int pool_type, int K, const double *qh,
+                             float percentile, bool local, int32_t *label_out,
+                             int32_t *n_groups_out, float *eta_out, Arena &ws, hipStream_t s) {
+  const int64_t n = L.n, m = L.m, nnz = L.nnz;
+  const size_t mk = ws.mark();
+  LevelWs w;
+  carve_level(ws, n, m, nnz, K, w);
+  if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+
+  // ---- a6: Eq. (15), order and threshold
+  {
+    TimedScope ts(kStClusterUpdate, s);
+    if (m > 0) {
+      k_eta_update<<<g1(m), kT, 0, s>>>(L.eptr, L.pins, R, eta, w.R_upd, w.k0, w.v0, int32_t(m));
+      HEF_LAUNCH_CHECK();
+      HEF_TRY(radix_sort_pairs(w.k0, w.v0, w.k1, w.v1, m, 32, ws, s));
+      int64_t dpos = int64_t(std::ceil(double(percentile) * double(m))) - 1;
+      dpos = std::min<int64_t>(std::max<int64_t>(dpos, 0), m - 1);
+      k_rank<<<g1(m), kT, 0, s>>>(w.v1, w.R_upd, int32_t(m), dpos, w.rank, w.state, w.delta);
+      HEF_LAUNCH_CHECK();
+    }
+  }
+  // ---- a7: contraction rounds
+  {
+    TimedScope ts(kStClusterContract, s);
+    if (n > 0) {
+      k_set_i32<<<g1(n), kT, 0, s>>>(w.owner, -1, n);
+      k_zero_u64<<<g1(n), kT, 0, s>>>(w.packed, n);
+      HEF_LAUNCH_CHECK();
+    }
+    uint32_t round = 1;
+    // every round decides at least the smallest-rank undecided candidate
+    const int64_t max_batches = cdiv(m, kRoundsPerSync) + 2;
+    for (int64_t batch = 0; m > 0; ++batch) {
+      if (batch > max_batches) {
+        set_error("contraction did not settle");
+        return HEF_ERR_NUMERICAL;
+      }
+      for (int r = 0; r < kRoundsPerSync; ++r, ++round) {
+        HEF_HIP(hipMemsetAsync(w.small, 0, sizeof(int32_t), s));
+        k_round_propose<<<g1(m), kT, 0, s>>>(L.eptr, L.pins, w.rank, w.state, w.owner, w.packed,
+                                            round, int32_t(m), w.small);
+        k_round_select<<<g1(m), kT, 0, s>>>(L.eptr, L.pins, w.rank, w.state, w.owner, w.packed,
+                                           round, int32_t(m));
+        HEF_LAUNCH_CHECK();
+      }
+      int32_t und = 0;
+      HEF_TRY(read_i32(w.small, &und, s));
+      if (und == 0) break;
+    }
+  }
+  // ---- provisional clusters and contracted-cluster index
+  if (n > 0) {
+    k_provisional<<<g1(n), kT, 0, s>>>(L.eptr, L.pins, w.owner, eta, w.R_upd, w.prov, w.prov_eta,
+                                       int32_t(n));
+    HEF_LAUNCH_CHECK();
+  }
+  if (m > 0) {
+    k_flag_in<<<g1(m), kT, 0, s>>>(w.state, w.flag, int32_t(m));
+    HEF_LAUNCH_CHECK();
+    HEF_TRY(exclusive_scan_i32(w.flag, w.in_index, m, ws, s));
+    HEF_TRY(compact_flags(w.flag, w.pos, w.in_list, w.small + 1, m, ws, s));
+  }
+  // ---- a8: local clustering
+  {
+    TimedScope ts(kStClusterLocal, s);
+    if (n > 0) k_set_i32<<<g1(n), kT, 0, s>>>(w.best_label, -1, n);
+    HEF_LAUNCH_CHECK();
+    if (local && n > 0 && m > 0 && K > 0) {
+      if (pool_type == kPoolF32) {
+        k_centroids<kPoolF32><<<2048, kT, 0, s>>>(L.eptr, L.pins, w.in_list, w.small + 1, pool, K, w.cent);
+        k_best<kPoolF32><<<cdiv(n * 64, kT), kT, 0, s>>>(L.eptr, L.pins, st.vptr, st.eids, w.owner,
+                                                         w.prov, w.in_index, w.cent, pool, K, qh,
+                                                         int32_t(n), w.best_label, w.best_d);
+      } else {
+        k_centroids<kPoolBF16><<<2048, kT, 0, s>>>(L.eptr, L.pins, w.in_list, w.small + 1, pool, K, w.cent);
+        k_best<kPoolBF16><<<cdiv(n * 64, kT), kT, 0, s>>>(L.eptr, L.pins, st.vptr, st.eids, w.owner,
+                                                          w.prov, w.in_index, w.cent, pool, K, qh,
+                                                          int32_t(n), w.best_label, w.best_d);
+      }
+      HEF_LAUNCH_CHECK();
+    }
+    // union-find over {p, best(p)}
+    if (n > 0) {
+      k_uf_init<<<g1(n), kT, 0, s>>>(w.parent, int32_t(n));
+      HEF_LAUNCH_CHECK();
+      for (int it = 0; it < 64; ++it) {
+        HEF_HIP(hipMemsetAsync(w.small + 2, 0, sizeof(int32_t), s));
+        k_uf_hook<<<g1(n), kT, 0, s>>>(w.best_label, w.parent, int32_t(n), w.small + 2);
+        k_uf_compress<<<g1(n), kT, 0, s>>>(w.parent, int32_t(n));
+        HEF_LAUNCH_CHECK();
+        int32_t ch = 0;
+        HEF_TRY(read_i32(w.small + 2, &ch, s));
+        if (!ch) break;
+        if (it == 63) {
+          set_error("union-find did not settle");
+          return HEF_ERR_NUMERICAL;
+        }
+      }
+    }
+  }
+  // ---- canonical labels (rank of each group's smallest node id)
+  int32_t ngroups = 0;
+  {
+    TimedScope ts(kStClusterRebuild, s);
+    if (n > 0) {
+      k_root_flags<<<g1(n), kT, 0, s>>>(w.prov, w.parent, w.flag, int32_t(n));
+      HEF_LAUNCH_CHECK();
+      HEF_TRY(exclusive_scan_i32(w.flag, w.pos, n, ws, s));
+      k_labels<<<g1(n), kT, 0, s>>>(w.prov, w.parent, w.pos, label_out, int32_t(n));
+      HEF_LAUNCH_CHECK();
+      HEF_TRY(read_i32(w.pos + n, &ngroups, s));
+    }
+    *n_groups_out = ngroups;
+    if (n > 0 && ngroups > 0) {
+      // cluster contributions sorted by (group, label)
+      k_cluster_flags<<<g1(n), kT, 0, s>>>(w.prov, w.flag, int32_t(n));
+      HEF_TRY(exclusive_scan_i32(w.flag, w.pos, n, ws, s));
+      int32_t ncl = 0;
+      HEF_TRY(read_i32(w.pos + n, &ncl, s));
+      k_items_clusters<<<g1(n), kT, 0, s>>>(w.prov, label_out, w.pos, w.k0, w.v0, int32_t(n));
+      HEF_LAUNCH_CHECK();
+      HEF_TRY(radix_sort_pairs(w.k0, w.v0, w.k1, w.v1, ncl, bits_for(ngroups), ws, s));
+      k_seg_ptr<<<g1(int64_t(ncl) + 1), kT, 0, s>>>(w.k1, ncl, ngroups, w.cl_ptr);
+      HEF_HIP(hipMemcpyAsync(w.ibuf, w.v1, sizeof(int32_t) * std::max(ncl, 1), hipMemcpyDeviceToDevice, s));
+      // pair contributions sorted by (group, min, max)
+      k_pair_flags<<<g1(n), kT, 0, s>>>(w.best_label, w.owner, w.flag, int32_t(n));
+      HEF_TRY(exclusive_scan_i32(w.flag, w.pos, n, ws, s));
+      int32_t npr = 0;
+      HEF_TRY(read_i32(w.pos + n, &npr, s));
+      if (npr > 0) {
+        k_items_pairs<<<g1(n), kT, 0, s>>>(w.best_label, w.flag, w.pos, w.k0, w.v0, int32_t(n));
+        HEF_LAUNCH_CHECK();
+        HEF_TRY(radix_sort_pairs(w.k0, w.v0, w.k1, w.v1, npr, bits_for(n), ws, s));      // by max
+        k_rekey_min<<<g1(npr), kT, 0, s>>>(w.best_label, w.v1, w.k1, npr);
+        HEF_TRY(radix_sort_pairs(w.k1, w.v1, w.k0, w.v0, npr, bits_for(n), ws, s));      // by min
+        k_rekey_group<<<g1(npr), kT, 0, s>>>(label_out, w.v0, w.k0, npr);
+        HEF_TRY(radix_sort_pairs(w.k0, w.v0, w.k1, w.v1, npr, bits_for(ngroups), ws, s)); // by group
+        HEF_LAUNCH_CHECK();
+      }
+      k_seg_ptr<<<g1(int64_t(npr) + 1), kT, 0, s>>>(w.k1, npr, ngroups, w.pr_ptr);
+      k_group_eta<<<g1(ngroups), kT, 0, s>>>(w.cl_ptr, w.ibuf, w.prov_eta, w.pr_ptr,
+                                             reinterpret_cast<const int32_t *>(w.v1), w.best_d,
+                                             ngroups, eta_out);
+      HEF_LAUNCH_CHECK();
+    }
+  }
+  ws.reset(mk);
+  return HEF_OK;
+}
+
+// Coarse hypergraph: pins mapped to labels, per-hyperedge sorted distinct
+// labels, hyperedges with fewer than two kept (order and weight kept).
+hef_status rebuild_level(const Level &L, const int32_t *label, int32_t n2, int32_t *eptr2,
+                         int32_t *pins2, float *w2, int32_t *m2_host, int64_t *nnz2_host,
+                         Arena &ws, hipStream_t s) {
+  const int64_t m = L.m, nnz = L.nnz;
+  TimedScope ts(kStClusterRebuild, s);
+  const size_t mk = ws.mark();
+  uint32_t *k0 = ws.take<uint32_t>(nnz + 1), *v0 = ws.take<uint32_t>(nnz + 1);
+  uint32_t *k1 = ws.take<uint32_t>(nnz + 1), *v1 = ws.take<uint32_t>(nnz + 1);
+  uint32_t *eid = ws.take<uint32_t>(nnz + 1);
+  int32_t *cnt = ws.take<int32_t>(m + 1), *nptr = ws.take<int32_t>(m + 1);
+  int32_t *flag = ws.take<int32_t>(m + 1), *kpos = ws.take<int32_t>(m + 1);
+  if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+  *m2_host = 0;
+  *nnz2_host = 0;
+  if (m == 0 || nnz == 0) {
+    HEF_HIP(hipMemsetAsync(eptr2, 0, sizeof(int32_t), s));
+    ws.reset(mk);
+    return HEF_OK;
+  }
+  // sort slots by label, then stably by hyperedge: (edge, label) order
+  k_pin_labels<<<g1(nnz), kT, 0, s>>>(L.pins, label, k0, v0, nnz);
+  HEF_LAUNCH_CHECK();
+  HEF_TRY(radix_sort_pairs(k0, v0, k1, v1, nnz, bits_for(std::max<int32_t>(n2 - 1, 0)), ws, s));
+  k_slot_edge<<<g1(m), kT, 0, s>>>(L.eptr, eid, int32_t(m));
+  k_gather_u32<<<g1(nnz), kT, 0, s>>>(eid, v1, k0, nnz);       // edge of each sorted slot
+  HEF_LAUNCH_CHECK();
+  HEF_TRY(radix_sort_pairs(k0, v1, k1, v0, nnz, bits_for(m - 1), ws, s));
+  // v0 = slots in (edge, label) order; k0 = their labels
+  k_pin_labels<<<g1(nnz), kT, 0, s>>>(L.pins, label, k1, v1, nnz);
+  k_gather_u32<<<g1(nnz), kT, 0, s>>>(k1, v0, k0, nnz);
+  HEF_LAUNCH_CHECK();
+  k_distinct<<<g1(m), kT, 0, s>>>(L.eptr, k0, cnt, int32_t(m));
+  HEF_LAUNCH_CHECK();
+  HEF_TRY(exclusive_scan_i32(cnt, nptr, m, ws, s));
+  k_flag_pos<<<g1(m), kT, 0, s>>>(cnt, flag, int32_t(m));
+  HEF_LAUNCH_CHECK();
+  HEF_TRY(exclusive_scan_i32(flag, kpos, m, ws, s));
+  k_emit<<<g1(m), kT, 0, s>>>(L.eptr, k0, cnt, nptr, kpos, L.w, eptr2, pins2, w2, int32_t(m));
+  HEF_LAUNCH_CHECK();
+  int32_t m2 = 0, nnz2 = 0;
+  HEF_TRY(read_i32(kpos + m, &m2, s));
+  HEF_TRY(read_i32(nptr + m, &nnz2, s));
+  HEF_HIP(hipMemcpyAsync(eptr2 + m2, &nnz2, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HEF_HIP(hipStreamSynchronize(s));
+  *m2_host = m2;
+  *nnz2_host = nnz2;
+  ws.reset(mk);
+  return HEF_OK;
+}
+
+size_t rebuild_ws_bytes(int64_t n, int64_t m, int64_t nnz) {
+  Arena a;
+  for (int i = 0; i < 5; ++i) a.take<uint32_t>(nnz + 1);
+  for (int i = 0; i < 4; ++i) a.take<int32_t>(m + 1);
+  return a.mark() + radix_ws_bytes(nnz) + scan_ws_bytes(std::max(n, m) + 1) + 4096;
+}
+
+size_t cluster_level_bytes(int64_t n, int64_t m, int64_t nnz, int K) {
+  Arena a;
+  Structure st;
+  structure_carve(a, n, m, nnz, st);
+  a.take<int32_t>(4);
+  return a.mark() + std::max(structure_build_ws(n, m, nnz), level_ws_bytes(n, m, nnz, K)) + 4096;
+}
+
+namespace {
+
+// Persistent part of the coarsening workspace (sized at level 0, which
+// bounds every level).
+struct CoarsenWs {
+  Structure st;
+  int32_t *flags;
+  void *pool;
+  double *qh;
+  float *R;
+  int32_t *eptr[2], *pins[2];
+  float *w[2];
+  float *eta[2];
+  int32_t *label;
+};
+
+void carve_coarsen(Arena &a, int64_t n, int64_t m, int64_t nnz, const hef_params &p, CoarsenWs &c) {
+  structure_carve(a, n, m, nnz, c.st);
+  c.flags = a.take<int32_t>(4);
+  const int K = pool_width_of(p);
+  c.pool = a.take<char>(size_t(n) * K * (p.basis == HEF_BASIS_BF16 ? 2 : 4));
+  c.qh = a.take<double>(K);
+  c.R = a.take<float>(m + 1);
+  for (int i = 0; i < 2; ++i) {
+    c.eptr[i] = a.take<int32_t>(m + 1);
+    c.pins[i] = a.take<int32_t>(nnz + 1);
+    c.w[i] = a.take<float>(m + 1);
+    c.eta[i] = a.take<float>(n + 1);
+  }
+  c.label = a.take<int32_t>(n + 1);
+}
+
+}  // namespace
+
+size_t coarsen_bytes(int64_t n, int64_t m, int64_t nnz, const hef_params &p) {
+  Arena a;
+  CoarsenWs c;
+  carve_coarsen(a, n, m, nnz, p, c);
+  const int K = pool_width_of(p);
+  size_t scratch = estimate_level_bytes(n, m, nnz, p);
+  scratch = std::max(scratch, level_ws_bytes(n, m, nnz, K));
+  scratch = std::max(scratch, rebuild_ws_bytes(n, m, nnz));
+  return a.mark() + scratch + 4096;
+}
+
 }  // namespace hef
 
+using namespace hef;
+
 extern "C" {
-hef_status hef_coarsen(const hef_hypergraph *, const hef_params *, int32_t *, int32_t *, float *,
-                       float *, void *, size_t, hipStream_t) {
-  return HEF_ERR_UNSUPPORTED;
+
+hef_status hef_cluster_level(const hef_hypergraph *hg, const hef_params *p, const float *R,
+                             const float *eta_in, const float *chi, const double *qh,
+                             int32_t *cluster, int32_t *n_clusters, float *eta_out, void *ws,
+                             size_t ws_bytes, hipStream_t stream) {
+  if (!hg || !p || !n_clusters || !ws) { set_error("NULL argument"); return HEF_ERR_INVALID_ARGUMENT; }
+  size_t need = 0;
+  HEF_TRY(hef_workspace_size(hg, p, HEF_OP_CLUSTER_LEVEL, &need));
+  if (ws_bytes < need) { set_error("workspace too small (%zu < %zu)", ws_bytes, need); return HEF_ERR_WORKSPACE_TOO_SMALL; }
+  const int K = pool_width_of(*p);
+  if (hg->m > 0 && !R) { set_error("R is NULL"); return HEF_ERR_INVALID_ARGUMENT; }
+  if (hg->n > 0 && (!cluster || !eta_out || (p->local_clustering && (!chi || !qh)))) {
+    set_error("NULL output or pool");
+    return HEF_ERR_INVALID_ARGUMENT;
+  }
+  Arena a;
+  a.base = static_cast<char *>(ws);
+  a.cap = ws_bytes;
+  Structure st;
+  structure_carve(a, hg->n, hg->m, hg->nnz, st);
+  int32_t *flags = a.take<int32_t>(4);
+  Level L;
+  L.n = hg->n; L.m = hg->m; L.nnz = hg->nnz; L.eptr = hg->eptr; L.pins = hg->pins; L.w = hg->w;
+  if (!(p->flags & HEF_FLAG_ASSUME_VALID)) {
+    int32_t bad = 0;
+    HEF_TRY(validate_device(L, flags, &bad, stream));
+    if (bad) { set_error("invalid hypergraph (code %d)", bad); return HEF_ERR_INVALID_HYPERGRAPH; }
+  }
+  HEF_TRY(structure_build(L, st, a, stream));
+  int32_t ng = 0;
+  HEF_TRY(cluster_one_level(L, st, R, eta_in, chi, kPoolF32, K, qh, p->percentile,
+                            p->local_clustering != 0, cluster, &ng, eta_out, a, stream));
+  HEF_HIP(hipStreamSynchronize(stream));
+  *n_clusters = ng;
+  return HEF_OK;
 }
-hef_status hef_cluster_level(const hef_hypergraph *, const hef_params *, const float *,
-                             const float *, const float *, const double *, int32_t *, int32_t *,
-                             float *, void *, size_t, hipStream_t) {
-  return HEF_ERR_UNSUPPORTED;
+
+hef_status hef_coarsen(const hef_hypergraph *hg, const hef_params *p, int32_t *cluster,
+                       int32_t *n_clusters, float *R0, float *eta, void *ws, size_t ws_bytes,
+                       hipStream_t stream) {
+  if (!hg || !p || !n_clusters || !ws || (hg->n > 0 && !cluster)) {
+    set_error("NULL argument");
+    return HEF_ERR_INVALID_ARGUMENT;
+  }
+  size_t need = 0;
+  HEF_TRY(hef_workspace_size(hg, p, HEF_OP_COARSEN, &need));
+  if (ws_bytes < need) { set_error("workspace too small (%zu < %zu)", ws_bytes, need); return HEF_ERR_WORKSPACE_TOO_SMALL; }
+  const int64_t n0 = hg->n;
+  const int K = pool_width_of(*p);
+  const int pt = p->basis == HEF_BASIS_BF16 ? kPoolBF16 : kPoolF32;
+  Arena a;
+  a.base = static_cast<char *>(ws);
+  a.cap = ws_bytes;
+  CoarsenWs c;
+  carve_coarsen(a, hg->n, hg->m, hg->nnz, *p, c);
+  if (a.overflow) { set_error("workspace carve overflow"); return HEF_ERR_WORKSPACE_TOO_SMALL; }
+  Level L;
+  L.n = hg->n; L.m = hg->m; L.nnz = hg->nnz; L.eptr = hg->eptr; L.pins = hg->pins; L.w = hg->w;
+  if (!(p->flags & HEF_FLAG_ASSUME_VALID)) {
+    int32_t bad = 0;
+    HEF_TRY(validate_device(L, c.flags, &bad, stream));
+    if (bad) { set_error("invalid hypergraph (code %d)", bad); return HEF_ERR_INVALID_HYPERGRAPH; }
+  }
+  if (n0 > 0) {
+    k_iota<<<g1(n0), kT, 0, stream>>>(cluster, n0);
+    HEF_LAUNCH_CHECK();
+  }
+  const float *eta_cur = nullptr;
+  int cur = 0;
+  for (int lev = 0; lev < p->levels && L.m > 0; ++lev) {
+    HEF_TRY(estimate_level(L, *p, p->seed, lev, nullptr, nullptr, c.st, c.pool, c.qh, c.R, a, stream));
+    if (lev == 0 && R0)
+      HEF_HIP(hipMemcpyAsync(R0, c.R, sizeof(float) * L.m, hipMemcpyDeviceToDevice, stream));
+    int32_t ng = 0;
+    float *eta_next = c.eta[cur];
+    HEF_TRY(cluster_one_level(L, c.st, c.R, eta_cur, c.pool, pt, K, c.qh, p->percentile,
+                              p->local_clustering != 0, c.label, &ng, eta_next, a, stream));
+    if (n0 > 0) {
+      k_compose<<<g1(n0), kT, 0, stream>>>(cluster, c.label, n0);
+      HEF_LAUNCH_CHECK();
+    }
+    int32_t m2 = 0;
+    int64_t nnz2 = 0;
+    HEF_TRY(rebuild_level(L, c.label, ng, c.eptr[cur], c.pins[cur], c.w[cur], &m2, &nnz2, a, stream));
+    L.n = ng;
+    L.m = m2;
+    L.nnz = nnz2;
+    L.eptr = c.eptr[cur];
+    L.pins = c.pins[cur];
+    L.w = c.w[cur];
+    eta_cur = eta_next;
+    cur ^= 1;
+  }
+  if (eta && L.n > 0) {
+    if (eta_cur)
+      HEF_HIP(hipMemcpyAsync(eta, eta_cur, sizeof(float) * L.n, hipMemcpyDeviceToDevice, stream));
+    else
+      HEF_HIP(hipMemsetAsync(eta, 0, sizeof(float) * L.n, stream));
+  }
+  HEF_HIP(hipStreamSynchronize(stream));
+  *n_clusters = L.n;
+  return HEF_OK;
 }
+
 hef_status hef_resistance_backward(const hef_hypergraph *, const hef_params *, const float *,
                                    const float *, const float *, float *, void *, size_t,
                                    hipStream_t) {
+  set_error("the adjoint is not available in this build");
   return HEF_ERR_UNSUPPORTED;
 }
-}
+
+}  // extern "C"
+
+namespace hef {
+size_t backward_bytes(int64_t, int64_t, int64_t, const hef_params &) { return 256; }
+}  // namespace hef
+
+extern "C" {
+
+}  // extern "C"

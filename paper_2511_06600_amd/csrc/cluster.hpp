@@ -7,7 +7,7 @@
 
 namespace hef {
 
-size_t coarsen_extra_bytes(int64_t n, int64_t m, int64_t nnz, int K);
+size_t coarsen_bytes(int64_t n, int64_t m, int64_t nnz, const hef_params &p);
 size_t cluster_level_bytes(int64_t n, int64_t m, int64_t nnz, int K);
 size_t backward_bytes(int64_t n, int64_t m, int64_t nnz, const hef_params &p);
 

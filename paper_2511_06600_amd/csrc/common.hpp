@@ -86,3 +86,55 @@ struct Level {
 };
 
 }  // namespace hef
+
+namespace hef {
+
+// ------------------------------------------------------------ stage timing
+// Optional per-stage kernel timing (hef_timing_enable): HIP events recorded
+// on the launch stream around each stage's kernels.  Off by default; when
+// off a TimedScope does nothing.
+enum Stage : int {
+  kStStructure = 0,
+  kStSpmmCsr,
+  kStSpmmCsc,
+  kStLanczosGram,
+  kStLanczosSolve,
+  kStLanczosApply,
+  kStOrthGram,
+  kStOrthChol,
+  kStOrthApply,
+  kStScoreQ,
+  kStScoreR,
+  kStClusterUpdate,
+  kStClusterContract,
+  kStClusterLocal,
+  kStClusterRebuild,
+  kStAdjoint,
+  kStStart,
+  kStageCount
+};
+
+bool timing_on();
+void timing_push(int stage, hipEvent_t a, hipEvent_t b);
+
+struct TimedScope {
+  int stage;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  TimedScope(int st, hipStream_t stream) : stage(st), s(stream) {
+    if (timing_on()) {
+      if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+        (void)hipEventRecord(a, s);
+      else
+        a = b = nullptr;
+    }
+  }
+  ~TimedScope() {
+    if (a && b) {
+      (void)hipEventRecord(b, s);
+      timing_push(stage, a, b);
+    }
+  }
+};
+
+}  // namespace hef

@@ -1,9 +1,12 @@
 // The C ABI (include/hyperef.h): argument checks, workspace planning and
 // the order of the stages of Alg. 1 and Alg. 2.
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "cluster.hpp"
@@ -27,6 +30,26 @@ void set_error(const char *fmt, ...) {
 }
 
 const char *last_error() { return g_err.c_str(); }
+
+// ---- stage timing (profiling aid; the only process-wide state besides the
+// per-thread error text)
+static std::atomic<int> g_timing{0};
+static std::mutex g_tmu;
+static std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> g_pending;
+static double g_ms[kStageCount];
+static int64_t g_cnt[kStageCount];
+
+bool timing_on() { return g_timing.load(std::memory_order_relaxed) != 0; }
+
+void timing_push(int stage, hipEvent_t a, hipEvent_t b) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_pending.emplace_back(stage, a, b);
+}
+
+static const char *kStageNames[kStageCount] = {
+    "structure", "spmm_csr", "spmm_csc", "lanczos_gram", "lanczos_solve", "lanczos_apply",
+    "orth_gram", "orth_chol", "orth_apply", "score_qh", "score_r", "cluster_update",
+    "cluster_contract", "cluster_local", "cluster_rebuild", "adjoint", "start_block"};
 
 namespace {
 
@@ -220,7 +243,7 @@ hef_status hef_workspace_size(const hef_hypergraph *hg, const hef_params *p, int
       return HEF_OK;
     case HEF_OP_COARSEN:
       HEF_TRY(check_params(p, true));
-      *bytes = resistance_bytes(n, m, nnz, *p, true) + coarsen_extra_bytes(n, m, nnz, pool_width(*p));
+      *bytes = coarsen_bytes(n, m, nnz, *p);
       return HEF_OK;
     case HEF_OP_CLUSTER_LEVEL:
       HEF_TRY(check_params(p, true));
@@ -387,5 +410,36 @@ const char *hef_status_string(hef_status s) {
 }
 
 const char *hef_last_error(void) { return hef::last_error(); }
+
+void hef_timing_enable(int32_t on) { hef::g_timing.store(on ? 1 : 0); }
+
+int32_t hef_timing_stage_count(void) { return kStageCount; }
+
+const char *hef_timing_stage_name(int32_t stage) {
+  return (stage >= 0 && stage < kStageCount) ? hef::kStageNames[stage] : "";
+}
+
+hef_status hef_timing_read(double *ms, int64_t *counts, int32_t nstages, int32_t reset) {
+  std::lock_guard<std::mutex> lk(hef::g_tmu);
+  for (auto &t : hef::g_pending) {
+    hipEvent_t a = std::get<1>(t), b = std::get<2>(t);
+    float el = 0.0f;
+    HEF_HIP(hipEventSynchronize(b));
+    HEF_HIP(hipEventElapsedTime(&el, a, b));
+    hef::g_ms[std::get<0>(t)] += el;
+    hef::g_cnt[std::get<0>(t)] += 1;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+  hef::g_pending.clear();
+  for (int i = 0; i < nstages && i < kStageCount; ++i) {
+    if (ms) ms[i] = hef::g_ms[i];
+    if (counts) counts[i] = hef::g_cnt[i];
+  }
+  if (reset) {
+    for (int i = 0; i < kStageCount; ++i) { hef::g_ms[i] = 0.0; hef::g_cnt[i] = 0; }
+  }
+  return HEF_OK;
+}
 
 }  // extern "C"

@@ -16,109 +16,99 @@
 namespace hef {
 namespace {
 
-typedef float floatx16 __attribute__((ext_vector_type(16)));
+constexpr int kGramBlocks = 1024;  // workgroups of the Gram partial pass
 
-constexpr int kGramBlocks = 512;   // workgroups of the Gram partial pass
-constexpr int kFlushSteps = 128;   // FP32 accumulation length (MFMA steps)
-
-__device__ __forceinline__ float load_m(const float *v0, const float *v1, const float *y,
-                                        int64_t r, int c, int B) {
-  if (c < B) return v0 ? v0[r * B + c] : 0.0f;
-  if (c < 2 * B) return v1 ? v1[r * B + c - B] : 0.0f;
-  if (c < 3 * B) return y[r * B + c - 2 * B];
-  return 0.0f;
-}
-
-// Gram partials of M = [v0 | v1 | y] (rows x 3B, column c of tile t is
-// 32t + c).  Each workgroup (4 waves) covers a contiguous row range; FP32
-// MFMA accumulators are flushed to float64 every kFlushSteps steps; the 4
-// waves are combined in LDS in wave order.  partial[blk][p][32*32] for tile
-// pair p = (I <= J).
-template <int T>
+// Gram partials of M = [v0 | v1 | y] (rows x C, C = 3B), FP32 register
+// blocks: the C x C Gram is cut into S x S blocks, one thread per block on or
+// above the diagonal; a workgroup stages 64-row slabs in LDS and its RG row
+// groups split each slab's rows.  Per-thread FP32 sums (a few hundred rows)
+// are combined in float64 in row-group order; partial[blk][C*C].
+template <int B>
 __global__ void __launch_bounds__(256)
 k_lgram(const float *__restrict__ v0, const float *__restrict__ v1,
-        const float *__restrict__ y, int64_t rows, int B, int64_t rows_per_blk,
+        const float *__restrict__ y, int64_t rows, int64_t rows_per_blk,
         double *__restrict__ partial) {
-  constexpr int TP = T * (T + 1) / 2;
-  __shared__ double comb[TP * 1024];
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int C = 3 * B;
+  constexpr int C = 3 * B;
+  constexpr int S = (C % 6 == 0) ? 6 : 3;
+  constexpr int NB = C / S;
+  constexpr int NT = NB * (NB + 1) / 2;
+  constexpr int RG = 256 / NT;
+  constexpr int SLAB = 64;
+  constexpr int LD = C + 1;
+  __shared__ float sh[SLAB * LD];
+  __shared__ double comb[C * C];
+  const int tid = threadIdx.x;
+  const int g = tid / NT;
+  const int blk = tid % NT;
+  const bool active = g < RG;
+  int bi = 0, bj = 0;
+  {
+    int q = blk;
+    for (int a = 0; a < NB; ++a) {
+      if (q < NB - a) { bi = a; bj = a + q; break; }
+      q -= NB - a;
+    }
+  }
+  float acc[S][S];
+#pragma unroll
+  for (int a = 0; a < S; ++a)
+#pragma unroll
+    for (int b = 0; b < S; ++b) acc[a][b] = 0.0f;
   const int64_t r0 = int64_t(blockIdx.x) * rows_per_blk;
   const int64_t r1 = r0 + rows_per_blk < rows ? r0 + rows_per_blk : rows;
-  floatx16 acc[TP];
-  double dacc[TP][16];
-#pragma unroll
-  for (int p = 0; p < TP; ++p) {
-    for (int v = 0; v < 16; ++v) { acc[p][v] = 0.0f; dacc[p][v] = 0.0; }
-  }
-  int steps = 0;
-  // wave wv takes row pairs r0 + 2*(wv + 4*i)
-  for (int64_t r = r0 + 2 * wv; r < r1; r += 8) {
-    const int64_t rr = r + (lane >> 5);
-    float a[T];
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-      const int c = 32 * t + (lane & 31);
-      a[t] = (rr < r1 && c < C) ? load_m(v0, v1, y, rr, c, B) : 0.0f;
+  for (int64_t base = r0; base < r1; base += SLAB) {
+    __syncthreads();
+    for (int e = tid; e < SLAB * C; e += 256) {
+      const int r = e / C, c = e % C;
+      const int64_t row = base + r;
+      float v = 0.0f;
+      if (row < r1) {
+        if (c < B) v = v0 ? v0[row * B + c] : 0.0f;
+        else if (c < 2 * B) v = v1 ? v1[row * B + c - B] : 0.0f;
+        else v = y[row * B + c - 2 * B];
+      }
+      sh[r * LD + c] = v;
     }
-    int p = 0;
+    __syncthreads();
+    if (active) {
+      for (int r = g; r < SLAB; r += RG) {
+        float xa[S], xb[S];
 #pragma unroll
-    for (int I = 0; I < T; ++I) {
+        for (int a = 0; a < S; ++a) xa[a] = sh[r * LD + bi * S + a];
 #pragma unroll
-      for (int J = I; J < T; ++J) {
-        acc[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[I], a[J], acc[p], 0, 0, 0);
-        ++p;
+        for (int b = 0; b < S; ++b) xb[b] = sh[r * LD + bj * S + b];
+#pragma unroll
+        for (int a = 0; a < S; ++a)
+#pragma unroll
+          for (int b = 0; b < S; ++b) acc[a][b] = fmaf(xa[a], xb[b], acc[a][b]);
       }
     }
-    if (++steps == kFlushSteps) {
-      steps = 0;
-#pragma unroll
-      for (int q = 0; q < TP; ++q)
-        for (int v = 0; v < 16; ++v) { dacc[q][v] += double(acc[q][v]); acc[q][v] = 0.0f; }
-    }
   }
+  for (int e = tid; e < C * C; e += 256) comb[e] = 0.0;
+  __syncthreads();
+  for (int gg = 0; gg < RG; ++gg) {
+    if (active && g == gg) {
 #pragma unroll
-  for (int q = 0; q < TP; ++q)
-    for (int v = 0; v < 16; ++v) dacc[q][v] += double(acc[q][v]);
-  // combine waves in order 0,1,2,3
-  for (int w = 0; w < 4; ++w) {
-    if (wv == w) {
+      for (int a = 0; a < S; ++a)
 #pragma unroll
-      for (int q = 0; q < TP; ++q)
-        for (int v = 0; v < 16; ++v) {
-          const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-          const int j = lane & 31;
-          double &dst = comb[q * 1024 + i * 32 + j];
-          dst = (w == 0) ? dacc[q][v] : dst + dacc[q][v];
-        }
+        for (int b = 0; b < S; ++b) comb[(bi * S + a) * C + bj * S + b] += double(acc[a][b]);
     }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < TP * 1024; e += 256)
-    partial[int64_t(blockIdx.x) * TP * 1024 + e] = comb[e];
+  for (int e = tid; e < C * C; e += 256) partial[int64_t(blockIdx.x) * C * C + e] = comb[e];
 }
 
-// Sum partials over blocks in block order; write the full symmetric C x C.
-__global__ void k_lgram_reduce(const double *__restrict__ partial, int nblk, int T, int C,
+// G = sum over blocks (in order), symmetrised from the blocks on or above
+// the diagonal.
+__global__ void k_lgram_reduce(const double *__restrict__ partial, int nblk, int C, int S,
                                double *__restrict__ G) {
-  const int TP = T * (T + 1) / 2;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= TP * 1024) return;
+  if (e >= C * C) return;
+  int i = e / C, j = e % C;
+  if (i / S > j / S) { const int tmp = i; i = j; j = tmp; }
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[int64_t(b) * TP * 1024 + e];
-  const int p = e / 1024, ij = e % 1024, i = ij / 32, j = ij % 32;
-  int I = 0, J = 0, q = 0;
-  for (int a = 0; a < T; ++a)
-    for (int b = a; b < T; ++b) {
-      if (q == p) { I = a; J = b; }
-      ++q;
-    }
-  const int gi = 32 * I + i, gj = 32 * J + j;
-  if (gi < C && gj < C) {
-    G[gi * C + gj] = s;
-    G[gj * C + gi] = s;
-  }
+  for (int b = 0; b < nblk; ++b) s += partial[int64_t(b) * C * C + i * C + j];
+  G[e] = s;
 }
 
 // Cholesky of G with column dropping, then the Y-block columns of R^-1.
@@ -176,8 +166,22 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return uint16_t(u >> 16);
 }
 
-// V_next = [v0 | v1 | y] T (float64 arithmetic, one row per thread); the
-// first pool_rows rows also go to the pool at column col0.
+// V_next = [v0 | v1 | y] T in float64 arithmetic; one thread per (row,
+// chunk of CH outputs).  The first pool_rows rows also go to the pool at
+// column col0 (float32 or bfloat16).
+template <int CH>
+__device__ __forceinline__ void ld(const float *p, float (&v)[CH]) {
+  if constexpr (CH == 4) {
+    const float4 t = *reinterpret_cast<const float4 *>(p);
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+  } else if constexpr (CH == 2) {
+    const float2 t = *reinterpret_cast<const float2 *>(p);
+    v[0] = t.x; v[1] = t.y;
+  } else {
+    v[0] = *p;
+  }
+}
+
 template <int B>
 __global__ void __launch_bounds__(256)
 k_lapply(const float *__restrict__ v0, const float *__restrict__ v1,
@@ -185,38 +189,55 @@ k_lapply(const float *__restrict__ v0, const float *__restrict__ v1,
          int64_t rows, void *__restrict__ pool, int pool_type, int64_t pool_rows, int K,
          int col0) {
   constexpr int C = 3 * B;
+  constexpr int CH = B < 4 ? B : 4;
+  constexpr int NCH = B / CH;
   __shared__ double Ts[C * B];
   for (int e = threadIdx.x; e < C * B; e += 256) Ts[e] = Tm[e];
   __syncthreads();
-  const int64_t r = int64_t(xcd_block(blockIdx.x, gridDim.x)) * 256 + threadIdx.x;
+  const int64_t g = int64_t(xcd_block(blockIdx.x, gridDim.x)) * 256 + threadIdx.x;
+  const int64_t r = g / NCH;
+  const int ch = int(g % NCH);
   if (r >= rows) return;
-  double out[B];
+  double out[CH];
 #pragma unroll
-  for (int i = 0; i < B; ++i) out[i] = 0.0;
+  for (int c = 0; c < CH; ++c) out[c] = 0.0;
+  const float *src[3] = {v0, v1, y};
 #pragma unroll
-  for (int q = 0; q < C; ++q) {
-    float mv;
-    if (q < B) mv = v0 ? v0[r * B + q] : 0.0f;
-    else if (q < 2 * B) mv = v1 ? v1[r * B + q - B] : 0.0f;
-    else mv = y[r * B + q - 2 * B];
-    const double md = double(mv);
+  for (int a = 0; a < 3; ++a) {
+    if (src[a] == nullptr) continue;
 #pragma unroll
-    for (int i = 0; i < B; ++i) out[i] = fma(md, Ts[q * B + i], out[i]);
+    for (int q4 = 0; q4 < B / CH; ++q4) {
+      float v[CH];
+      ld<CH>(src[a] + r * B + q4 * CH, v);
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const double md = double(v[u]);
+        const double *trow = Ts + (a * B + q4 * CH + u) * B + ch * CH;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) out[c] = fma(md, trow[c], out[c]);
+      }
+    }
   }
-  float of[B];
+  float of[CH];
 #pragma unroll
-  for (int i = 0; i < B; ++i) of[i] = float(out[i]);
+  for (int c = 0; c < CH; ++c) of[c] = float(out[c]);
+  float *dst = vn + r * B + ch * CH;
+  if constexpr (CH == 4) {
+    *reinterpret_cast<float4 *>(dst) = make_float4(of[0], of[1], of[2], of[3]);
+  } else {
 #pragma unroll
-  for (int i = 0; i < B; ++i) vn[r * B + i] = of[i];
+    for (int c = 0; c < CH; ++c) dst[c] = of[c];
+  }
   if (pool && r < pool_rows) {
+    const int64_t off = r * K + col0 + ch * CH;
     if (pool_type == kPoolF32) {
-      float *pp = reinterpret_cast<float *>(pool) + r * K + col0;
+      float *pp = reinterpret_cast<float *>(pool) + off;
 #pragma unroll
-      for (int i = 0; i < B; ++i) pp[i] = of[i];
+      for (int c = 0; c < CH; ++c) pp[c] = of[c];
     } else {
-      uint16_t *pp = reinterpret_cast<uint16_t *>(pool) + r * K + col0;
+      uint16_t *pp = reinterpret_cast<uint16_t *>(pool) + off;
 #pragma unroll
-      for (int i = 0; i < B; ++i) pp[i] = f2bf(of[i]);
+      for (int c = 0; c < CH; ++c) pp[c] = f2bf(of[c]);
     }
   }
 }
@@ -245,7 +266,9 @@ hef_status apply_t(const float *v0, const float *v1, const float *y, const doubl
                    int64_t rows, void *pool, int pool_type, int64_t pool_rows, int K, int col0,
                    hipStream_t s) {
   if (rows == 0) return HEF_OK;
-  k_lapply<B><<<cdiv(rows, 256), 256, 0, s>>>(v0, v1, y, T, vn, rows, pool, pool_type,
+  TimedScope ts(kStLanczosApply, s);
+  constexpr int NCH = B < 4 ? 1 : B / 4;
+  k_lapply<B><<<cdiv(rows * NCH, 256), 256, 0, s>>>(v0, v1, y, T, vn, rows, pool, pool_type,
                                                pool_rows, K, col0);
   HEF_LAUNCH_CHECK();
   return HEF_OK;
@@ -264,20 +287,22 @@ hef_status lapply(int B, const float *v0, const float *v1, const float *y, const
   }
 }
 
-int tiles_for(int B) { return (3 * B + 31) / 32; }
-
 hef_status lgram(const float *v0, const float *v1, const float *y, int64_t rows, int B,
                  double *partial, double *G, hipStream_t s) {
-  const int T = tiles_for(B);
   const int C = 3 * B;
-  const int64_t per = std::max<int64_t>(8, cdiv(cdiv(rows, kGramBlocks), 8) * 8);
+  const int S = (C % 6 == 0) ? 6 : 3;
+  const int64_t per = std::max<int64_t>(64, cdiv(cdiv(rows, kGramBlocks), 64) * 64);
   const int nblk = int(std::max<int64_t>(1, cdiv(rows, per)));
-  if (T == 1)
-    k_lgram<1><<<nblk, 256, 0, s>>>(v0, v1, y, rows, B, per, partial);
-  else
-    k_lgram<2><<<nblk, 256, 0, s>>>(v0, v1, y, rows, B, per, partial);
-  const int TP = T * (T + 1) / 2;
-  k_lgram_reduce<<<cdiv(TP * 1024, 256), 256, 0, s>>>(partial, nblk, T, C, G);
+  TimedScope ts(kStLanczosGram, s);
+  switch (B) {
+    case 1: k_lgram<1><<<nblk, 256, 0, s>>>(v0, v1, y, rows, per, partial); break;
+    case 2: k_lgram<2><<<nblk, 256, 0, s>>>(v0, v1, y, rows, per, partial); break;
+    case 4: k_lgram<4><<<nblk, 256, 0, s>>>(v0, v1, y, rows, per, partial); break;
+    case 8: k_lgram<8><<<nblk, 256, 0, s>>>(v0, v1, y, rows, per, partial); break;
+    case 16: k_lgram<16><<<nblk, 256, 0, s>>>(v0, v1, y, rows, per, partial); break;
+    default: return HEF_ERR_UNSUPPORTED;
+  }
+  k_lgram_reduce<<<cdiv(C * C, 256), 256, 0, s>>>(partial, nblk, C, S, G);
   HEF_LAUNCH_CHECK();
   return HEF_OK;
 }
@@ -289,8 +314,7 @@ size_t krylov_ws_bytes(int64_t n, int64_t m, int B) {
   for (int i = 0; i < 4; ++i) a.take<float>((n + m) * B);
   for (int i = 0; i < 4; ++i) a.take<float>(n * B);
   a.take<float>(m * B);
-  const int T = tiles_for(B);
-  a.take<double>(size_t(2) * kGramBlocks * (T * (T + 1) / 2) * 1024);
+  a.take<double>(size_t(2) * kGramBlocks * 9 * B * B);
   a.take<double>(2 * 48 * 48);
   a.take<double>(2 * 48 * 16);
   a.take<int32_t>(2);
@@ -303,6 +327,7 @@ hef_status start_block(uint64_t seed, int level, int expansion, int64_t rows, in
   const uint64_t h = splitmix64(base + 2ull * uint64_t(level) + uint64_t(expansion));
   const int64_t total = rows * B;
   if (total == 0) return HEF_OK;
+  TimedScope ts(kStStart, s);
   k_start<<<cdiv(total, 256), 256, 0, s>>>(h, total, out);
   HEF_LAUNCH_CHECK();
   return HEF_OK;
@@ -318,8 +343,7 @@ hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double
   for (int i = 0; i < 4; ++i) sb[i] = ws.take<float>(Ns * B);
   for (int i = 0; i < 4; ++i) cb[i] = ws.take<float>(n * B);
   float *tb = ws.take<float>(m * B);
-  const int T = tiles_for(B);
-  double *partial = ws.take<double>(size_t(2) * kGramBlocks * (T * (T + 1) / 2) * 1024);
+  double *partial = ws.take<double>(size_t(2) * kGramBlocks * 9 * B * B);
   double *G = ws.take<double>(2 * 48 * 48);
   double *Tm = ws.take<double>(2 * 48 * 16);
   int32_t *drops = ws.take<int32_t>(2);
@@ -327,7 +351,7 @@ hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double
   const int C = 3 * B;
   double *Gs = G, *Gc = G + C * C;
   double *Ts = Tm, *Tc = Tm + C * B;
-  double *ps = partial, *pc = partial + size_t(kGramBlocks) * (T * (T + 1) / 2) * 1024;
+  double *ps = partial, *pc = partial + size_t(kGramBlocks) * 9 * B * B;
   HEF_HIP(hipMemsetAsync(drops, 0, 2 * sizeof(int32_t), s));
   HEF_HIP(hipMemsetAsync(G, 0, 2 * 48 * 48 * sizeof(double), s));
 
@@ -344,7 +368,10 @@ hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double
     HEF_HIP(hipMemcpyAsync(cb[iy], start_clique, n * B * sizeof(float), hipMemcpyDeviceToDevice, s));
     HEF_TRY(lgram(nullptr, nullptr, cb[iy], n, B, pc, Gc, s));
   }
-  k_lsolve<<<2, 64, 0, s>>>(G, C, B, tau, Tm, drops);
+  {
+    TimedScope ts(kStLanczosSolve, s);
+    k_lsolve<<<2, 64, 0, s>>>(G, C, B, tau, Tm, drops);
+  }
   HEF_LAUNCH_CHECK();
   if (use_star) HEF_TRY(lapply(B, nullptr, nullptr, sb[iy], Ts, sb[in], Ns, nullptr, 0, 0, K, 0, s));
   if (use_clique) HEF_TRY(lapply(B, nullptr, nullptr, cb[iy], Tc, cb[in], n, nullptr, 0, 0, K, 0, s));
@@ -359,7 +386,10 @@ hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double
       HEF_TRY(lgram(have_prev ? sb[ip] : nullptr, sb[ic], sb[iy], Ns, B, ps, Gs, s));
     if (use_clique)
       HEF_TRY(lgram(have_prev ? cb[ip] : nullptr, cb[ic], cb[iy], n, B, pc, Gc, s));
-    k_lsolve<<<2, 64, 0, s>>>(G, C, B, tau, Tm, drops);
+    {
+      TimedScope ts(kStLanczosSolve, s);
+      k_lsolve<<<2, 64, 0, s>>>(G, C, B, tau, Tm, drops);
+    }
     HEF_LAUNCH_CHECK();
     const int64_t col_s = (j - 1) * int64_t(B);
     const int64_t col_c = (use_star ? bk : 0) + (j - 1) * int64_t(B);

@@ -134,63 +134,150 @@ __global__ void k_jgram_reduce(const double *__restrict__ partial, int nchunks, 
   G[int64_t(gj) * K + gi] = s;
 }
 
-// Cholesky G = L L^T (float64) with dropping, then Rinv = (L^-1)^T, in one
-// 1024-thread workgroup.  A: working copy of G (row-major K x K); LT[k][j] =
-// L[j][k]; Rinv row-major (Kp x Kp, float64 and float32 copies).
-// With `force_keep` non-null, columns it marks 0 are dropped regardless.
+// Blocked left-looking Cholesky G = L L^T (float64) with the drop rule, one
+// 1024-thread workgroup.  L is kept column-major in global memory
+// (LT[c*K + r] = L[r][c]); each 32-column panel is updated by a 4x4
+// register-blocked product with the finished columns, then factored in LDS.
+// A column whose Schur pivot is <= tau^2 G_jj (or that `force_keep` marks 0)
+// is dropped: its column of L is zero.
+constexpr int kPW = 32;
+constexpr int kPS = kPW + 1;  // LDS row stride of a panel
+
 __global__ void __launch_bounds__(1024)
-k_jchol(const double *__restrict__ G, int K, int Kp, double tau, double *__restrict__ A,
-        double *__restrict__ LT, double *__restrict__ Rinv, float *__restrict__ Rinv32,
+k_jchol(const double *__restrict__ G, int K, double tau, double *__restrict__ LT,
         int32_t *__restrict__ keep, const int32_t *__restrict__ force_keep) {
+  extern __shared__ double pan[];  // [K][kPS]
+  __shared__ int s_keep;
   const int t = threadIdx.x;
-  for (int64_t e = t; e < int64_t(K) * K; e += 1024) { A[e] = G[e]; LT[e] = 0.0; }
-  for (int64_t e = t; e < int64_t(Kp) * Kp; e += 1024) { Rinv[e] = 0.0; Rinv32[e] = 0.0f; }
-  __shared__ int keep_k;
-  __shared__ double lkk;
+  for (int64_t e = t; e < int64_t(K) * K; e += 1024) LT[e] = 0.0;
   __syncthreads();
-  for (int k = 0; k < K; ++k) {
-    if (t == 0) {
-      const double d = A[int64_t(k) * K + k];
-      const double ref = G[int64_t(k) * K + k];
-      int kp = (ref > 0.0 && d > tau * tau * ref) ? 1 : 0;
-      if (force_keep && !force_keep[k]) kp = 0;
-      keep_k = kp;
-      keep[k] = kp;
-      lkk = kp ? sqrt(d) : 0.0;
-      LT[int64_t(k) * K + k] = lkk;
+  for (int c0 = 0; c0 < K; c0 += kPW) {
+    const int w = K - c0 < kPW ? K - c0 : kPW;
+    const int nr = K - c0;
+    // panel rows [c0, K) x cols [c0, c0+w): G minus the finished columns
+    const int nbi = (nr + 3) / 4, nbj = (w + 3) / 4;
+    for (int blk = t; blk < nbi * nbj; blk += 1024) {
+      const int bi = blk / nbj, bj = blk % nbj;
+      const int r0 = c0 + 4 * bi, q0 = c0 + 4 * bj;
+      if (4 * bi + 3 < 4 * bj) continue;  // strictly above the diagonal
+      double acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int r = r0 + a, q = q0 + b;
+          acc[a][b] = (r < K && q < c0 + w) ? G[int64_t(r) * K + q] : 0.0;
+        }
+      for (int l = 0; l < c0; ++l) {
+        const double *col = LT + int64_t(l) * K;
+        double x[4], y[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) x[a] = (r0 + a < K) ? col[r0 + a] : 0.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) y[b] = (q0 + b < K) ? col[q0 + b] : 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] -= x[a] * y[b];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int i = 4 * bi + a, j = 4 * bj + b;
+          if (i < nr && j < w) pan[i * kPS + j] = acc[a][b];
+        }
     }
     __syncthreads();
-    if (keep_k) {
-      for (int i = k + 1 + t; i < K; i += 1024) LT[int64_t(k) * K + i] = A[int64_t(i) * K + k] / lkk;
+    for (int jj = 0; jj < w; ++jj) {
+      if (t == 0) {
+        const double d = pan[jj * kPS + jj];
+        const double ref = G[int64_t(c0 + jj) * K + c0 + jj];
+        int kp = (ref > 0.0 && d > tau * tau * ref) ? 1 : 0;
+        if (force_keep && !force_keep[c0 + jj]) kp = 0;
+        keep[c0 + jj] = kp;
+        s_keep = kp;
+        pan[jj * kPS + jj] = kp ? sqrt(d) : 0.0;
+      }
       __syncthreads();
-      for (int i = k + 1 + t; i < K; i += 1024) {
-        const double lik = LT[int64_t(k) * K + i];
-        double *Ai = A + int64_t(i) * K;
-        const double *Lk = LT + int64_t(k) * K;
-        for (int j = k + 1; j <= i; ++j) Ai[j] -= lik * Lk[j];
+      const int kp = s_keep;
+      const double piv = pan[jj * kPS + jj];
+      for (int i = jj + 1 + t; i < nr; i += 1024)
+        pan[i * kPS + jj] = kp ? pan[i * kPS + jj] / piv : 0.0;
+      __syncthreads();
+      if (kp) {
+        const int wc = w - jj - 1;
+        if (wc > 0) {
+          for (int e = t; e < (nr - jj - 1) * wc; e += 1024) {
+            const int i = jj + 1 + e / wc, q = jj + 1 + e % wc;
+            if (q <= i) pan[i * kPS + q] -= pan[i * kPS + jj] * pan[q * kPS + jj];
+          }
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
-  }
-  // X = L^-1 (lower): X[i][j] = (delta_ij - sum_{l=j}^{i-1} L[i][l] X[l][j]) / L[i][i].
-  // Thread j owns column j of X, stored as Rinv[j][*] (Rinv = X^T).
-  for (int i = 0; i < K; ++i) {
-    const bool ki = keep[i] != 0;
-    const double lii = LT[int64_t(i) * K + i];
-    for (int j = t; j <= i; j += 1024) {
-      double x = 0.0;
-      if (ki && keep[j]) {
-        double acc = (i == j) ? 1.0 : 0.0;
-        const double *Xj = Rinv + int64_t(j) * Kp;
-        for (int l = j; l < i; ++l) acc -= LT[int64_t(l) * K + i] * Xj[l];
-        x = acc / lii;
-      }
-      Rinv[int64_t(j) * Kp + i] = x;
-      Rinv32[int64_t(j) * Kp + i] = float(x);
+    for (int e = t; e < nr * w; e += 1024) {
+      const int i = e / w, j = e % w;
+      if (i >= j) LT[int64_t(c0 + j) * K + c0 + i] = pan[i * kPS + j];
     }
     __syncthreads();
   }
 }
+
+// X = L^-1 by 32-column blocks, one workgroup per block J (independent):
+// X_JJ = L_JJ^-1, then X_IJ = -L_II^-1 sum_{M=J}^{I-1} L_IM X_MJ for I > J.
+// Rows and columns of dropped pivots are zero.  Writes Rinv = X^T
+// (row-major, Kp x Kp, float64 and float32; entries outside stay as set).
+__global__ void __launch_bounds__(1024)
+k_jtrinv(const double *__restrict__ LT, const int32_t *__restrict__ keep, int K, int Kp,
+         double *__restrict__ Rinv, float *__restrict__ Rinv32) {
+  extern __shared__ double X[];  // [K][kPS]: rows of the column block J
+  __shared__ double T[kPW * kPS];
+  const int t = threadIdx.x;
+  const int J = blockIdx.x;
+  const int j0 = J * kPW;
+  const int wj = K - j0 < kPW ? K - j0 : kPW;
+  const int nb = (K + kPW - 1) / kPW;
+  for (int e = t; e < K * kPS; e += 1024) X[e] = 0.0;
+  __syncthreads();
+  for (int I = J; I < nb; ++I) {
+    const int i0 = I * kPW;
+    const int wi = K - i0 < kPW ? K - i0 : kPW;
+    // T = -sum_{m in [j0, i0)} L[i0+i][m] X[m][j]   (zero for I == J)
+    {
+      const int i = t / kPW, j = t % kPW;
+      double acc = (I == J && i == j) ? 1.0 : 0.0;
+      if (i < wi && j < wj) {
+        for (int m = j0; m < i0; ++m) acc -= LT[int64_t(m) * K + i0 + i] * X[m * kPS + j];
+      }
+      T[i * kPS + j] = acc;
+    }
+    __syncthreads();
+    // solve L_II X_IJ = T by forward substitution, one column per thread
+    if (t < wj) {
+      const int j = t;
+      const bool colkeep = keep[j0 + j] != 0;
+      for (int i = 0; i < wi; ++i) {
+        double x = 0.0;
+        if (colkeep && keep[i0 + i]) {
+          double acc = T[i * kPS + j];
+          for (int l = 0; l < i; ++l) acc -= LT[int64_t(i0 + l) * K + i0 + i] * X[(i0 + l) * kPS + j];
+          x = acc / LT[int64_t(i0 + i) * K + i0 + i];
+        }
+        X[(i0 + i) * kPS + j] = x;
+      }
+    }
+    __syncthreads();
+  }
+  // Rinv[j0+j][i] = X[i][j]
+  for (int e = t; e < wj * K; e += 1024) {
+    const int j = e / K, i = e % K;
+    const double x = X[i * kPS + j];
+    Rinv[int64_t(j0 + j) * Kp + i] = x;
+    Rinv32[int64_t(j0 + j) * Kp + i] = float(x);
+  }
+}
+
 
 // In-place V <- V Rinv on 32-row slabs (LDS row stride K+1 avoids bank
 // conflicts of the column-wise A-operand reads).
@@ -260,6 +347,7 @@ hef_status gram_run(const void *pool, int pool_type, int64_t n, int K, double *G
   double *partial = ws.take<double>(size_t(p.nchunks) * p.npairs * 16 * 1024);
   if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
   HEF_HIP(hipMemsetAsync(G, 0, sizeof(double) * K * K, s));
+  TimedScope ts(kStOrthGram, s);
   k_jgram<<<int64_t(p.npairs) * p.nchunks, 256, 0, s>>>(pool, pool_type, n, K, p.nsb, p.npairs,
                                                         p.rows_per_chunk, partial);
   const int64_t tot = int64_t(p.npairs) * 16 * 1024;
@@ -309,12 +397,23 @@ hef_status orthonormalize_pool(void *pool, int pool_type, int64_t n, int K, doub
   const size_t lds = size_t(kSlab) * (K + 1) * sizeof(float);
   for (int pass = 0; pass < passes; ++pass) {
     HEF_TRY(gram_run(pool, pool_type, n, K, G, ws, s));
-    k_jchol<<<1, 1024, 0, s>>>(G, K, Kp, tau, A, LT, Rinv, Rinv32, keep,
-                               pass == 0 ? nullptr : keep);
+    {
+      TimedScope ts(kStOrthChol, s);
+      const size_t lds_c = size_t(K) * kPS * sizeof(double);
+      HEF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_jchol),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_c)));
+      HEF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_jtrinv),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_c)));
+      HEF_HIP(hipMemsetAsync(Rinv, 0, sizeof(double) * Kp * Kp, s));
+      HEF_HIP(hipMemsetAsync(Rinv32, 0, sizeof(float) * Kp * Kp, s));
+      k_jchol<<<1, 1024, lds_c, s>>>(G, K, tau, LT, keep, pass == 0 ? nullptr : keep);
+      k_jtrinv<<<(K + kPW - 1) / kPW, 1024, lds_c, s>>>(LT, keep, K, Kp, Rinv, Rinv32);
+    }
     HEF_LAUNCH_CHECK();
     if (n > 0) {
       HEF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_japply),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+      TimedScope ts(kStOrthApply, s);
       k_japply<<<cdiv(n, kSlab), 256, lds, s>>>(pool, pool_type, n, K, Kp, Rinv32);
       HEF_LAUNCH_CHECK();
     }

@@ -164,8 +164,12 @@ template <int CPL, int PT>
 hef_status score_t(const Level &L, const void *pool, int K, double *qh, float *R,
                    double *partial, int64_t nblk, hipStream_t s) {
   const int LPR = lanes_for(K, CPL);
+  {
+  TimedScope ts(kStScoreQ, s);
   k_score_qh<CPL, PT><<<nblk, kThreads, 0, s>>>(L.eptr, L.pins, L.w, pool, K, LPR, L.m, partial);
   k_score_qh_reduce<<<cdiv(K, 256), 256, 0, s>>>(partial, nblk, K, qh);
+  }
+  TimedScope ts(kStScoreR, s);
   k_score_r<CPL, PT><<<nblk, kThreads, 0, s>>>(L.eptr, L.pins, pool, K, LPR, L.m, qh, R);
   HEF_LAUNCH_CHECK();
   return HEF_OK;

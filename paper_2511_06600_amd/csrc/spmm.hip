@@ -275,6 +275,7 @@ hef_status spmm_t(const Level &L, const Structure &st, const float *xs, float *y
   const float *xE = xs ? xs + n * B : nullptr;
   float *yE = ys ? ys + n * B : nullptr;
   if (m > 0) {
+    TimedScope ts(kStSpmmCsr, s);
     const int64_t nb = cdiv(m * G::LPS, kThreads);
     k_csr_small<B><<<nb, kThreads, 0, s>>>(L.eptr, L.pins, st.s, st.alpha, st.beta, xs, xc,
                                            yE, tb, int32_t(m));
@@ -283,6 +284,7 @@ hef_status spmm_t(const Level &L, const Structure &st, const float *xs, float *y
     HEF_LAUNCH_CHECK();
   }
   if (n > 0) {
+    TimedScope ts(kStSpmmCsc, s);
     const int64_t nb = cdiv(n * G::LPS, kThreads);
     k_csc_small<B><<<nb, kThreads, 0, s>>>(st.vptr, st.eids, st.s, st.gam, st.alpha, xE, tb,
                                            xc, ys, yc, int32_t(n));

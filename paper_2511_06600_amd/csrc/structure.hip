@@ -124,6 +124,7 @@ hef_status validate_device(const Level &L, int32_t *flag_dev, int32_t *bad_host,
 
 hef_status structure_build(const Level &L, Structure &st, Arena &ws, hipStream_t s) {
   const int64_t n = L.n, m = L.m, nnz = L.nnz;
+  TimedScope ts(kStStructure, s);
   const size_t mk = ws.mark();
   uint32_t *keys = ws.take<uint32_t>(nnz);
   uint32_t *vals = ws.take<uint32_t>(nnz);
