@@ -5,12 +5,13 @@
 
 One step is one pass of the whole path over the synthetic 2M-node / 2.2M-net
 hypergraph (k = 30 Krylov steps per expansion, b = 8 start vectors, pool
-width K = 480, 3 coarsening levels): per level, the implicit star+clique
-block Krylov recurrence, the joint orthonormalisation, the resistance ratios,
-the Eq. (15) update, threshold contraction, local clustering and coarse
-rebuild.  Inputs are resident in HBM before timing starts.  The metric is ER
-estimates per second: hyperedge resistances estimated over all levels of a
-step, divided by the step time.  Rank 0 prints one JSON line.
+width K = 480, 3 coarsening levels, local clustering on): per level, the
+implicit star+clique block Krylov recurrence, the joint orthonormalisation,
+the resistance ratios, the Eq. (15) update, threshold contraction, local
+clustering and coarse rebuild (hef_coarsen).  Inputs are resident in HBM
+before timing starts.  The metric is ER estimates per second: hyperedge
+resistances estimated over all levels of a step, divided by the step time.
+Rank 0 prints one JSON line.
 """
 from __future__ import annotations
 
@@ -24,18 +25,58 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E, GB/s
-PEAK_FP32_MFMA = 157.3    # TFLOP/s dense
+PEAK_FP32_MFMA = 157.3    # TFLOP/s, dense FP32 matrix
 
 
-def spmm_step_bytes(n, m, nnz, b, s=4):
-    """Algorithmic bytes of one fused Krylov step (both expansions, b columns):
-    CSR pass: eptr, pins, gathered node scales, alpha/beta, node rows of both
-    vectors read once, hyperedge rows of both outputs written; CSC pass:
-    vptr, eids, alpha, hyperedge rows read once, own clique row, s and gamma,
-    node rows of both outputs written."""
+def spmm_bytes(n, m, nnz, b, s=4):
+    """Algorithmic bytes of one CSR pass and one CSC pass of a fused Krylov
+    step (both expansions, b columns).  CSR: eptr, pins, the node scales,
+    alpha and beta, the node rows of both input vectors once, the hyperedge
+    rows of both outputs.  CSC: vptr, eids, alpha, the hyperedge rows of
+    both inputs once, the own clique row, s and gamma, the node rows of both
+    outputs."""
     csr = 4 * (m + 1) + 4 * nnz + 4 * n + 8 * m + 2 * n * b * s + 2 * m * b * s
     csc = 4 * (n + 1) + 4 * nnz + 4 * m + 2 * m * b * s + n * b * s + 8 * n + 2 * n * b * s
     return csr, csc
+
+
+def gram_flops(n, K):
+    """FP32 matrix-core flops of one joint Gram (upper 128x128 super tiles,
+    diagonal super tiles computed on and above their 32x32 diagonal)."""
+    nsb = (K + 127) // 128
+    tiles = 0
+    for a in range(nsb):
+        for b in range(a, nsb):
+            tiles += 10 if a == b else 16
+    return 2.0 * n * 32 * 32 * tiles
+
+
+def cpu_baseline(cfg_name, seconds_hint):
+    """The FP64 oracle (as it stands) on a bounded sample of the workload:
+    the same recipe (size law, locality, weights, k, b, levels) at 1% of
+    the node and hyperedge counts."""
+    import numpy as np
+    from oracle import coarsen as oco
+    from synth import generate, get_config, start_block
+    cfg = get_config(cfg_name)
+    n, m = cfg["n"] // 100, cfg["m"] // 100
+    h = generate(n, m, cfg["lo"], cfg["hi"], cfg["alpha"], cfg["p_loc"],
+                 weights=cfg["weights"], seed=20251106 + cfg["index"])
+    start = lambda lev, x, rows, b: start_block(7, lev, x, rows, b)  # noqa: E731
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    out = oco.coarsen(h.n, h.m, h.eptr, h.pins, h.w, cfg["k"], cfg["b"], cfg["levels"], start,
+                      cfg["percentile"], cfg["local_clustering"])
+    dt = time.perf_counter() - t0
+    est = sum(lv[1] for lv in out.levels)
+    return {"value": est / dt, "unit": "estimates/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{cfg_name} recipe at n={h.n}, m={h.m} (1% of the nodes and nets), "
+                      f"k={cfg['k']}, b={cfg['b']}, {cfg['levels']} levels: {est} estimates "
+                      f"in {dt:.1f} s"}
 
 
 def main():
@@ -46,14 +87,13 @@ def main():
     ap.add_argument("--config", default="large2m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the BF16 and forward+backward side measurements")
+                    help="skip the Alg. 1-only and BF16 side measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                           "(the multi-GPU sharding is a design only)"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2511_06600_amd as hef
@@ -69,52 +109,66 @@ def main():
     print(f"# {args.config}: n={h.n} m={h.m} nnz={h.nnz} K={params.K} levels={params.levels}",
           file=sys.stderr, flush=True)
 
-    try:
-        hef.coarsen(dh, params)
-        whole_path = True
-    except hef.HefError as exc:
-        if exc.status != 6:
-            raise
-        whole_path = False
-    torch.cuda.synchronize()
-
-    def step():
-        if whole_path:
-            return hef.coarsen(dh, params)
-        return hef.resistance(dh, params)
-
     for _ in range(args.warmup):
-        step()
+        hef.coarsen(dh, params)
     torch.cuda.synchronize()
     hef.timing_read(reset=True)
     hef.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        out = step()
+        hef.coarsen(dh, params)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     hef.timing_enable(False)
     stages = hef.timing_read(reset=True)
+    levels = hef.last_coarsen_levels()
     ms_step = (t1 - t0) / args.steps * 1e3
-    print(f"# step {ms_step:.2f} ms", file=sys.stderr, flush=True)
-
-    # hyperedges estimated per step (every level runs Alg. 1 on its hypergraph)
-    est_per_step = h.m
-    if whole_path:
-        est_per_step = int(hef.last_level_sizes_sum()) if hasattr(hef, "last_level_sizes_sum") else h.m
+    est_per_step = sum(lv[1] for lv in levels)
     value = est_per_step / (ms_step / 1e3)
+    print(f"# step {ms_step:.2f} ms, levels {levels}", file=sys.stderr, flush=True)
 
-    # roofline of the dominant kernel
-    csr_b, csc_b = spmm_step_bytes(h.n, h.m, h.nnz, params.b)
-    per = {k: (v[0] / max(v[1], 1), v[1], v[0] / args.steps) for k, v in stages.items() if v[1]}
-    dominant = max(per, key=lambda k: per[k][2])
-    roof = None
+    # ---- rooflines from the HIP-event stage timings of the timed region
+    per = {k: v for k, v in stages.items() if v[1]}
+    stage_ms = {k: round(v[0] / args.steps, 3) for k, v in sorted(per.items(), key=lambda kv: -kv[1][0])}
+    k_steps = params.k
+    csr_tot = csc_tot = 0
+    for (n_l, m_l, z_l) in levels:
+        a, b_ = spmm_bytes(n_l, m_l, z_l, params.b)
+        csr_tot += a * k_steps
+        csc_tot += b_ * k_steps
+    csr_tot *= args.steps
+    csc_tot *= args.steps
+    rooflines = {}
+    if "spmm_csr" in per:
+        ms, cnt = per["spmm_csr"]
+        ach = csr_tot / (ms / 1e3) / 1e9
+        rooflines["k_csr_small"] = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS,
+                                    "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                                    "avg_launch_us": ms / cnt * 1e3, "launches": cnt}
     if "spmm_csc" in per:
-        # fused Krylov step at level 0 only is exact for the level-0 launches;
-        # report the level-0 CSC pass (per-launch mean over all levels is in stages)
-        pass
-    stage_ms = {k: round(v[2], 3) for k, v in sorted(per.items(), key=lambda kv: -kv[1][2])}
+        ms, cnt = per["spmm_csc"]
+        ach = csc_tot / (ms / 1e3) / 1e9
+        rooflines["k_csc_small"] = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS,
+                                    "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                                    "avg_launch_us": ms / cnt * 1e3, "launches": cnt}
+    if "orth_gram" in per:
+        ms, cnt = per["orth_gram"]
+        fl = sum(gram_flops(n_l, params.K) for (n_l, _, _) in levels) * args.steps
+        ach = fl / (ms / 1e3) / 1e12
+        rooflines["k_jgram"] = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA,
+                                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA,
+                                "avg_launch_us": ms / cnt * 1e3, "launches": cnt}
+    # the dominant kernel among those with a defined roofline
+    kernel_stage = {"k_csr_small": "spmm_csr", "k_csc_small": "spmm_csc", "k_jgram": "orth_gram"}
+    dom = max(rooflines, key=lambda k: per[kernel_stage[k]][0]) if rooflines else None
+    roof = None
+    if dom:
+        r = rooflines[dom]
+        roof = {"bound": r["bound"], "achieved": r["achieved"], "peak": r["peak"],
+                "unit": r["unit"], "frac": r["frac"], "traffic": None, "kernel": dom,
+                "avg_launch_us": r["avg_launch_us"]}
+
     result = {
         "metric": "ER estimates/s (2M-node FP32 hot path)",
         "value": value,
@@ -128,13 +182,46 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: n={h.n} m={h.m} nnz={h.nnz} k={params.k} "
-                               f"b={params.b} K={params.K} levels={params.levels}",
-                   "whole_path": whole_path},
+        "config": {"workload": f"{args.config}: n={h.n}, m={h.m}, nnz={h.nnz}, k={params.k}, "
+                               f"b={params.b}, K={params.K}, {params.levels} coarsening levels, "
+                               f"local clustering on (hef_coarsen)",
+                   "levels": [list(lv) for lv in levels]},
         "stage_ms_per_step": stage_ms,
-        "dominant_stage": dominant,
+        "rooflines": rooflines,
         "roofline": roof,
     }
+
+    if not args.no_extras:
+        # Alg. 1 alone at level 0 (the resistance estimate), FP32 and BF16 pool
+        extra = {}
+        for basis in ("fp32", "bf16"):
+            p1 = hef.Params(k=cfg["k"], b=cfg["b"], basis=basis, assume_valid=True)
+            hef.resistance(dh, p1)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            reps = 3
+            for _ in range(reps):
+                hef.resistance(dh, p1)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - ta) / reps
+            extra[f"alg1_{basis}_estimates_per_s"] = h.m / dt
+            extra[f"alg1_{basis}_ms"] = dt * 1e3
+            pc = hef.Params(k=cfg["k"], b=cfg["b"], levels=cfg["levels"], basis=basis,
+                            assume_valid=True)
+            if basis == "bf16":
+                hef.coarsen(dh, pc)
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                hef.coarsen(dh, pc)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - ta
+                lv = hef.last_coarsen_levels()
+                extra["coarsen_bf16_estimates_per_s"] = sum(x[1] for x in lv) / dt
+                extra["coarsen_bf16_ms"] = dt * 1e3
+        result["extras"] = extra
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(args.config, 20)
     print(json.dumps(result))
 
 

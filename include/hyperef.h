@@ -155,6 +155,11 @@ hef_status hef_coarsen(const hef_hypergraph *hg, const hef_params *p,
                        int32_t *cluster, int32_t *n_clusters, float *R0,
                        float *eta, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Sizes (n, m, nnz; HOST arrays of `cap` entries, any may be NULL) of the
+ * levels whose resistances the calling thread's last hef_coarsen call
+ * estimated; returns the number of such levels. */
+int32_t hef_last_coarsen_levels(int32_t *n, int32_t *m, int64_t *nnz, int32_t cap);
+
 /* One level of Alg. 2 (steps 4-10) from GIVEN inputs, so that a caller can
  * feed the same resistances to two implementations:
  *   R        DEVICE [m] float32 resistances of this level;

@@ -228,6 +228,18 @@ def validate_host(n, m, eptr, pins, w=None) -> int:
                                      None if ww is None else ww.ctypes.data))
 
 
+def last_coarsen_levels() -> list:
+    """[(n, m, nnz)] of the levels the calling thread's last coarsen estimated."""
+    lib = load()
+    cap = 64
+    n = (C.c_int32 * cap)()
+    m = (C.c_int32 * cap)()
+    z = (C.c_int64 * cap)()
+    k = lib.hef_last_coarsen_levels(C.cast(n, C.c_void_p), C.cast(m, C.c_void_p),
+                                    C.cast(z, C.c_void_p), cap)
+    return [(n[i], m[i], z[i]) for i in range(min(k, cap))]
+
+
 def timing_enable(on: bool = True) -> None:
     """Per-stage HIP-event timing inside the library (profiling aid)."""
     load().hef_timing_enable(1 if on else 0)

@@ -22,7 +22,7 @@ EXPORTS = [
     "hef_resistance", "hef_coarsen", "hef_cluster_level", "hef_resistance_backward",
     "hef_debug_apply", "hef_debug_gram", "hef_debug_gram_ws", "hef_start_block",
     "hef_status_string", "hef_last_error", "hef_timing_enable", "hef_timing_stage_count",
-    "hef_timing_stage_name", "hef_timing_read",
+    "hef_timing_stage_name", "hef_timing_read", "hef_last_coarsen_levels",
 ]
 
 
@@ -77,6 +77,7 @@ def load() -> C.CDLL:
         "hef_timing_stage_count": (i32, []),
         "hef_timing_stage_name": (C.c_char_p, [i32]),
         "hef_timing_read": (i32, [vp, vp, i32, i32]),
+        "hef_last_coarsen_levels": (i32, [vp, vp, vp, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

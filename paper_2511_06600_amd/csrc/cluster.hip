@@ -165,17 +165,77 @@ __global__ void k_centroids(const int32_t *__restrict__ eptr, const int32_t *__r
 }
 
 // ---- a8: best neighbouring cluster of every isolated node --------------------
-// One wave per node; lanes split the columns.  For every co-pin v of every
-// hyperedge of p, C = prov[v] and d(p, C) as above; best = (smallest d,
-// smallest label).
+// Columns with Q_H > 0 sorted by ascending Q_H (largest weights first).
+__global__ void __launch_bounds__(512)
+k_qh_order(const double *__restrict__ qh, int K, int32_t *__restrict__ perm,
+           float *__restrict__ inv32, int32_t *__restrict__ nuse) {
+  const int i = threadIdx.x;
+  if (i < K && qh[i] > 0.0) {
+    int r = 0;
+    for (int j = 0; j < K; ++j)
+      if (qh[j] > 0.0 && (qh[j] < qh[i] || (qh[j] == qh[i] && j < i))) ++r;
+    perm[r] = i;
+    inv32[r] = float(1.0 / qh[i]);
+  }
+  if (i == 0) {
+    int c = 0;
+    for (int j = 0; j < K; ++j) c += qh[j] > 0.0 ? 1 : 0;
+    *nuse = c;
+  }
+  __syncthreads();
+  for (int q = i; q < 512; q += 512)
+    if (q >= *nuse) { perm[q] = 0; inv32[q] = 0.0f; }
+}
+
+// cperm[C][q] = float32 of cluster C's centroid in column perm[q] (zero for
+// q >= nuse), for every cluster id C (a node that is its cluster's smallest
+// member).  Row width Kq = K rounded up to 64.
+template <int PT>
+__global__ void k_cperm(const int32_t *__restrict__ prov, const int32_t *__restrict__ owner,
+                        const int32_t *__restrict__ in_index, const double *__restrict__ cent,
+                        const void *__restrict__ pool, int K, int Kq,
+                        const int32_t *__restrict__ perm, const int32_t *__restrict__ nuse,
+                        float *__restrict__ cperm, int32_t n) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(n) * Kq) return;
+  const int64_t v = idx / Kq;
+  const int q = int(idx % Kq);
+  if (prov[v] != v) return;
+  float val = 0.0f;
+  if (q < *nuse) {
+    const int col = perm[q];
+    const int32_t ow = owner[v];
+    val = ow < 0 ? float(pool_val<PT>(pool, v * K + col))
+                 : float(cent[int64_t(in_index[ow]) * K + col]);
+  }
+  cperm[v * Kq + q] = val;
+}
+
+// Safe float32 lower bound of one column's term (x - c)^2 / Q_H given the
+// float32 copy s of c (|s - c| <= 2^-24 |c| < 2^-23 |s|).
+__device__ __forceinline__ float lb_term(float x, float s, float iq) {
+  float dev = fabsf(x - s) - 0x1p-23f * fabsf(s);
+  dev = dev > 0.0f ? dev : 0.0f;
+  return dev * dev * iq;
+}
+
+// One wave per isolated node p.  For every co-pin v of every hyperedge of p,
+// C = prov[v]; best = (smallest d(p, C), smallest label).  Candidates are
+// screened by float32 lower bounds of d (first the 64, then the 256
+// largest-weight columns), which exceed the exact float64 value by at most
+// a relative 1e-6; a candidate whose bound exceeds the best exact distance
+// so far times (1 + 1e-5) cannot be the minimum or tie with it.  Survivors
+// get the exact float64 distance.
 template <int PT>
 __global__ void __launch_bounds__(kT)
 k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
        const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
        const int32_t *__restrict__ owner, const int32_t *__restrict__ prov,
        const int32_t *__restrict__ in_index, const double *__restrict__ cent,
-       const void *__restrict__ pool, int K, const double *__restrict__ qh,
-       int32_t n, int32_t *__restrict__ best_label, double *__restrict__ best_d) {
+       const float *__restrict__ cperm, int Kq, const int32_t *__restrict__ perm,
+       const float *__restrict__ inv32, const void *__restrict__ pool, int K,
+       const double *__restrict__ qh, int32_t n, int32_t *__restrict__ best_label,
+       double *__restrict__ best_d) {
   const int lane = threadIdx.x & 63;
   const int64_t p = (int64_t(blockIdx.x) * kT + threadIdx.x) >> 6;
   if (p >= n) return;
@@ -183,7 +243,8 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
     if (lane == 0) best_label[p] = -1;
     return;
   }
-  // this lane's columns: lane, lane+64, ... ; xp and 1/qh flags kept in registers
+  constexpr double kMargin = 1.0 + 1e-5;
+  // exact stage: natural columns lane + 64q
   constexpr int MAXC = 8;
   double xp[MAXC], qv[MAXC];
 #pragma unroll
@@ -192,36 +253,98 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
     xp[q] = col < K ? pool_val<PT>(pool, p * K + col) : 0.0;
     qv[q] = col < K ? qh[col] : 0.0;
   }
+  // stage A: lane group g = lane/8 screens candidate g of a batch; lane
+  // a = lane%8 covers permuted columns 8a..8a+7
+  const int a8 = lane & 7;
+  float xa[8], ia[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int q = 8 * a8 + t;
+    xa[t] = q < Kq ? float(pool_val<PT>(pool, p * K + perm[q])) : 0.0f;
+    ia[t] = q < Kq ? inv32[q] : 0.0f;
+  }
+  // stage B: lane a of a group covers permuted columns 32a..32a+31 (from LDS)
+  __shared__ float xs_all[kT / 64][256];
+  __shared__ float is_all[kT / 64][256];
+  float *xsw = xs_all[threadIdx.x >> 6];
+  float *isw = is_all[threadIdx.x >> 6];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int q = lane + 64 * t;
+    xsw[q] = q < Kq ? float(pool_val<PT>(pool, p * K + perm[q])) : 0.0f;
+    isw[q] = q < Kq ? inv32[q] : 0.0f;
+  }
+  const int kb = Kq < 256 ? Kq : 256;  // stage-B width
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
   double bd = DBL_MAX;
   int32_t bl = INT32_MAX;
+  int32_t last = -1;
   for (int32_t jj = vptr[p]; jj < vptr[p + 1]; ++jj) {
     const int32_t e = eids[jj];
-    for (int32_t j = eptr[e]; j < eptr[e + 1]; ++j) {
-      const int32_t v = pins[j];
-      if (v == p) continue;
-      const int32_t C = prov[v];
-      const int32_t ow = owner[v];
-      // centroid row: the node itself (singleton) or the contracted cluster
-      const int64_t crow = ow < 0 ? -1 : int64_t(in_index[ow]);
-      double dl = 0.0;
+    const int32_t ea = eptr[e], eb = eptr[e + 1];
+    for (int32_t j0 = ea; j0 < eb; j0 += 8) {
+      const int32_t jg = j0 + (lane >> 3);
+      int32_t vg = jg < eb ? pins[jg] : -1;
+      if (vg == p) vg = -1;
+      const int32_t Cg = vg >= 0 ? prov[vg] : -1;
+      float lbg = 0.0f;
+      if (Cg >= 0 && 8 * a8 < Kq) {
+        const float4 *row = reinterpret_cast<const float4 *>(cperm + int64_t(Cg) * Kq + 8 * a8);
+        const float4 s0 = row[0], s1 = row[1];
+        const float sv[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
 #pragma unroll
-      for (int q = 0; q < MAXC; ++q) {
-        const int col = lane + 64 * q;
-        if (col < K && qv[q] > 0.0) {
-          const double c = crow < 0 ? pool_val<PT>(pool, int64_t(v) * K + col) : cent[crow * K + col];
-          const double diff = xp[q] - c;
-          const double sq = diff * diff;
-          const double r = sq / qv[q];
-          dl = r > dl ? r : dl;
+        for (int t = 0; t < 8; ++t) lbg = fmaxf(lbg, lb_term(xa[t], sv[t], ia[t]));
+      }
+      for (int off = 4; off > 0; off >>= 1) lbg = fmaxf(lbg, __shfl_xor(lbg, off, 8));
+      // stage B, per group, for candidates stage A did not rule out
+      if (Cg >= 0 && bd != DBL_MAX && !(double(lbg) > bd * kMargin) && kb > 64) {
+        const int q0 = 32 * a8;
+        if (q0 < kb) {
+          const float4 *row = reinterpret_cast<const float4 *>(cperm + int64_t(Cg) * Kq + q0);
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const float4 sv = row[u];
+            const int q = q0 + 4 * u;
+            lbg = fmaxf(lbg, lb_term(xsw[q], sv.x, isw[q]));
+            lbg = fmaxf(lbg, lb_term(xsw[q + 1], sv.y, isw[q + 1]));
+            lbg = fmaxf(lbg, lb_term(xsw[q + 2], sv.z, isw[q + 2]));
+            lbg = fmaxf(lbg, lb_term(xsw[q + 3], sv.w, isw[q + 3]));
+          }
         }
+        for (int off = 4; off > 0; off >>= 1) lbg = fmaxf(lbg, __shfl_xor(lbg, off, 8));
       }
-      for (int off = 32; off > 0; off >>= 1) {
-        const double o = __shfl_xor(dl, off, 64);
-        dl = o > dl ? o : dl;
-      }
-      if (dl < bd || (dl == bd && C < bl)) {
-        bd = dl;
-        bl = C;
+      const int nb = (eb - j0) < 8 ? (eb - j0) : 8;
+      for (int t = 0; t < nb; ++t) {
+        const int32_t v = __shfl(vg, 8 * t, 64);
+        if (v < 0) continue;
+        const int32_t C = __shfl(Cg, 8 * t, 64);
+        const float lba = __shfl(lbg, 8 * t, 64);
+        if (C == last) continue;
+        last = C;
+        if (bd != DBL_MAX && double(lba) > bd * kMargin) continue;
+        const int32_t ow = owner[v];
+        const int64_t crow = ow < 0 ? -1 : int64_t(in_index[ow]);
+        double dl = 0.0;
+#pragma unroll
+        for (int q = 0; q < MAXC; ++q) {
+          const int col = lane + 64 * q;
+          if (col < K && qv[q] > 0.0) {
+            const double c = crow < 0 ? pool_val<PT>(pool, int64_t(v) * K + col) : cent[crow * K + col];
+            const double diff = xp[q] - c;
+            const double sq = diff * diff;
+            const double r = sq / qv[q];
+            dl = r > dl ? r : dl;
+          }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          const double o = __shfl_xor(dl, off, 64);
+          dl = o > dl ? o : dl;
+        }
+        if (dl < bd || (dl == bd && C < bl)) {
+          bd = dl;
+          bl = C;
+        }
       }
     }
   }
@@ -447,6 +570,8 @@ struct LevelWs {
   unsigned long long *packed;
   float *prov_eta;
   double *best_d, *cent;
+  float *cperm, *inv32;
+  int32_t *perm;
   int32_t *small;  // [8] device scalars
   float *delta;
 };
@@ -476,6 +601,9 @@ void carve_level(Arena &a, int64_t n, int64_t m, int64_t nnz, int K, LevelWs &w)
   w.prov_eta = a.take<float>(n + 1);
   w.best_d = a.take<double>(n + 1);
   w.cent = a.take<double>((n / 2 + 1) * int64_t(K));
+  w.cperm = a.take<float>((n + 1) * int64_t((K + 63) / 64 * 64));
+  w.inv32 = a.take<float>(512);
+  w.perm = a.take<int32_t>(512);
   w.small = a.take<int32_t>(8);
   w.delta = a.take<float>(1);
 }
@@ -568,16 +696,24 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
     if (n > 0) k_set_i32<<<g1(n), kT, 0, s>>>(w.best_label, -1, n);
     HEF_LAUNCH_CHECK();
     if (local && n > 0 && m > 0 && K > 0) {
+      const int Kq = (K + 63) / 64 * 64;
+      k_qh_order<<<1, 512, 0, s>>>(qh, K, w.perm, w.inv32, w.small + 3);
       if (pool_type == kPoolF32) {
         k_centroids<kPoolF32><<<2048, kT, 0, s>>>(L.eptr, L.pins, w.in_list, w.small + 1, pool, K, w.cent);
+        k_cperm<kPoolF32><<<g1(n * Kq), kT, 0, s>>>(w.prov, w.owner, w.in_index, w.cent, pool, K, Kq,
+                                                   w.perm, w.small + 3, w.cperm, int32_t(n));
         k_best<kPoolF32><<<cdiv(n * 64, kT), kT, 0, s>>>(L.eptr, L.pins, st.vptr, st.eids, w.owner,
-                                                         w.prov, w.in_index, w.cent, pool, K, qh,
-                                                         int32_t(n), w.best_label, w.best_d);
+                                                     w.prov, w.in_index, w.cent, w.cperm, Kq, w.perm,
+                                                     w.inv32, pool, K, qh, int32_t(n),
+                                                     w.best_label, w.best_d);
       } else {
         k_centroids<kPoolBF16><<<2048, kT, 0, s>>>(L.eptr, L.pins, w.in_list, w.small + 1, pool, K, w.cent);
+        k_cperm<kPoolBF16><<<g1(n * Kq), kT, 0, s>>>(w.prov, w.owner, w.in_index, w.cent, pool, K, Kq,
+                                                   w.perm, w.small + 3, w.cperm, int32_t(n));
         k_best<kPoolBF16><<<cdiv(n * 64, kT), kT, 0, s>>>(L.eptr, L.pins, st.vptr, st.eids, w.owner,
-                                                          w.prov, w.in_index, w.cent, pool, K, qh,
-                                                          int32_t(n), w.best_label, w.best_d);
+                                                     w.prov, w.in_index, w.cent, w.cperm, Kq, w.perm,
+                                                     w.inv32, pool, K, qh, int32_t(n),
+                                                     w.best_label, w.best_d);
       }
       HEF_LAUNCH_CHECK();
     }
@@ -719,12 +855,19 @@ size_t cluster_level_bytes(int64_t n, int64_t m, int64_t nnz, int K) {
 
 namespace {
 
+// Sizes of the levels of the calling thread's last hef_coarsen call.
+constexpr int kMaxLevelLog = 64;
+thread_local int32_t g_levels_run = 0;
+thread_local int32_t g_level_n[kMaxLevelLog];
+thread_local int32_t g_level_m[kMaxLevelLog];
+thread_local int64_t g_level_nnz[kMaxLevelLog];
+
 // Persistent part of the coarsening workspace (sized at level 0, which
 // bounds every level).
 struct CoarsenWs {
   Structure st;
   int32_t *flags;
-  void *pool;
+  void *pool, *pool2;
   double *qh;
   float *R;
   int32_t *eptr[2], *pins[2];
@@ -738,6 +881,7 @@ void carve_coarsen(Arena &a, int64_t n, int64_t m, int64_t nnz, const hef_params
   c.flags = a.take<int32_t>(4);
   const int K = pool_width_of(p);
   c.pool = a.take<char>(size_t(n) * K * (p.basis == HEF_BASIS_BF16 ? 2 : 4));
+  c.pool2 = a.take<char>(size_t(n) * K * (p.basis == HEF_BASIS_BF16 ? 2 : 4));
   c.qh = a.take<double>(K);
   c.R = a.take<float>(m + 1);
   for (int i = 0; i < 2; ++i) {
@@ -836,8 +980,16 @@ hef_status hef_coarsen(const hef_hypergraph *hg, const hef_params *p, int32_t *c
   }
   const float *eta_cur = nullptr;
   int cur = 0;
+  g_levels_run = 0;
   for (int lev = 0; lev < p->levels && L.m > 0; ++lev) {
-    HEF_TRY(estimate_level(L, *p, p->seed, lev, nullptr, nullptr, c.st, c.pool, c.qh, c.R, a, stream));
+    if (lev < kMaxLevelLog) {
+      g_level_n[lev] = L.n;
+      g_level_m[lev] = L.m;
+      g_level_nnz[lev] = L.nnz;
+      g_levels_run = lev + 1;
+    }
+    HEF_TRY(estimate_level(L, *p, p->seed, lev, nullptr, nullptr, c.st, c.pool, c.pool2, c.qh,
+                           c.R, a, stream));
     if (lev == 0 && R0)
       HEF_HIP(hipMemcpyAsync(R0, c.R, sizeof(float) * L.m, hipMemcpyDeviceToDevice, stream));
     int32_t ng = 0;
@@ -869,6 +1021,16 @@ hef_status hef_coarsen(const hef_hypergraph *hg, const hef_params *p, int32_t *c
   HEF_HIP(hipStreamSynchronize(stream));
   *n_clusters = L.n;
   return HEF_OK;
+}
+
+int32_t hef_last_coarsen_levels(int32_t *n, int32_t *m, int64_t *nnz, int32_t cap) {
+  const int32_t k = g_levels_run < cap ? g_levels_run : cap;
+  for (int32_t i = 0; i < k; ++i) {
+    if (n) n[i] = g_level_n[i];
+    if (m) m[i] = g_level_m[i];
+    if (nnz) nnz[i] = g_level_nnz[i];
+  }
+  return g_levels_run;
 }
 
 hef_status hef_resistance_backward(const hef_hypergraph *, const hef_params *, const float *,

@@ -111,6 +111,8 @@ enum Stage : int {
   kStClusterRebuild,
   kStAdjoint,
   kStStart,
+  kStSpmmCsrBig,
+  kStSpmmCscBig,
   kStageCount
 };
 

@@ -12,6 +12,7 @@
 #include <cmath>
 
 #include "krylov.hpp"
+#include "prims.hpp"
 
 namespace hef {
 namespace {
@@ -33,7 +34,7 @@ k_lgram(const float *__restrict__ v0, const float *__restrict__ v1,
   constexpr int NB = C / S;
   constexpr int NT = NB * (NB + 1) / 2;
   constexpr int RG = 256 / NT;
-  constexpr int SLAB = 64;
+  constexpr int SLAB = 128;
   constexpr int LD = C + 1;
   __shared__ float sh[SLAB * LD];
   __shared__ double comb[C * C];
@@ -58,16 +59,32 @@ k_lgram(const float *__restrict__ v0, const float *__restrict__ v1,
   const int64_t r1 = r0 + rows_per_blk < rows ? r0 + rows_per_blk : rows;
   for (int64_t base = r0; base < r1; base += SLAB) {
     __syncthreads();
-    for (int e = tid; e < SLAB * C; e += 256) {
-      const int r = e / C, c = e % C;
-      const int64_t row = base + r;
-      float v = 0.0f;
-      if (row < r1) {
-        if (c < B) v = v0 ? v0[row * B + c] : 0.0f;
-        else if (c < 2 * B) v = v1 ? v1[row * B + c - B] : 0.0f;
-        else v = y[row * B + c - 2 * B];
+    if constexpr (B >= 4) {
+      // float4 loads: each array's rows are contiguous B-float records
+      constexpr int Q = B / 4;
+      for (int e = tid; e < SLAB * 3 * Q; e += 256) {
+        const int a = e / (SLAB * Q);
+        const int rem = e % (SLAB * Q);
+        const int r = rem / Q, q = rem % Q;
+        const int64_t row = base + r;
+        const float *src = a == 0 ? v0 : (a == 1 ? v1 : y);
+        float4 t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (row < r1 && src) t = *reinterpret_cast<const float4 *>(src + row * B + 4 * q);
+        float *d = sh + r * LD + a * B + 4 * q;
+        d[0] = t.x; d[1] = t.y; d[2] = t.z; d[3] = t.w;
       }
-      sh[r * LD + c] = v;
+    } else {
+      for (int e = tid; e < SLAB * C; e += 256) {
+        const int r = e / C, c = e % C;
+        const int64_t row = base + r;
+        float v = 0.0f;
+        if (row < r1) {
+          if (c < B) v = v0 ? v0[row * B + c] : 0.0f;
+          else if (c < 2 * B) v = v1 ? v1[row * B + c - B] : 0.0f;
+          else v = y[row * B + c - 2 * B];
+        }
+        sh[r * LD + c] = v;
+      }
     }
     __syncthreads();
     if (active) {
@@ -98,17 +115,12 @@ k_lgram(const float *__restrict__ v0, const float *__restrict__ v1,
   for (int e = tid; e < C * C; e += 256) partial[int64_t(blockIdx.x) * C * C + e] = comb[e];
 }
 
-// G = sum over blocks (in order), symmetrised from the blocks on or above
-// the diagonal.
-__global__ void k_lgram_reduce(const double *__restrict__ partial, int nblk, int C, int S,
-                               double *__restrict__ G) {
+// Entries in blocks below the diagonal are copied from their mirror.
+__global__ void k_lgram_sym(double *__restrict__ G, int C, int S) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= C * C) return;
-  int i = e / C, j = e % C;
-  if (i / S > j / S) { const int tmp = i; i = j; j = tmp; }
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[int64_t(b) * C * C + i * C + j];
-  G[e] = s;
+  const int i = e / C, j = e % C;
+  if (i / S > j / S) G[e] = G[j * C + i];
 }
 
 // Cholesky of G with column dropping, then the Y-block columns of R^-1.
@@ -302,7 +314,9 @@ hef_status lgram(const float *v0, const float *v1, const float *y, int64_t rows,
     case 16: k_lgram<16><<<nblk, 256, 0, s>>>(v0, v1, y, rows, per, partial); break;
     default: return HEF_ERR_UNSUPPORTED;
   }
-  k_lgram_reduce<<<cdiv(C * C, 256), 256, 0, s>>>(partial, nblk, C, S, G);
+  HEF_LAUNCH_CHECK();
+  HEF_TRY(reduce_cols_f64(partial, nblk, int64_t(C) * C, G, s));
+  k_lgram_sym<<<cdiv(C * C, 256), 256, 0, s>>>(G, C, S);
   HEF_LAUNCH_CHECK();
   return HEF_OK;
 }

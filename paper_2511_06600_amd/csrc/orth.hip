@@ -3,22 +3,20 @@
 //   G = V^T V      FP32 matrix-core tiles over 32-row LDS slabs, FP32
 //                  accumulation flushed to float64 every 128 rows, float64
 //                  across row chunks (fixed order);
-//   G = R^T R      float64 Cholesky, one workgroup, with the drop rule;
-//   V <- V R^-1    FP32 matrix cores, in place, one 32-row slab per workgroup.
+//   G = R^T R      blocked float64 Cholesky with the drop rule, and R^-1;
+//   Q = V R^-1     FP32 matrix-core GEMM into the second pool buffer.
 // Cholesky QR produces the same Q as Gram-Schmidt (positive diag(R)).
 #include <cmath>
 
 #include "krylov.hpp"
 #include "orth.hpp"
+#include "prims.hpp"
 
 namespace hef {
 namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int kSB = 128;        // super-block width (4 MFMA tiles)
-constexpr int kSlab = 32;       // rows per LDS slab
-constexpr int kFlushSlabs = 4;  // FP32 accumulation over 128 rows
 
 __device__ __forceinline__ float pool_at(const void *pool, int pool_type, int64_t idx) {
   if (pool_type == kPoolF32) return reinterpret_cast<const float *>(pool)[idx];
@@ -30,108 +28,6 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
   u += 0x7FFFu + ((u >> 16) & 1u);
   return uint16_t(u >> 16);
-}
-
-// Loads rows [r, r+32) x cols [c0, c0+128) into sh[32][128] (zeros outside).
-__device__ __forceinline__ void load_slab(float *sh, const void *pool, int pool_type,
-                                          int64_t r, int64_t r_end, int c0, int K) {
-  const int col = threadIdx.x & 127;
-  const int rsub = threadIdx.x >> 7;  // 0..1
-#pragma unroll
-  for (int i = 0; i < kSlab / 2; ++i) {
-    const int rr = rsub + 2 * i;
-    const int64_t row = r + rr;
-    const int c = c0 + col;
-    sh[rr * kSB + col] = (row < r_end && c < K) ? pool_at(pool, pool_type, row * K + c) : 0.0f;
-  }
-}
-
-// Gram partials.  Block = (chunk, pair); pair p = (a <= b) of super blocks.
-// Wave w owns tile row w of the 128x128 super tile and its 4 column tiles.
-__device__ __forceinline__ int2 pair_of(int p, int nsb) {
-  for (int a = 0; a < nsb; ++a) {
-    if (p < nsb - a) return make_int2(a, a + p);
-    p -= nsb - a;
-  }
-  return make_int2(0, 0);
-}
-
-__global__ void __launch_bounds__(256)
-k_jgram(const void *__restrict__ pool, int pool_type, int64_t n, int K, int nsb,
-        int npairs, int64_t rows_per_chunk, double *__restrict__ partial) {
-  __shared__ float As[kSlab * kSB];
-  __shared__ float Bs[kSlab * kSB];
-  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const int pair = int(lb % npairs);
-  const int64_t chunk = lb / npairs;
-  const int2 ab = pair_of(pair, nsb);
-  const bool diag = ab.x == ab.y;
-  const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
-  const int64_t r0 = chunk * rows_per_chunk;
-  const int64_t r1 = r0 + rows_per_chunk < n ? r0 + rows_per_chunk : n;
-  floatx16 acc[4];
-  double dacc[4][16];
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) { acc[t][v] = 0.0f; dacc[t][v] = 0.0; }
-  const float *Bsrc = diag ? As : Bs;
-  int slabs = 0;
-  for (int64_t r = r0; r < r1; r += kSlab) {
-    __syncthreads();
-    load_slab(As, pool, pool_type, r, r1, ab.x * kSB, K);
-    if (!diag) load_slab(Bs, pool, pool_type, r, r1, ab.y * kSB, K);
-    __syncthreads();
-#pragma unroll 4
-    for (int s = 0; s < kSlab / 2; ++s) {
-      const int row = 2 * s + (lane >> 5);
-      const float a_op = As[row * kSB + 32 * w + (lane & 31)];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (!diag || t >= w) {
-          const float b_op = Bsrc[row * kSB + 32 * t + (lane & 31)];
-          acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op, b_op, acc[t], 0, 0, 0);
-        }
-      }
-    }
-    if (++slabs == kFlushSlabs) {
-      slabs = 0;
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) { dacc[t][v] += double(acc[t][v]); acc[t][v] = 0.0f; }
-    }
-  }
-  double *out = partial + (chunk * npairs + pair) * (16 * 1024);
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-      const int j = lane & 31;
-      out[(w * 4 + t) * 1024 + i * 32 + j] = dacc[t][v] + double(acc[t][v]);
-    }
-}
-
-// G[gi][gj] = sum over chunks (in order) of the partial tiles.
-__global__ void k_jgram_reduce(const double *__restrict__ partial, int nchunks, int nsb,
-                               int npairs, int K, double *__restrict__ G) {
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= int64_t(npairs) * 16 * 1024) return;
-  const int pair = int(e / (16 * 1024));
-  const int rem = int(e % (16 * 1024));
-  const int wt = rem / 1024, ij = rem % 1024;
-  const int w = wt / 4, t = wt % 4, i = ij / 32, j = ij % 32;
-  const int2 ab = pair_of(pair, nsb);
-  if (ab.x == ab.y && t < w) return;
-  const int gi = ab.x * kSB + 32 * w + i;
-  const int gj = ab.y * kSB + 32 * t + j;
-  if (gi >= K || gj >= K) return;
-  double s = 0.0;
-  for (int c = 0; c < nchunks; ++c) s += partial[(int64_t(c) * npairs + pair) * (16 * 1024) + rem];
-  G[int64_t(gi) * K + gj] = s;
-  G[int64_t(gj) * K + gi] = s;
 }
 
 // Blocked left-looking Cholesky G = L L^T (float64) with the drop rule, one
@@ -279,48 +175,250 @@ k_jtrinv(const double *__restrict__ LT, const int32_t *__restrict__ keep, int K,
 }
 
 
-// In-place V <- V Rinv on 32-row slabs (LDS row stride K+1 avoids bank
-// conflicts of the column-wise A-operand reads).
-__global__ void __launch_bounds__(256)
-k_japply(void *__restrict__ pool, int pool_type, int64_t n, int K, int Kp,
-         const float *__restrict__ Rinv32) {
-  extern __shared__ float slab[];
-  const int ld = K + 1;
-  const int64_t r0 = int64_t(xcd_block(blockIdx.x, gridDim.x)) * kSlab;
-  for (int e = threadIdx.x; e < kSlab * K; e += 256) {
-    const int i = e / K, c = e % K;
-    const int64_t row = r0 + i;
-    slab[i * ld + c] = row < n ? pool_at(pool, pool_type, row * K + c) : 0.0f;
+// ---------------------------------------------------------------- Gram
+// G = V^T V.  Block = (row chunk, super-tile pair (a <= b) of 128-column
+// super blocks).  8 waves; wave w owns the 32x32 tiles (w/2, 2(w%2)) and
+// (w/2, 2(w%2)+1) of the 128x128 super tile (tiles below the diagonal of a
+// diagonal super tile are skipped).  32-row slabs of both super blocks are
+// double-buffered in LDS; FP32 MFMA accumulators are flushed to float64
+// registers every 128 rows.
+constexpr int kSB = 128;        // super-block width (4 MFMA tiles)
+constexpr int kSlab = 32;       // rows per LDS slab
+constexpr int kFlushSlabs = 4;  // FP32 accumulation over 128 rows
+constexpr int kGT = 512;        // Gram workgroup size
+
+__device__ __forceinline__ int2 pair_of(int p, int nsb) {
+  for (int a = 0; a < nsb; ++a) {
+    if (p < nsb - a) return make_int2(a, a + p);
+    p -= nsb - a;
   }
-  for (int i = threadIdx.x; i < kSlab; i += 256) slab[i * ld + K] = 0.0f;
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
-  const int ntile = (K + 31) / 32;
-  for (int J = w; J < ntile; J += 4) {
-    floatx16 acc;
+  return make_int2(0, 0);
+}
+
+// 8 consecutive pool values (columns c..c+7 of row `row`) as floats; zeros
+// past the matrix.  Vector loads when the row stride allows.
+__device__ __forceinline__ void load8(const void *pool, int pool_type, int64_t row, int64_t rows,
+                                      int c, int K, float (&v)[8]) {
+  if (row >= rows || c >= K) {
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
-    const int kend = (32 * J + 32 < K) ? 32 * J + 32 : K;
-    const int c = 32 * J + (lane & 31);
-    for (int k0 = 0; k0 < kend; k0 += 2) {
-      const int k = k0 + (lane >> 5);
-      const float a_op = k < K ? slab[(lane & 31) * ld + k] : 0.0f;
-      const float b_op = k < K ? Rinv32[int64_t(k) * Kp + c] : 0.0f;
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op, b_op, acc, 0, 0, 0);
+    for (int q = 0; q < 8; ++q) v[q] = 0.0f;
+    return;
+  }
+  const int64_t off = row * K + c;
+  if (pool_type == kPoolF32) {
+    const float *p = reinterpret_cast<const float *>(pool) + off;
+    if ((K & 3) == 0 && c + 8 <= K) {
+      const float4 a = *reinterpret_cast<const float4 *>(p);
+      const float4 b = *reinterpret_cast<const float4 *>(p + 4);
+      v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+      v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = (c + q < K) ? p[q] : 0.0f;
     }
+  } else {
+    const uint16_t *p = reinterpret_cast<const uint16_t *>(pool) + off;
+    if ((K & 7) == 0 && c + 8 <= K) {
+      const uint4 a = *reinterpret_cast<const uint4 *>(p);
+      const uint32_t u[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-      const int64_t row = r0 + i;
-      if (row < n && c < K) {
-        if (pool_type == kPoolF32)
-          reinterpret_cast<float *>(pool)[row * K + c] = acc[v];
-        else
-          reinterpret_cast<uint16_t *>(pool)[row * K + c] = f2bf(acc[v]);
+      for (int q = 0; q < 4; ++q) {
+        v[2 * q] = __uint_as_float(u[q] << 16);
+        v[2 * q + 1] = __uint_as_float(u[q] & 0xFFFF0000u);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        v[q] = (c + q < K) ? __uint_as_float(uint32_t(p[q]) << 16) : 0.0f;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kGT)
+k_jgram(const void *__restrict__ pool, int pool_type, int64_t n, int K, int nsb, int npairs,
+        int64_t rows_per_chunk, double *__restrict__ partial) {
+  __shared__ float As[2][kSlab * kSB];
+  __shared__ float Bs[2][kSlab * kSB];
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int pair = int(lb % npairs);
+  const int64_t chunk = lb / npairs;
+  const int2 ab = pair_of(pair, nsb);
+  const bool diag = ab.x == ab.y;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int ti = w >> 1;                // tile row
+  const int tj0 = 2 * (w & 1);          // first of two tile columns
+  const bool on0 = !diag || tj0 >= ti;
+  const bool on1 = !diag || tj0 + 1 >= ti;
+  const int64_t r0 = chunk * rows_per_chunk;
+  const int64_t r1 = r0 + rows_per_chunk < n ? r0 + rows_per_chunk : n;
+  // loader: 32 rows x 128 cols = 512 groups of 8; thread -> (row, 8 cols)
+  const int lrow = tid >> 4, lcol = (tid & 15) * 8;
+  floatx16 acc0, acc1;
+  double d0[16], d1[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) { acc0[v] = 0.0f; acc1[v] = 0.0f; d0[v] = 0.0; d1[v] = 0.0; }
+  float ra[8], rb[8];
+  load8(pool, pool_type, r0 + lrow, r1, ab.x * kSB + lcol, K, ra);
+  if (!diag) load8(pool, pool_type, r0 + lrow, r1, ab.y * kSB + lcol, K, rb);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    As[0][lrow * kSB + lcol + q] = ra[q];
+    if (!diag) Bs[0][lrow * kSB + lcol + q] = rb[q];
+  }
+  __syncthreads();
+  int buf = 0, slabs = 0;
+  for (int64_t r = r0; r < r1; r += kSlab) {
+    const bool more = r + kSlab < r1;
+    if (more) {
+      load8(pool, pool_type, r + kSlab + lrow, r1, ab.x * kSB + lcol, K, ra);
+      if (!diag) load8(pool, pool_type, r + kSlab + lrow, r1, ab.y * kSB + lcol, K, rb);
+    }
+    const float *A = As[buf];
+    const float *Bm = diag ? As[buf] : Bs[buf];
+#pragma unroll 4
+    for (int s = 0; s < kSlab / 2; ++s) {
+      const int row = 2 * s + (lane >> 5);
+      const float a_op = A[row * kSB + 32 * ti + (lane & 31)];
+      if (on0) {
+        const float b0 = Bm[row * kSB + 32 * tj0 + (lane & 31)];
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op, b0, acc0, 0, 0, 0);
+      }
+      if (on1) {
+        const float b1 = Bm[row * kSB + 32 * (tj0 + 1) + (lane & 31)];
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op, b1, acc1, 0, 0, 0);
       }
     }
+    if (++slabs == kFlushSlabs) {
+      slabs = 0;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        d0[v] += double(acc0[v]); acc0[v] = 0.0f;
+        d1[v] += double(acc1[v]); acc1[v] = 0.0f;
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        As[buf ^ 1][lrow * kSB + lcol + q] = ra[q];
+        if (!diag) Bs[buf ^ 1][lrow * kSB + lcol + q] = rb[q];
+      }
+    }
+    __syncthreads();
+    buf ^= 1;
   }
+  double *out = partial + (chunk * npairs + pair) * (16 * 1024);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    const int j = lane & 31;
+    out[(ti * 4 + tj0) * 1024 + i * 32 + j] = on0 ? d0[v] + double(acc0[v]) : 0.0;
+    out[(ti * 4 + tj0 + 1) * 1024 + i * 32 + j] = on1 ? d1[v] + double(acc1[v]) : 0.0;
+  }
+}
+
+// G[gi][gj] from the chunk-summed tiles.
+__global__ void k_jgram_scatter(const double *__restrict__ sums, int nsb, int npairs, int K,
+                                double *__restrict__ G) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= int64_t(npairs) * 16 * 1024) return;
+  const int pair = int(e / (16 * 1024));
+  const int rem = int(e % (16 * 1024));
+  const int wt = rem / 1024, ij = rem % 1024;
+  const int ti = wt / 4, tj = wt % 4, i = ij / 32, j = ij % 32;
+  const int2 ab = pair_of(pair, nsb);
+  if (ab.x == ab.y && tj < ti) return;
+  const int gi = ab.x * kSB + 32 * ti + i;
+  const int gj = ab.y * kSB + 32 * tj + j;
+  if (gi >= K || gj >= K) return;
+  const double s = sums[e];
+  G[int64_t(gi) * K + gj] = s;
+  G[int64_t(gj) * K + gi] = s;
+}
+
+// ---------------------------------------------------------------- apply
+// Q = V Rinv (n x K times upper-triangular K x K), out of place.  Block =
+// 128 x 128 output tile; 4 waves of 64 x 64 (2 x 2 MFMA tiles).  The k
+// loop runs over 32-wide chunks up to the tile's last column (Rinv is zero
+// below its diagonal); both operand chunks are staged in LDS.
+constexpr int kAT = 256;
+constexpr int kAM = 128, kAN = 128, kAK = 32;
+constexpr int kALDA = kAK + 1;   // A chunk [128][33]
+constexpr int kALDB = kAN + 1;   // B chunk [32][129]
+
+__global__ void __launch_bounds__(kAT)
+k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int64_t n, int K,
+         int Kp, const float *__restrict__ Rinv32, int ncb) {
+  __shared__ float As[kAM * kALDA];
+  __shared__ float Bs[kAK * kALDB];
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int cb = int(lb % ncb);
+  const int64_t rt = lb / ncb;
+  const int64_t row0 = rt * kAM;
+  const int col0 = cb * kAN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
+  const int kend = (col0 + kAN < K) ? col0 + kAN : K;
+  for (int k0 = 0; k0 < kend; k0 += kAK) {
+    __syncthreads();
+    // A chunk: rows row0..+127, cols k0..k0+31 of V (8 floats per thread... 2 x 8)
+    for (int g = tid; g < kAM * (kAK / 8); g += kAT) {
+      const int r = g / (kAK / 8), c8 = (g % (kAK / 8)) * 8;
+      float v[8];
+      load8(V, pool_type, row0 + r, n, k0 + c8, K, v);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) As[r * kALDA + c8 + q] = (k0 + c8 + q < kend) ? v[q] : 0.0f;
+    }
+    // B chunk: rows k0..k0+31, cols col0..col0+127 of Rinv32 (row stride Kp)
+    for (int g = tid; g < kAK * (kAN / 4); g += kAT) {
+      const int r = g / (kAN / 4), c4 = (g % (kAN / 4)) * 4;
+      const int kk = k0 + r, cc = col0 + c4;
+      float4 t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (kk < kend && cc < Kp) t = *reinterpret_cast<const float4 *>(Rinv32 + int64_t(kk) * Kp + cc);
+      float *d = Bs + r * kALDB + c4;
+      d[0] = t.x; d[1] = t.y; d[2] = t.z; d[3] = t.w;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int s = 0; s < kAK / 2; ++s) {
+      const int kk = 2 * s + (lane >> 5);
+      float a_op[2], b_op[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) a_op[a] = As[(wr + 32 * a + (lane & 31)) * kALDA + kk];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) b_op[b] = Bs[kk * kALDB + wc + 32 * b + (lane & 31)];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[a], b_op[b], acc[a][b], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = row0 + wr + 32 * a + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int col = col0 + wc + 32 * b + (lane & 31);
+        if (row < n && col < K) {
+          if (pool_type == kPoolF32)
+            reinterpret_cast<float *>(Q)[row * K + col] = acc[a][b][v];
+          else
+            reinterpret_cast<uint16_t *>(Q)[row * K + col] = f2bf(acc[a][b][v]);
+        }
+      }
 }
 
 struct GramPlan {
@@ -332,7 +430,7 @@ GramPlan gram_plan(int64_t n, int K) {
   GramPlan p;
   p.nsb = (K + kSB - 1) / kSB;
   p.npairs = p.nsb * (p.nsb + 1) / 2;
-  int64_t want = std::max<int64_t>(1, 768 / p.npairs);
+  int64_t want = std::max<int64_t>(1, 512 / p.npairs);
   int64_t per = cdiv(std::max<int64_t>(n, 1), want);
   per = std::max<int64_t>(kSlab, cdiv(per, kSlab) * kSlab);
   p.rows_per_chunk = per;
@@ -345,15 +443,28 @@ hef_status gram_run(const void *pool, int pool_type, int64_t n, int K, double *G
   const GramPlan p = gram_plan(n, K);
   const size_t mk = ws.mark();
   double *partial = ws.take<double>(size_t(p.nchunks) * p.npairs * 16 * 1024);
+  const int64_t tot = int64_t(p.npairs) * 16 * 1024;
+  double *sums = ws.take<double>(tot);
   if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
   HEF_HIP(hipMemsetAsync(G, 0, sizeof(double) * K * K, s));
   TimedScope ts(kStOrthGram, s);
-  k_jgram<<<int64_t(p.npairs) * p.nchunks, 256, 0, s>>>(pool, pool_type, n, K, p.nsb, p.npairs,
+  k_jgram<<<int64_t(p.npairs) * p.nchunks, kGT, 0, s>>>(pool, pool_type, n, K, p.nsb, p.npairs,
                                                         p.rows_per_chunk, partial);
-  const int64_t tot = int64_t(p.npairs) * 16 * 1024;
-  k_jgram_reduce<<<cdiv(tot, 256), 256, 0, s>>>(partial, p.nchunks, p.nsb, p.npairs, K, G);
+  HEF_LAUNCH_CHECK();
+  HEF_TRY(reduce_cols_f64(partial, p.nchunks, tot, sums, s));
+  k_jgram_scatter<<<cdiv(tot, 256), 256, 0, s>>>(sums, p.nsb, p.npairs, K, G);
   HEF_LAUNCH_CHECK();
   ws.reset(mk);
+  return HEF_OK;
+}
+
+hef_status apply_run(const void *V, void *Q, int pool_type, int64_t n, int K, int Kp,
+                     const float *Rinv32, hipStream_t s) {
+  if (n == 0) return HEF_OK;
+  TimedScope ts(kStOrthApply, s);
+  const int ncb = (K + kAN - 1) / kAN;
+  k_japply<<<cdiv(n, kAM) * ncb, kAT, 0, s>>>(V, Q, pool_type, n, K, Kp, Rinv32, ncb);
+  HEF_LAUNCH_CHECK();
   return HEF_OK;
 }
 
@@ -364,12 +475,12 @@ size_t orth_ws_bytes(int64_t n, int K) {
   const GramPlan p = gram_plan(n, K);
   Arena a;
   a.take<double>(int64_t(K) * K);    // G
-  a.take<double>(int64_t(K) * K);    // A
   a.take<double>(int64_t(K) * K);    // LT
   a.take<double>(int64_t(Kp) * Kp);  // Rinv
   a.take<float>(int64_t(Kp) * Kp);   // Rinv32
   a.take<int32_t>(K);                // keep
   a.take<double>(size_t(p.nchunks) * p.npairs * 16 * 1024);
+  a.take<double>(size_t(p.npairs) * 16 * 1024);
   return a.mark() + 1024;
 }
 
@@ -378,8 +489,10 @@ hef_status gram_f32(const float *X, int64_t n, int K, double *G, Arena &ws, hipS
   return gram_run(X, kPoolF32, n, K, G, ws, s);
 }
 
-hef_status orthonormalize_pool(void *pool, int pool_type, int64_t n, int K, double tau,
-                               int passes, int32_t *keep_out, Arena &ws, hipStream_t s) {
+hef_status orthonormalize_pool(void *pool, void *pool2, int pool_type, int64_t n, int K,
+                               double tau, int passes, int32_t *keep_out, void **result,
+                               Arena &ws, hipStream_t s) {
+  *result = pool;
   if (K <= 0) return HEF_OK;
   if (K > 512) {
     set_error("pool width %d exceeds 512", K);
@@ -388,15 +501,14 @@ hef_status orthonormalize_pool(void *pool, int pool_type, int64_t n, int K, doub
   const int Kp = (K + 31) / 32 * 32;
   const size_t mk = ws.mark();
   double *G = ws.take<double>(int64_t(K) * K);
-  double *A = ws.take<double>(int64_t(K) * K);
   double *LT = ws.take<double>(int64_t(K) * K);
   double *Rinv = ws.take<double>(int64_t(Kp) * Kp);
   float *Rinv32 = ws.take<float>(int64_t(Kp) * Kp);
   int32_t *keep = ws.take<int32_t>(K);
   if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
-  const size_t lds = size_t(kSlab) * (K + 1) * sizeof(float);
+  void *src = pool, *dst = pool2;
   for (int pass = 0; pass < passes; ++pass) {
-    HEF_TRY(gram_run(pool, pool_type, n, K, G, ws, s));
+    HEF_TRY(gram_run(src, pool_type, n, K, G, ws, s));
     {
       TimedScope ts(kStOrthChol, s);
       const size_t lds_c = size_t(K) * kPS * sizeof(double);
@@ -408,16 +520,12 @@ hef_status orthonormalize_pool(void *pool, int pool_type, int64_t n, int K, doub
       HEF_HIP(hipMemsetAsync(Rinv32, 0, sizeof(float) * Kp * Kp, s));
       k_jchol<<<1, 1024, lds_c, s>>>(G, K, tau, LT, keep, pass == 0 ? nullptr : keep);
       k_jtrinv<<<(K + kPW - 1) / kPW, 1024, lds_c, s>>>(LT, keep, K, Kp, Rinv, Rinv32);
-    }
-    HEF_LAUNCH_CHECK();
-    if (n > 0) {
-      HEF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_japply),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-      TimedScope ts(kStOrthApply, s);
-      k_japply<<<cdiv(n, kSlab), 256, lds, s>>>(pool, pool_type, n, K, Kp, Rinv32);
       HEF_LAUNCH_CHECK();
     }
+    HEF_TRY(apply_run(src, dst, pool_type, n, K, Kp, Rinv32, s));
+    std::swap(src, dst);
   }
+  *result = src;
   if (keep_out) HEF_HIP(hipMemcpyAsync(keep_out, keep, K * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   ws.reset(mk);
   return HEF_OK;

@@ -148,12 +148,45 @@ __global__ void k_compact(const int32_t *flag, const int32_t *pos, int32_t *idx_
   if (i == 0) *count_dev = pos[n];
 }
 
+// 256 threads = 8 columns x 32 row lanes.
+__global__ void __launch_bounds__(256)
+k_reduce_cols(const double *__restrict__ in, int64_t nrows, int64_t ncols,
+              double *__restrict__ out) {
+  __shared__ double red[32][9];
+  const int cl = threadIdx.x & 7, rl = threadIdx.x >> 3;
+  const int64_t c = int64_t(blockIdx.x) * 8 + cl;
+  double a0 = 0.0, a1 = 0.0;
+  if (c < ncols) {
+    int64_t r = rl;
+    for (; r + 32 < nrows; r += 64) {
+      a0 += in[r * ncols + c];
+      a1 += in[(r + 32) * ncols + c];
+    }
+    if (r < nrows) a0 += in[r * ncols + c];
+  }
+  red[rl][cl] = a0 + a1;
+  __syncthreads();
+  for (int off = 16; off > 0; off >>= 1) {
+    if (rl < off) red[rl][cl] += red[rl + off][cl];
+    __syncthreads();
+  }
+  if (rl == 0 && c < ncols) out[c] = red[0][cl];
+}
+
 __global__ void k_flag_copy(const int32_t *flag, int32_t *out, int64_t n) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) out[i] = flag[i] ? 1 : 0;
 }
 
 }  // namespace
+
+hef_status reduce_cols_f64(const double *in, int64_t nrows, int64_t ncols, double *out,
+                           hipStream_t s) {
+  if (ncols <= 0) return HEF_OK;
+  k_reduce_cols<<<cdiv(ncols, 8), 256, 0, s>>>(in, nrows, ncols, out);
+  HEF_LAUNCH_CHECK();
+  return HEF_OK;
+}
 
 size_t scan_ws_bytes(int64_t n) {
   Arena a;

@@ -27,6 +27,12 @@ hef_status radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_out,
 hef_status compact_flags(const int32_t *flag, int32_t *scratch, int32_t *idx_out,
                          int32_t *count_dev, int64_t n, Arena &ws, hipStream_t s);
 
+// out[c] = sum_r in[r * ncols + c] (float64) in a fixed order that does not
+// depend on timing: 32 row lanes per column each sum every 32nd row (two
+// interleaved accumulators), then a fixed tree over the lanes.
+hef_status reduce_cols_f64(const double *in, int64_t nrows, int64_t ncols, double *out,
+                           hipStream_t s);
+
 inline int bits_for(int64_t maxval) {
   int b = 1;
   while (b < 32 && (int64_t(1) << b) <= maxval) ++b;

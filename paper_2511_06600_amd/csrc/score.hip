@@ -14,6 +14,7 @@
 #include <cfloat>
 
 #include "krylov.hpp"
+#include "prims.hpp"
 #include "score.hpp"
 
 namespace hef {
@@ -113,15 +114,6 @@ k_score_qh(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
   for (int c = tid; c < K; c += kThreads) partial[blk * K + c] = comb[c];
 }
 
-__global__ void k_score_qh_reduce(const double *__restrict__ partial, int64_t nblk, int K,
-                                  double *__restrict__ qh) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= K) return;
-  double s = 0.0;
-  for (int64_t b = 0; b < nblk; ++b) s += partial[b * K + c];
-  qh[c] = s;
-}
-
 template <int CPL, int PT>
 __global__ void __launch_bounds__(kThreads)
 k_score_r(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
@@ -167,7 +159,7 @@ hef_status score_t(const Level &L, const void *pool, int K, double *qh, float *R
   {
   TimedScope ts(kStScoreQ, s);
   k_score_qh<CPL, PT><<<nblk, kThreads, 0, s>>>(L.eptr, L.pins, L.w, pool, K, LPR, L.m, partial);
-  k_score_qh_reduce<<<cdiv(K, 256), 256, 0, s>>>(partial, nblk, K, qh);
+  HEF_TRY(reduce_cols_f64(partial, nblk, K, qh, s));
   }
   TimedScope ts(kStScoreR, s);
   k_score_r<CPL, PT><<<nblk, kThreads, 0, s>>>(L.eptr, L.pins, pool, K, LPR, L.m, qh, R);

@@ -69,13 +69,27 @@ k_csr_small(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
   float acc[G::CH];
 #pragma unroll
   for (int c = 0; c < G::CH; ++c) acc[c] = 0.0f;
-  for (int32_t j = a; j < b; ++j) {
-    const int32_t p = pins[j];
-    const float sp = s[p];
-    float v[G::CH];
-    load_ch<G::CH>(x + int64_t(p) * B + ch * G::CH, v);
+  // chunks of 8 pins: all ids first, then all rows, so the loads overlap
+  for (int32_t j0 = a; j0 < b; j0 += 8) {
+    int32_t pp[8];
 #pragma unroll
-    for (int c = 0; c < G::CH; ++c) acc[c] = fmaf(sp, v[c], acc[c]);
+    for (int u = 0; u < 8; ++u) pp[u] = (j0 + u < b) ? pins[j0 + u] : -1;
+    float sp[8], v[8][G::CH];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (pp[u] >= 0) {
+        sp[u] = s[pp[u]];
+        load_ch<G::CH>(x + int64_t(pp[u]) * B + ch * G::CH, v[u]);
+      } else {
+        sp[u] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < G::CH; ++c) v[u][c] = 0.0f;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int c = 0; c < G::CH; ++c) acc[c] = fmaf(sp[u], v[u][c], acc[c]);
   }
   const float f = vec == 0 ? alpha[e] : beta[e];
 #pragma unroll
@@ -162,22 +176,33 @@ k_csc_small(const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
   float acc[G::CH];
 #pragma unroll
   for (int c = 0; c < G::CH; ++c) acc[c] = 0.0f;
-  if (vec == 0) {
-    for (int32_t j = a; j < b; ++j) {
-      const int32_t e = eids[j];
-      const float f = alpha[e];
-      float v[G::CH];
-      load_ch<G::CH>(xE + int64_t(e) * B + ch * G::CH, v);
+  // chunks of 8 hyperedges: all ids first, then all rows
+  for (int32_t j0 = a; j0 < b; j0 += 8) {
+    int32_t ee[8];
 #pragma unroll
-      for (int c = 0; c < G::CH; ++c) acc[c] = fmaf(f, v[c], acc[c]);
+    for (int u = 0; u < 8; ++u) ee[u] = (j0 + u < b) ? eids[j0 + u] : -1;
+    float f[8], v[8][G::CH];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (ee[u] >= 0) {
+        f[u] = vec == 0 ? alpha[ee[u]] : 1.0f;
+        load_ch<G::CH>((vec == 0 ? xE : tb) + int64_t(ee[u]) * B + ch * G::CH, v[u]);
+      } else {
+        f[u] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < G::CH; ++c) v[u][c] = 0.0f;
+      }
     }
-  } else {
-    for (int32_t j = a; j < b; ++j) {
-      const int32_t e = eids[j];
-      float v[G::CH];
-      load_ch<G::CH>(tb + int64_t(e) * B + ch * G::CH, v);
+    if (vec == 0) {
 #pragma unroll
-      for (int c = 0; c < G::CH; ++c) acc[c] += v[c];
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int c = 0; c < G::CH; ++c) acc[c] = fmaf(f[u], v[u][c], acc[c]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int c = 0; c < G::CH; ++c) acc[c] += v[u][c];
     }
   }
   const float su = s[u];
@@ -275,21 +300,31 @@ hef_status spmm_t(const Level &L, const Structure &st, const float *xs, float *y
   const float *xE = xs ? xs + n * B : nullptr;
   float *yE = ys ? ys + n * B : nullptr;
   if (m > 0) {
-    TimedScope ts(kStSpmmCsr, s);
     const int64_t nb = cdiv(m * G::LPS, kThreads);
-    k_csr_small<B><<<nb, kThreads, 0, s>>>(L.eptr, L.pins, st.s, st.alpha, st.beta, xs, xc,
-                                           yE, tb, int32_t(m));
-    k_csr_big<B><<<kBigGrid, kThreads, 0, s>>>(st.big_e, st.n_big, L.eptr, L.pins, st.s,
-                                               st.alpha, st.beta, xs, xc, yE, tb);
+    {
+      TimedScope ts(kStSpmmCsr, s);
+      k_csr_small<B><<<nb, kThreads, 0, s>>>(L.eptr, L.pins, st.s, st.alpha, st.beta, xs, xc,
+                                             yE, tb, int32_t(m));
+    }
+    {
+      TimedScope ts(kStSpmmCsrBig, s);
+      k_csr_big<B><<<kBigGrid, kThreads, 0, s>>>(st.big_e, st.n_big, L.eptr, L.pins, st.s,
+                                                 st.alpha, st.beta, xs, xc, yE, tb);
+    }
     HEF_LAUNCH_CHECK();
   }
   if (n > 0) {
-    TimedScope ts(kStSpmmCsc, s);
     const int64_t nb = cdiv(n * G::LPS, kThreads);
-    k_csc_small<B><<<nb, kThreads, 0, s>>>(st.vptr, st.eids, st.s, st.gam, st.alpha, xE, tb,
-                                           xc, ys, yc, int32_t(n));
-    k_csc_big<B><<<kBigGrid, kThreads, 0, s>>>(st.big_v, st.n_big + 1, st.vptr, st.eids, st.s,
-                                               st.gam, st.alpha, xE, tb, xc, ys, yc);
+    {
+      TimedScope ts(kStSpmmCsc, s);
+      k_csc_small<B><<<nb, kThreads, 0, s>>>(st.vptr, st.eids, st.s, st.gam, st.alpha, xE, tb,
+                                             xc, ys, yc, int32_t(n));
+    }
+    {
+      TimedScope ts(kStSpmmCscBig, s);
+      k_csc_big<B><<<kBigGrid, kThreads, 0, s>>>(st.big_v, st.n_big + 1, st.vptr, st.eids, st.s,
+                                                 st.gam, st.alpha, xE, tb, xc, ys, yc);
+    }
     HEF_LAUNCH_CHECK();
   }
   return HEF_OK;
