@@ -1033,19 +1033,5 @@ int32_t hef_last_coarsen_levels(int32_t *n, int32_t *m, int64_t *nnz, int32_t ca
   return g_levels_run;
 }
 
-hef_status hef_resistance_backward(const hef_hypergraph *, const hef_params *, const float *,
-                                   const float *, const float *, float *, void *, size_t,
-                                   hipStream_t) {
-  set_error("the adjoint is not available in this build");
-  return HEF_ERR_UNSUPPORTED;
-}
-
-}  // extern "C"
-
-namespace hef {
-size_t backward_bytes(int64_t, int64_t, int64_t, const hef_params &) { return 256; }
-}  // namespace hef
-
-extern "C" {
 
 }  // extern "C"

@@ -128,7 +128,8 @@ __global__ void k_lgram_sym(double *__restrict__ G, int C, int S) {
 // reference length is 0 or its Schur pivot d_c <= tau^2 * G_cc.
 __global__ void __launch_bounds__(64)
 k_lsolve(const double *__restrict__ Gall, int C, int B, double tau,
-         double *__restrict__ Tall, int32_t *__restrict__ drops) {
+         double *__restrict__ Tall, int32_t *__restrict__ drops,
+         double *__restrict__ Rall) {
   __shared__ double A[48 * 48];
   __shared__ double Lm[48 * 48];
   __shared__ int keep[48];
@@ -169,6 +170,23 @@ k_lsolve(const double *__restrict__ Gall, int C, int B, double tau,
     }
     for (int i = 0; i < C; ++i) T[i * B + t] = x[i];
     if (!keep[c]) atomicAdd(&drops[blockIdx.x], 1);
+  }
+  // optionally the whole R^-1 (row-major C x C), zero rows/columns for drops
+  if (Rall && t < C) {
+    double *Rf = Rall + blockIdx.x * C * C;
+    const int c = t;
+    double x[48];
+    for (int i = 0; i < C; ++i) x[i] = 0.0;
+    if (keep[c]) {
+      x[c] = 1.0 / Lm[c * C + c];
+      for (int i = c - 1; i >= 0; --i) {
+        if (!keep[i]) continue;
+        double acc = 0.0;
+        for (int l = i + 1; l <= c; ++l) acc += Lm[l * C + i] * x[l];
+        x[i] = -acc / Lm[i * C + i];
+      }
+    }
+    for (int i = 0; i < C; ++i) Rf[i * C + c] = x[i];
   }
 }
 
@@ -323,6 +341,27 @@ hef_status lgram(const float *v0, const float *v1, const float *y, int64_t rows,
 
 }  // namespace
 
+size_t lanczos_partial_elems(int B) { return size_t(kGramBlocks) * 9 * B * B; }
+
+hef_status lanczos_gram(const float *v0, const float *v1, const float *y, int64_t rows, int B,
+                        double *partial, double *G, hipStream_t s) {
+  return lgram(v0, v1, y, rows, B, partial, G, s);
+}
+
+hef_status lanczos_solve(const double *G2, int B, double tau, double *T2, int32_t *drops,
+                         double *R2, hipStream_t s) {
+  TimedScope ts(kStLanczosSolve, s);
+  k_lsolve<<<2, 64, 0, s>>>(G2, 3 * B, B, tau, T2, drops, R2);
+  HEF_LAUNCH_CHECK();
+  return HEF_OK;
+}
+
+hef_status lanczos_apply(int B, const float *v0, const float *v1, const float *y, const double *T,
+                         float *vn, int64_t rows, void *pool, int pool_type, int64_t pool_rows,
+                         int K, int col0, hipStream_t s) {
+  return lapply(B, v0, v1, y, T, vn, rows, pool, pool_type, pool_rows, K, col0, s);
+}
+
 size_t krylov_ws_bytes(int64_t n, int64_t m, int B) {
   Arena a;
   for (int i = 0; i < 4; ++i) a.take<float>((n + m) * B);
@@ -349,7 +388,8 @@ hef_status start_block(uint64_t seed, int level, int expansion, int64_t rows, in
 
 hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double tau,
                        const float *start_star, const float *start_clique, bool use_star,
-                       bool use_clique, KrylovOut &out, Arena &ws, hipStream_t s) {
+                       bool use_clique, KrylovOut &out, Arena &ws, hipStream_t s,
+                       const KrylovTape *tape) {
   const int64_t n = L.n, m = L.m;
   const int64_t Ns = n + m;
   const size_t mk = ws.mark();
@@ -364,10 +404,32 @@ hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double
   if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
   const int C = 3 * B;
   double *Gs = G, *Gc = G + C * C;
-  double *Ts = Tm, *Tc = Tm + C * B;
   double *ps = partial, *pc = partial + size_t(kGramBlocks) * 9 * B * B;
   HEF_HIP(hipMemsetAsync(drops, 0, 2 * sizeof(int32_t), s));
   HEF_HIP(hipMemsetAsync(G, 0, 2 * 48 * 48 * sizeof(double), s));
+  // per-step T (and R^-1 for the adjoint)
+  auto t_of = [&](int j) { return tape ? tape->T + size_t(j) * 2 * C * B : Tm; };
+  auto r_of = [&](int j) { return tape ? tape->Rinv + size_t(j) * 2 * C * C : nullptr; };
+  const int seg = tape ? (tape->seg > 0 && tape->seg < k ? tape->seg : k) : 0;
+  // checkpoint slot j/seg <- (V_{j-1}, V_j) at the start of each segment
+  auto checkpoint = [&](int j, const float *vs_prev, const float *vs, const float *vc_prev,
+                        const float *vc) -> hef_status {
+    if (!tape || j % seg != 0 || j >= k) return HEF_OK;
+    const size_t slot = size_t(j / seg);
+    if (use_star) {
+      float *d = tape->ck_star + slot * 2 * Ns * B;
+      if (vs_prev) HEF_HIP(hipMemcpyAsync(d, vs_prev, Ns * B * sizeof(float), hipMemcpyDeviceToDevice, s));
+      else HEF_HIP(hipMemsetAsync(d, 0, Ns * B * sizeof(float), s));
+      HEF_HIP(hipMemcpyAsync(d + Ns * B, vs, Ns * B * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
+    if (use_clique) {
+      float *d = tape->ck_clique + slot * 2 * n * B;
+      if (vc_prev) HEF_HIP(hipMemcpyAsync(d, vc_prev, n * B * sizeof(float), hipMemcpyDeviceToDevice, s));
+      else HEF_HIP(hipMemsetAsync(d, 0, n * B * sizeof(float), s));
+      HEF_HIP(hipMemcpyAsync(d + n * B, vc, n * B * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
+    return HEF_OK;
+  };
 
   // indices into the rolling buffers: prev, cur, y, next
   int ip = 0, ic = 1, iy = 2, in = 3;
@@ -384,11 +446,12 @@ hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double
   }
   {
     TimedScope ts(kStLanczosSolve, s);
-    k_lsolve<<<2, 64, 0, s>>>(G, C, B, tau, Tm, drops);
+    k_lsolve<<<2, 64, 0, s>>>(G, C, B, tau, t_of(0), drops, r_of(0));
   }
   HEF_LAUNCH_CHECK();
-  if (use_star) HEF_TRY(lapply(B, nullptr, nullptr, sb[iy], Ts, sb[in], Ns, nullptr, 0, 0, K, 0, s));
-  if (use_clique) HEF_TRY(lapply(B, nullptr, nullptr, cb[iy], Tc, cb[in], n, nullptr, 0, 0, K, 0, s));
+  if (use_star) HEF_TRY(lapply(B, nullptr, nullptr, sb[iy], t_of(0), sb[in], Ns, nullptr, 0, 0, K, 0, s));
+  if (use_clique) HEF_TRY(lapply(B, nullptr, nullptr, cb[iy], t_of(0) + C * B, cb[in], n, nullptr, 0, 0, K, 0, s));
+  HEF_TRY(checkpoint(0, nullptr, sb[in], nullptr, cb[in]));
   // rotate: cur <- next; prev stays "absent" for step 1
   std::swap(ic, in);
   bool have_prev = false;
@@ -400,19 +463,21 @@ hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double
       HEF_TRY(lgram(have_prev ? sb[ip] : nullptr, sb[ic], sb[iy], Ns, B, ps, Gs, s));
     if (use_clique)
       HEF_TRY(lgram(have_prev ? cb[ip] : nullptr, cb[ic], cb[iy], n, B, pc, Gc, s));
+    double *Tj = t_of(j);
     {
       TimedScope ts(kStLanczosSolve, s);
-      k_lsolve<<<2, 64, 0, s>>>(G, C, B, tau, Tm, drops);
+      k_lsolve<<<2, 64, 0, s>>>(G, C, B, tau, Tj, drops, r_of(j));
     }
     HEF_LAUNCH_CHECK();
     const int64_t col_s = (j - 1) * int64_t(B);
     const int64_t col_c = (use_star ? bk : 0) + (j - 1) * int64_t(B);
     if (use_star)
-      HEF_TRY(lapply(B, have_prev ? sb[ip] : nullptr, sb[ic], sb[iy], Ts, sb[in], Ns, out.pool,
+      HEF_TRY(lapply(B, have_prev ? sb[ip] : nullptr, sb[ic], sb[iy], Tj, sb[in], Ns, out.pool,
                      out.pool_type, n, K, int(col_s), s));
     if (use_clique)
-      HEF_TRY(lapply(B, have_prev ? cb[ip] : nullptr, cb[ic], cb[iy], Tc, cb[in], n, out.pool,
+      HEF_TRY(lapply(B, have_prev ? cb[ip] : nullptr, cb[ic], cb[iy], Tj + C * B, cb[in], n, out.pool,
                      out.pool_type, n, K, int(col_c), s));
+    HEF_TRY(checkpoint(j, sb[ic], sb[in], cb[ic], cb[in]));
     // rotate prev <- cur <- next, next <- old prev
     const int old_prev = ip;
     ip = ic;

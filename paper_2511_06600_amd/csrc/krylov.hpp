@@ -6,7 +6,7 @@
 
 namespace hef {
 
-// Row-major blocks with row stride B (= b, a power of two, 1..16):
+// Row-major blocks with row stride B (= b: 1, 2, 4, 8 or 16):
 //   star   block: (n+m) x B, node rows [0,n) then hyperedge rows [n, n+m)
 //   clique block: n x B
 struct Blocks {
@@ -36,16 +36,51 @@ struct KrylovOut {
 
 size_t krylov_ws_bytes(int64_t n, int64_t m, int B);
 
+// What the adjoint keeps of a forward run (all device memory, caller-owned):
+//  * T[j]    (j = 0..k): the two C x B matrices R^-1[:, y columns] of step j
+//    (star then clique, C = 3B), float64;
+//  * Rinv[j] (j = 0..k): the two whole C x C matrices R^-1, float64;
+//  * ck_star / ck_clique: checkpoint pairs (V_{sc-1}, V_{sc}) for segments
+//    s = 0..nseg-1 of `seg` steps (nseg = ceil(k/seg)); slot s holds
+//    2 blocks of (n+m) x B (star) or n x B (clique); V_{-1} is zero.
+struct KrylovTape {
+  int seg = 0;
+  double *T = nullptr;
+  double *Rinv = nullptr;
+  float *ck_star = nullptr;
+  float *ck_clique = nullptr;
+};
+
 // k steps of block Lanczos per expansion (three-term recurrence; each new
 // block is orthonormalised against the previous two in a float64 Gram
 // metric, with the drop rule for breakdowns); writes the pool columns
 // [star steps 1..k | clique steps 1..k], b columns per step, star node rows
 // only.  `start_star` ((n+m) x B) and `start_clique` (n x B) are consumed.
 // `use_star` / `use_clique` select the expansions (the pool then holds
-// b*k columns of the one selected).
+// b*k columns of the one selected).  `tape` (nullable) records what the
+// adjoint needs.
 hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double tau,
                        const float *start_star, const float *start_clique, bool use_star,
-                       bool use_clique, KrylovOut &out, Arena &ws, hipStream_t s);
+                       bool use_clique, KrylovOut &out, Arena &ws, hipStream_t s,
+                       const KrylovTape *tape = nullptr);
+
+// The steps of one block-Lanczos iteration, for callers that drive the
+// recurrence themselves (the adjoint):
+//  * lanczos_gram: G (3B x 3B, float64) of M = [v0 | v1 | y] (null = zero
+//    block) over `rows` rows; `partial` holds lanczos_partial_elems(B);
+//  * lanczos_solve: for two expansions' Grams G2 = [G_star | G_clique]
+//    (C x C each, C = 3B, consecutive), Cholesky with the drop rule and
+//    T2 = [T_star | T_clique], T = R^-1[:, y columns] (C x B each); R2
+//    (nullable) receives both whole R^-1 (C x C each, consecutive);
+//  * lanczos_apply: vn = M T (float64 arithmetic), optional pool write.
+size_t lanczos_partial_elems(int B);
+hef_status lanczos_gram(const float *v0, const float *v1, const float *y, int64_t rows, int B,
+                        double *partial, double *G, hipStream_t s);
+hef_status lanczos_solve(const double *G2, int B, double tau, double *T2, int32_t *drops,
+                         double *R2, hipStream_t s);
+hef_status lanczos_apply(int B, const float *v0, const float *v1, const float *y, const double *T,
+                         float *vn, int64_t rows, void *pool, int pool_type, int64_t pool_rows,
+                         int K, int col0, hipStream_t s);
 
 // Counter-based N(0,1) start block (splitmix64 + Box-Muller in float64).
 hef_status start_block(uint64_t seed, int level, int expansion, int64_t rows, int B,

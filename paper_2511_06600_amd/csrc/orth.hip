@@ -235,15 +235,19 @@ __device__ __forceinline__ void load8(const void *pool, int pool_type, int64_t r
 }
 
 __global__ void __launch_bounds__(kGT)
-k_jgram(const void *__restrict__ pool, int pool_type, int64_t n, int K, int nsb, int npairs,
-        int64_t rows_per_chunk, double *__restrict__ partial) {
+k_jgram(const void *__restrict__ pool, const void *__restrict__ poolB, int pool_type, int64_t n,
+        int K, int nsb, int npairs, int64_t rows_per_chunk, double *__restrict__ partial) {
   __shared__ float As[2][kSlab * kSB];
   __shared__ float Bs[2][kSlab * kSB];
   const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
   const int pair = int(lb % npairs);
   const int64_t chunk = lb / npairs;
-  const int2 ab = pair_of(pair, nsb);
-  const bool diag = ab.x == ab.y;
+  // symmetric (poolB null): super-tile pairs a <= b of V^T V;
+  // cross: every (a, b) of V^T W with W = poolB
+  const bool cross = poolB != nullptr;
+  const int2 ab = cross ? make_int2(pair / nsb, pair % nsb) : pair_of(pair, nsb);
+  const bool diag = !cross && ab.x == ab.y;
+  const void *srcB = cross ? poolB : pool;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = tid >> 6;
@@ -261,7 +265,7 @@ k_jgram(const void *__restrict__ pool, int pool_type, int64_t n, int K, int nsb,
   for (int v = 0; v < 16; ++v) { acc0[v] = 0.0f; acc1[v] = 0.0f; d0[v] = 0.0; d1[v] = 0.0; }
   float ra[8], rb[8];
   load8(pool, pool_type, r0 + lrow, r1, ab.x * kSB + lcol, K, ra);
-  if (!diag) load8(pool, pool_type, r0 + lrow, r1, ab.y * kSB + lcol, K, rb);
+  if (!diag) load8(srcB, pool_type, r0 + lrow, r1, ab.y * kSB + lcol, K, rb);
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     As[0][lrow * kSB + lcol + q] = ra[q];
@@ -273,7 +277,7 @@ k_jgram(const void *__restrict__ pool, int pool_type, int64_t n, int K, int nsb,
     const bool more = r + kSlab < r1;
     if (more) {
       load8(pool, pool_type, r + kSlab + lrow, r1, ab.x * kSB + lcol, K, ra);
-      if (!diag) load8(pool, pool_type, r + kSlab + lrow, r1, ab.y * kSB + lcol, K, rb);
+      if (!diag) load8(srcB, pool_type, r + kSlab + lrow, r1, ab.y * kSB + lcol, K, rb);
     }
     const float *A = As[buf];
     const float *Bm = diag ? As[buf] : Bs[buf];
@@ -318,23 +322,23 @@ k_jgram(const void *__restrict__ pool, int pool_type, int64_t n, int K, int nsb,
   }
 }
 
-// G[gi][gj] from the chunk-summed tiles.
+// G[gi][gj] from the chunk-summed tiles (mirrored unless `cross`).
 __global__ void k_jgram_scatter(const double *__restrict__ sums, int nsb, int npairs, int K,
-                                double *__restrict__ G) {
+                                int cross, double *__restrict__ G) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= int64_t(npairs) * 16 * 1024) return;
   const int pair = int(e / (16 * 1024));
   const int rem = int(e % (16 * 1024));
   const int wt = rem / 1024, ij = rem % 1024;
   const int ti = wt / 4, tj = wt % 4, i = ij / 32, j = ij % 32;
-  const int2 ab = pair_of(pair, nsb);
-  if (ab.x == ab.y && tj < ti) return;
+  const int2 ab = cross ? make_int2(pair / nsb, pair % nsb) : pair_of(pair, nsb);
+  if (!cross && ab.x == ab.y && tj < ti) return;
   const int gi = ab.x * kSB + 32 * ti + i;
   const int gj = ab.y * kSB + 32 * tj + j;
   if (gi >= K || gj >= K) return;
   const double s = sums[e];
   G[int64_t(gi) * K + gj] = s;
-  G[int64_t(gj) * K + gi] = s;
+  if (!cross) G[int64_t(gj) * K + gi] = s;
 }
 
 // ---------------------------------------------------------------- apply
@@ -349,7 +353,7 @@ constexpr int kALDB = kAN + 1;   // B chunk [32][129]
 
 __global__ void __launch_bounds__(kAT)
 k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int64_t n, int K,
-         int Kp, const float *__restrict__ Rinv32, int ncb) {
+         int Kp, const float *__restrict__ Rinv32, int ncb, int full, int accumulate) {
   __shared__ float As[kAM * kALDA];
   __shared__ float Bs[kAK * kALDB];
   const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
@@ -368,7 +372,8 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int64_
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
-  const int kend = (col0 + kAN < K) ? col0 + kAN : K;
+  // Rinv is upper triangular: rows past the tile's last column are zero
+  const int kend = (!full && col0 + kAN < K) ? col0 + kAN : K;
   for (int k0 = 0; k0 < kend; k0 += kAK) {
     __syncthreads();
     // A chunk: rows row0..+127, cols k0..k0+31 of V (8 floats per thread... 2 x 8)
@@ -413,7 +418,9 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int64_
         const int64_t row = row0 + wr + 32 * a + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         const int col = col0 + wc + 32 * b + (lane & 31);
         if (row < n && col < K) {
-          if (pool_type == kPoolF32)
+          if (accumulate)  // float32 only
+            reinterpret_cast<float *>(Q)[row * K + col] += acc[a][b][v];
+          else if (pool_type == kPoolF32)
             reinterpret_cast<float *>(Q)[row * K + col] = acc[a][b][v];
           else
             reinterpret_cast<uint16_t *>(Q)[row * K + col] = f2bf(acc[a][b][v]);
@@ -426,10 +433,10 @@ struct GramPlan {
   int64_t rows_per_chunk = 0;
 };
 
-GramPlan gram_plan(int64_t n, int K) {
+GramPlan gram_plan(int64_t n, int K, bool cross = false) {
   GramPlan p;
   p.nsb = (K + kSB - 1) / kSB;
-  p.npairs = p.nsb * (p.nsb + 1) / 2;
+  p.npairs = cross ? p.nsb * p.nsb : p.nsb * (p.nsb + 1) / 2;
   int64_t want = std::max<int64_t>(1, 512 / p.npairs);
   int64_t per = cdiv(std::max<int64_t>(n, 1), want);
   per = std::max<int64_t>(kSlab, cdiv(per, kSlab) * kSlab);
@@ -438,9 +445,9 @@ GramPlan gram_plan(int64_t n, int K) {
   return p;
 }
 
-hef_status gram_run(const void *pool, int pool_type, int64_t n, int K, double *G, Arena &ws,
-                    hipStream_t s) {
-  const GramPlan p = gram_plan(n, K);
+hef_status gram_run(const void *pool, const void *poolB, int pool_type, int64_t n, int K,
+                    double *G, Arena &ws, hipStream_t s) {
+  const GramPlan p = gram_plan(n, K, poolB != nullptr);
   const size_t mk = ws.mark();
   double *partial = ws.take<double>(size_t(p.nchunks) * p.npairs * 16 * 1024);
   const int64_t tot = int64_t(p.npairs) * 16 * 1024;
@@ -448,22 +455,24 @@ hef_status gram_run(const void *pool, int pool_type, int64_t n, int K, double *G
   if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
   HEF_HIP(hipMemsetAsync(G, 0, sizeof(double) * K * K, s));
   TimedScope ts(kStOrthGram, s);
-  k_jgram<<<int64_t(p.npairs) * p.nchunks, kGT, 0, s>>>(pool, pool_type, n, K, p.nsb, p.npairs,
-                                                        p.rows_per_chunk, partial);
+  k_jgram<<<int64_t(p.npairs) * p.nchunks, kGT, 0, s>>>(pool, poolB, pool_type, n, K, p.nsb,
+                                                        p.npairs, p.rows_per_chunk, partial);
   HEF_LAUNCH_CHECK();
   HEF_TRY(reduce_cols_f64(partial, p.nchunks, tot, sums, s));
-  k_jgram_scatter<<<cdiv(tot, 256), 256, 0, s>>>(sums, p.nsb, p.npairs, K, G);
+  k_jgram_scatter<<<cdiv(tot, 256), 256, 0, s>>>(sums, p.nsb, p.npairs, K, poolB != nullptr, G);
   HEF_LAUNCH_CHECK();
   ws.reset(mk);
   return HEF_OK;
 }
 
 hef_status apply_run(const void *V, void *Q, int pool_type, int64_t n, int K, int Kp,
-                     const float *Rinv32, hipStream_t s) {
+                     const float *Rinv32, hipStream_t s, bool full = false,
+                     bool accumulate = false) {
   if (n == 0) return HEF_OK;
   TimedScope ts(kStOrthApply, s);
   const int ncb = (K + kAN - 1) / kAN;
-  k_japply<<<cdiv(n, kAM) * ncb, kAT, 0, s>>>(V, Q, pool_type, n, K, Kp, Rinv32, ncb);
+  k_japply<<<cdiv(n, kAM) * ncb, kAT, 0, s>>>(V, Q, pool_type, n, K, Kp, Rinv32, ncb, full,
+                                              accumulate);
   HEF_LAUNCH_CHECK();
   return HEF_OK;
 }
@@ -486,12 +495,32 @@ size_t orth_ws_bytes(int64_t n, int K) {
 
 hef_status gram_f32(const float *X, int64_t n, int K, double *G, Arena &ws, hipStream_t s) {
   if (K <= 0 || K > 512) return HEF_ERR_UNSUPPORTED;
-  return gram_run(X, kPoolF32, n, K, G, ws, s);
+  return gram_run(X, nullptr, kPoolF32, n, K, G, ws, s);
+}
+
+size_t gram_cross_ws_bytes(int64_t n, int K) {
+  const GramPlan p = gram_plan(n, K, true);
+  Arena a;
+  a.take<double>(size_t(p.nchunks) * p.npairs * 16 * 1024);
+  a.take<double>(size_t(p.npairs) * 16 * 1024);
+  return a.mark() + 1024;
+}
+
+hef_status gram_cross_f32(const float *X, const float *W, int64_t n, int K, double *G, Arena &ws,
+                          hipStream_t s) {
+  if (K <= 0 || K > 512) return HEF_ERR_UNSUPPORTED;
+  return gram_run(X, W, kPoolF32, n, K, G, ws, s);
+}
+
+hef_status gemm_f32(const float *X, int64_t n, int K, const float *W, int Kp, float *out,
+                    bool accumulate, hipStream_t s) {
+  if (K <= 0 || K > 512) return HEF_ERR_UNSUPPORTED;
+  return apply_run(X, out, kPoolF32, n, K, Kp, W, s, true, accumulate);
 }
 
 hef_status orthonormalize_pool(void *pool, void *pool2, int pool_type, int64_t n, int K,
                                double tau, int passes, int32_t *keep_out, void **result,
-                               Arena &ws, hipStream_t s) {
+                               Arena &ws, hipStream_t s, double *rinv_out) {
   *result = pool;
   if (K <= 0) return HEF_OK;
   if (K > 512) {
@@ -508,7 +537,7 @@ hef_status orthonormalize_pool(void *pool, void *pool2, int pool_type, int64_t n
   if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
   void *src = pool, *dst = pool2;
   for (int pass = 0; pass < passes; ++pass) {
-    HEF_TRY(gram_run(src, pool_type, n, K, G, ws, s));
+    HEF_TRY(gram_run(src, nullptr, pool_type, n, K, G, ws, s));
     {
       TimedScope ts(kStOrthChol, s);
       const size_t lds_c = size_t(K) * kPS * sizeof(double);
@@ -527,6 +556,8 @@ hef_status orthonormalize_pool(void *pool, void *pool2, int pool_type, int64_t n
   }
   *result = src;
   if (keep_out) HEF_HIP(hipMemcpyAsync(keep_out, keep, K * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  if (rinv_out)
+    HEF_HIP(hipMemcpyAsync(rinv_out, Rinv, sizeof(double) * Kp * Kp, hipMemcpyDeviceToDevice, s));
   ws.reset(mk);
   return HEF_OK;
 }

@@ -15,13 +15,26 @@ size_t orth_ws_bytes(int64_t n, int K);
 // (the second pass keeps the first pass's drops), alternating between
 // `pool` and `pool2`; *result is the buffer holding Q (pool2 after one
 // pass, pool after two).  `keep_out` (device int32 [K], may be null)
-// receives 1 for kept and 0 for dropped columns.
+// receives 1 for kept and 0 for dropped columns; `rinv_out` (device float64
+// [Kp x Kp], Kp = K rounded up to 32, may be null) receives the last pass's
+// R^-1 (row-major, upper triangular, zero rows and columns for drops).
 hef_status orthonormalize_pool(void *pool, void *pool2, int pool_type, int64_t n, int K,
                                double tau, int passes, int32_t *keep_out, void **result,
-                               Arena &ws, hipStream_t s);
+                               Arena &ws, hipStream_t s, double *rinv_out = nullptr);
 
 // Test hook: G = X^T X (float64, K x K) of a row-major n x K float32 matrix,
 // through the same matrix-core Gram kernels.
 hef_status gram_f32(const float *X, int64_t n, int K, double *G, Arena &ws, hipStream_t s);
+
+// G = X^T W (float64, K x K, not symmetric) of two row-major n x K float32
+// matrices, through the same kernels; scratch gram_cross_ws_bytes(n, K).
+size_t gram_cross_ws_bytes(int64_t n, int K);
+hef_status gram_cross_f32(const float *X, const float *W, int64_t n, int K, double *G, Arena &ws,
+                          hipStream_t s);
+
+// out (n x K) = X W, or out += X W if `accumulate`, for a general K x K
+// float32 matrix W (row-major, row stride Kp), on the matrix cores.
+hef_status gemm_f32(const float *X, int64_t n, int K, const float *W, int Kp, float *out,
+                    bool accumulate, hipStream_t s);
 
 }  // namespace hef
