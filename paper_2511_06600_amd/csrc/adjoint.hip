@@ -502,7 +502,9 @@ k_wedge(int64_t n, int64_t m, const int32_t *__restrict__ eptr, const float *__r
   }
   if (tbar) {
     double ec = 0.0;
-    for (int c = 0; c < B; ++c) ec += double(tbar[e * B + c]) * double(tf[e * B + c]);
+    // T_e lives in the SpMM scratch at row stride 2B, offset B
+    for (int c = 0; c < B; ++c)
+      ec += double(tbar[e * 2 * B + B + c]) * double(tf[e * 2 * B + B + c]);
     const double k = double(eptr[e + 1] - eptr[e]);
     acc += ec * (k * (k - 1.0)) / (we * we);  // = ec / (w_e beta_e)
   }
@@ -593,7 +595,7 @@ void carve(Arena &a, int64_t n, int64_t m, int64_t nnz, const hef_params &p, Bwd
   w.vseg_c = a.take<float>(int64_t(seg) * n * B);
   w.yseg_s = a.take<float>(int64_t(seg) * Ns * B);
   w.yseg_c = a.take<float>(int64_t(seg) * n * B);
-  w.tseg = a.take<float>(int64_t(seg) * m * B);
+  w.tseg = a.take<float>(int64_t(seg) * spmm_scratch_floats(n, m, B));
   w.abar_s = a.take<float>(3 * Ns * B);
   w.abar_c = a.take<float>(3 * n * B);
   w.vb_s = a.take<float>(Ns * B);
@@ -602,7 +604,7 @@ void carve(Arena &a, int64_t n, int64_t m, int64_t nnz, const hef_params &p, Bwd
   w.yb_c = a.take<float>(n * B);
   w.ay_s = a.take<float>(Ns * B);
   w.ay_c = a.take<float>(n * B);
-  w.tbar = a.take<float>(m * B);
+  w.tbar = a.take<float>(spmm_scratch_floats(n, m, B));
   w.xpart = a.take<double>(int64_t(2) * kXBlocks * C * B);
   w.X3 = a.take<double>(2 * C * B);
   w.Tadj = a.take<double>(2 * (C + B) * C);
@@ -836,7 +838,7 @@ hef_status resistance_backward(const Level &L, const hef_params &p, const float 
       const int t = j - j0 - 1;
       float *ysj = w.yseg_s + size_t(t) * Ns * B;
       float *ycj = w.yseg_c + size_t(t) * n * B;
-      float *tj = w.tseg + size_t(t) * m * B;
+      float *tj = w.tseg + size_t(t) * spmm_scratch_floats(n, m, B);
       HEF_TRY(spmm_apply(L, st, B, use_star ? vs(j - 1) : nullptr, use_star ? ysj : nullptr,
                          use_clique ? vc(j - 1) : nullptr, use_clique ? ycj : nullptr, tj, s));
       if (j < j1) {
@@ -853,7 +855,7 @@ hef_status resistance_backward(const Level &L, const hef_params &p, const float 
       const int t = j - j0 - 1;
       const float *ysj = w.yseg_s + size_t(t) * Ns * B;
       const float *ycj = w.yseg_c + size_t(t) * n * B;
-      const float *tj = w.tseg + size_t(t) * m * B;
+      const float *tj = w.tseg + size_t(t) * spmm_scratch_floats(n, m, B);
       const float *ps = j >= 2 ? vs(j - 2) : nullptr, *pc = j >= 2 ? vc(j - 2) : nullptr;
       float *as_j = w.abar_s + size_t(j % 3) * Ns * B;
       float *as_1 = j >= 2 ? w.abar_s + size_t((j - 1) % 3) * Ns * B : nullptr;

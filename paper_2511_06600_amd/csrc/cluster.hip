@@ -45,6 +45,7 @@ namespace hef {
 namespace {
 
 constexpr int kT = 256;
+constexpr int kSeedSeg = 64;  // hyperedges this short seed the best-first search
 constexpr int kRoundsPerSync = 16;
 constexpr int32_t kStUndecided = 0, kStIn = 1, kStOut = 2, kStNone = 3;
 
@@ -189,18 +190,21 @@ k_qh_order(const double *__restrict__ qh, int K, int32_t *__restrict__ perm,
 
 // cperm[C][q] = float32 of cluster C's centroid in column perm[q] (zero for
 // q >= nuse), for every cluster id C (a node that is its cluster's smallest
-// member).  Row width Kq = K rounded up to 64.
+// member).  Row width Kq = K rounded up to 64.  crow[C] = the row of C's
+// float64 centroid (-1: singleton, the centroid is its pool row).
 template <int PT>
 __global__ void k_cperm(const int32_t *__restrict__ prov, const int32_t *__restrict__ owner,
                         const int32_t *__restrict__ in_index, const double *__restrict__ cent,
                         const void *__restrict__ pool, int K, int Kq,
                         const int32_t *__restrict__ perm, const int32_t *__restrict__ nuse,
-                        float *__restrict__ cperm, int32_t n) {
+                        float *__restrict__ cperm, int32_t *__restrict__ crow, int32_t n) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= int64_t(n) * Kq) return;
   const int64_t v = idx / Kq;
   const int q = int(idx % Kq);
   if (prov[v] != v) return;
+  // row of the cluster's float64 centroid, or -1 for a singleton (its pool row)
+  if (q == 0) crow[v] = owner[v] < 0 ? -1 : in_index[owner[v]];
   float val = 0.0f;
   if (q < *nuse) {
     const int col = perm[q];
@@ -219,137 +223,307 @@ __device__ __forceinline__ float lb_term(float x, float s, float iq) {
   return dev * dev * iq;
 }
 
-// One wave per isolated node p.  For every co-pin v of every hyperedge of p,
-// C = prov[v]; best = (smallest d(p, C), smallest label).  Candidates are
-// screened by float32 lower bounds of d (first the 64, then the 256
-// largest-weight columns), which exceed the exact float64 value by at most
-// a relative 1e-6; a candidate whose bound exceeds the best exact distance
-// so far times (1 + 1e-5) cannot be the minimum or tie with it.  Survivors
-// get the exact float64 distance.
+// Safe float32 upper bound of one column's term (scaled by 1 + 2e-6 by the
+// caller to cover the float32 roundings).
+__device__ __forceinline__ float ub_term(float x, float s, float iq) {
+  const float dev = fabsf(x - s) + 0x1p-23f * fabsf(s);
+  return dev * dev * iq;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Exact float64 distance d(p, C) = max_i (chi_p^(i) - c_C^(i))^2 / Q_H(i)
+// (Eqs. (13), (14) applied to a node and a centroid), no FMA; full wave.
+template <int PT>
+__device__ __forceinline__ double exact_d(int64_t p, int32_t C, int lane, const int32_t *crow,
+                                          const double *cent, const void *pool, int K,
+                                          const double *qh) {
+  constexpr int MAXC = 8;
+  const int64_t cr = crow[C];
+  double dl = 0.0;
+#pragma unroll
+  for (int q = 0; q < MAXC; ++q) {
+    const int col = lane + 64 * q;
+    if (col < K) {
+      const double qv = qh[col];
+      if (qv > 0.0) {
+        const double x = pool_val<PT>(pool, p * K + col);
+        const double c = cr < 0 ? pool_val<PT>(pool, int64_t(C) * K + col) : cent[cr * K + col];
+        const double diff = x - c;
+        const double sq = diff * diff;
+        const double r = sq / qv;
+        dl = r > dl ? r : dl;
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(dl, off, 64);
+    dl = o > dl ? o : dl;
+  }
+  return dl;
+}
+
+// One wave per isolated node p; its candidates are the clusters C = prov[v]
+// of the co-pins v of its hyperedges, and best(p) = (smallest exact float64
+// d(p, C), smallest label).  The wave filters the candidates with float32
+// bounds in the permuted column order (largest weights first):
+//   stage A  one lane per candidate, lower bound over 64 columns;
+//   stage B  8 lanes per candidate, lower bound over 256 columns;
+//   stage C  8 lanes per candidate, lower and upper bounds over all columns.
+// Lower bounds exceed the exact value by at most a relative 1e-6 and upper
+// bounds (times 1 + 2e-6) are never below it.  `ub` is the smallest upper
+// bound found, so no candidate whose lower bound exceeds ub (1 + 1e-5) can
+// be the minimum or tie with it.  Candidates that reach the end unexcluded
+// (near-ties only) get the exact float64 distance.  Hyperedges of at most
+// kSeedSeg pins are visited first; the first candidate batch seeds ub with
+// its smallest stage-A bound's candidate.  The result is the exact argmin
+// whatever the visiting order.
+constexpr int kQCap = 72;   // stage-B queue: 8 + one batch of 64
+constexpr int kFCap = 32;   // candidates awaiting the exact distance
+constexpr int kEB = 64;     // hyperedges of p per batch
+
 template <int PT>
 __global__ void __launch_bounds__(kT)
 k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
        const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
        const int32_t *__restrict__ owner, const int32_t *__restrict__ prov,
-       const int32_t *__restrict__ in_index, const double *__restrict__ cent,
+       const int32_t *__restrict__ crow, const double *__restrict__ cent,
        const float *__restrict__ cperm, int Kq, const int32_t *__restrict__ perm,
        const float *__restrict__ inv32, const void *__restrict__ pool, int K,
        const double *__restrict__ qh, int32_t n, int32_t *__restrict__ best_label,
        double *__restrict__ best_d) {
+  constexpr int NW = kT / 64;
+  __shared__ float xs_all[NW][512];
+  __shared__ float is_all[NW][512];
+  __shared__ int32_t es_all[NW][kEB];      // first pin position per hyperedge (batch order)
+  __shared__ int32_t ep_all[NW][kEB + 1];  // exclusive prefix of sizes
+  __shared__ int32_t qc_all[NW][kQCap];
+  __shared__ float ql_all[NW][kQCap];
+  __shared__ int32_t fc_all[NW][kFCap];
+  __shared__ float fl_all[NW][kFCap];
+  const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int64_t p = (int64_t(blockIdx.x) * kT + threadIdx.x) >> 6;
+  const int g = lane >> 3, a8 = lane & 7;
+  const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
+  const int64_t p = int64_t(blockIdx.x) * NW + w;
   if (p >= n) return;
-  if (owner[p] >= 0 || vptr[p] == vptr[p + 1]) {
+  const int32_t v0 = vptr[p], deg = vptr[p + 1] - v0;
+  if (owner[p] >= 0 || deg == 0) {
     if (lane == 0) best_label[p] = -1;
     return;
   }
-  constexpr double kMargin = 1.0 + 1e-5;
-  // exact stage: natural columns lane + 64q
-  constexpr int MAXC = 8;
-  double xp[MAXC], qv[MAXC];
-#pragma unroll
-  for (int q = 0; q < MAXC; ++q) {
-    const int col = lane + 64 * q;
-    xp[q] = col < K ? pool_val<PT>(pool, p * K + col) : 0.0;
-    qv[q] = col < K ? qh[col] : 0.0;
+  constexpr float kMargin = 1.0f + 1e-5f;
+  constexpr float kUbScale = 1.0f + 2e-6f;
+  float *xs = xs_all[w];
+  float *is = is_all[w];
+  int32_t *es = es_all[w];
+  int32_t *ep = ep_all[w];
+  int32_t *qc = qc_all[w];
+  float *ql = ql_all[w];
+  int32_t *fc = fc_all[w];
+  float *fl = fl_all[w];
+  for (int q = lane; q < Kq; q += 64) {
+    xs[q] = float(pool_val<PT>(pool, p * K + perm[q]));
+    is[q] = inv32[q];
   }
-  // stage A: lane group g = lane/8 screens candidate g of a batch; lane
-  // a = lane%8 covers permuted columns 8a..8a+7
-  const int a8 = lane & 7;
-  float xa[8], ia[8];
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const int q = 8 * a8 + t;
-    xa[t] = q < Kq ? float(pool_val<PT>(pool, p * K + perm[q])) : 0.0f;
-    ia[t] = q < Kq ? inv32[q] : 0.0f;
-  }
-  // stage B: lane a of a group covers permuted columns 32a..32a+31 (from LDS)
-  __shared__ float xs_all[kT / 64][256];
-  __shared__ float is_all[kT / 64][256];
-  float *xsw = xs_all[threadIdx.x >> 6];
-  float *isw = is_all[threadIdx.x >> 6];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int q = lane + 64 * t;
-    xsw[q] = q < Kq ? float(pool_val<PT>(pool, p * K + perm[q])) : 0.0f;
-    isw[q] = q < Kq ? inv32[q] : 0.0f;
-  }
-  const int kb = Kq < 256 ? Kq : 256;  // stage-B width
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  double bd = DBL_MAX;
+  const int kb = Kq < 256 ? Kq : 256;
+  wave_sync();
+
+  float ub = FLT_MAX;            // smallest upper bound so far (wave-uniform)
+  int nq = 0, nf = 0;            // queue / exact-list fill (wave-uniform)
+  double bd = DBL_MAX;           // exact best of flushed entries
   int32_t bl = INT32_MAX;
-  int32_t last = -1;
-  for (int32_t jj = vptr[p]; jj < vptr[p + 1]; ++jj) {
-    const int32_t e = eids[jj];
-    const int32_t ea = eptr[e], eb = eptr[e + 1];
-    for (int32_t j0 = ea; j0 < eb; j0 += 8) {
-      const int32_t jg = j0 + (lane >> 3);
-      int32_t vg = jg < eb ? pins[jg] : -1;
-      if (vg == p) vg = -1;
-      const int32_t Cg = vg >= 0 ? prov[vg] : -1;
-      float lbg = 0.0f;
-      if (Cg >= 0 && 8 * a8 < Kq) {
-        const float4 *row = reinterpret_cast<const float4 *>(cperm + int64_t(Cg) * Kq + 8 * a8);
-        const float4 s0 = row[0], s1 = row[1];
-        const float sv[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
-#pragma unroll
-        for (int t = 0; t < 8; ++t) lbg = fmaxf(lbg, lb_term(xa[t], sv[t], ia[t]));
+
+  // exact distances of the listed candidates still within the bound
+  auto flush = [&]() {
+    for (int i = 0; i < nf; ++i) {
+      const int32_t C = fc[i];
+      if (fl[i] > ub * kMargin) continue;
+      const double dl = exact_d<PT>(p, C, lane, crow, cent, pool, K, qh);
+      if (dl < bd || (dl == bd && C < bl)) {
+        bd = dl;
+        bl = C;
       }
-      for (int off = 4; off > 0; off >>= 1) lbg = fmaxf(lbg, __shfl_xor(lbg, off, 8));
-      // stage B, per group, for candidates stage A did not rule out
-      if (Cg >= 0 && bd != DBL_MAX && !(double(lbg) > bd * kMargin) && kb > 64) {
-        const int q0 = 32 * a8;
-        if (q0 < kb) {
-          const float4 *row = reinterpret_cast<const float4 *>(cperm + int64_t(Cg) * Kq + q0);
+    }
+    nf = 0;
+    if (bd != DBL_MAX) ub = fminf(ub, float(bd) * kUbScale * kUbScale);
+    wave_sync();
+  };
+  // stage C of candidate C on the 8 lanes of a group: (lower, upper) bound
+  auto stage_c = [&](int32_t C, float &lo, float &hi) {
+    lo = 0.0f;
+    hi = 0.0f;
+    const float *row = cperm + int64_t(C) * Kq;
+    for (int q0 = 4 * a8; q0 < Kq; q0 += 32) {
+      const float4 sv = *reinterpret_cast<const float4 *>(row + q0);
+      const float c4[4] = {sv.x, sv.y, sv.z, sv.w};
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const float4 sv = row[u];
-            const int q = q0 + 4 * u;
-            lbg = fmaxf(lbg, lb_term(xsw[q], sv.x, isw[q]));
-            lbg = fmaxf(lbg, lb_term(xsw[q + 1], sv.y, isw[q + 1]));
-            lbg = fmaxf(lbg, lb_term(xsw[q + 2], sv.z, isw[q + 2]));
-            lbg = fmaxf(lbg, lb_term(xsw[q + 3], sv.w, isw[q + 3]));
-          }
-        }
-        for (int off = 4; off > 0; off >>= 1) lbg = fmaxf(lbg, __shfl_xor(lbg, off, 8));
+      for (int u = 0; u < 4; ++u) {
+        lo = fmaxf(lo, lb_term(xs[q0 + u], c4[u], is[q0 + u]));
+        hi = fmaxf(hi, ub_term(xs[q0 + u], c4[u], is[q0 + u]));
       }
-      const int nb = (eb - j0) < 8 ? (eb - j0) : 8;
-      for (int t = 0; t < nb; ++t) {
-        const int32_t v = __shfl(vg, 8 * t, 64);
-        if (v < 0) continue;
-        const int32_t C = __shfl(Cg, 8 * t, 64);
-        const float lba = __shfl(lbg, 8 * t, 64);
-        if (C == last) continue;
-        last = C;
-        if (bd != DBL_MAX && double(lba) > bd * kMargin) continue;
-        const int32_t ow = owner[v];
-        const int64_t crow = ow < 0 ? -1 : int64_t(in_index[ow]);
-        double dl = 0.0;
+    }
+    for (int off = 4; off > 0; off >>= 1) {
+      lo = fmaxf(lo, __shfl_xor(lo, off, 8));
+      hi = fmaxf(hi, __shfl_xor(hi, off, 8));
+    }
+    hi *= kUbScale;
+  };
+  // append the groups' candidates with bound <= ub (1 + 1e-5) to the exact list
+  auto push_f = [&](bool ok, int32_t C, float lo) {
+    const uint64_t m = __ballot(ok && a8 == 0);
+    const int cnt = __popcll(m);
+    if (cnt == 0) return;
+    if (nf + cnt > kFCap) flush();
+    if (ok && a8 == 0) {
+      const int at = nf + __popcll(m & lt_mask);
+      fc[at] = C;
+      fl[at] = lo;
+    }
+    nf += cnt;
+    wave_sync();
+  };
+  // stages B and C for up to 8 queued candidates (taken from the queue's end)
+  auto batch = [&](int cnt) {
+    int32_t C = -1;
+    float lo = FLT_MAX;
+    if (g < cnt) {
+      C = qc[nq - cnt + g];
+      lo = ql[nq - cnt + g];
+    }
+    nq -= cnt;
+    wave_sync();
+    bool live = C >= 0 && !(lo > ub * kMargin);
+    if (live && kb > 64) {
+      const int q0 = 32 * a8;
+      if (q0 < kb) {
+        const float4 *row = reinterpret_cast<const float4 *>(cperm + int64_t(C) * Kq + q0);
 #pragma unroll
-        for (int q = 0; q < MAXC; ++q) {
-          const int col = lane + 64 * q;
-          if (col < K && qv[q] > 0.0) {
-            const double c = crow < 0 ? pool_val<PT>(pool, int64_t(v) * K + col) : cent[crow * K + col];
-            const double diff = xp[q] - c;
-            const double sq = diff * diff;
-            const double r = sq / qv[q];
-            dl = r > dl ? r : dl;
-          }
-        }
-        for (int off = 32; off > 0; off >>= 1) {
-          const double o = __shfl_xor(dl, off, 64);
-          dl = o > dl ? o : dl;
-        }
-        if (dl < bd || (dl == bd && C < bl)) {
-          bd = dl;
-          bl = C;
+        for (int u = 0; u < 8; ++u) {
+          const float4 sv = row[u];
+          const int q = q0 + 4 * u;
+          lo = fmaxf(lo, lb_term(xs[q], sv.x, is[q]));
+          lo = fmaxf(lo, lb_term(xs[q + 1], sv.y, is[q + 1]));
+          lo = fmaxf(lo, lb_term(xs[q + 2], sv.z, is[q + 2]));
+          lo = fmaxf(lo, lb_term(xs[q + 3], sv.w, is[q + 3]));
         }
       }
     }
+    for (int off = 4; off > 0; off >>= 1) lo = fmaxf(lo, __shfl_xor(lo, off, 8));
+    live = live && !(lo > ub * kMargin);
+    float hi = FLT_MAX;
+    if (live) {
+      float lc;
+      stage_c(C, lc, hi);
+      lo = fmaxf(lo, lc);
+    }
+    float mh = hi;
+    for (int off = 8; off < 64; off <<= 1) mh = fminf(mh, __shfl_xor(mh, off, 64));
+    ub = fminf(ub, mh);
+    push_f(live && !(lo > ub * kMargin), C, lo);
+  };
+
+  for (int32_t e0 = 0; e0 < deg; e0 += kEB) {
+    const int nb = deg - e0 < kEB ? deg - e0 : kEB;
+    // this batch's hyperedges, the short ones first
+    int32_t ea = 0, sz = 0;
+    if (lane < nb) {
+      const int32_t e = eids[v0 + e0 + lane];
+      ea = eptr[e];
+      sz = eptr[e + 1] - ea;
+    }
+    const bool sm = lane < nb && sz <= kSeedSeg;
+    const uint64_t msm = __ballot(sm);
+    const uint64_t mbg = __ballot(lane < nb && !sm);
+    const int at = sm ? __popcll(msm & lt_mask) : __popcll(msm) + __popcll(mbg & lt_mask);
+    if (lane < nb) {
+      es[at] = ea;
+      ep[at] = sz;
+    }
+    wave_sync();
+    int32_t my = lane < nb ? ep[lane] : 0;
+    int32_t inc = my;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t o = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += o;
+    }
+    const int32_t total = __shfl(inc, 63, 64);
+    wave_sync();
+    if (lane < nb) ep[lane] = inc - my;
+    if (lane == 0) ep[nb] = total;
+    wave_sync();
+    for (int32_t t0 = 0; t0 < total; t0 += 64) {
+      const int32_t t = t0 + lane;
+      int32_t C = -1;
+      float lo = FLT_MAX;
+      if (t < total) {
+        int lo_i = 0, hi_i = nb;  // last i with ep[i] <= t
+        while (hi_i - lo_i > 1) {
+          const int mid = (lo_i + hi_i) >> 1;
+          if (ep[mid] <= t) lo_i = mid; else hi_i = mid;
+        }
+        const int32_t v = pins[es[lo_i] + (t - ep[lo_i])];
+        if (v != p) C = prov[v];
+      }
+      if (C >= 0) {
+        lo = 0.0f;
+        const float4 *row = reinterpret_cast<const float4 *>(cperm + int64_t(C) * Kq);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const float4 sv = row[u];
+          const int q = 4 * u;
+          lo = fmaxf(lo, lb_term(xs[q], sv.x, is[q]));
+          lo = fmaxf(lo, lb_term(xs[q + 1], sv.y, is[q + 1]));
+          lo = fmaxf(lo, lb_term(xs[q + 2], sv.z, is[q + 2]));
+          lo = fmaxf(lo, lb_term(xs[q + 3], sv.w, is[q + 3]));
+        }
+      }
+      if (ub == FLT_MAX) {
+        // seed: the candidate with the smallest (bound, label) of this batch
+        float sl = lo;
+        int32_t sc = C >= 0 ? C : INT32_MAX;
+        for (int off = 1; off < 64; off <<= 1) {
+          const float ol = __shfl_xor(sl, off, 64);
+          const int32_t oc = __shfl_xor(sc, off, 64);
+          if (ol < sl || (ol == sl && oc < sc)) {
+            sl = ol;
+            sc = oc;
+          }
+        }
+        if (sc != INT32_MAX) {
+          float slo = 0.0f, shi = FLT_MAX;
+          if (g == 0) stage_c(sc, slo, shi);
+          slo = __shfl(slo, 0, 64);
+          shi = __shfl(shi, 0, 64);
+          ub = fminf(ub, shi);
+          if (lane == 0) {
+            fc[nf] = sc;
+            fl[nf] = slo;
+          }
+          nf += 1;
+          wave_sync();
+        }
+      }
+      const bool ok = C >= 0 && !(lo > ub * kMargin);
+      const uint64_t m = __ballot(ok);
+      if (ok) {
+        const int at2 = nq + __popcll(m & lt_mask);
+        qc[at2] = C;
+        ql[at2] = lo;
+      }
+      nq += __popcll(m);
+      wave_sync();
+      while (nq >= 8) batch(8);
+    }
+    wave_sync();
   }
+  if (nq > 0) batch(nq);
+  flush();
   if (lane == 0) {
-    best_label[p] = bl;
+    best_label[p] = bl == INT32_MAX ? -1 : bl;
     best_d[p] = bd;
   }
 }
@@ -572,6 +746,7 @@ struct LevelWs {
   double *best_d, *cent;
   float *cperm, *inv32;
   int32_t *perm;
+  int32_t *crow;   // [n] centroid row per cluster id
   int32_t *small;  // [8] device scalars
   float *delta;
 };
@@ -604,6 +779,7 @@ void carve_level(Arena &a, int64_t n, int64_t m, int64_t nnz, int K, LevelWs &w)
   w.cperm = a.take<float>((n + 1) * int64_t((K + 63) / 64 * 64));
   w.inv32 = a.take<float>(512);
   w.perm = a.take<int32_t>(512);
+  w.crow = a.take<int32_t>(n + 1);
   w.small = a.take<int32_t>(8);
   w.delta = a.take<float>(1);
 }
@@ -701,17 +877,17 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
       if (pool_type == kPoolF32) {
         k_centroids<kPoolF32><<<2048, kT, 0, s>>>(L.eptr, L.pins, w.in_list, w.small + 1, pool, K, w.cent);
         k_cperm<kPoolF32><<<g1(n * Kq), kT, 0, s>>>(w.prov, w.owner, w.in_index, w.cent, pool, K, Kq,
-                                                   w.perm, w.small + 3, w.cperm, int32_t(n));
-        k_best<kPoolF32><<<cdiv(n * 64, kT), kT, 0, s>>>(L.eptr, L.pins, st.vptr, st.eids, w.owner,
-                                                     w.prov, w.in_index, w.cent, w.cperm, Kq, w.perm,
+                                                   w.perm, w.small + 3, w.cperm, w.crow, int32_t(n));
+        k_best<kPoolF32><<<cdiv(n, kT / 64), kT, 0, s>>>(L.eptr, L.pins, st.vptr, st.eids, w.owner,
+                                                     w.prov, w.crow, w.cent, w.cperm, Kq, w.perm,
                                                      w.inv32, pool, K, qh, int32_t(n),
                                                      w.best_label, w.best_d);
       } else {
         k_centroids<kPoolBF16><<<2048, kT, 0, s>>>(L.eptr, L.pins, w.in_list, w.small + 1, pool, K, w.cent);
         k_cperm<kPoolBF16><<<g1(n * Kq), kT, 0, s>>>(w.prov, w.owner, w.in_index, w.cent, pool, K, Kq,
-                                                   w.perm, w.small + 3, w.cperm, int32_t(n));
-        k_best<kPoolBF16><<<cdiv(n * 64, kT), kT, 0, s>>>(L.eptr, L.pins, st.vptr, st.eids, w.owner,
-                                                     w.prov, w.in_index, w.cent, w.cperm, Kq, w.perm,
+                                                   w.perm, w.small + 3, w.cperm, w.crow, int32_t(n));
+        k_best<kPoolBF16><<<cdiv(n, kT / 64), kT, 0, s>>>(L.eptr, L.pins, st.vptr, st.eids, w.owner,
+                                                     w.prov, w.crow, w.cent, w.cperm, Kq, w.perm,
                                                      w.inv32, pool, K, qh, int32_t(n),
                                                      w.best_label, w.best_d);
       }

@@ -269,7 +269,7 @@ hef_status hef_workspace_size(const hef_hypergraph *hg, const hef_params *p, int
       Arena a;
       Structure st;
       structure_carve(a, n, m, nnz, st);
-      a.take<float>(m * 16);
+      a.take<float>(spmm_scratch_floats(n, m, 16));
       *bytes = a.mark() + structure_build_ws(n, m, nnz) + 1024;
       return HEF_OK;
     }
@@ -377,7 +377,7 @@ hef_status hef_debug_apply(const hef_hypergraph *hg, int32_t expansion, int32_t 
   a.cap = ws_bytes;
   Structure st;
   structure_carve(a, hg->n, hg->m, hg->nnz, st);
-  float *tb = a.take<float>(int64_t(hg->m) * 16);
+  float *tb = a.take<float>(spmm_scratch_floats(hg->n, hg->m, 16));
   const Level L = level_of(hg);
   HEF_TRY(structure_build(L, st, a, stream));
   if (expansion == 0)

@@ -366,7 +366,7 @@ size_t krylov_ws_bytes(int64_t n, int64_t m, int B) {
   Arena a;
   for (int i = 0; i < 4; ++i) a.take<float>((n + m) * B);
   for (int i = 0; i < 4; ++i) a.take<float>(n * B);
-  a.take<float>(m * B);
+  a.take<float>(spmm_scratch_floats(n, m, B));
   a.take<double>(size_t(2) * kGramBlocks * 9 * B * B);
   a.take<double>(2 * 48 * 48);
   a.take<double>(2 * 48 * 16);
@@ -396,7 +396,7 @@ hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double
   float *sb[4], *cb[4];
   for (int i = 0; i < 4; ++i) sb[i] = ws.take<float>(Ns * B);
   for (int i = 0; i < 4; ++i) cb[i] = ws.take<float>(n * B);
-  float *tb = ws.take<float>(m * B);
+  float *tb = ws.take<float>(spmm_scratch_floats(n, m, B));
   double *partial = ws.take<double>(size_t(2) * kGramBlocks * 9 * B * B);
   double *G = ws.take<double>(2 * 48 * 48);
   double *Tm = ws.take<double>(2 * 48 * 16);

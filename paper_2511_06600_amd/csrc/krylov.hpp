@@ -21,9 +21,12 @@ struct Blocks {
 //          y_V[u] = s_u sum_{e ∋ u} alpha_e x_E[e]
 //   clique T_e    = beta_e sum_{p in e} s_p x_c[p]
 //          y_c[u] = s_u sum_{e ∋ u} T_e - gam_u x_c[u]
-// `tbuf` holds T (m x B).  Either expansion may be skipped (null pointers).
+// `scratch` (spmm_scratch_floats) holds W (m x 2B, [alpha_e x_E | T_e]) then
+// U (n x 2B, [s_p x_V | s_p x_c]); after the call T_e is at
+// scratch[e * 2B + B + c].  Either expansion may be skipped (null pointers).
+inline int64_t spmm_scratch_floats(int64_t n, int64_t m, int B) { return 2 * int64_t(B) * (n + m); }
 hef_status spmm_apply(const Level &L, const Structure &st, int B, const float *xs,
-                      float *ys, const float *xc, float *yc, float *tbuf, hipStream_t s);
+                      float *ys, const float *xc, float *yc, float *scratch, hipStream_t s);
 
 // Pool column storage.
 enum PoolType { kPoolF32 = 0, kPoolBF16 = 1 };

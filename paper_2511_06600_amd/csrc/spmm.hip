@@ -2,9 +2,13 @@
 // (Section III-A: G_b with z_b(e,p) = w_e/|e|, G_c with
 // z_c(u,v) = sum_e w_e / C(|e|,2); A = D^-1/2 W D^-1/2).  Neither expansion
 // is materialised: a CSR pass over hyperedges gathers node rows, a CSC pass
-// over nodes gathers hyperedge rows.  Segments up to kSmallSeg pins go to
-// lane groups (one group of 2*B/CH lanes per segment, one lane per CH-float
-// chunk of a row); longer segments get a whole workgroup.
+// over nodes gathers hyperedge rows.  Both passes gather one interleaved
+// row of 2B floats per incidence: U[p] = [s_p x_V[p] | s_p x_c[p]] (scaled
+// node rows, written by a short prep pass) and W[e] = [alpha_e x_E[e] | T_e]
+// (written by the CSR pass), so each incidence costs one 8B-byte gather and
+// no scale gathers.  Segments up to kSmallSeg go to lane groups (2B/CH
+// lanes per segment, one lane per CH-float chunk of a row); longer segments
+// get one wave each.
 #include "krylov.hpp"
 
 namespace hef {
@@ -37,33 +41,83 @@ __device__ __forceinline__ void store_ch(float *p, const float (&v)[CH]) {
 template <int B>
 struct Geo {
   static constexpr int CH = B < 4 ? B : 4;  // floats per lane
-  static constexpr int NCH = B / CH;        // lanes per vector row
-  static constexpr int LPS = 2 * NCH;       // lanes per segment (2 vectors)
+  static constexpr int NCH = B / CH;        // lanes per B-float half row
+  static constexpr int LPS = 2 * NCH;       // lanes per 2B-float row
+  static constexpr int RW = 2 * B;          // interleaved row width
 };
 
 constexpr int kThreads = 256;
-constexpr int kBigGrid = 1024;
+constexpr int kWaves = kThreads / 64;
+constexpr int kBigGrid = 2048;
 
-// ---- CSR pass: per hyperedge e ------------------------------------------
-// vec 0 (star):   yE[e] = alpha_e * sum_{p in e} s_p xs[p]
-// vec 1 (clique): tb[e] = beta_e  * sum_{p in e} s_p xc[p]
+// U[p] = [s_p xs[p] | s_p xc[p]] (node rows; a missing expansion gives zeros).
+template <int B>
+__global__ void __launch_bounds__(kThreads)
+k_prep(int64_t n, const float *__restrict__ s, const float *__restrict__ xs,
+       const float *__restrict__ xc, float *__restrict__ U) {
+  using G = Geo<B>;
+  const int64_t g = int64_t(xcd_block(blockIdx.x, gridDim.x)) * kThreads + threadIdx.x;
+  const int64_t p = g / G::LPS;
+  const int sub = int(g % G::LPS);
+  if (p >= n) return;
+  const int vec = sub / G::NCH, ch = sub % G::NCH;
+  const float *x = vec == 0 ? xs : xc;
+  float v[G::CH];
+  if (x) {
+    load_ch<G::CH>(x + p * B + ch * G::CH, v);
+    const float sp = s[p];
+#pragma unroll
+    for (int c = 0; c < G::CH; ++c) v[c] *= sp;
+  } else {
+#pragma unroll
+    for (int c = 0; c < G::CH; ++c) v[c] = 0.0f;
+  }
+  store_ch<G::CH>(U + p * G::RW + sub * G::CH, v);
+}
+
+// ---- CSR pass: per hyperedge e (lane sub < NCH: star, else clique) -------
+//   star:   yE[e] = alpha_e * sum_{p in e} U_star[p];  W_star[e] = alpha_e xE[e]
+//   clique: W_T[e] = T_e = beta_e * sum_{p in e} U_clique[p]
+template <int B>
+__device__ __forceinline__ void csr_finish(int64_t e, int sub, const float (&acc)[Geo<B>::CH],
+                                           const float *__restrict__ alpha,
+                                           const float *__restrict__ beta,
+                                           const float *__restrict__ xE, float *__restrict__ yE,
+                                           float *__restrict__ W) {
+  using G = Geo<B>;
+  const int vec = sub / G::NCH, ch = sub % G::NCH;
+  float out[G::CH];
+  if (vec == 0) {
+    const float a = alpha[e];
+#pragma unroll
+    for (int c = 0; c < G::CH; ++c) out[c] = a * acc[c];
+    store_ch<G::CH>(yE + e * B + ch * G::CH, out);
+    float xv[G::CH];
+    load_ch<G::CH>(xE + e * B + ch * G::CH, xv);
+#pragma unroll
+    for (int c = 0; c < G::CH; ++c) xv[c] *= a;
+    store_ch<G::CH>(W + e * G::RW + ch * G::CH, xv);
+  } else {
+    const float bt = beta[e];
+#pragma unroll
+    for (int c = 0; c < G::CH; ++c) out[c] = bt * acc[c];
+    store_ch<G::CH>(W + e * G::RW + B + ch * G::CH, out);
+  }
+}
+
 template <int B>
 __global__ void __launch_bounds__(kThreads)
 k_csr_small(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
-            const float *__restrict__ s, const float *__restrict__ alpha,
-            const float *__restrict__ beta, const float *__restrict__ xs,
-            const float *__restrict__ xc, float *__restrict__ yE, float *__restrict__ tb,
-            int32_t m) {
+            const float *__restrict__ U, const float *__restrict__ alpha,
+            const float *__restrict__ beta, const float *__restrict__ xE,
+            float *__restrict__ yE, float *__restrict__ W, int32_t m, int on_mask) {
   using G = Geo<B>;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t g = blk * kThreads + threadIdx.x;
   const int64_t e = g / G::LPS;
   const int sub = int(g % G::LPS);
   if (e >= m) return;
-  const int vec = sub / G::NCH;
-  const int ch = sub % G::NCH;
-  const float *x = vec == 0 ? xs : xc;
-  if (x == nullptr) return;
+  if (!((on_mask >> (sub / G::NCH)) & 1)) return;
   const int32_t a = eptr[e], b = eptr[e + 1];
   if (b - a > kSmallSeg) return;
   float acc[G::CH];
@@ -74,14 +128,12 @@ k_csr_small(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
     int32_t pp[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) pp[u] = (j0 + u < b) ? pins[j0 + u] : -1;
-    float sp[8], v[8][G::CH];
+    float v[8][G::CH];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       if (pp[u] >= 0) {
-        sp[u] = s[pp[u]];
-        load_ch<G::CH>(x + int64_t(pp[u]) * B + ch * G::CH, v[u]);
+        load_ch<G::CH>(U + int64_t(pp[u]) * G::RW + sub * G::CH, v[u]);
       } else {
-        sp[u] = 0.0f;
 #pragma unroll
         for (int c = 0; c < G::CH; ++c) v[u][c] = 0.0f;
       }
@@ -89,122 +141,75 @@ k_csr_small(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
 #pragma unroll
     for (int u = 0; u < 8; ++u)
 #pragma unroll
-      for (int c = 0; c < G::CH; ++c) acc[c] = fmaf(sp[u], v[u][c], acc[c]);
+      for (int c = 0; c < G::CH; ++c) acc[c] += v[u][c];
   }
-  const float f = vec == 0 ? alpha[e] : beta[e];
-#pragma unroll
-  for (int c = 0; c < G::CH; ++c) acc[c] *= f;
-  store_ch<G::CH>((vec == 0 ? yE : tb) + e * B + ch * G::CH, acc);
+  csr_finish<B>(e, sub, acc, alpha, beta, xE, yE, W);
 }
 
+// One wave per long hyperedge: 64/LPS slots stride over its pins, then a
+// fixed xor tree across slots.
 template <int B>
 __global__ void __launch_bounds__(kThreads)
 k_csr_big(const int32_t *__restrict__ list, const int32_t *__restrict__ count,
           const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
-          const float *__restrict__ s, const float *__restrict__ alpha,
-          const float *__restrict__ beta, const float *__restrict__ xs,
-          const float *__restrict__ xc, float *__restrict__ yE, float *__restrict__ tb) {
+          const float *__restrict__ U, const float *__restrict__ alpha,
+          const float *__restrict__ beta, const float *__restrict__ xE,
+          float *__restrict__ yE, float *__restrict__ W, int on_mask) {
   using G = Geo<B>;
-  constexpr int SLOTS = kThreads / G::LPS;
-  __shared__ float red[kThreads * G::CH];
-  const int tid = threadIdx.x;
-  const int slot = tid / G::LPS;
-  const int sub = tid % G::LPS;
-  const int vec = sub / G::NCH;
-  const int ch = sub % G::NCH;
-  const float *x = vec == 0 ? xs : xc;
+  constexpr int SLOTS = 64 / G::LPS;
+  const int lane = threadIdx.x & 63;
+  const int slot = lane / G::LPS;
+  const int sub = lane % G::LPS;
+  const bool on = (on_mask >> (sub / G::NCH)) & 1;
   const int32_t cnt = *count;
-  for (int32_t bi = blockIdx.x; bi < cnt; bi += gridDim.x) {
+  for (int32_t bi = blockIdx.x * kWaves + (threadIdx.x >> 6); bi < cnt;
+       bi += gridDim.x * kWaves) {
     const int32_t e = list[bi];
     const int32_t a = eptr[e], b = eptr[e + 1];
     float acc[G::CH];
 #pragma unroll
     for (int c = 0; c < G::CH; ++c) acc[c] = 0.0f;
-    if (x != nullptr) {
-      for (int32_t j = a + slot; j < b; j += SLOTS) {
-        const int32_t p = pins[j];
-        const float sp = s[p];
-        float v[G::CH];
-        load_ch<G::CH>(x + int64_t(p) * B + ch * G::CH, v);
+    if (on) {
+      // 8 incidences per slot in flight: ids first, then rows
+      for (int32_t j0 = a + slot; j0 < b; j0 += 8 * SLOTS) {
+        int32_t pp[8];
 #pragma unroll
-        for (int c = 0; c < G::CH; ++c) acc[c] = fmaf(sp, v[c], acc[c]);
+        for (int q = 0; q < 8; ++q) pp[q] = (j0 + q * SLOTS < b) ? pins[j0 + q * SLOTS] : -1;
+        float v[8][G::CH];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          if (pp[q] >= 0) {
+            load_ch<G::CH>(U + int64_t(pp[q]) * G::RW + sub * G::CH, v[q]);
+          } else {
+#pragma unroll
+            for (int c = 0; c < G::CH; ++c) v[q][c] = 0.0f;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+          for (int c = 0; c < G::CH; ++c) acc[c] += v[q][c];
       }
     }
 #pragma unroll
-    for (int c = 0; c < G::CH; ++c) red[tid * G::CH + c] = acc[c];
-    __syncthreads();
-    for (int stride = SLOTS / 2; stride > 0; stride >>= 1) {
-      if (slot < stride) {
+    for (int off = 32; off >= G::LPS; off >>= 1)
 #pragma unroll
-        for (int c = 0; c < G::CH; ++c)
-          red[tid * G::CH + c] += red[(tid + stride * G::LPS) * G::CH + c];
-      }
-      __syncthreads();
-    }
-    if (slot == 0 && x != nullptr) {
-      float out[G::CH];
-      const float f = vec == 0 ? alpha[e] : beta[e];
-#pragma unroll
-      for (int c = 0; c < G::CH; ++c) out[c] = red[tid * G::CH + c] * f;
-      store_ch<G::CH>((vec == 0 ? yE : tb) + int64_t(e) * B + ch * G::CH, out);
-    }
-    __syncthreads();
+      for (int c = 0; c < G::CH; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
+    if (slot == 0 && on) csr_finish<B>(e, sub, acc, alpha, beta, xE, yE, W);
   }
 }
 
-// ---- CSC pass: per node u -----------------------------------------------
-// vec 0 (star):   yV[u] = s_u * sum_{e ∋ u} alpha_e xE[e]
-// vec 1 (clique): yc[u] = s_u * sum_{e ∋ u} tb[e] - gam_u xc[u]
+// ---- CSC pass: per node u ---------------------------------------------------
+//   star:   yV[u] = s_u * sum_{e ∋ u} W_star[e]
+//   clique: yc[u] = s_u * sum_{e ∋ u} W_T[e] - gam_u xc[u]
 template <int B>
-__global__ void __launch_bounds__(kThreads)
-k_csc_small(const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
-            const float *__restrict__ s, const float *__restrict__ gam,
-            const float *__restrict__ alpha, const float *__restrict__ xE,
-            const float *__restrict__ tb, const float *__restrict__ xc,
-            float *__restrict__ yV, float *__restrict__ yc, int32_t n) {
+__device__ __forceinline__ void csc_finish(int64_t u, int sub, const float (&acc)[Geo<B>::CH],
+                                           const float *__restrict__ s,
+                                           const float *__restrict__ gam,
+                                           const float *__restrict__ xc, float *__restrict__ yV,
+                                           float *__restrict__ yc) {
   using G = Geo<B>;
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t g = blk * kThreads + threadIdx.x;
-  const int64_t u = g / G::LPS;
-  const int sub = int(g % G::LPS);
-  if (u >= n) return;
-  const int vec = sub / G::NCH;
-  const int ch = sub % G::NCH;
-  if (vec == 0 ? (xE == nullptr) : (xc == nullptr)) return;
-  const int32_t a = vptr[u], b = vptr[u + 1];
-  if (b - a > kSmallSeg) return;
-  float acc[G::CH];
-#pragma unroll
-  for (int c = 0; c < G::CH; ++c) acc[c] = 0.0f;
-  // chunks of 8 hyperedges: all ids first, then all rows
-  for (int32_t j0 = a; j0 < b; j0 += 8) {
-    int32_t ee[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) ee[u] = (j0 + u < b) ? eids[j0 + u] : -1;
-    float f[8], v[8][G::CH];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      if (ee[u] >= 0) {
-        f[u] = vec == 0 ? alpha[ee[u]] : 1.0f;
-        load_ch<G::CH>((vec == 0 ? xE : tb) + int64_t(ee[u]) * B + ch * G::CH, v[u]);
-      } else {
-        f[u] = 0.0f;
-#pragma unroll
-        for (int c = 0; c < G::CH; ++c) v[u][c] = 0.0f;
-      }
-    }
-    if (vec == 0) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-#pragma unroll
-        for (int c = 0; c < G::CH; ++c) acc[c] = fmaf(f[u], v[u][c], acc[c]);
-    } else {
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-#pragma unroll
-        for (int c = 0; c < G::CH; ++c) acc[c] += v[u][c];
-    }
-  }
+  const int vec = sub / G::NCH, ch = sub % G::NCH;
   const float su = s[u];
   float out[G::CH];
   if (vec == 0) {
@@ -223,93 +228,121 @@ k_csc_small(const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
 
 template <int B>
 __global__ void __launch_bounds__(kThreads)
+k_csc_small(const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
+            const float *__restrict__ W, const float *__restrict__ s,
+            const float *__restrict__ gam, const float *__restrict__ xc,
+            float *__restrict__ yV, float *__restrict__ yc, int32_t n, int on_mask) {
+  using G = Geo<B>;
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t g = blk * kThreads + threadIdx.x;
+  const int64_t u = g / G::LPS;
+  const int sub = int(g % G::LPS);
+  if (u >= n) return;
+  if (!((on_mask >> (sub / G::NCH)) & 1)) return;
+  const int32_t a = vptr[u], b = vptr[u + 1];
+  if (b - a > kSmallSeg) return;
+  float acc[G::CH];
+#pragma unroll
+  for (int c = 0; c < G::CH; ++c) acc[c] = 0.0f;
+  // chunks of 8 hyperedges: all ids first, then all rows
+  for (int32_t j0 = a; j0 < b; j0 += 8) {
+    int32_t ee[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ee[q] = (j0 + q < b) ? eids[j0 + q] : -1;
+    float v[8][G::CH];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (ee[q] >= 0) {
+        load_ch<G::CH>(W + int64_t(ee[q]) * G::RW + sub * G::CH, v[q]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < G::CH; ++c) v[q][c] = 0.0f;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int c = 0; c < G::CH; ++c) acc[c] += v[q][c];
+  }
+  csc_finish<B>(u, sub, acc, s, gam, xc, yV, yc);
+}
+
+template <int B>
+__global__ void __launch_bounds__(kThreads)
 k_csc_big(const int32_t *__restrict__ list, const int32_t *__restrict__ count,
           const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
-          const float *__restrict__ s, const float *__restrict__ gam,
-          const float *__restrict__ alpha, const float *__restrict__ xE,
-          const float *__restrict__ tb, const float *__restrict__ xc,
-          float *__restrict__ yV, float *__restrict__ yc) {
+          const float *__restrict__ W, const float *__restrict__ s,
+          const float *__restrict__ gam, const float *__restrict__ xc,
+          float *__restrict__ yV, float *__restrict__ yc, int on_mask) {
   using G = Geo<B>;
-  constexpr int SLOTS = kThreads / G::LPS;
-  __shared__ float red[kThreads * G::CH];
-  const int tid = threadIdx.x;
-  const int slot = tid / G::LPS;
-  const int sub = tid % G::LPS;
-  const int vec = sub / G::NCH;
-  const int ch = sub % G::NCH;
-  const bool on = vec == 0 ? (xE != nullptr) : (xc != nullptr);
+  constexpr int SLOTS = 64 / G::LPS;
+  const int lane = threadIdx.x & 63;
+  const int slot = lane / G::LPS;
+  const int sub = lane % G::LPS;
+  const bool on = (on_mask >> (sub / G::NCH)) & 1;
   const int32_t cnt = *count;
-  for (int32_t bi = blockIdx.x; bi < cnt; bi += gridDim.x) {
+  for (int32_t bi = blockIdx.x * kWaves + (threadIdx.x >> 6); bi < cnt;
+       bi += gridDim.x * kWaves) {
     const int32_t u = list[bi];
     const int32_t a = vptr[u], b = vptr[u + 1];
     float acc[G::CH];
 #pragma unroll
     for (int c = 0; c < G::CH; ++c) acc[c] = 0.0f;
     if (on) {
-      for (int32_t j = a + slot; j < b; j += SLOTS) {
-        const int32_t e = eids[j];
-        float v[G::CH];
-        if (vec == 0) {
-          const float f = alpha[e];
-          load_ch<G::CH>(xE + int64_t(e) * B + ch * G::CH, v);
+      for (int32_t j0 = a + slot; j0 < b; j0 += 8 * SLOTS) {
+        int32_t ee[8];
 #pragma unroll
-          for (int c = 0; c < G::CH; ++c) acc[c] = fmaf(f, v[c], acc[c]);
-        } else {
-          load_ch<G::CH>(tb + int64_t(e) * B + ch * G::CH, v);
+        for (int q = 0; q < 8; ++q) ee[q] = (j0 + q * SLOTS < b) ? eids[j0 + q * SLOTS] : -1;
+        float v[8][G::CH];
 #pragma unroll
-          for (int c = 0; c < G::CH; ++c) acc[c] += v[c];
+        for (int q = 0; q < 8; ++q) {
+          if (ee[q] >= 0) {
+            load_ch<G::CH>(W + int64_t(ee[q]) * G::RW + sub * G::CH, v[q]);
+          } else {
+#pragma unroll
+            for (int c = 0; c < G::CH; ++c) v[q][c] = 0.0f;
+          }
         }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+          for (int c = 0; c < G::CH; ++c) acc[c] += v[q][c];
       }
     }
 #pragma unroll
-    for (int c = 0; c < G::CH; ++c) red[tid * G::CH + c] = acc[c];
-    __syncthreads();
-    for (int stride = SLOTS / 2; stride > 0; stride >>= 1) {
-      if (slot < stride) {
+    for (int off = 32; off >= G::LPS; off >>= 1)
 #pragma unroll
-        for (int c = 0; c < G::CH; ++c)
-          red[tid * G::CH + c] += red[(tid + stride * G::LPS) * G::CH + c];
-      }
-      __syncthreads();
-    }
-    if (slot == 0 && on) {
-      const float su = s[u];
-      float out[G::CH];
-      if (vec == 0) {
-#pragma unroll
-        for (int c = 0; c < G::CH; ++c) out[c] = su * red[tid * G::CH + c];
-        store_ch<G::CH>(yV + int64_t(u) * B + ch * G::CH, out);
-      } else {
-        const float gu = gam[u];
-        float own[G::CH];
-        load_ch<G::CH>(xc + int64_t(u) * B + ch * G::CH, own);
-#pragma unroll
-        for (int c = 0; c < G::CH; ++c) out[c] = su * red[tid * G::CH + c] - gu * own[c];
-        store_ch<G::CH>(yc + int64_t(u) * B + ch * G::CH, out);
-      }
-    }
-    __syncthreads();
+      for (int c = 0; c < G::CH; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
+    if (slot == 0 && on) csc_finish<B>(u, sub, acc, s, gam, xc, yV, yc);
   }
 }
 
 template <int B>
 hef_status spmm_t(const Level &L, const Structure &st, const float *xs, float *ys,
-                  const float *xc, float *yc, float *tb, hipStream_t s) {
+                  const float *xc, float *yc, float *scratch, hipStream_t s) {
   using G = Geo<B>;
   const int64_t n = L.n, m = L.m;
   const float *xE = xs ? xs + n * B : nullptr;
   float *yE = ys ? ys + n * B : nullptr;
+  float *W = scratch;
+  float *U = scratch + m * G::RW;
+  const int on = (xs ? 1 : 0) | (xc ? 2 : 0);
+  if (n > 0) {
+    TimedScope ts(kStSpmmCsr, s);
+    k_prep<B><<<cdiv(n * G::LPS, kThreads), kThreads, 0, s>>>(n, st.s, xs, xc, U);
+    HEF_LAUNCH_CHECK();
+  }
   if (m > 0) {
     const int64_t nb = cdiv(m * G::LPS, kThreads);
     {
       TimedScope ts(kStSpmmCsr, s);
-      k_csr_small<B><<<nb, kThreads, 0, s>>>(L.eptr, L.pins, st.s, st.alpha, st.beta, xs, xc,
-                                             yE, tb, int32_t(m));
+      k_csr_small<B><<<nb, kThreads, 0, s>>>(L.eptr, L.pins, U, st.alpha, st.beta, xE, yE, W,
+                                             int32_t(m), on);
     }
     {
       TimedScope ts(kStSpmmCsrBig, s);
-      k_csr_big<B><<<kBigGrid, kThreads, 0, s>>>(st.big_e, st.n_big, L.eptr, L.pins, st.s,
-                                                 st.alpha, st.beta, xs, xc, yE, tb);
+      k_csr_big<B><<<kBigGrid, kThreads, 0, s>>>(st.big_e, st.n_big, L.eptr, L.pins, U,
+                                                 st.alpha, st.beta, xE, yE, W, on);
     }
     HEF_LAUNCH_CHECK();
   }
@@ -317,13 +350,13 @@ hef_status spmm_t(const Level &L, const Structure &st, const float *xs, float *y
     const int64_t nb = cdiv(n * G::LPS, kThreads);
     {
       TimedScope ts(kStSpmmCsc, s);
-      k_csc_small<B><<<nb, kThreads, 0, s>>>(st.vptr, st.eids, st.s, st.gam, st.alpha, xE, tb,
-                                             xc, ys, yc, int32_t(n));
+      k_csc_small<B><<<nb, kThreads, 0, s>>>(st.vptr, st.eids, W, st.s, st.gam, xc, ys, yc,
+                                             int32_t(n), on);
     }
     {
       TimedScope ts(kStSpmmCscBig, s);
-      k_csc_big<B><<<kBigGrid, kThreads, 0, s>>>(st.big_v, st.n_big + 1, st.vptr, st.eids, st.s,
-                                                 st.gam, st.alpha, xE, tb, xc, ys, yc);
+      k_csc_big<B><<<kBigGrid, kThreads, 0, s>>>(st.big_v, st.n_big + 1, st.vptr, st.eids, W,
+                                                 st.s, st.gam, xc, ys, yc, on);
     }
     HEF_LAUNCH_CHECK();
   }
@@ -333,13 +366,13 @@ hef_status spmm_t(const Level &L, const Structure &st, const float *xs, float *y
 }  // namespace
 
 hef_status spmm_apply(const Level &L, const Structure &st, int B, const float *xs, float *ys,
-                      const float *xc, float *yc, float *tbuf, hipStream_t s) {
+                      const float *xc, float *yc, float *scratch, hipStream_t s) {
   switch (B) {
-    case 1: return spmm_t<1>(L, st, xs, ys, xc, yc, tbuf, s);
-    case 2: return spmm_t<2>(L, st, xs, ys, xc, yc, tbuf, s);
-    case 4: return spmm_t<4>(L, st, xs, ys, xc, yc, tbuf, s);
-    case 8: return spmm_t<8>(L, st, xs, ys, xc, yc, tbuf, s);
-    case 16: return spmm_t<16>(L, st, xs, ys, xc, yc, tbuf, s);
+    case 1: return spmm_t<1>(L, st, xs, ys, xc, yc, scratch, s);
+    case 2: return spmm_t<2>(L, st, xs, ys, xc, yc, scratch, s);
+    case 4: return spmm_t<4>(L, st, xs, ys, xc, yc, scratch, s);
+    case 8: return spmm_t<8>(L, st, xs, ys, xc, yc, scratch, s);
+    case 16: return spmm_t<16>(L, st, xs, ys, xc, yc, scratch, s);
     default: set_error("block width %d is not a power of two in 1..16", B);
              return HEF_ERR_UNSUPPORTED;
   }
