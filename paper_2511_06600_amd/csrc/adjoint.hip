@@ -538,7 +538,7 @@ struct BwdWs {
   Structure st;
   int32_t *flags = nullptr;
   float *xs = nullptr, *xc = nullptr;   // generated start blocks
-  float *P = nullptr, *chi = nullptr;   // pool before / after the joint QR
+  float *P = nullptr, *chi = nullptr;   // pool before (row-octet) / after the joint QR
   double *qh = nullptr;
   float *R = nullptr;
   double *rinvJ = nullptr;
@@ -571,7 +571,7 @@ void carve(Arena &a, int64_t n, int64_t m, int64_t nnz, const hef_params &p, Bwd
   w.flags = a.take<int32_t>(4);
   w.xs = a.take<float>(Ns * B);
   w.xc = a.take<float>(n * B);
-  w.P = a.take<float>(n * K);
+  w.P = a.take<float>(oct_rows(n) * K);
   w.chi = a.take<float>(n * K);
   w.qh = a.take<double>(K);
   w.R = a.take<float>(m);
@@ -774,10 +774,8 @@ hef_status resistance_backward(const Level &L, const hef_params &p, const float 
   ko.pool_type = kPoolF32;
   HEF_TRY(krylov_pool(L, st, B, k, double(p.drop_tol), start_star, start_clique, use_star,
                       use_clique, ko, a, s, &w.tape));
-  void *result = nullptr;
-  HEF_TRY(orthonormalize_pool(w.P, w.chi, kPoolF32, n, K, double(p.drop_tol), 1, nullptr,
-                              &result, a, s, w.rinvJ));
-  if (result != w.chi) { set_error("internal: pool buffers out of step"); return HEF_ERR_DEVICE; }
+  HEF_TRY(orthonormalize_pool(w.P, w.chi, kPoolF32, n, K, double(p.drop_tol), 1, nullptr, a, s,
+                              w.rinvJ));
   HEF_TRY(score_pool(L, w.chi, kPoolF32, K, w.qh, w.R, a, s));
 
   TimedScope ts(kStAdjoint, s);

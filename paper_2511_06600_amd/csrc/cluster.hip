@@ -1057,7 +1057,7 @@ void carve_coarsen(Arena &a, int64_t n, int64_t m, int64_t nnz, const hef_params
   c.flags = a.take<int32_t>(4);
   const int K = pool_width_of(p);
   c.pool = a.take<char>(size_t(n) * K * (p.basis == HEF_BASIS_BF16 ? 2 : 4));
-  c.pool2 = a.take<char>(size_t(n) * K * (p.basis == HEF_BASIS_BF16 ? 2 : 4));
+  c.pool2 = a.take<char>(size_t(oct_rows(n)) * K * (p.basis == HEF_BASIS_BF16 ? 2 : 4));
   c.qh = a.take<double>(K);
   c.R = a.take<float>(m + 1);
   for (int i = 0; i < 2; ++i) {

@@ -61,6 +61,12 @@ struct Arena {
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// The Krylov pool before orthonormalisation is stored in a row-octet layout:
+// rows in groups of 8, each column of a group contiguous, i.e. element
+// (r, c) of an n x K pool at ((r >> 3) * K + c) * 8 + (r & 7), with n
+// padded to oct_rows(n) (padding rows are zero).
+inline int64_t oct_rows(int64_t n) { return (n + 7) / 8 * 8; }
+
 // Map a launched block index to a logical one so that each of the 8 XCDs of
 // an MI355X (which receive blocks round-robin) walks a contiguous range of
 // logical blocks; neighbouring work then shares its XCD's L2.

@@ -149,7 +149,7 @@ size_t resistance_bytes(int64_t n, int64_t m, int64_t nnz, const hef_params &p, 
   a.take<int32_t>(4);  // flags
   const int K = pool_width(p);
   if (own_pool) a.take<char>(pool_bytes(n, K, p.basis));
-  a.take<char>(pool_bytes(n, K, p.basis));  // second buffer of the orthonormalisation
+  a.take<char>(pool_bytes(oct_rows(n), K, p.basis));  // the Krylov pool before orthonormalisation
   a.take<double>(K);  // qh
   a.take<float>(m);   // R
   return a.mark() + estimate_scratch(n, m, nnz, p) + 1024;
@@ -166,9 +166,9 @@ __global__ void k_check_finite(const float *R, int64_t m, const double *qh, int 
 
 }  // namespace
 
-// Alg. 1 on one level; the orthonormal pool ends in `pool` (`pool2` is the
-// second buffer of the orthonormalisation); qh and R are caller- or
-// arena-provided.
+// Alg. 1 on one level; the orthonormal pool ends in `pool` (n x K); `pool2`
+// (oct_rows(n) x K) holds the Krylov pool before orthonormalisation; qh and R
+// are caller- or arena-provided.
 hef_status estimate_level(const Level &L, const hef_params &p, uint64_t seed, int level,
                           const float *start_star, const float *start_clique, Structure &st,
                           void *pool, void *pool2, double *qh, float *R, Arena &ws,
@@ -193,22 +193,16 @@ hef_status estimate_level(const Level &L, const hef_params &p, uint64_t seed, in
     HEF_TRY(start_block(seed, level, 1, n, B, xc, s));
     start_clique = xc;
   }
-  // the Krylov pool goes where the orthonormalisation's passes end in `pool`
+  // the Krylov pool (row-octet layout) in pool2, its orthonormal basis in pool
   KrylovOut ko;
-  ko.pool = (p.orth_passes % 2 == 1) ? pool2 : pool;
+  ko.pool = pool2;
   ko.K = K;
   ko.pool_type = p.basis == HEF_BASIS_BF16 ? kPoolBF16 : kPoolF32;
   HEF_TRY(krylov_pool(L, st, B, p.k, double(p.drop_tol), start_star, start_clique, use_star,
                       use_clique, ko, ws, s));
   ws.reset(mk);
-  void *other = ko.pool == pool ? pool2 : pool;
-  void *result = nullptr;
-  HEF_TRY(orthonormalize_pool(ko.pool, other, ko.pool_type, n, K, double(p.drop_tol),
-                              p.orth_passes, nullptr, &result, ws, s));
-  if (result != pool) {
-    set_error("internal: pool buffers out of step");
-    return HEF_ERR_DEVICE;
-  }
+  HEF_TRY(orthonormalize_pool(pool2, pool, ko.pool_type, n, K, double(p.drop_tol),
+                              p.orth_passes, nullptr, ws, s));
   HEF_TRY(score_pool(L, pool, ko.pool_type, K, qh, R, ws, s));
   return HEF_OK;
 }
@@ -324,7 +318,7 @@ hef_status hef_resistance(const hef_hypergraph *hg, const hef_params *p, const f
   structure_carve(a, n, m, nnz, st);
   int32_t *flags = a.take<int32_t>(4);
   void *pool = chi ? chi : a.take<char>(pool_bytes(n, K, p->basis));
-  void *pool2 = a.take<char>(pool_bytes(n, K, p->basis));
+  void *pool2 = a.take<char>(pool_bytes(oct_rows(n), K, p->basis));
   double *qh_ws = a.take<double>(K);
   float *R_ws = a.take<float>(m);
   if (a.overflow) { set_error("workspace carve overflow"); return HEF_ERR_WORKSPACE_TOO_SMALL; }

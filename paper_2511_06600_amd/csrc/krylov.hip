@@ -19,11 +19,68 @@ namespace {
 
 constexpr int kGramBlocks = 1024;  // workgroups of the Gram partial pass
 
+// Register staging of one Gram slab of M = [v0 | v1 | y] (SLAB rows).
+template <int B, int SLAB>
+struct GramSlab {
+  static constexpr int C = 3 * B;
+  static constexpr int LD = C + 1;
+  static constexpr int Q = B >= 4 ? B / 4 : 1;  // float4 per row per array
+  static constexpr int TOT = B >= 4 ? SLAB * 3 * Q : SLAB * C;
+  static constexpr int NPT = (TOT + 255) / 256;
+  static __device__ __forceinline__ void fetch(float4 (&pre)[NPT], int tid, int64_t base,
+                                               int64_t r1, const float *v0, const float *v1,
+                                               const float *y) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int e = tid + 256 * i;
+      float4 t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (e < TOT) {
+        if constexpr (B >= 4) {
+          const int a = e / (SLAB * Q);
+          const int rem = e % (SLAB * Q);
+          const int r = rem / Q, q = rem % Q;
+          const int64_t row = base + r;
+          const float *src = a == 0 ? v0 : (a == 1 ? v1 : y);
+          if (row < r1 && src) t = *reinterpret_cast<const float4 *>(src + row * B + 4 * q);
+        } else {
+          const int r = e / C, c = e % C;
+          const int64_t row = base + r;
+          if (row < r1) {
+            if (c < B) t.x = v0 ? v0[row * B + c] : 0.0f;
+            else if (c < 2 * B) t.x = v1 ? v1[row * B + c - B] : 0.0f;
+            else t.x = y[row * B + c - 2 * B];
+          }
+        }
+      }
+      pre[i] = t;
+    }
+  }
+  static __device__ __forceinline__ void stash(const float4 (&pre)[NPT], int tid, float *sh) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int e = tid + 256 * i;
+      if (e < TOT) {
+        if constexpr (B >= 4) {
+          const int a = e / (SLAB * Q);
+          const int rem = e % (SLAB * Q);
+          const int r = rem / Q, q = rem % Q;
+          float *d = sh + r * LD + a * B + 4 * q;
+          d[0] = pre[i].x; d[1] = pre[i].y; d[2] = pre[i].z; d[3] = pre[i].w;
+        } else {
+          const int r = e / C, c = e % C;
+          sh[r * LD + c] = pre[i].x;
+        }
+      }
+    }
+  }
+};
+
 // Gram partials of M = [v0 | v1 | y] (rows x C, C = 3B), FP32 register
 // blocks: the C x C Gram is cut into S x S blocks, one thread per block on or
 // above the diagonal; a workgroup stages 64-row slabs in LDS and its RG row
 // groups split each slab's rows.  Per-thread FP32 sums (a few hundred rows)
-// are combined in float64 in row-group order; partial[blk][C*C].
+// are combined in float64 in row-group order; partial[blk][C*C].  The next
+// slab is loaded into registers while the current one is consumed.
 template <int B>
 __global__ void __launch_bounds__(256)
 k_lgram(const float *__restrict__ v0, const float *__restrict__ v1,
@@ -57,36 +114,15 @@ k_lgram(const float *__restrict__ v0, const float *__restrict__ v1,
     for (int b = 0; b < S; ++b) acc[a][b] = 0.0f;
   const int64_t r0 = int64_t(blockIdx.x) * rows_per_blk;
   const int64_t r1 = r0 + rows_per_blk < rows ? r0 + rows_per_blk : rows;
+  // the next slab is fetched into registers while the current one is used
+  using SL = GramSlab<B, SLAB>;
+  float4 pre[SL::NPT];
+  if (r0 < r1) SL::fetch(pre, tid, r0, r1, v0, v1, y);
   for (int64_t base = r0; base < r1; base += SLAB) {
     __syncthreads();
-    if constexpr (B >= 4) {
-      // float4 loads: each array's rows are contiguous B-float records
-      constexpr int Q = B / 4;
-      for (int e = tid; e < SLAB * 3 * Q; e += 256) {
-        const int a = e / (SLAB * Q);
-        const int rem = e % (SLAB * Q);
-        const int r = rem / Q, q = rem % Q;
-        const int64_t row = base + r;
-        const float *src = a == 0 ? v0 : (a == 1 ? v1 : y);
-        float4 t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (row < r1 && src) t = *reinterpret_cast<const float4 *>(src + row * B + 4 * q);
-        float *d = sh + r * LD + a * B + 4 * q;
-        d[0] = t.x; d[1] = t.y; d[2] = t.z; d[3] = t.w;
-      }
-    } else {
-      for (int e = tid; e < SLAB * C; e += 256) {
-        const int r = e / C, c = e % C;
-        const int64_t row = base + r;
-        float v = 0.0f;
-        if (row < r1) {
-          if (c < B) v = v0 ? v0[row * B + c] : 0.0f;
-          else if (c < 2 * B) v = v1 ? v1[row * B + c - B] : 0.0f;
-          else v = y[row * B + c - 2 * B];
-        }
-        sh[r * LD + c] = v;
-      }
-    }
+    SL::stash(pre, tid, sh);
     __syncthreads();
+    if (base + SLAB < r1) SL::fetch(pre, tid, base + SLAB, r1, v0, v1, y);
     if (active) {
       for (int r = g; r < SLAB; r += RG) {
         float xa[S], xb[S];
@@ -154,39 +190,29 @@ k_lsolve(const double *__restrict__ Gall, int C, int B, double tau,
     }
     __syncthreads();
   }
-  // column c of R^-1 (R = L^T) = row c of L^-1: L^T x = e_c by back substitution
-  if (t < B) {
-    const int c = 2 * B + t;
-    double x[48];
-    for (int i = 0; i < C; ++i) x[i] = 0.0;
-    if (keep[c]) {
-      x[c] = 1.0 / Lm[c * C + c];
-      for (int i = c - 1; i >= 0; --i) {
-        if (!keep[i]) continue;
-        double acc = 0.0;
-        for (int l = i + 1; l <= c; ++l) acc += Lm[l * C + i] * x[l];
-        x[i] = -acc / Lm[i * C + i];
-      }
-    }
-    for (int i = 0; i < C; ++i) T[i * B + t] = x[i];
-    if (!keep[c]) atomicAdd(&drops[blockIdx.x], 1);
-  }
-  // optionally the whole R^-1 (row-major C x C), zero rows/columns for drops
-  if (Rall && t < C) {
-    double *Rf = Rall + blockIdx.x * C * C;
+  // column c of R^-1 (R = L^T): L^T x = e_c by back substitution, one
+  // thread per column, the vectors in LDS
+  __shared__ double X[48 * 49];
+  if (t < C) {
     const int c = t;
-    double x[48];
-    for (int i = 0; i < C; ++i) x[i] = 0.0;
+    for (int i = 0; i < C; ++i) X[i * 49 + c] = 0.0;
     if (keep[c]) {
-      x[c] = 1.0 / Lm[c * C + c];
+      X[c * 49 + c] = 1.0 / Lm[c * C + c];
       for (int i = c - 1; i >= 0; --i) {
         if (!keep[i]) continue;
         double acc = 0.0;
-        for (int l = i + 1; l <= c; ++l) acc += Lm[l * C + i] * x[l];
-        x[i] = -acc / Lm[i * C + i];
+        for (int l = i + 1; l <= c; ++l) acc += Lm[l * C + i] * X[l * 49 + c];
+        X[i * 49 + c] = -acc / Lm[i * C + i];
       }
     }
-    for (int i = 0; i < C; ++i) Rf[i * C + c] = x[i];
+  }
+  __syncthreads();
+  for (int e = t; e < C * B; e += 64) T[e] = X[(e / B) * 49 + 2 * B + e % B];
+  if (t < B && !keep[2 * B + t]) atomicAdd(&drops[blockIdx.x], 1);
+  // optionally the whole R^-1 (row-major C x C), zero rows/columns for drops
+  if (Rall) {
+    double *Rf = Rall + blockIdx.x * C * C;
+    for (int e = t; e < C * C; e += 64) Rf[e] = X[(e / C) * 49 + e % C];
   }
 }
 
@@ -196,9 +222,11 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return uint16_t(u >> 16);
 }
 
-// V_next = [v0 | v1 | y] T in float64 arithmetic; one thread per (row,
-// chunk of CH outputs).  The first pool_rows rows also go to the pool at
-// column col0 (float32 or bfloat16).
+// V_next = [v0 | v1 | y] T in float64 arithmetic.  A workgroup stages its
+// rows of the three inputs in LDS with coalesced float4 loads, one thread per
+// row (two for B = 16) forms the outputs, which leave through LDS as
+// coalesced stores.  The first pool_rows rows also go to the pool (row-octet
+// layout, float32 or bfloat16) at column col0.
 template <int CH>
 __device__ __forceinline__ void ld(const float *p, float (&v)[CH]) {
   if constexpr (CH == 4) {
@@ -219,55 +247,96 @@ k_lapply(const float *__restrict__ v0, const float *__restrict__ v1,
          int64_t rows, void *__restrict__ pool, int pool_type, int64_t pool_rows, int K,
          int col0) {
   constexpr int C = 3 * B;
-  constexpr int CH = B < 4 ? B : 4;
-  constexpr int NCH = B / CH;
+  constexpr int RB = B <= 8 ? 256 : 128;  // rows per workgroup
+  constexpr int NSPL = 256 / RB;          // threads per row
+  constexpr int OPT = B / NSPL;           // outputs per thread
+  constexpr int LDR = B + 1;              // LDS row stride (odd: no bank conflicts)
   __shared__ double Ts[C * B];
-  for (int e = threadIdx.x; e < C * B; e += 256) Ts[e] = Tm[e];
-  __syncthreads();
-  const int64_t g = int64_t(xcd_block(blockIdx.x, gridDim.x)) * 256 + threadIdx.x;
-  const int64_t r = g / NCH;
-  const int ch = int(g % NCH);
-  if (r >= rows) return;
-  double out[CH];
-#pragma unroll
-  for (int c = 0; c < CH; ++c) out[c] = 0.0;
+  __shared__ float sm[3][RB * LDR];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < C * B; e += 256) Ts[e] = Tm[e];
+  const int64_t row0 = int64_t(xcd_block(blockIdx.x, gridDim.x)) * RB;
+  const int nrow = int(rows - row0 < RB ? rows - row0 : RB);
   const float *src[3] = {v0, v1, y};
+  // coalesced loads of the workgroup's rows into LDS
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (src[a] == nullptr) continue;
-#pragma unroll
-    for (int q4 = 0; q4 < B / CH; ++q4) {
-      float v[CH];
-      ld<CH>(src[a] + r * B + q4 * CH, v);
-#pragma unroll
-      for (int u = 0; u < CH; ++u) {
-        const double md = double(v[u]);
-        const double *trow = Ts + (a * B + q4 * CH + u) * B + ch * CH;
-#pragma unroll
-        for (int c = 0; c < CH; ++c) out[c] = fma(md, trow[c], out[c]);
+    const float *base = src[a] + row0 * B;
+    if constexpr (B >= 4) {
+      for (int i = tid; i < nrow * B / 4; i += 256) {
+        const float4 t = reinterpret_cast<const float4 *>(base)[i];
+        float *d = &sm[a][(4 * i / B) * LDR + (4 * i) % B];
+        d[0] = t.x; d[1] = t.y; d[2] = t.z; d[3] = t.w;
       }
+    } else {
+      for (int i = tid; i < nrow * B; i += 256) sm[a][(i / B) * LDR + i % B] = base[i];
     }
   }
-  float of[CH];
+  __syncthreads();
+  const int r = tid / NSPL, h = tid % NSPL;
+  float of[OPT];
+  {
+    double out[OPT];
 #pragma unroll
-  for (int c = 0; c < CH; ++c) of[c] = float(out[c]);
-  float *dst = vn + r * B + ch * CH;
-  if constexpr (CH == 4) {
-    *reinterpret_cast<float4 *>(dst) = make_float4(of[0], of[1], of[2], of[3]);
-  } else {
+    for (int c = 0; c < OPT; ++c) out[c] = 0.0;
+    if (r < nrow) {
 #pragma unroll
-    for (int c = 0; c < CH; ++c) dst[c] = of[c];
+      for (int a = 0; a < 3; ++a) {
+        if (src[a] == nullptr) continue;
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          const double md = double(sm[a][r * LDR + u]);
+          const double *trow = Ts + (a * B + u) * B + h * OPT;
+#pragma unroll
+          for (int c = 0; c < OPT; ++c) out[c] = fma(md, trow[c], out[c]);
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < OPT; ++c) of[c] = float(out[c]);
   }
-  if (pool && r < pool_rows) {
-    const int64_t off = r * K + col0 + ch * CH;
-    if (pool_type == kPoolF32) {
-      float *pp = reinterpret_cast<float *>(pool) + off;
+  __syncthreads();
+  if (r < nrow) {
 #pragma unroll
-      for (int c = 0; c < CH; ++c) pp[c] = of[c];
-    } else {
-      uint16_t *pp = reinterpret_cast<uint16_t *>(pool) + off;
+    for (int c = 0; c < OPT; ++c) sm[0][r * LDR + h * OPT + c] = of[c];
+  }
+  __syncthreads();
+  // coalesced stores of the new rows, then the pool columns
+  float *vbase = vn + row0 * B;
+  if constexpr (B >= 4) {
+    for (int i = tid; i < nrow * B / 4; i += 256) {
+      const float *d = &sm[0][(4 * i / B) * LDR + (4 * i) % B];
+      reinterpret_cast<float4 *>(vbase)[i] = make_float4(d[0], d[1], d[2], d[3]);
+    }
+  } else {
+    for (int i = tid; i < nrow * B; i += 256) vbase[i] = sm[0][(i / B) * LDR + i % B];
+  }
+  if (pool) {
+    // pool rows in the row-octet layout: per (octet, column) 8 consecutive
+    // values; rows at or past pool_rows are zero (row0 is a multiple of 8)
+    const int noct = (nrow + 7) / 8;
+    for (int i = tid; i < noct * B; i += 256) {
+      const int o = i / B, c = i % B;
+      const int64_t gr0 = row0 + 8 * o;
+      if (gr0 >= pool_rows) continue;
+      float v[8];
 #pragma unroll
-      for (int c = 0; c < CH; ++c) pp[c] = f2bf(of[c]);
+      for (int u = 0; u < 8; ++u)
+        v[u] = (8 * o + u < nrow && gr0 + u < pool_rows) ? sm[0][(8 * o + u) * LDR + c] : 0.0f;
+      const int64_t off = ((gr0 >> 3) * K + col0 + c) * 8;
+      if (pool_type == kPoolF32) {
+        float4 *pp = reinterpret_cast<float4 *>(reinterpret_cast<float *>(pool) + off);
+        pp[0] = make_float4(v[0], v[1], v[2], v[3]);
+        pp[1] = make_float4(v[4], v[5], v[6], v[7]);
+      } else {
+        uint32_t wv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          wv[q] = uint32_t(f2bf(v[2 * q])) | (uint32_t(f2bf(v[2 * q + 1])) << 16);
+        *reinterpret_cast<uint4 *>(reinterpret_cast<uint16_t *>(pool) + off) =
+            make_uint4(wv[0], wv[1], wv[2], wv[3]);
+      }
     }
   }
 }
@@ -297,9 +366,9 @@ hef_status apply_t(const float *v0, const float *v1, const float *y, const doubl
                    hipStream_t s) {
   if (rows == 0) return HEF_OK;
   TimedScope ts(kStLanczosApply, s);
-  constexpr int NCH = B < 4 ? 1 : B / 4;
-  k_lapply<B><<<cdiv(rows * NCH, 256), 256, 0, s>>>(v0, v1, y, T, vn, rows, pool, pool_type,
-                                               pool_rows, K, col0);
+  constexpr int RB = B <= 8 ? 256 : 128;
+  k_lapply<B><<<cdiv(rows, RB), 256, 0, s>>>(v0, v1, y, T, vn, rows, pool, pool_type, pool_rows,
+                                            K, col0);
   HEF_LAUNCH_CHECK();
   return HEF_OK;
 }

@@ -32,7 +32,7 @@ hef_status spmm_apply(const Level &L, const Structure &st, int B, const float *x
 enum PoolType { kPoolF32 = 0, kPoolBF16 = 1 };
 
 struct KrylovOut {
-  void *pool = nullptr;  // n x K row-major (fp32 or bf16)
+  void *pool = nullptr;  // oct_rows(n) x K, row-octet layout (fp32 or bf16)
   int K = 0;
   int pool_type = kPoolF32;
 };

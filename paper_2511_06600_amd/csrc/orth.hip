@@ -234,9 +234,59 @@ __device__ __forceinline__ void load8(const void *pool, int pool_type, int64_t r
   }
 }
 
+// The 8 rows rb..rb+7 (rb a multiple of 8) of column c of a pool in the
+// row-octet layout (element (r, c) at ((r >> 3) K + c) 8 + (r & 7)), as
+// floats; zeros past column K or row `rows`.
+__device__ __forceinline__ void load8oct(const void *pool, int pool_type, int64_t rb,
+                                         int64_t rows, int c, int K, float (&v)[8]) {
+  if (rb >= rows || c >= K) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = 0.0f;
+    return;
+  }
+  const int64_t off = ((rb >> 3) * K + c) * 8;
+  if (pool_type == kPoolF32) {
+    const float4 a = *reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(pool) + off);
+    const float4 b = *reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(pool) + off + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+    const uint4 a = *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint16_t *>(pool) + off);
+    const uint32_t u[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[2 * q] = __uint_as_float(u[q] << 16);
+      v[2 * q + 1] = __uint_as_float(u[q] & 0xFFFF0000u);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    if (rb + q >= rows) v[q] = 0.0f;
+}
+
+// One 32-row slab of a 128-column super block into registers: row-major
+// input (thread -> row, 8 columns) or row-octet input (thread -> octet of
+// rows, 1 column); the store puts it row-major in LDS.
+__device__ __forceinline__ void slab_load(const void *pool, int pool_type, bool oct, int64_t r,
+                                          int64_t r1, int cbase, int K, int tid, float (&v)[8]) {
+  if (oct) load8oct(pool, pool_type, r + 8 * (tid >> 7), r1, cbase + (tid & 127), K, v);
+  else load8(pool, pool_type, r + (tid >> 4), r1, cbase + (tid & 15) * 8, K, v);
+}
+
+__device__ __forceinline__ void slab_store(float *S, bool oct, int tid, const float (&v)[8]) {
+  if (oct) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) S[(8 * (tid >> 7) + u) * kSB + (tid & 127)] = v[u];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) S[(tid >> 4) * kSB + (tid & 15) * 8 + q] = v[q];
+  }
+}
+
 __global__ void __launch_bounds__(kGT)
-k_jgram(const void *__restrict__ pool, const void *__restrict__ poolB, int pool_type, int64_t n,
-        int K, int nsb, int npairs, int64_t rows_per_chunk, double *__restrict__ partial) {
+k_jgram(const void *__restrict__ pool, const void *__restrict__ poolB, int pool_type, int oct,
+        int64_t n, int K, int nsb, int npairs, int64_t rows_per_chunk,
+        double *__restrict__ partial) {
   __shared__ float As[2][kSlab * kSB];
   __shared__ float Bs[2][kSlab * kSB];
   const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
@@ -257,27 +307,23 @@ k_jgram(const void *__restrict__ pool, const void *__restrict__ poolB, int pool_
   const bool on1 = !diag || tj0 + 1 >= ti;
   const int64_t r0 = chunk * rows_per_chunk;
   const int64_t r1 = r0 + rows_per_chunk < n ? r0 + rows_per_chunk : n;
-  // loader: 32 rows x 128 cols = 512 groups of 8; thread -> (row, 8 cols)
-  const int lrow = tid >> 4, lcol = (tid & 15) * 8;
+  // loader: 32 rows x 128 cols = 512 groups of 8 values per thread
   floatx16 acc0, acc1;
   double d0[16], d1[16];
 #pragma unroll
   for (int v = 0; v < 16; ++v) { acc0[v] = 0.0f; acc1[v] = 0.0f; d0[v] = 0.0; d1[v] = 0.0; }
   float ra[8], rb[8];
-  load8(pool, pool_type, r0 + lrow, r1, ab.x * kSB + lcol, K, ra);
-  if (!diag) load8(srcB, pool_type, r0 + lrow, r1, ab.y * kSB + lcol, K, rb);
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    As[0][lrow * kSB + lcol + q] = ra[q];
-    if (!diag) Bs[0][lrow * kSB + lcol + q] = rb[q];
-  }
+  slab_load(pool, pool_type, oct, r0, r1, ab.x * kSB, K, tid, ra);
+  if (!diag) slab_load(srcB, pool_type, oct, r0, r1, ab.y * kSB, K, tid, rb);
+  slab_store(As[0], oct, tid, ra);
+  if (!diag) slab_store(Bs[0], oct, tid, rb);
   __syncthreads();
   int buf = 0, slabs = 0;
   for (int64_t r = r0; r < r1; r += kSlab) {
     const bool more = r + kSlab < r1;
     if (more) {
-      load8(pool, pool_type, r + kSlab + lrow, r1, ab.x * kSB + lcol, K, ra);
-      if (!diag) load8(srcB, pool_type, r + kSlab + lrow, r1, ab.y * kSB + lcol, K, rb);
+      slab_load(pool, pool_type, oct, r + kSlab, r1, ab.x * kSB, K, tid, ra);
+      if (!diag) slab_load(srcB, pool_type, oct, r + kSlab, r1, ab.y * kSB, K, tid, rb);
     }
     const float *A = As[buf];
     const float *Bm = diag ? As[buf] : Bs[buf];
@@ -303,11 +349,8 @@ k_jgram(const void *__restrict__ pool, const void *__restrict__ poolB, int pool_
       }
     }
     if (more) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        As[buf ^ 1][lrow * kSB + lcol + q] = ra[q];
-        if (!diag) Bs[buf ^ 1][lrow * kSB + lcol + q] = rb[q];
-      }
+      slab_store(As[buf ^ 1], oct, tid, ra);
+      if (!diag) slab_store(Bs[buf ^ 1], oct, tid, rb);
     }
     __syncthreads();
     buf ^= 1;
@@ -352,8 +395,8 @@ constexpr int kALDA = kAK + 1;   // A chunk [128][33]
 constexpr int kALDB = kAN + 1;   // B chunk [32][129]
 
 __global__ void __launch_bounds__(kAT)
-k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int64_t n, int K,
-         int Kp, const float *__restrict__ Rinv32, int ncb, int full, int accumulate) {
+k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oct, int64_t n,
+         int K, int Kp, const float *__restrict__ Rinv32, int ncb, int full, int accumulate) {
   __shared__ float As[kAM * kALDA];
   __shared__ float Bs[kAK * kALDB];
   const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
@@ -376,13 +419,20 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int64_
   const int kend = (!full && col0 + kAN < K) ? col0 + kAN : K;
   for (int k0 = 0; k0 < kend; k0 += kAK) {
     __syncthreads();
-    // A chunk: rows row0..+127, cols k0..k0+31 of V (8 floats per thread... 2 x 8)
+    // A chunk: rows row0..+127, cols k0..k0+31 of V (512 groups of 8 values)
     for (int g = tid; g < kAM * (kAK / 8); g += kAT) {
-      const int r = g / (kAK / 8), c8 = (g % (kAK / 8)) * 8;
       float v[8];
-      load8(V, pool_type, row0 + r, n, k0 + c8, K, v);
+      if (oct) {
+        const int o = g / kAK, c = g % kAK;
+        load8oct(V, pool_type, row0 + 8 * o, n, k0 + c, K, v);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) As[r * kALDA + c8 + q] = (k0 + c8 + q < kend) ? v[q] : 0.0f;
+        for (int q = 0; q < 8; ++q) As[(8 * o + q) * kALDA + c] = (k0 + c < kend) ? v[q] : 0.0f;
+      } else {
+        const int r = g / (kAK / 8), c8 = (g % (kAK / 8)) * 8;
+        load8(V, pool_type, row0 + r, n, k0 + c8, K, v);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) As[r * kALDA + c8 + q] = (k0 + c8 + q < kend) ? v[q] : 0.0f;
+      }
     }
     // B chunk: rows k0..k0+31, cols col0..col0+127 of Rinv32 (row stride Kp)
     for (int g = tid; g < kAK * (kAN / 4); g += kAT) {
@@ -428,6 +478,278 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int64_
       }
 }
 
+// ---------------------------------------------------------------- bf16 pool
+// With the pool stored as bfloat16 its values are exact bf16 numbers, so the
+// Gram runs on bf16 matrix cores (v_mfma_f32_32x32x16_bf16: exact products,
+// float32 sums) with the same float64 flush every 128 rows, and the apply
+// multiplies by R^-1 split into bf16 high and low parts (two products,
+// relative error about 2^-17 before the bf16 rounding of Q).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kBSlab = 64;           // rows per LDS slab
+constexpr int kBLd = kBSlab + 8;     // LDS column stride (bf16 elements)
+
+// 8 consecutive bf16 of row `row` from column c (zeros past the matrix)
+__device__ __forceinline__ uint4 load8_bf16(const uint16_t *pool, int64_t row, int64_t rows,
+                                            int c, int K) {
+  if (row >= rows || c >= K) return make_uint4(0u, 0u, 0u, 0u);
+  const uint16_t *p = pool + row * K + c;
+  if ((K & 7) == 0 && c + 8 <= K) return *reinterpret_cast<const uint4 *>(p);
+  uint32_t w[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t lo = (c + 2 * q < K) ? p[2 * q] : 0u;
+    const uint32_t hi = (c + 2 * q + 1 < K) ? p[2 * q + 1] : 0u;
+    w[q] = lo | (hi << 16);
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__device__ __forceinline__ void store_t8(uint16_t *T, int c8, int row, uint4 v) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    T[(c8 + 2 * q) * kBLd + row] = uint16_t(w[q] & 0xFFFFu);
+    T[(c8 + 2 * q + 1) * kBLd + row] = uint16_t(w[q] >> 16);
+  }
+}
+
+// G partials of V^T V for a bf16 pool; block / wave / output layout as k_jgram.
+// Slabs of 64 rows are stored transposed in LDS ([column][row]) so that the
+// 8 consecutive rows an MFMA lane needs are one 16-byte read.
+__global__ void __launch_bounds__(kGT)
+k_jgram_bf16(const uint16_t *__restrict__ pool, int oct, int64_t n, int K, int nsb, int npairs,
+             int64_t rows_per_chunk, double *__restrict__ partial) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[kSB * kBLd];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[kSB * kBLd];
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int pair = int(lb % npairs);
+  const int64_t chunk = lb / npairs;
+  const int2 ab = pair_of(pair, nsb);
+  const bool diag = ab.x == ab.y;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int ti = w >> 1;
+  const int tj0 = 2 * (w & 1);
+  const bool on0 = !diag || tj0 >= ti;
+  const bool on1 = !diag || tj0 + 1 >= ti;
+  const int64_t r0 = chunk * rows_per_chunk;
+  const int64_t r1 = r0 + rows_per_chunk < n ? r0 + rows_per_chunk : n;
+  floatx16 acc0, acc1;
+  double d0[16], d1[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) { acc0[v] = 0.0f; acc1[v] = 0.0f; d0[v] = 0.0; d1[v] = 0.0; }
+  const uint16_t *Bm = diag ? As : Bs;
+  int slabs = 0;
+  if (oct) {
+    // row-octet layout: the 8 rows of a column an MFMA lane needs are one
+    // 16-byte load; 4 k-steps (64 rows) are loaded before they are used
+    const int ca = ab.x * kSB + 32 * ti + (lane & 31);
+    const int cb0 = ab.y * kSB + 32 * tj0 + (lane & 31);
+    const int cb1 = cb0 + 32;
+    auto ld = [&](int64_t rb, int c) -> bf16x8 {
+      uint4 u = make_uint4(0u, 0u, 0u, 0u);
+      if (rb < r1 && c < K) u = *reinterpret_cast<const uint4 *>(pool + ((rb >> 3) * K + c) * 8);
+      return *reinterpret_cast<const bf16x8 *>(&u);
+    };
+    for (int64_t r = r0; r < r1; r += 64) {
+      bf16x8 av[4], bv0[4], bv1[4];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int64_t rb = r + 16 * st + 8 * (lane >> 5);
+        av[st] = ld(rb, ca);
+        bv0[st] = on0 ? ld(rb, cb0) : av[st];
+        bv1[st] = on1 ? ld(rb, cb1) : av[st];
+      }
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        if (on0) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[st], bv0[st], acc0, 0, 0, 0);
+        if (on1) acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[st], bv1[st], acc1, 0, 0, 0);
+      }
+      if (++slabs == 2) {  // float32 sums over 128 rows, then float64
+        slabs = 0;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          d0[v] += double(acc0[v]); acc0[v] = 0.0f;
+          d1[v] += double(acc1[v]); acc1[v] = 0.0f;
+        }
+      }
+    }
+  }
+  for (int64_t r = r0; r < (oct ? r0 : r1); r += kBSlab) {
+    uint4 ra[2], rb[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int g = tid + kGT * h;  // 64 rows x 16 groups of 8 columns
+      const int row = g >> 4, c8 = (g & 15) * 8;
+      ra[h] = load8_bf16(pool, r + row, r1, ab.x * kSB + c8, K);
+      if (!diag) rb[h] = load8_bf16(pool, r + row, r1, ab.y * kSB + c8, K);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int g = tid + kGT * h;
+      const int row = g >> 4, c8 = (g & 15) * 8;
+      store_t8(As, c8, row, ra[h]);
+      if (!diag) store_t8(Bs, c8, row, rb[h]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < kBSlab / 16; ++st) {
+      const int kk = 16 * st + 8 * (lane >> 5);
+      const bf16x8 a_op = *reinterpret_cast<const bf16x8 *>(As + (32 * ti + (lane & 31)) * kBLd + kk);
+      if (on0) {
+        const bf16x8 b0 = *reinterpret_cast<const bf16x8 *>(Bm + (32 * tj0 + (lane & 31)) * kBLd + kk);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_op, b0, acc0, 0, 0, 0);
+      }
+      if (on1) {
+        const bf16x8 b1 = *reinterpret_cast<const bf16x8 *>(Bm + (32 * (tj0 + 1) + (lane & 31)) * kBLd + kk);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_op, b1, acc1, 0, 0, 0);
+      }
+    }
+    if (++slabs == 2) {  // float32 sums over 128 rows, then float64
+      slabs = 0;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        d0[v] += double(acc0[v]); acc0[v] = 0.0f;
+        d1[v] += double(acc1[v]); acc1[v] = 0.0f;
+      }
+    }
+  }
+  double *out = partial + (chunk * npairs + pair) * (16 * 1024);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    const int j = lane & 31;
+    out[(ti * 4 + tj0) * 1024 + i * 32 + j] = on0 ? d0[v] + double(acc0[v]) : 0.0;
+    out[(ti * 4 + tj0 + 1) * 1024 + i * 32 + j] = on1 ? d1[v] + double(acc1[v]) : 0.0;
+  }
+}
+
+// RhT[j][k] = bf16(R^-1[k][j]), RlT[j][k] = bf16(R^-1[k][j] - RhT[j][k])
+// (transposed, row stride Kp; zero outside K x K)
+__global__ void k_split_rinv(const double *__restrict__ Rinv, int K, int Kp,
+                             uint16_t *__restrict__ RhT, uint16_t *__restrict__ RlT) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(Kp) * Kp) return;
+  const int j = int(idx / Kp), k = int(idx % Kp);
+  uint16_t h = 0, l = 0;
+  if (j < K && k < K) {
+    const float r = float(Rinv[int64_t(k) * Kp + j]);
+    h = f2bf(r);
+    l = f2bf(r - __uint_as_float(uint32_t(h) << 16));
+  }
+  RhT[idx] = h;
+  RlT[idx] = l;
+}
+
+// Q (bf16) = V (bf16) (Rh + Rl): 128 x 128 output tiles, 4 waves of 64 x 64,
+// k chunks of 32 (two bf16 MFMA steps) staged in LDS; the k loop stops at the
+// tile's last column (R^-1 is upper triangular).
+constexpr int kALd = 32 + 8;  // LDS row stride of the bf16 apply chunks
+__global__ void __launch_bounds__(kAT)
+k_japply_bf16(const uint16_t *__restrict__ V, uint16_t *__restrict__ Q, int oct, int64_t n, int K,
+              int Kp, const uint16_t *__restrict__ RhT, const uint16_t *__restrict__ RlT,
+              int ncb) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[kAM * kALd];
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[kAN * kALd];
+  __shared__ __attribute__((aligned(16))) uint16_t Bl[kAN * kALd];
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int cb = int(lb % ncb);
+  const int64_t rt = lb / ncb;
+  const int64_t row0 = rt * kAM;
+  const int col0 = cb * kAN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
+  const int kend = (col0 + kAN < K) ? col0 + kAN : K;
+  for (int k0 = 0; k0 < kend; k0 += 32) {
+    __syncthreads();
+    // A chunk: 128 rows x 32 columns of V = 512 groups of 8 (2 per thread)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int g = tid + kAT * h;
+      if (oct) {
+        // 8 rows of one column, transposed into the row-major chunk
+        const int o = g >> 5, c = g & 31;
+        uint4 u = make_uint4(0u, 0u, 0u, 0u);
+        const int64_t rb = row0 + 8 * o;
+        if (rb < n && k0 + c < kend)
+          u = *reinterpret_cast<const uint4 *>(V + ((rb >> 3) * K + k0 + c) * 8);
+        const uint32_t wv[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          As[(8 * o + 2 * q) * kALd + c] = uint16_t(wv[q] & 0xFFFFu);
+          As[(8 * o + 2 * q + 1) * kALd + c] = uint16_t(wv[q] >> 16);
+        }
+      } else {
+        const int r = g >> 2, k8 = (g & 3) * 8;
+        uint4 v = load8_bf16(V, row0 + r, n, k0 + k8, K);
+        if (k0 + k8 + 8 > kend) {  // columns past kend are zero in R^-1 anyway
+          uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (k0 + k8 + q >= kend) wv[q >> 1] &= (q & 1) ? 0x0000FFFFu : 0xFFFF0000u;
+          v = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+        }
+        *reinterpret_cast<uint4 *>(As + r * kALd + k8) = v;
+      }
+    }
+    // B chunks: columns col0..col0+127 (rows of the transposed split), k0..k0+31
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int g = tid + kAT * h;
+      const int j = g >> 2, k8 = (g & 3) * 8;
+      uint4 vh = make_uint4(0u, 0u, 0u, 0u), vl = vh;
+      if (col0 + j < Kp && k0 + k8 < Kp) {
+        vh = *reinterpret_cast<const uint4 *>(RhT + int64_t(col0 + j) * Kp + k0 + k8);
+        vl = *reinterpret_cast<const uint4 *>(RlT + int64_t(col0 + j) * Kp + k0 + k8);
+      }
+      *reinterpret_cast<uint4 *>(Bh + j * kALd + k8) = vh;
+      *reinterpret_cast<uint4 *>(Bl + j * kALd + k8) = vl;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      const int kk = 16 * st + 8 * (lane >> 5);
+      bf16x8 a_op[2], bh[2], bl[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+        a_op[a] = *reinterpret_cast<const bf16x8 *>(As + (wr + 32 * a + (lane & 31)) * kALd + kk);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        bh[b] = *reinterpret_cast<const bf16x8 *>(Bh + (wc + 32 * b + (lane & 31)) * kALd + kk);
+        bl[b] = *reinterpret_cast<const bf16x8 *>(Bl + (wc + 32 * b + (lane & 31)) * kALd + kk);
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_op[a], bh[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_op[a], bl[b], acc[a][b], 0, 0, 0);
+        }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = row0 + wr + 32 * a + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int col = col0 + wc + 32 * b + (lane & 31);
+        if (row < n && col < K) Q[row * K + col] = f2bf(acc[a][b][v]);
+      }
+}
+
 struct GramPlan {
   int nsb = 0, npairs = 0, nchunks = 0;
   int64_t rows_per_chunk = 0;
@@ -439,14 +761,14 @@ GramPlan gram_plan(int64_t n, int K, bool cross = false) {
   p.npairs = cross ? p.nsb * p.nsb : p.nsb * (p.nsb + 1) / 2;
   int64_t want = std::max<int64_t>(1, 512 / p.npairs);
   int64_t per = cdiv(std::max<int64_t>(n, 1), want);
-  per = std::max<int64_t>(kSlab, cdiv(per, kSlab) * kSlab);
+  per = std::max<int64_t>(128, cdiv(per, 128) * 128);  // whole slabs of both kernels
   p.rows_per_chunk = per;
   p.nchunks = int(std::max<int64_t>(1, cdiv(n, per)));
   return p;
 }
 
 hef_status gram_run(const void *pool, const void *poolB, int pool_type, int64_t n, int K,
-                    double *G, Arena &ws, hipStream_t s) {
+                    double *G, Arena &ws, hipStream_t s, bool oct = false) {
   const GramPlan p = gram_plan(n, K, poolB != nullptr);
   const size_t mk = ws.mark();
   double *partial = ws.take<double>(size_t(p.nchunks) * p.npairs * 16 * 1024);
@@ -455,8 +777,13 @@ hef_status gram_run(const void *pool, const void *poolB, int pool_type, int64_t 
   if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
   HEF_HIP(hipMemsetAsync(G, 0, sizeof(double) * K * K, s));
   TimedScope ts(kStOrthGram, s);
-  k_jgram<<<int64_t(p.npairs) * p.nchunks, kGT, 0, s>>>(pool, poolB, pool_type, n, K, p.nsb,
-                                                        p.npairs, p.rows_per_chunk, partial);
+  if (pool_type == kPoolBF16 && !poolB)
+    k_jgram_bf16<<<int64_t(p.npairs) * p.nchunks, kGT, 0, s>>>(
+        reinterpret_cast<const uint16_t *>(pool), oct, n, K, p.nsb, p.npairs, p.rows_per_chunk,
+        partial);
+  else
+    k_jgram<<<int64_t(p.npairs) * p.nchunks, kGT, 0, s>>>(pool, poolB, pool_type, oct, n, K, p.nsb,
+                                                          p.npairs, p.rows_per_chunk, partial);
   HEF_LAUNCH_CHECK();
   HEF_TRY(reduce_cols_f64(partial, p.nchunks, tot, sums, s));
   k_jgram_scatter<<<cdiv(tot, 256), 256, 0, s>>>(sums, p.nsb, p.npairs, K, poolB != nullptr, G);
@@ -467,11 +794,11 @@ hef_status gram_run(const void *pool, const void *poolB, int pool_type, int64_t 
 
 hef_status apply_run(const void *V, void *Q, int pool_type, int64_t n, int K, int Kp,
                      const float *Rinv32, hipStream_t s, bool full = false,
-                     bool accumulate = false) {
+                     bool accumulate = false, bool oct = false) {
   if (n == 0) return HEF_OK;
   TimedScope ts(kStOrthApply, s);
   const int ncb = (K + kAN - 1) / kAN;
-  k_japply<<<cdiv(n, kAM) * ncb, kAT, 0, s>>>(V, Q, pool_type, n, K, Kp, Rinv32, ncb, full,
+  k_japply<<<cdiv(n, kAM) * ncb, kAT, 0, s>>>(V, Q, pool_type, oct, n, K, Kp, Rinv32, ncb, full,
                                               accumulate);
   HEF_LAUNCH_CHECK();
   return HEF_OK;
@@ -487,6 +814,8 @@ size_t orth_ws_bytes(int64_t n, int K) {
   a.take<double>(int64_t(K) * K);    // LT
   a.take<double>(int64_t(Kp) * Kp);  // Rinv
   a.take<float>(int64_t(Kp) * Kp);   // Rinv32
+  a.take<uint16_t>(int64_t(Kp) * Kp);  // RhT
+  a.take<uint16_t>(int64_t(Kp) * Kp);  // RlT
   a.take<int32_t>(K);                // keep
   a.take<double>(size_t(p.nchunks) * p.npairs * 16 * 1024);
   a.take<double>(size_t(p.npairs) * 16 * 1024);
@@ -518,10 +847,9 @@ hef_status gemm_f32(const float *X, int64_t n, int K, const float *W, int Kp, fl
   return apply_run(X, out, kPoolF32, n, K, Kp, W, s, true, accumulate);
 }
 
-hef_status orthonormalize_pool(void *pool, void *pool2, int pool_type, int64_t n, int K,
-                               double tau, int passes, int32_t *keep_out, void **result,
-                               Arena &ws, hipStream_t s, double *rinv_out) {
-  *result = pool;
+hef_status orthonormalize_pool(void *P, void *out, int pool_type, int64_t n, int K, double tau,
+                               int passes, int32_t *keep_out, Arena &ws, hipStream_t s,
+                               double *rinv_out) {
   if (K <= 0) return HEF_OK;
   if (K > 512) {
     set_error("pool width %d exceeds 512", K);
@@ -533,11 +861,17 @@ hef_status orthonormalize_pool(void *pool, void *pool2, int pool_type, int64_t n
   double *LT = ws.take<double>(int64_t(K) * K);
   double *Rinv = ws.take<double>(int64_t(Kp) * Kp);
   float *Rinv32 = ws.take<float>(int64_t(Kp) * Kp);
+  uint16_t *RhT = ws.take<uint16_t>(int64_t(Kp) * Kp);
+  uint16_t *RlT = ws.take<uint16_t>(int64_t(Kp) * Kp);
   int32_t *keep = ws.take<int32_t>(K);
   if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
-  void *src = pool, *dst = pool2;
   for (int pass = 0; pass < passes; ++pass) {
-    HEF_TRY(gram_run(src, nullptr, pool_type, n, K, G, ws, s));
+    // pass 0: P (row-octet layout) -> out; pass 1: out -> P (reused,
+    // row-major), copied back to out
+    const bool oct = pass == 0;
+    const void *src = pass == 0 ? P : out;
+    void *dst = pass == 0 ? out : P;
+    HEF_TRY(gram_run(src, nullptr, pool_type, n, K, G, ws, s, oct));
     {
       TimedScope ts(kStOrthChol, s);
       const size_t lds_c = size_t(K) * kPS * sizeof(double);
@@ -551,10 +885,22 @@ hef_status orthonormalize_pool(void *pool, void *pool2, int pool_type, int64_t n
       k_jtrinv<<<(K + kPW - 1) / kPW, 1024, lds_c, s>>>(LT, keep, K, Kp, Rinv, Rinv32);
       HEF_LAUNCH_CHECK();
     }
-    HEF_TRY(apply_run(src, dst, pool_type, n, K, Kp, Rinv32, s));
-    std::swap(src, dst);
+    if (pool_type == kPoolBF16) {
+      TimedScope ts(kStOrthApply, s);
+      k_split_rinv<<<cdiv(int64_t(Kp) * Kp, 256), 256, 0, s>>>(Rinv, K, Kp, RhT, RlT);
+      const int ncb = (K + kAN - 1) / kAN;
+      if (n > 0)
+        k_japply_bf16<<<cdiv(n, kAM) * ncb, kAT, 0, s>>>(
+            reinterpret_cast<const uint16_t *>(src), reinterpret_cast<uint16_t *>(dst), oct, n, K,
+            Kp, RhT, RlT, ncb);
+      HEF_LAUNCH_CHECK();
+    } else {
+      HEF_TRY(apply_run(src, dst, pool_type, n, K, Kp, Rinv32, s, false, false, oct));
+    }
+    if (pass == 1)
+      HEF_HIP(hipMemcpyAsync(out, P, size_t(n) * K * (pool_type == kPoolBF16 ? 2 : 4),
+                             hipMemcpyDeviceToDevice, s));
   }
-  *result = src;
   if (keep_out) HEF_HIP(hipMemcpyAsync(keep_out, keep, K * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   if (rinv_out)
     HEF_HIP(hipMemcpyAsync(rinv_out, Rinv, sizeof(double) * Kp * Kp, hipMemcpyDeviceToDevice, s));

@@ -7,20 +7,19 @@ namespace hef {
 
 size_t orth_ws_bytes(int64_t n, int K);
 
-// Orthonormalises the n x K row-major pool (Alg. 1 step 4, the joint
-// Gram-Schmidt of [star | clique]): G = V^T V (FP32 matrix-core tiles,
-// float64 across row chunks), Cholesky G = R^T R in float64 with the drop
-// rule (column j dropped when its Schur pivot <= tau^2 G_jj), Q = V R^-1
-// written to the other buffer.  `passes` = 1 or 2 repeats the factorisation
-// (the second pass keeps the first pass's drops), alternating between
-// `pool` and `pool2`; *result is the buffer holding Q (pool2 after one
-// pass, pool after two).  `keep_out` (device int32 [K], may be null)
+// Orthonormalises the Krylov pool (Alg. 1 step 4, the joint Gram-Schmidt
+// of [star | clique]): G = V^T V (matrix-core tiles, float64 across row
+// chunks), Cholesky G = R^T R in float64 with the drop rule (column j
+// dropped when its Schur pivot <= tau^2 G_jj), Q = V R^-1.  `P` holds V in
+// the row-octet layout (oct_rows(n) x K); Q goes to `out` (n x K row-major).
+// `passes` = 2 repeats the factorisation on Q (keeping the first pass's
+// drops), using P as scratch.  `keep_out` (device int32 [K], may be null)
 // receives 1 for kept and 0 for dropped columns; `rinv_out` (device float64
-// [Kp x Kp], Kp = K rounded up to 32, may be null) receives the last pass's
-// R^-1 (row-major, upper triangular, zero rows and columns for drops).
-hef_status orthonormalize_pool(void *pool, void *pool2, int pool_type, int64_t n, int K,
-                               double tau, int passes, int32_t *keep_out, void **result,
-                               Arena &ws, hipStream_t s, double *rinv_out = nullptr);
+// [Kp x Kp], Kp = K rounded up to 32, may be null) the last pass's R^-1
+// (row-major, upper triangular, zero rows and columns for drops).
+hef_status orthonormalize_pool(void *P, void *out, int pool_type, int64_t n, int K, double tau,
+                               int passes, int32_t *keep_out, Arena &ws, hipStream_t s,
+                               double *rinv_out = nullptr);
 
 // Test hook: G = X^T X (float64, K x K) of a row-major n x K float32 matrix,
 // through the same matrix-core Gram kernels.
