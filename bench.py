@@ -9,9 +9,15 @@ width K = 480, 3 coarsening levels, local clustering on): per level, the
 implicit star+clique block Krylov recurrence, the joint orthonormalisation,
 the resistance ratios, the Eq. (15) update, threshold contraction, local
 clustering and coarse rebuild (hef_coarsen).  Inputs are resident in HBM
-before timing starts.  The metric is ER estimates per second: hyperedge
+before timing starts.  `value` is ER estimates per second: hyperedge
 resistances estimated over all levels of a step, divided by the step time.
 Rank 0 prints one JSON line.
+
+Rooflines use the library's per-kernel HIP-event timings (recorded on the
+launch stream) over the timed region and the algorithmic bytes / flops of
+each kernel at the levels' sizes (the formulas below).  `traffic` comes from
+the committed rocprofv3 PMC summary (FETCH_SIZE / WRITE_SIZE of the same
+workload, scaled by the reading of a copy of known size).
 """
 from __future__ import annotations
 
@@ -26,36 +32,73 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E, GB/s
 PEAK_FP32_MFMA = 157.3    # TFLOP/s, dense FP32 matrix
+PEAK_BF16_MFMA = 2500.0   # TFLOP/s, dense BF16 matrix
+METRIC = "ER estimates/s & Krylov SpMV GB/s at 2M nodes; FP32 vs BF16 basis; fwd+bwd"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_large2m.txt")
 
 
-def spmm_bytes(n, m, nnz, b, s=4):
-    """Algorithmic bytes of one CSR pass and one CSC pass of a fused Krylov
-    step (both expansions, b columns).  CSR: eptr, pins, the node scales,
-    alpha and beta, the node rows of both input vectors once, the hyperedge
-    rows of both outputs.  CSC: vptr, eids, alpha, the hyperedge rows of
-    both inputs once, the own clique row, s and gamma, the node rows of both
-    outputs."""
-    csr = 4 * (m + 1) + 4 * nnz + 4 * n + 8 * m + 2 * n * b * s + 2 * m * b * s
-    csc = 4 * (n + 1) + 4 * nnz + 4 * m + 2 * m * b * s + n * b * s + 8 * n + 2 * n * b * s
-    return csr, csc
+# ---------------------------------------------------------------- work models
+def spmm_step_bytes(n, m, nnz, b, s=4):
+    """Algorithmic HBM bytes of one fused Krylov step (both expansions, b
+    columns): pins and hyperedge ids once per pass (8 nnz), both pointer
+    arrays, per-hyperedge factors alpha and beta, the two node scales, and
+    each vector row read or written once: the CSR pass reads x_V, x_c and
+    writes y_E and the clique sums; the CSC pass reads x_E and the sums plus
+    the own x_c and writes y_V, y_c: s b (5n + 4m)."""
+    return 8 * nnz + 4 * (n + m + 2) + 8 * m + 8 * n + s * b * (5 * n + 4 * m)
+
+
+def lanczos_bytes(n, m, b, k, s=4):
+    """(Gram, apply) bytes of one level: the Gram reads [V_{j-2}|V_{j-1}|Y]
+    (1, 2 then 3 blocks over steps 0..k) of both expansions; the apply reads
+    the same and writes V_j, and steps 1..k also write b pool columns of n
+    rows per expansion."""
+    rows = (n + m) + n
+    blocks = 1 + 2 + 3 * (k - 1)
+    gram = s * b * rows * blocks
+    apply = gram + s * b * rows * (k + 1) + s * b * n * 2 * k
+    return gram, apply
 
 
 def gram_flops(n, K):
-    """FP32 matrix-core flops of one joint Gram (upper 128x128 super tiles,
-    diagonal super tiles computed on and above their 32x32 diagonal)."""
+    """Matrix-core flops of one joint Gram (upper 128x128 super tiles; the
+    diagonal ones computed on and above their 32x32 diagonal)."""
     nsb = (K + 127) // 128
-    tiles = 0
-    for a in range(nsb):
-        for b in range(a, nsb):
-            tiles += 10 if a == b else 16
+    tiles = sum(10 if a == b else 16 for a in range(nsb) for b in range(a, nsb))
     return 2.0 * n * 32 * 32 * tiles
 
 
-def cpu_baseline(cfg_name, seconds_hint):
+def apply_flops(n, K):
+    """Useful flops of Q = V R^-1 with R^-1 upper triangular: column j takes
+    j + 1 products per row."""
+    return float(n) * K * (K + 1)
+
+
+def score_bytes(n, m, nnz, K, s=4):
+    """One scoring pass: the pool once, the pins, the pointers and one
+    per-hyperedge value (w read or R written)."""
+    return n * K * s + 4 * nnz + 4 * (m + 1) + 4 * m
+
+
+def read_traffic():
+    """{kernel: (fetch bytes, write bytes) per coarsen step} from the PMC
+    summary, or {} if it is absent."""
+    out = {}
+    if not os.path.exists(TRAFFIC_FILE):
+        return out
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("#") or not line.strip():
+            continue
+        parts = line.split()
+        if len(parts) >= 3:
+            out[parts[0]] = (float(parts[1]), float(parts[2]))
+    return out
+
+
+def cpu_baseline(cfg_name):
     """The FP64 oracle (as it stands) on a bounded sample of the workload:
     the same recipe (size law, locality, weights, k, b, levels) at 1% of
     the node and hyperedge counts."""
-    import numpy as np
     from oracle import coarsen as oco
     from synth import generate, get_config, start_block
     cfg = get_config(cfg_name)
@@ -79,6 +122,16 @@ def cpu_baseline(cfg_name, seconds_hint):
                       f"in {dt:.1f} s"}
 
 
+def roofline_entry(bound, amount, ms_total, launches, peak, unit, kernels, traffic=None):
+    if bound == "hbm":
+        ach = amount / (ms_total / 1e3) / 1e9
+    else:
+        ach = amount / (ms_total / 1e3) / 1e12
+    return {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+            "avg_launch_us": ms_total / max(launches, 1) * 1e3, "launches": launches,
+            "kernels": kernels, "traffic": traffic}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,7 +140,9 @@ def main():
     ap.add_argument("--config", default="large2m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the Alg. 1-only and BF16 side measurements")
+                    help="skip the Alg. 1-only, BF16 and adjoint side measurements")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="copy 1 GiB once before timing (the reference kernel of PMC runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -108,6 +163,12 @@ def main():
                         assume_valid=True)
     print(f"# {args.config}: n={h.n} m={h.m} nnz={h.nnz} K={params.K} levels={params.levels}",
           file=sys.stderr, flush=True)
+    if args.calibration_copy:
+        x = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
 
     for _ in range(args.warmup):
         hef.coarsen(dh, params)
@@ -128,49 +189,63 @@ def main():
     value = est_per_step / (ms_step / 1e3)
     print(f"# step {ms_step:.2f} ms, levels {levels}", file=sys.stderr, flush=True)
 
-    # ---- rooflines from the HIP-event stage timings of the timed region
+    # ---- rooflines over the timed region
     per = {k: v for k, v in stages.items() if v[1]}
-    stage_ms = {k: round(v[0] / args.steps, 3) for k, v in sorted(per.items(), key=lambda kv: -kv[1][0])}
-    k_steps = params.k
-    csr_tot = csc_tot = 0
-    for (n_l, m_l, z_l) in levels:
-        a, b_ = spmm_bytes(n_l, m_l, z_l, params.b)
-        csr_tot += a * k_steps
-        csc_tot += b_ * k_steps
-    csr_tot *= args.steps
-    csc_tot *= args.steps
-    rooflines = {}
-    if "spmm_csr" in per:
-        ms, cnt = per["spmm_csr"]
-        ach = csr_tot / (ms / 1e3) / 1e9
-        rooflines["k_csr_small"] = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS,
-                                    "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
-                                    "avg_launch_us": ms / cnt * 1e3, "launches": cnt}
-    if "spmm_csc" in per:
-        ms, cnt = per["spmm_csc"]
-        ach = csc_tot / (ms / 1e3) / 1e9
-        rooflines["k_csc_small"] = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS,
-                                    "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
-                                    "avg_launch_us": ms / cnt * 1e3, "launches": cnt}
-    if "orth_gram" in per:
-        ms, cnt = per["orth_gram"]
-        fl = sum(gram_flops(n_l, params.K) for (n_l, _, _) in levels) * args.steps
-        ach = fl / (ms / 1e3) / 1e12
-        rooflines["k_jgram"] = {"bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA,
-                                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA,
-                                "avg_launch_us": ms / cnt * 1e3, "launches": cnt}
-    # the dominant kernel among those with a defined roofline
-    kernel_stage = {"k_csr_small": "spmm_csr", "k_csc_small": "spmm_csc", "k_jgram": "orth_gram"}
-    dom = max(rooflines, key=lambda k: per[kernel_stage[k]][0]) if rooflines else None
-    roof = None
-    if dom:
-        r = rooflines[dom]
-        roof = {"bound": r["bound"], "achieved": r["achieved"], "peak": r["peak"],
-                "unit": r["unit"], "frac": r["frac"], "traffic": None, "kernel": dom,
-                "avg_launch_us": r["avg_launch_us"]}
+    stage_ms = {k: round(v[0] / args.steps, 3)
+                for k, v in sorted(per.items(), key=lambda kv: -kv[1][0])}
+    S, B, k, K = args.steps, params.b, params.k, params.K
+    spmm_b = sum(spmm_step_bytes(n, m, z, B) for (n, m, z) in levels) * k * S
+    lg_b = sum(lanczos_bytes(n, m, B, k)[0] for (n, m, _) in levels) * S
+    la_b = sum(lanczos_bytes(n, m, B, k)[1] for (n, m, _) in levels) * S
+    jg_f = sum(gram_flops(n, K) for (n, _, _) in levels) * S
+    ja_f = sum(apply_flops(n, K) for (n, _, _) in levels) * S
+    sc_b = sum(score_bytes(n, m, z, K) for (n, m, z) in levels) * S
+    traffic = read_traffic()
+    nfused = k * len(levels)  # fused SpMM launches per step
+
+    def ms_of(*names):
+        return sum(per[x][0] for x in names if x in per)
+
+    def traffic_of(kernels, launches):
+        if not traffic or not all(kk in traffic for kk in kernels):
+            return None
+        tot = sum(traffic[kk][0] + traffic[kk][1] for kk in kernels)
+        return tot / launches
+
+    spmm_stages = ("spmm_prep", "spmm_csr", "spmm_csr_big", "spmm_csc", "spmm_csc_big")
+    rooflines = {
+        "a2_spmm": roofline_entry(
+            "hbm", spmm_b, ms_of(*spmm_stages), nfused * S, PEAK_HBM_GBS, "GB/s",
+            ["k_prep", "k_csr_small", "k_csr_big", "k_csc_small", "k_csc_big"],
+            traffic_of(["k_prep", "k_csr_small", "k_csr_big", "k_csc_small", "k_csc_big"],
+                       nfused)),
+        "k_lgram": roofline_entry("hbm", lg_b, ms_of("lanczos_gram"), per.get("lanczos_gram", (0, 0))[1],
+                                  PEAK_HBM_GBS, "GB/s", ["k_lgram"],
+                                  traffic_of(["k_lgram"], 2 * (k + 1) * len(levels))),
+        "k_lapply": roofline_entry("hbm", la_b, ms_of("lanczos_apply"), per.get("lanczos_apply", (0, 0))[1],
+                                   PEAK_HBM_GBS, "GB/s", ["k_lapply"],
+                                   traffic_of(["k_lapply"], 2 * (k + 1) * len(levels))),
+        "k_jgram": roofline_entry("mfma", jg_f, ms_of("orth_gram"), per.get("orth_gram", (0, 0))[1],
+                                  PEAK_FP32_MFMA, "TFLOP/s", ["k_jgram"],
+                                  traffic_of(["k_jgram"], len(levels))),
+        "k_japply": roofline_entry("mfma", ja_f, ms_of("orth_apply"), per.get("orth_apply", (0, 0))[1],
+                                   PEAK_FP32_MFMA, "TFLOP/s", ["k_japply"],
+                                   traffic_of(["k_japply"], len(levels))),
+        "k_score_r": roofline_entry("hbm", sc_b, ms_of("score_r"), per.get("score_r", (0, 0))[1],
+                                    PEAK_HBM_GBS, "GB/s", ["k_score_r"],
+                                    traffic_of(["k_score_r"], len(levels))),
+    }
+    # the dominant kernel (by time) among those with an algorithmic count;
+    # the local-clustering search (cluster_best) has none: its work is the
+    # candidate screening that its bounds prune, see its stage time
+    dom = max(rooflines, key=lambda kk: rooflines[kk]["avg_launch_us"] * rooflines[kk]["launches"])
+    r = rooflines[dom]
+    roof = {"bound": r["bound"], "achieved": r["achieved"], "peak": r["peak"], "unit": r["unit"],
+            "frac": r["frac"], "traffic": r["traffic"], "kernel": dom,
+            "avg_launch_us": r["avg_launch_us"]}
 
     result = {
-        "metric": "ER estimates/s (2M-node FP32 hot path)",
+        "metric": METRIC,
         "value": value,
         "unit": "estimates/s",
         "n_gpus": 1,
@@ -184,7 +259,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: n={h.n}, m={h.m}, nnz={h.nnz}, k={params.k}, "
                                f"b={params.b}, K={params.K}, {params.levels} coarsening levels, "
-                               f"local clustering on (hef_coarsen)",
+                               f"local clustering on (hef_coarsen, FP32 pool)",
                    "levels": [list(lv) for lv in levels]},
         "stage_ms_per_step": stage_ms,
         "rooflines": rooflines,
@@ -192,36 +267,70 @@ def main():
     }
 
     if not args.no_extras:
-        # Alg. 1 alone at level 0 (the resistance estimate), FP32 and BF16 pool
         extra = {}
+        # Alg. 1 alone at level 0 (the resistance estimate), FP32 and BF16 pool
         for basis in ("fp32", "bf16"):
             p1 = hef.Params(k=cfg["k"], b=cfg["b"], basis=basis, assume_valid=True)
             hef.resistance(dh, p1)
             torch.cuda.synchronize()
+            hef.timing_read(reset=True)
+            hef.timing_enable(True)
             ta = time.perf_counter()
             reps = 3
             for _ in range(reps):
                 hef.resistance(dh, p1)
             torch.cuda.synchronize()
             dt = (time.perf_counter() - ta) / reps
+            hef.timing_enable(False)
+            st1 = hef.timing_read(reset=True)
             extra[f"alg1_{basis}_estimates_per_s"] = h.m / dt
             extra[f"alg1_{basis}_ms"] = dt * 1e3
-            pc = hef.Params(k=cfg["k"], b=cfg["b"], levels=cfg["levels"], basis=basis,
-                            assume_valid=True)
-            if basis == "bf16":
-                hef.coarsen(dh, pc)
-                torch.cuda.synchronize()
-                ta = time.perf_counter()
-                hef.coarsen(dh, pc)
-                torch.cuda.synchronize()
-                dt = time.perf_counter() - ta
-                lv = hef.last_coarsen_levels()
-                extra["coarsen_bf16_estimates_per_s"] = sum(x[1] for x in lv) / dt
-                extra["coarsen_bf16_ms"] = dt * 1e3
+            if basis == "fp32":
+                ms_sp = sum(st1[x][0] for x in spmm_stages if x in st1) / reps
+                extra["alg1_spmm_GBps"] = spmm_step_bytes(h.n, h.m, h.nnz, B) * k / (ms_sp / 1e3) / 1e9
+        pc = hef.Params(k=cfg["k"], b=cfg["b"], levels=cfg["levels"], basis="bf16",
+                        assume_valid=True)
+        hef.coarsen(dh, pc)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        hef.coarsen(dh, pc)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - ta
+        lv = hef.last_coarsen_levels()
+        extra["coarsen_bf16_estimates_per_s"] = sum(x[1] for x in lv) / dt
+        extra["coarsen_bf16_ms"] = dt * 1e3
+        del dh
+        torch.cuda.empty_cache()
+        # forward + backward of Alg. 1 at the gradient workload
+        gname = "grad200k"
+        gc = get_config(gname)
+        g = make_hypergraph(gname)
+        dg = hef.DeviceHypergraph.from_arrays(g.n, g.m, g.eptr, g.pins, g.w, device=dev)
+        pg = hef.Params(k=gc["k"], b=gc["b"], assume_valid=True)
+        dR = torch.randn(g.m, device=dev, generator=torch.Generator(dev).manual_seed(11))
+        hef.resistance(dg, pg)
+        hef.resistance_backward(dg, pg, dR)
+        torch.cuda.synchronize()
+        reps = 5
+        ta = time.perf_counter()
+        for _ in range(reps):
+            hef.resistance(dg, pg)
+        torch.cuda.synchronize()
+        tf = (time.perf_counter() - ta) / reps
+        ta = time.perf_counter()
+        for _ in range(reps):
+            hef.resistance(dg, pg)
+            hef.resistance_backward(dg, pg, dR)
+        torch.cuda.synchronize()
+        tfb = (time.perf_counter() - ta) / reps
+        extra["adjoint_workload"] = f"{gname}: n={g.n}, m={g.m}, k={gc['k']}, b={gc['b']}"
+        extra["fwd_ms"] = tf * 1e3
+        extra["fwd_bwd_ms"] = tfb * 1e3
+        extra["fwd_bwd_over_fwd"] = tfb / tf
         result["extras"] = extra
 
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(args.config, 20)
+        result["cpu_baseline"] = cpu_baseline(args.config)
     print(json.dumps(result))
 
 

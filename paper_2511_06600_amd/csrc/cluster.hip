@@ -878,18 +878,24 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
         k_centroids<kPoolF32><<<2048, kT, 0, s>>>(L.eptr, L.pins, w.in_list, w.small + 1, pool, K, w.cent);
         k_cperm<kPoolF32><<<g1(n * Kq), kT, 0, s>>>(w.prov, w.owner, w.in_index, w.cent, pool, K, Kq,
                                                    w.perm, w.small + 3, w.cperm, w.crow, int32_t(n));
-        k_best<kPoolF32><<<cdiv(n, kT / 64), kT, 0, s>>>(L.eptr, L.pins, st.vptr, st.eids, w.owner,
-                                                     w.prov, w.crow, w.cent, w.cperm, Kq, w.perm,
-                                                     w.inv32, pool, K, qh, int32_t(n),
+        {
+          TimedScope tb(kStClusterBest, s);
+          k_best<kPoolF32><<<cdiv(n, kT / 64), kT, 0, s>>>(L.eptr, L.pins, st.vptr, st.eids,
+                                                     w.owner, w.prov, w.crow, w.cent, w.cperm, Kq,
+                                                     w.perm, w.inv32, pool, K, qh, int32_t(n),
                                                      w.best_label, w.best_d);
+        }
       } else {
         k_centroids<kPoolBF16><<<2048, kT, 0, s>>>(L.eptr, L.pins, w.in_list, w.small + 1, pool, K, w.cent);
         k_cperm<kPoolBF16><<<g1(n * Kq), kT, 0, s>>>(w.prov, w.owner, w.in_index, w.cent, pool, K, Kq,
                                                    w.perm, w.small + 3, w.cperm, w.crow, int32_t(n));
-        k_best<kPoolBF16><<<cdiv(n, kT / 64), kT, 0, s>>>(L.eptr, L.pins, st.vptr, st.eids, w.owner,
-                                                     w.prov, w.crow, w.cent, w.cperm, Kq, w.perm,
-                                                     w.inv32, pool, K, qh, int32_t(n),
+        {
+          TimedScope tb(kStClusterBest, s);
+          k_best<kPoolBF16><<<cdiv(n, kT / 64), kT, 0, s>>>(L.eptr, L.pins, st.vptr, st.eids,
+                                                     w.owner, w.prov, w.crow, w.cent, w.cperm, Kq,
+                                                     w.perm, w.inv32, pool, K, qh, int32_t(n),
                                                      w.best_label, w.best_d);
+        }
       }
       HEF_LAUNCH_CHECK();
     }

@@ -119,6 +119,11 @@ enum Stage : int {
   kStStart,
   kStSpmmCsrBig,
   kStSpmmCscBig,
+  kStSpmmPrep,
+  kStLanczosReduce,
+  kStOrthReduce,
+  kStScoreReduce,
+  kStClusterBest,
   kStageCount
 };
 

@@ -392,6 +392,7 @@ hef_status lgram(const float *v0, const float *v1, const float *y, int64_t rows,
   const int S = (C % 6 == 0) ? 6 : 3;
   const int64_t per = std::max<int64_t>(64, cdiv(cdiv(rows, kGramBlocks), 64) * 64);
   const int nblk = int(std::max<int64_t>(1, cdiv(rows, per)));
+  {
   TimedScope ts(kStLanczosGram, s);
   switch (B) {
     case 1: k_lgram<1><<<nblk, 256, 0, s>>>(v0, v1, y, rows, per, partial); break;
@@ -402,6 +403,8 @@ hef_status lgram(const float *v0, const float *v1, const float *y, int64_t rows,
     default: return HEF_ERR_UNSUPPORTED;
   }
   HEF_LAUNCH_CHECK();
+  }
+  TimedScope ts(kStLanczosReduce, s);
   HEF_TRY(reduce_cols_f64(partial, nblk, int64_t(C) * C, G, s));
   k_lgram_sym<<<cdiv(C * C, 256), 256, 0, s>>>(G, C, S);
   HEF_LAUNCH_CHECK();

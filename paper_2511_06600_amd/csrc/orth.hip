@@ -776,6 +776,7 @@ hef_status gram_run(const void *pool, const void *poolB, int pool_type, int64_t 
   double *sums = ws.take<double>(tot);
   if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
   HEF_HIP(hipMemsetAsync(G, 0, sizeof(double) * K * K, s));
+  {
   TimedScope ts(kStOrthGram, s);
   if (pool_type == kPoolBF16 && !poolB)
     k_jgram_bf16<<<int64_t(p.npairs) * p.nchunks, kGT, 0, s>>>(
@@ -785,6 +786,8 @@ hef_status gram_run(const void *pool, const void *poolB, int pool_type, int64_t 
     k_jgram<<<int64_t(p.npairs) * p.nchunks, kGT, 0, s>>>(pool, poolB, pool_type, oct, n, K, p.nsb,
                                                           p.npairs, p.rows_per_chunk, partial);
   HEF_LAUNCH_CHECK();
+  }
+  TimedScope ts(kStOrthReduce, s);
   HEF_TRY(reduce_cols_f64(partial, p.nchunks, tot, sums, s));
   k_jgram_scatter<<<cdiv(tot, 256), 256, 0, s>>>(sums, p.nsb, p.npairs, K, poolB != nullptr, G);
   HEF_LAUNCH_CHECK();
@@ -886,8 +889,11 @@ hef_status orthonormalize_pool(void *P, void *out, int pool_type, int64_t n, int
       HEF_LAUNCH_CHECK();
     }
     if (pool_type == kPoolBF16) {
+      {
+        TimedScope ts(kStOrthChol, s);
+        k_split_rinv<<<cdiv(int64_t(Kp) * Kp, 256), 256, 0, s>>>(Rinv, K, Kp, RhT, RlT);
+      }
       TimedScope ts(kStOrthApply, s);
-      k_split_rinv<<<cdiv(int64_t(Kp) * Kp, 256), 256, 0, s>>>(Rinv, K, Kp, RhT, RlT);
       const int ncb = (K + kAN - 1) / kAN;
       if (n > 0)
         k_japply_bf16<<<cdiv(n, kAM) * ncb, kAT, 0, s>>>(

@@ -159,6 +159,10 @@ hef_status score_t(const Level &L, const void *pool, int K, double *qh, float *R
   {
   TimedScope ts(kStScoreQ, s);
   k_score_qh<CPL, PT><<<nblk, kThreads, 0, s>>>(L.eptr, L.pins, L.w, pool, K, LPR, L.m, partial);
+  HEF_LAUNCH_CHECK();
+  }
+  {
+  TimedScope ts(kStScoreReduce, s);
   HEF_TRY(reduce_cols_f64(partial, nblk, K, qh, s));
   }
   TimedScope ts(kStScoreR, s);

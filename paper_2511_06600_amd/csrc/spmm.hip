@@ -328,7 +328,7 @@ hef_status spmm_t(const Level &L, const Structure &st, const float *xs, float *y
   float *U = scratch + m * G::RW;
   const int on = (xs ? 1 : 0) | (xc ? 2 : 0);
   if (n > 0) {
-    TimedScope ts(kStSpmmCsr, s);
+    TimedScope ts(kStSpmmPrep, s);
     k_prep<B><<<cdiv(n * G::LPS, kThreads), kThreads, 0, s>>>(n, st.s, xs, xc, U);
     HEF_LAUNCH_CHECK();
   }
