@@ -74,6 +74,8 @@ typedef enum {
 #define HEF_FLAG_ASSUME_VALID 1u  /* skip the device validation (no sync)  */
 #define HEF_FLAG_STAR_ONLY 2u     /* pool from the star expansion only     */
 #define HEF_FLAG_CLIQUE_ONLY 4u   /* pool from the clique expansion only   */
+#define HEF_FLAG_TAPED 8u         /* backward: the tape of a preceding
+                                     hef_resistance_taped is in `ws`        */
 
 typedef struct {
   int32_t n, m;          /* nodes, hyperedges                               */
@@ -177,16 +179,32 @@ hef_status hef_cluster_level(const hef_hypergraph *hg, const hef_params *p,
                              float *eta_out, void *ws, size_t ws_bytes,
                              hipStream_t stream);
 
-/* Adjoint of hef_resistance with respect to the hyperedge weights: given
- * dR = dL/dR (DEVICE [m] float32), writes dw = dL/dw (DEVICE [m] float32).
- * Recomputes the forward pass with the same start blocks (which must be the
- * ones the forward used; NULL = counter generator) and keeps Krylov
- * checkpoints every p->ckpt_every steps.  Ties in a maximum take the lowest
- * column index and the lowest CSR position.  FP32 pool only. */
+/* Adjoint of hef_resistance with respect to the hyperedge weights (the
+ * derivative of Eqs. (9), (13), (14) through the Krylov bases of
+ * Section III-B, serving the resistance-based hyperedge weighting of
+ * Section I): given dR = dL/dR (DEVICE [m] float32), writes dw = dL/dw
+ * (DEVICE [m] float32).  Unless p->flags has HEF_FLAG_TAPED it first
+ * recomputes the forward pass with the same start blocks (which must be the
+ * ones the forward used; NULL = counter generator), keeping Krylov
+ * checkpoints every p->ckpt_every steps; with HEF_FLAG_TAPED it uses the
+ * tape that hef_resistance_taped left in `ws` (same hypergraph, params and
+ * workspace, untouched in between).  Ties in a maximum take the lowest
+ * column index and the lowest CSR position.  The derivative is that of the
+ * FP32-pool computation (a BF16 request differentiates the FP32 path);
+ * orth_passes must be 1 (else HEF_ERR_UNSUPPORTED).  Workspace:
+ * hef_workspace_size(..., HEF_OP_BACKWARD, ...). */
 hef_status hef_resistance_backward(const hef_hypergraph *hg, const hef_params *p,
                                    const float *start_star, const float *start_clique,
                                    const float *dR, float *dw,
                                    void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* The forward pass of hef_resistance (FP32 pool) writing R (DEVICE [m]
+ * float32) and keeping in `ws` (sized for HEF_OP_BACKWARD) the tape that a
+ * following hef_resistance_backward with HEF_FLAG_TAPED reverses, so that
+ * forward + backward costs one forward and one reverse sweep. */
+hef_status hef_resistance_taped(const hef_hypergraph *hg, const hef_params *p,
+                                const float *start_star, const float *start_clique, float *R,
+                                void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Test hook: y = A x for one normalised expansion adjacency
  * (expansion 0 = star, x and y DEVICE [(n+m) x b]; 1 = clique, [n x b]),

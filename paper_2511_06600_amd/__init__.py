@@ -154,33 +154,57 @@ def cluster_level(hg: DeviceHypergraph, params: Params, R: torch.Tensor,
 
 def resistance_backward(hg: DeviceHypergraph, params: Params, dR: torch.Tensor,
                         start_star: torch.Tensor | None = None,
-                        start_clique: torch.Tensor | None = None) -> torch.Tensor:
-    """dL/dw for dL/dR = dR (the adjoint of Alg. 1)."""
+                        start_clique: torch.Tensor | None = None,
+                        tape: torch.Tensor | None = None) -> torch.Tensor:
+    """dL/dw for dL/dR = dR (the adjoint of Alg. 1).  With `tape` (the
+    workspace returned by resistance_taped for the same hypergraph and
+    params) only the reverse sweep runs."""
     lib = load()
     dw = torch.empty(hg.m, dtype=torch.float32, device=hg.device)
-    ws = _workspace(hg, params, _lib.OP_BACKWARD)
-    check(lib.hef_resistance_backward(C.byref(hg.c()), C.byref(params.c()), _ptr(start_star),
+    pc = params.c()
+    if tape is not None:
+        pc.flags |= _lib.FLAG_TAPED
+        ws = tape
+    else:
+        ws = _workspace(hg, params, _lib.OP_BACKWARD)
+    check(lib.hef_resistance_backward(C.byref(hg.c()), C.byref(pc), _ptr(start_star),
                                       _ptr(start_clique), _ptr(dR.contiguous()), _ptr(dw),
                                       _ptr(ws), ws.numel(), _stream(hg.device)),
           "hef_resistance_backward")
     return dw
 
 
+def resistance_taped(hg: DeviceHypergraph, params: Params, start_star: torch.Tensor | None = None,
+                     start_clique: torch.Tensor | None = None):
+    """The forward of Alg. 1 (FP32 pool) keeping the adjoint's tape: returns
+    (R [m] float32, tape workspace for resistance_backward)."""
+    lib = load()
+    R = torch.empty(hg.m, dtype=torch.float32, device=hg.device)
+    ws = _workspace(hg, params, _lib.OP_BACKWARD)
+    check(lib.hef_resistance_taped(C.byref(hg.c()), C.byref(params.c()), _ptr(start_star),
+                                   _ptr(start_clique), _ptr(R), _ptr(ws), ws.numel(),
+                                   _stream(hg.device)), "hef_resistance_taped")
+    return R, ws
+
+
 class HyperEFResistance(torch.autograd.Function):
     """R = HyperEFResistance.apply(w, hg, params[, start_star, start_clique]):
-    resistances as a differentiable function of the hyperedge weights."""
+    resistances as a differentiable function of the hyperedge weights.  The
+    forward keeps the Krylov tape in its workspace, so the backward runs only
+    the reverse sweep."""
 
     @staticmethod
     def forward(ctx, w, hg, params, start_star=None, start_clique=None):
         h = DeviceHypergraph(hg.n, hg.m, hg.eptr, hg.pins, w.detach().contiguous())
-        R, _, _ = resistance(h, params, start_star, start_clique)
-        ctx.h, ctx.params = h, params
+        R, tape = resistance_taped(h, params, start_star, start_clique)
+        ctx.h, ctx.params, ctx.tape = h, params, tape
         ctx.starts = (start_star, start_clique)
         return R
 
     @staticmethod
     def backward(ctx, dR):
-        dw = resistance_backward(ctx.h, ctx.params, dR.float(), *ctx.starts)
+        dw = resistance_backward(ctx.h, ctx.params, dR.float(), *ctx.starts, tape=ctx.tape)
+        ctx.tape = None
         return dw, None, None, None, None
 
 

@@ -742,23 +742,17 @@ size_t backward_bytes(int64_t n, int64_t m, int64_t nnz, const hef_params &p) {
   return a.mark() + transient_bytes(n, m, nnz, p) + 1024;
 }
 
-// The adjoint proper (arguments already checked; n, m > 0).
-hef_status resistance_backward(const Level &L, const hef_params &p, const float *start_star,
-                               const float *start_clique, const float *dR, float *dw, Arena &a,
-                               hipStream_t s) {
-  const int64_t n = L.n, m = L.m, nnz = L.nnz;
-  const int B = p.b, k = p.k, K = pool_width_of(p), C = 3 * B;
-  const int Kp = (K + 31) / 32 * 32;
+// The forward with tape (the computation of hef_resistance, FP32 pool): the
+// structure, pool, orthonormal pool, Q_H, R and the Krylov tape stay in the
+// carved part of the workspace (arguments already checked; n, m > 0).
+hef_status taped_forward(const Level &L, const hef_params &p, const float *start_star,
+                         const float *start_clique, BwdWs &w, Arena &a, hipStream_t s) {
+  const int64_t n = L.n, m = L.m;
+  const int B = p.b, k = p.k, K = pool_width_of(p);
   const int64_t Ns = n + m;
   const bool use_star = !(p.flags & HEF_FLAG_CLIQUE_ONLY);
   const bool use_clique = !(p.flags & HEF_FLAG_STAR_ONLY);
-  const int64_t bk = int64_t(B) * k;
-  BwdWs w;
-  carve(a, n, m, nnz, p, w);
-  if (a.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
   const Structure &st = w.st;
-
-  // ---- forward with tape (the computation of hef_resistance, FP32 pool)
   HEF_TRY(structure_build(L, w.st, a, s));
   if (use_star && !start_star) {
     HEF_TRY(start_block(p.seed, 0, 0, Ns, B, w.xs, s));
@@ -777,7 +771,20 @@ hef_status resistance_backward(const Level &L, const hef_params &p, const float 
   HEF_TRY(orthonormalize_pool(w.P, w.chi, kPoolF32, n, K, double(p.drop_tol), 1, nullptr, a, s,
                               w.rinvJ));
   HEF_TRY(score_pool(L, w.chi, kPoolF32, K, w.qh, w.R, a, s));
+  return HEF_OK;
+}
 
+// The reverse sweep from the tape left by taped_forward in the same workspace.
+hef_status reverse_sweep(const Level &L, const hef_params &p, const float *dR, float *dw,
+                         BwdWs &w, Arena &a, hipStream_t s) {
+  const int64_t n = L.n, m = L.m, nnz = L.nnz;
+  const int B = p.b, k = p.k, K = pool_width_of(p), C = 3 * B;
+  const int Kp = (K + 31) / 32 * 32;
+  const int64_t Ns = n + m;
+  const bool use_star = !(p.flags & HEF_FLAG_CLIQUE_ONLY);
+  const bool use_clique = !(p.flags & HEF_FLAG_STAR_ONLY);
+  const int64_t bk = int64_t(B) * k;
+  const Structure &st = w.st;
   TimedScope ts(kStAdjoint, s);
   // ---- 1. ratios -> chibar
   {
@@ -920,7 +927,7 @@ hef_status hef_resistance_backward(const hef_hypergraph *hg, const hef_params *p
   a.cap = ws_bytes;
   Level L;
   L.n = hg->n; L.m = hg->m; L.nnz = hg->nnz; L.eptr = hg->eptr; L.pins = hg->pins; L.w = hg->w;
-  if (!(p->flags & HEF_FLAG_ASSUME_VALID)) {
+  if (!(p->flags & (HEF_FLAG_ASSUME_VALID | HEF_FLAG_TAPED))) {
     Arena t = a;
     Structure st;
     structure_carve(t, L.n, L.m, L.nnz, st);
@@ -934,7 +941,55 @@ hef_status hef_resistance_backward(const hef_hypergraph *hg, const hef_params *p
     HEF_HIP(hipMemsetAsync(dw, 0, sizeof(float) * L.m, stream));
     return HEF_OK;
   }
-  return resistance_backward(L, *p, start_star, start_clique, dR, dw, a, stream);
+  BwdWs w;
+  carve(a, L.n, L.m, L.nnz, *p, w);
+  if (a.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+  if (!(p->flags & HEF_FLAG_TAPED))
+    HEF_TRY(taped_forward(L, *p, start_star, start_clique, w, a, stream));
+  return reverse_sweep(L, *p, dR, dw, w, a, stream);
+}
+
+hef_status hef_resistance_taped(const hef_hypergraph *hg, const hef_params *p,
+                                const float *start_star, const float *start_clique, float *R,
+                                void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (!hg || !p) { set_error("NULL argument"); return HEF_ERR_INVALID_ARGUMENT; }
+  size_t need = 0;
+  HEF_TRY(hef_workspace_size(hg, p, HEF_OP_BACKWARD, &need));
+  if (!ws) { set_error("workspace is NULL"); return HEF_ERR_INVALID_ARGUMENT; }
+  if (ws_bytes < need) {
+    set_error("workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+    return HEF_ERR_WORKSPACE_TOO_SMALL;
+  }
+  if (hg->m > 0 && !R) { set_error("R is NULL"); return HEF_ERR_INVALID_ARGUMENT; }
+  if (p->orth_passes != 1) {
+    set_error("the adjoint supports orth_passes = 1");
+    return HEF_ERR_UNSUPPORTED;
+  }
+  Arena a;
+  a.base = static_cast<char *>(ws);
+  a.cap = ws_bytes;
+  Level L;
+  L.n = hg->n; L.m = hg->m; L.nnz = hg->nnz; L.eptr = hg->eptr; L.pins = hg->pins; L.w = hg->w;
+  if (!(p->flags & HEF_FLAG_ASSUME_VALID)) {
+    Arena t = a;
+    Structure st;
+    structure_carve(t, L.n, L.m, L.nnz, st);
+    int32_t *flags = t.take<int32_t>(4);
+    int32_t bad = 0;
+    HEF_TRY(validate_device(L, flags, &bad, stream));
+    if (bad) { set_error("invalid hypergraph (code %d)", bad); return HEF_ERR_INVALID_HYPERGRAPH; }
+  }
+  if (L.m == 0) return HEF_OK;
+  if (L.n == 0) {
+    HEF_HIP(hipMemsetAsync(R, 0, sizeof(float) * L.m, stream));
+    return HEF_OK;
+  }
+  BwdWs w;
+  carve(a, L.n, L.m, L.nnz, *p, w);
+  if (a.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+  HEF_TRY(taped_forward(L, *p, start_star, start_clique, w, a, stream));
+  HEF_HIP(hipMemcpyAsync(R, w.R, sizeof(float) * L.m, hipMemcpyDeviceToDevice, stream));
+  return HEF_OK;
 }
 
 }  // extern "C"

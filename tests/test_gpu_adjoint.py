@@ -95,6 +95,20 @@ def test_single_expansion_euler(flags):
     assert abs(euler + L) <= 1e-3 * abs(L)
 
 
+def test_taped_forward_matches_forward_and_backward():
+    h = generate(3000, 3200, 2, 40, 2.5, p_loc=0.6, win=200, weights="lognormal", seed=23)
+    dh = to_device(h)
+    p = hef.Params(k=10, b=2)
+    say(f"case: taped forward n={h.n}")
+    R0, _, _ = hef.resistance(dh, p)
+    R1, tape = hef.resistance_taped(dh, p)
+    assert torch.equal(R0, R1)
+    dR = torch.randn(h.m, device="cuda", generator=torch.Generator("cuda").manual_seed(4))
+    g_tape = hef.resistance_backward(dh, p, dR, tape=tape)
+    g_full = hef.resistance_backward(dh, p, dR)
+    assert torch.equal(g_tape, g_full)
+
+
 def test_autograd_function():
     h = generate(1000, 1100, 2, 15, 2.5, p_loc=0.5, win=100, weights="lognormal", seed=21)
     dh = to_device(h)
