@@ -188,7 +188,7 @@ k_qh_order(const double *__restrict__ qh, int K, int32_t *__restrict__ perm,
     if (q >= *nuse) { perm[q] = 0; inv32[q] = 0.0f; }
 }
 
-// cperm[C][q] = float32 of cluster C's centroid in column perm[q] (zero for
+// cperm[C][q] = float16 of cluster C's centroid in column perm[q] (zero for
 // q >= nuse), for every cluster id C (a node that is its cluster's smallest
 // member).  Row width Kq = K rounded up to 64.  crow[C] = the row of C's
 // float64 centroid (-1: singleton, the centroid is its pool row).
@@ -197,7 +197,7 @@ __global__ void k_cperm(const int32_t *__restrict__ prov, const int32_t *__restr
                         const int32_t *__restrict__ in_index, const double *__restrict__ cent,
                         const void *__restrict__ pool, int K, int Kq,
                         const int32_t *__restrict__ perm, const int32_t *__restrict__ nuse,
-                        float *__restrict__ cperm, int32_t *__restrict__ crow, int32_t n) {
+                        _Float16 *__restrict__ cperm, int32_t *__restrict__ crow, int32_t n) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= int64_t(n) * Kq) return;
   const int64_t v = idx / Kq;
@@ -212,27 +212,36 @@ __global__ void k_cperm(const int32_t *__restrict__ prov, const int32_t *__restr
     val = ow < 0 ? float(pool_val<PT>(pool, v * K + col))
                  : float(cent[int64_t(in_index[ow]) * K + col]);
   }
-  cperm[v * Kq + q] = val;
-}
-
-// Safe float32 lower bound of one column's term (x - c)^2 / Q_H given the
-// float32 copy s of c (|s - c| <= 2^-24 |c| < 2^-23 |s|).
-__device__ __forceinline__ float lb_term(float x, float s, float iq) {
-  float dev = fabsf(x - s) - 0x1p-23f * fabsf(s);
-  dev = dev > 0.0f ? dev : 0.0f;
-  return dev * dev * iq;
-}
-
-// Safe float32 upper bound of one column's term (scaled by 1 + 2e-6 by the
-// caller to cover the float32 roundings).
-__device__ __forceinline__ float ub_term(float x, float s, float iq) {
-  const float dev = fabsf(x - s) + 0x1p-23f * fabsf(s);
-  return dev * dev * iq;
+  cperm[v * Kq + q] = _Float16(val);
 }
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
+}
+
+// Safe float32 lower bound of one column's term (x - c)^2 / Q_H from the
+// float16 copy h of c: |h - c| <= 2^-10 |h| + 2^-24 (float16 rounding of the
+// float32 rounding of c, subnormals included; |c| <= 1 for an orthonormal
+// basis).
+__device__ __forceinline__ float lb16_term(float x, float h, float iq) {
+  float dev = fabsf(x - h) - (0x1p-10f * fabsf(h) + 0x1p-24f);
+  dev = dev > 0.0f ? dev : 0.0f;
+  return dev * dev * iq;
+}
+
+// max over the 8 float16 values of v against xs/is[q0 .. q0+8)
+__device__ __forceinline__ float lb16_8(const uint4 v, const float *xs, const float *is, int q0) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+  float lo = 0.0f;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const float h0 = float(__builtin_bit_cast(_Float16, uint16_t(w[u] & 0xFFFFu)));
+    const float h1 = float(__builtin_bit_cast(_Float16, uint16_t(w[u] >> 16)));
+    lo = fmaxf(lo, lb16_term(xs[q0 + 2 * u], h0, is[q0 + 2 * u]));
+    lo = fmaxf(lo, lb16_term(xs[q0 + 2 * u + 1], h1, is[q0 + 2 * u + 1]));
+  }
+  return lo;
 }
 
 // Exact float64 distance d(p, C) = max_i (chi_p^(i) - c_C^(i))^2 / Q_H(i)
@@ -269,21 +278,20 @@ __device__ __forceinline__ double exact_d(int64_t p, int32_t C, int lane, const 
 // One wave per isolated node p; its candidates are the clusters C = prov[v]
 // of the co-pins v of its hyperedges, and best(p) = (smallest exact float64
 // d(p, C), smallest label).  The wave filters the candidates with float32
-// bounds in the permuted column order (largest weights first):
-//   stage A  one lane per candidate, lower bound over 64 columns;
-//   stage B  8 lanes per candidate, lower bound over 256 columns;
-//   stage C  8 lanes per candidate, lower and upper bounds over all columns.
-// Lower bounds exceed the exact value by at most a relative 1e-6 and upper
-// bounds (times 1 + 2e-6) are never below it.  `ub` is the smallest upper
-// bound found, so no candidate whose lower bound exceeds ub (1 + 1e-5) can
-// be the minimum or tie with it.  Candidates that reach the end unexcluded
-// (near-ties only) get the exact float64 distance.  Hyperedges of at most
-// kSeedSeg pins are visited first; the first candidate batch seeds ub with
-// its smallest stage-A bound's candidate.  The result is the exact argmin
-// whatever the visiting order.
+// lower bounds computed from float16 copies of the centroids in the
+// permuted column order (largest weights first):
+//   stage A  one lane per candidate, 128 columns;
+//   stage B  8 lanes per candidate, all columns;
+// and evaluates the exact distance of the candidates the bounds leave.  A
+// lower bound exceeds the exact value by at most a relative 1e-6, so a
+// candidate whose bound is above the best exact distance found times
+// (1 + 1e-5) can neither be the minimum nor tie with it.  Hyperedges of at
+// most kSeedSeg pins are visited first, and the first candidate batch seeds
+// the search with the exact distance of its smallest stage-A bound.  The
+// result is the exact argmin whatever the visiting order.
 constexpr int kQCap = 72;   // stage-B queue: 8 + one batch of 64
-constexpr int kFCap = 32;   // candidates awaiting the exact distance
 constexpr int kEB = 64;     // hyperedges of p per batch
+constexpr int kAq = 128;    // stage-A columns
 
 template <int PT>
 __global__ void __launch_bounds__(kT)
@@ -291,7 +299,7 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
        const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
        const int32_t *__restrict__ owner, const int32_t *__restrict__ prov,
        const int32_t *__restrict__ crow, const double *__restrict__ cent,
-       const float *__restrict__ cperm, int Kq, const int32_t *__restrict__ perm,
+       const _Float16 *__restrict__ cperm, int Kq, const int32_t *__restrict__ perm,
        const float *__restrict__ inv32, const void *__restrict__ pool, int K,
        const double *__restrict__ qh, int32_t n, int32_t *__restrict__ best_label,
        double *__restrict__ best_d) {
@@ -302,8 +310,6 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
   __shared__ int32_t ep_all[NW][kEB + 1];  // exclusive prefix of sizes
   __shared__ int32_t qc_all[NW][kQCap];
   __shared__ float ql_all[NW][kQCap];
-  __shared__ int32_t fc_all[NW][kFCap];
-  __shared__ float fl_all[NW][kFCap];
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int g = lane >> 3, a8 = lane & 7;
@@ -323,70 +329,27 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
   int32_t *ep = ep_all[w];
   int32_t *qc = qc_all[w];
   float *ql = ql_all[w];
-  int32_t *fc = fc_all[w];
-  float *fl = fl_all[w];
   for (int q = lane; q < Kq; q += 64) {
     xs[q] = float(pool_val<PT>(pool, p * K + perm[q]));
     is[q] = inv32[q];
   }
-  const int kb = Kq < 256 ? Kq : 256;
+  const int ka = Kq < kAq ? Kq : kAq;  // stage-A width (a multiple of 64)
   wave_sync();
 
-  float ub = FLT_MAX;            // smallest upper bound so far (wave-uniform)
-  int nq = 0, nf = 0;            // queue / exact-list fill (wave-uniform)
-  double bd = DBL_MAX;           // exact best of flushed entries
+  double bd = DBL_MAX;           // best exact distance (wave-uniform)
   int32_t bl = INT32_MAX;
-
-  // exact distances of the listed candidates still within the bound
-  auto flush = [&]() {
-    for (int i = 0; i < nf; ++i) {
-      const int32_t C = fc[i];
-      if (fl[i] > ub * kMargin) continue;
-      const double dl = exact_d<PT>(p, C, lane, crow, cent, pool, K, qh);
-      if (dl < bd || (dl == bd && C < bl)) {
-        bd = dl;
-        bl = C;
-      }
+  float ub = FLT_MAX;            // float32 upper bound of bd
+  int nq = 0;                    // queue fill (wave-uniform)
+  auto consider = [&](int32_t C) {
+    const double dl = exact_d<PT>(p, C, lane, crow, cent, pool, K, qh);
+    if (dl < bd || (dl == bd && C < bl)) {
+      bd = dl;
+      bl = C;
+      ub = fminf(ub, float(bd) * kUbScale * kUbScale);
     }
-    nf = 0;
-    if (bd != DBL_MAX) ub = fminf(ub, float(bd) * kUbScale * kUbScale);
-    wave_sync();
   };
-  // stage C of candidate C on the 8 lanes of a group: (lower, upper) bound
-  auto stage_c = [&](int32_t C, float &lo, float &hi) {
-    lo = 0.0f;
-    hi = 0.0f;
-    const float *row = cperm + int64_t(C) * Kq;
-    for (int q0 = 4 * a8; q0 < Kq; q0 += 32) {
-      const float4 sv = *reinterpret_cast<const float4 *>(row + q0);
-      const float c4[4] = {sv.x, sv.y, sv.z, sv.w};
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        lo = fmaxf(lo, lb_term(xs[q0 + u], c4[u], is[q0 + u]));
-        hi = fmaxf(hi, ub_term(xs[q0 + u], c4[u], is[q0 + u]));
-      }
-    }
-    for (int off = 4; off > 0; off >>= 1) {
-      lo = fmaxf(lo, __shfl_xor(lo, off, 8));
-      hi = fmaxf(hi, __shfl_xor(hi, off, 8));
-    }
-    hi *= kUbScale;
-  };
-  // append the groups' candidates with bound <= ub (1 + 1e-5) to the exact list
-  auto push_f = [&](bool ok, int32_t C, float lo) {
-    const uint64_t m = __ballot(ok && a8 == 0);
-    const int cnt = __popcll(m);
-    if (cnt == 0) return;
-    if (nf + cnt > kFCap) flush();
-    if (ok && a8 == 0) {
-      const int at = nf + __popcll(m & lt_mask);
-      fc[at] = C;
-      fl[at] = lo;
-    }
-    nf += cnt;
-    wave_sync();
-  };
-  // stages B and C for up to 8 queued candidates (taken from the queue's end)
+  // stage B for up to 8 queued candidates (taken from the queue's end), then
+  // the exact distance of those it leaves
   auto batch = [&](int cnt) {
     int32_t C = -1;
     float lo = FLT_MAX;
@@ -396,34 +359,19 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
     }
     nq -= cnt;
     wave_sync();
-    bool live = C >= 0 && !(lo > ub * kMargin);
-    if (live && kb > 64) {
-      const int q0 = 32 * a8;
-      if (q0 < kb) {
-        const float4 *row = reinterpret_cast<const float4 *>(cperm + int64_t(C) * Kq + q0);
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const float4 sv = row[u];
-          const int q = q0 + 4 * u;
-          lo = fmaxf(lo, lb_term(xs[q], sv.x, is[q]));
-          lo = fmaxf(lo, lb_term(xs[q + 1], sv.y, is[q + 1]));
-          lo = fmaxf(lo, lb_term(xs[q + 2], sv.z, is[q + 2]));
-          lo = fmaxf(lo, lb_term(xs[q + 3], sv.w, is[q + 3]));
-        }
-      }
+    const bool live = C >= 0 && !(lo > ub * kMargin);
+    if (live) {
+      const _Float16 *row = cperm + int64_t(C) * Kq;
+      for (int q0 = 8 * a8; q0 < Kq; q0 += 64)
+        lo = fmaxf(lo, lb16_8(*reinterpret_cast<const uint4 *>(row + q0), xs, is, q0));
     }
     for (int off = 4; off > 0; off >>= 1) lo = fmaxf(lo, __shfl_xor(lo, off, 8));
-    live = live && !(lo > ub * kMargin);
-    float hi = FLT_MAX;
-    if (live) {
-      float lc;
-      stage_c(C, lc, hi);
-      lo = fmaxf(lo, lc);
+    for (int t = 0; t < cnt; ++t) {
+      const int32_t Ct = __shfl(C, 8 * t, 64);
+      const float lt = __shfl(lo, 8 * t, 64);
+      if (Ct < 0 || Ct == bl || lt > ub * kMargin) continue;
+      consider(Ct);
     }
-    float mh = hi;
-    for (int off = 8; off < 64; off <<= 1) mh = fminf(mh, __shfl_xor(mh, off, 64));
-    ub = fminf(ub, mh);
-    push_f(live && !(lo > ub * kMargin), C, lo);
   };
 
   for (int32_t e0 = 0; e0 < deg; e0 += kEB) {
@@ -470,18 +418,11 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
       }
       if (C >= 0) {
         lo = 0.0f;
-        const float4 *row = reinterpret_cast<const float4 *>(cperm + int64_t(C) * Kq);
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const float4 sv = row[u];
-          const int q = 4 * u;
-          lo = fmaxf(lo, lb_term(xs[q], sv.x, is[q]));
-          lo = fmaxf(lo, lb_term(xs[q + 1], sv.y, is[q + 1]));
-          lo = fmaxf(lo, lb_term(xs[q + 2], sv.z, is[q + 2]));
-          lo = fmaxf(lo, lb_term(xs[q + 3], sv.w, is[q + 3]));
-        }
+        const _Float16 *row = cperm + int64_t(C) * Kq;
+        for (int q0 = 0; q0 < ka; q0 += 8)
+          lo = fmaxf(lo, lb16_8(*reinterpret_cast<const uint4 *>(row + q0), xs, is, q0));
       }
-      if (ub == FLT_MAX) {
+      if (bl == INT32_MAX) {
         // seed: the candidate with the smallest (bound, label) of this batch
         float sl = lo;
         int32_t sc = C >= 0 ? C : INT32_MAX;
@@ -493,21 +434,9 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
             sc = oc;
           }
         }
-        if (sc != INT32_MAX) {
-          float slo = 0.0f, shi = FLT_MAX;
-          if (g == 0) stage_c(sc, slo, shi);
-          slo = __shfl(slo, 0, 64);
-          shi = __shfl(shi, 0, 64);
-          ub = fminf(ub, shi);
-          if (lane == 0) {
-            fc[nf] = sc;
-            fl[nf] = slo;
-          }
-          nf += 1;
-          wave_sync();
-        }
+        if (sc != INT32_MAX) consider(sc);
       }
-      const bool ok = C >= 0 && !(lo > ub * kMargin);
+      const bool ok = C >= 0 && C != bl && !(lo > ub * kMargin);
       const uint64_t m = __ballot(ok);
       if (ok) {
         const int at2 = nq + __popcll(m & lt_mask);
@@ -521,7 +450,6 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
     wave_sync();
   }
   if (nq > 0) batch(nq);
-  flush();
   if (lane == 0) {
     best_label[p] = bl == INT32_MAX ? -1 : bl;
     best_d[p] = bd;
@@ -744,7 +672,8 @@ struct LevelWs {
   unsigned long long *packed;
   float *prov_eta;
   double *best_d, *cent;
-  float *cperm, *inv32;
+  _Float16 *cperm;
+  float *inv32;
   int32_t *perm;
   int32_t *crow;   // [n] centroid row per cluster id
   int32_t *small;  // [8] device scalars
@@ -776,7 +705,7 @@ void carve_level(Arena &a, int64_t n, int64_t m, int64_t nnz, int K, LevelWs &w)
   w.prov_eta = a.take<float>(n + 1);
   w.best_d = a.take<double>(n + 1);
   w.cent = a.take<double>((n / 2 + 1) * int64_t(K));
-  w.cperm = a.take<float>((n + 1) * int64_t((K + 63) / 64 * 64));
+  w.cperm = a.take<_Float16>((n + 1) * int64_t((K + 63) / 64 * 64));
   w.inv32 = a.take<float>(512);
   w.perm = a.take<int32_t>(512);
   w.crow = a.take<int32_t>(n + 1);
