@@ -30,93 +30,93 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return uint16_t(u >> 16);
 }
 
-// Blocked left-looking Cholesky G = L L^T (float64) with the drop rule, one
-// 1024-thread workgroup.  L is kept column-major in global memory
-// (LT[c*K + r] = L[r][c]); each 32-column panel is updated by a 4x4
-// register-blocked product with the finished columns, then factored in LDS.
-// A column whose Schur pivot is <= tau^2 G_jj (or that `force_keep` marks 0)
-// is dropped: its column of L is zero.
+// Blocked Cholesky G = L L^T (float64) with the drop rule.  L is kept
+// column-major in global memory (LT[c*K + r] = L[r][c]).  A column whose
+// Schur pivot is <= tau^2 G_jj (or that `force_keep` marks 0) is dropped:
+// its column of L is zero.
 constexpr int kPW = 32;
 constexpr int kPS = kPW + 1;  // LDS row stride of a panel
 
+// Right-looking: A holds G minus the contributions of the finished panels
+// (lower triangle).  Panel [c0, c0+w) is factored by one workgroup in LDS
+// (32 column steps); k_chol_update then subtracts its columns from the
+// trailing matrix, tile by tile, so every entry sees its subtractions in
+// ascending column order.
 __global__ void __launch_bounds__(1024)
-k_jchol(const double *__restrict__ G, int K, double tau, double *__restrict__ LT,
-        int32_t *__restrict__ keep, const int32_t *__restrict__ force_keep) {
-  extern __shared__ double pan[];  // [K][kPS]
+k_chol_panel(const double *__restrict__ A, const double *__restrict__ G, int K, int c0,
+             double tau, double *__restrict__ LT, int32_t *__restrict__ keep,
+             const int32_t *__restrict__ force_keep) {
+  extern __shared__ double pan[];  // [K - c0][kPS]
   __shared__ int s_keep;
   const int t = threadIdx.x;
-  for (int64_t e = t; e < int64_t(K) * K; e += 1024) LT[e] = 0.0;
+  const int w = K - c0 < kPW ? K - c0 : kPW;
+  const int nr = K - c0;
+  for (int e = t; e < nr * w; e += 1024) {
+    const int i = e / w, j = e % w;
+    pan[i * kPS + j] = i >= j ? A[int64_t(c0 + i) * K + c0 + j] : 0.0;
+  }
   __syncthreads();
-  for (int c0 = 0; c0 < K; c0 += kPW) {
-    const int w = K - c0 < kPW ? K - c0 : kPW;
-    const int nr = K - c0;
-    // panel rows [c0, K) x cols [c0, c0+w): G minus the finished columns
-    const int nbi = (nr + 3) / 4, nbj = (w + 3) / 4;
-    for (int blk = t; blk < nbi * nbj; blk += 1024) {
-      const int bi = blk / nbj, bj = blk % nbj;
-      const int r0 = c0 + 4 * bi, q0 = c0 + 4 * bj;
-      if (4 * bi + 3 < 4 * bj) continue;  // strictly above the diagonal
-      double acc[4][4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int r = r0 + a, q = q0 + b;
-          acc[a][b] = (r < K && q < c0 + w) ? G[int64_t(r) * K + q] : 0.0;
-        }
-      for (int l = 0; l < c0; ++l) {
-        const double *col = LT + int64_t(l) * K;
-        double x[4], y[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) x[a] = (r0 + a < K) ? col[r0 + a] : 0.0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) y[b] = (q0 + b < K) ? col[q0 + b] : 0.0;
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a][b] -= x[a] * y[b];
-      }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int i = 4 * bi + a, j = 4 * bj + b;
-          if (i < nr && j < w) pan[i * kPS + j] = acc[a][b];
-        }
+  for (int jj = 0; jj < w; ++jj) {
+    if (t == 0) {
+      const double d = pan[jj * kPS + jj];
+      const double ref = G[int64_t(c0 + jj) * K + c0 + jj];
+      int kp = (ref > 0.0 && d > tau * tau * ref) ? 1 : 0;
+      if (force_keep && !force_keep[c0 + jj]) kp = 0;
+      keep[c0 + jj] = kp;
+      s_keep = kp;
+      pan[jj * kPS + jj] = kp ? sqrt(d) : 0.0;
     }
     __syncthreads();
-    for (int jj = 0; jj < w; ++jj) {
-      if (t == 0) {
-        const double d = pan[jj * kPS + jj];
-        const double ref = G[int64_t(c0 + jj) * K + c0 + jj];
-        int kp = (ref > 0.0 && d > tau * tau * ref) ? 1 : 0;
-        if (force_keep && !force_keep[c0 + jj]) kp = 0;
-        keep[c0 + jj] = kp;
-        s_keep = kp;
-        pan[jj * kPS + jj] = kp ? sqrt(d) : 0.0;
-      }
-      __syncthreads();
-      const int kp = s_keep;
-      const double piv = pan[jj * kPS + jj];
-      for (int i = jj + 1 + t; i < nr; i += 1024)
-        pan[i * kPS + jj] = kp ? pan[i * kPS + jj] / piv : 0.0;
-      __syncthreads();
-      if (kp) {
-        const int wc = w - jj - 1;
-        if (wc > 0) {
-          for (int e = t; e < (nr - jj - 1) * wc; e += 1024) {
-            const int i = jj + 1 + e / wc, q = jj + 1 + e % wc;
-            if (q <= i) pan[i * kPS + q] -= pan[i * kPS + jj] * pan[q * kPS + jj];
-          }
+    const int kp = s_keep;
+    const double piv = pan[jj * kPS + jj];
+    for (int i = jj + 1 + t; i < nr; i += 1024)
+      pan[i * kPS + jj] = kp ? pan[i * kPS + jj] / piv : 0.0;
+    __syncthreads();
+    if (kp) {
+      const int wc = w - jj - 1;
+      if (wc > 0) {
+        for (int e = t; e < (nr - jj - 1) * wc; e += 1024) {
+          const int i = jj + 1 + e / wc, q = jj + 1 + e % wc;
+          if (q <= i) pan[i * kPS + q] -= pan[i * kPS + jj] * pan[q * kPS + jj];
         }
       }
-      __syncthreads();
-    }
-    for (int e = t; e < nr * w; e += 1024) {
-      const int i = e / w, j = e % w;
-      if (i >= j) LT[int64_t(c0 + j) * K + c0 + i] = pan[i * kPS + j];
     }
     __syncthreads();
+  }
+  for (int e = t; e < nr * w; e += 1024) {
+    const int i = e / w, j = e % w;
+    if (i >= j) LT[int64_t(c0 + j) * K + c0 + i] = pan[i * kPS + j];
+  }
+}
+
+// A[i][q] -= sum_{l in [c0, c0+w)} L[i][l] L[q][l] for c0+w <= q <= i < K:
+// one workgroup per 32 x 32 tile of the trailing lower triangle.
+__global__ void __launch_bounds__(256)
+k_chol_update(double *__restrict__ A, const double *__restrict__ LT, int K, int c0, int w) {
+  __shared__ double Li[kPW][kPS];
+  __shared__ double Lq[kPW][kPS];
+  const int r0 = c0 + w;
+  int tile = blockIdx.x, ti = 0;
+  while (tile > ti) { tile -= ti + 1; ++ti; }
+  const int tj = tile;
+  const int i0 = r0 + kPW * ti, q0 = r0 + kPW * tj;
+  const int t = threadIdx.x;
+  for (int e = t; e < kPW * w; e += 256) {
+    const int l = e / kPW, a = e % kPW;
+    Li[a][l] = i0 + a < K ? LT[int64_t(c0 + l) * K + i0 + a] : 0.0;
+    Lq[a][l] = q0 + a < K ? LT[int64_t(c0 + l) * K + q0 + a] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = t + 256 * u;
+    const int a = e / kPW, b = e % kPW;
+    const int i = i0 + a, q = q0 + b;
+    if (i < K && q <= i) {
+      double acc = A[int64_t(i) * K + q];
+      for (int l = 0; l < w; ++l) acc -= Li[a][l] * Lq[b][l];
+      A[int64_t(i) * K + q] = acc;
+    }
   }
 }
 
@@ -129,6 +129,7 @@ k_jtrinv(const double *__restrict__ LT, const int32_t *__restrict__ keep, int K,
          double *__restrict__ Rinv, float *__restrict__ Rinv32) {
   extern __shared__ double X[];  // [K][kPS]: rows of the column block J
   __shared__ double T[kPW * kPS];
+  __shared__ double Lb[kPW * kPS];
   const int t = threadIdx.x;
   const int J = blockIdx.x;
   const int j0 = J * kPW;
@@ -139,12 +140,21 @@ k_jtrinv(const double *__restrict__ LT, const int32_t *__restrict__ keep, int K,
   for (int I = J; I < nb; ++I) {
     const int i0 = I * kPW;
     const int wi = K - i0 < kPW ? K - i0 : kPW;
-    // T = -sum_{m in [j0, i0)} L[i0+i][m] X[m][j]   (zero for I == J)
+    // T = -sum_{m in [j0, i0)} L[i0+i][m] X[m][j]   (zero for I == J), the
+    // rows of L staged in LDS one 32 x 32 block at a time
     {
       const int i = t / kPW, j = t % kPW;
       double acc = (I == J && i == j) ? 1.0 : 0.0;
-      if (i < wi && j < wj) {
-        for (int m = j0; m < i0; ++m) acc -= LT[int64_t(m) * K + i0 + i] * X[m * kPS + j];
+      for (int M0 = j0; M0 < i0; M0 += kPW) {
+        __syncthreads();
+        {
+          const int mm = t / kPW, ii = t % kPW;
+          Lb[ii * kPS + mm] = ii < wi ? LT[int64_t(M0 + mm) * K + i0 + ii] : 0.0;
+        }
+        __syncthreads();
+        if (i < wi && j < wj) {
+          for (int mm = 0; mm < kPW; ++mm) acc -= Lb[i * kPS + mm] * X[(M0 + mm) * kPS + j];
+        }
       }
       T[i * kPS + j] = acc;
     }
@@ -815,6 +825,7 @@ size_t orth_ws_bytes(int64_t n, int K) {
   Arena a;
   a.take<double>(int64_t(K) * K);    // G
   a.take<double>(int64_t(K) * K);    // LT
+  a.take<double>(int64_t(K) * K);    // trailing matrix of the Cholesky
   a.take<double>(int64_t(Kp) * Kp);  // Rinv
   a.take<float>(int64_t(Kp) * Kp);   // Rinv32
   a.take<uint16_t>(int64_t(Kp) * Kp);  // RhT
@@ -862,6 +873,7 @@ hef_status orthonormalize_pool(void *P, void *out, int pool_type, int64_t n, int
   const size_t mk = ws.mark();
   double *G = ws.take<double>(int64_t(K) * K);
   double *LT = ws.take<double>(int64_t(K) * K);
+  double *A = ws.take<double>(int64_t(K) * K);
   double *Rinv = ws.take<double>(int64_t(Kp) * Kp);
   float *Rinv32 = ws.take<float>(int64_t(Kp) * Kp);
   uint16_t *RhT = ws.take<uint16_t>(int64_t(Kp) * Kp);
@@ -878,13 +890,21 @@ hef_status orthonormalize_pool(void *P, void *out, int pool_type, int64_t n, int
     {
       TimedScope ts(kStOrthChol, s);
       const size_t lds_c = size_t(K) * kPS * sizeof(double);
-      HEF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_jchol),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_c)));
       HEF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_jtrinv),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_c)));
       HEF_HIP(hipMemsetAsync(Rinv, 0, sizeof(double) * Kp * Kp, s));
       HEF_HIP(hipMemsetAsync(Rinv32, 0, sizeof(float) * Kp * Kp, s));
-      k_jchol<<<1, 1024, lds_c, s>>>(G, K, tau, LT, keep, pass == 0 ? nullptr : keep);
+      HEF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_chol_panel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_c)));
+      HEF_HIP(hipMemcpyAsync(A, G, sizeof(double) * K * K, hipMemcpyDeviceToDevice, s));
+      HEF_HIP(hipMemsetAsync(LT, 0, sizeof(double) * K * K, s));
+      for (int c0 = 0; c0 < K; c0 += kPW) {
+        const int w = K - c0 < kPW ? K - c0 : kPW;
+        k_chol_panel<<<1, 1024, size_t(K - c0) * kPS * sizeof(double), s>>>(
+            A, G, K, c0, tau, LT, keep, pass == 0 ? nullptr : keep);
+        const int nt = (K - c0 - w + kPW - 1) / kPW;
+        if (nt > 0) k_chol_update<<<nt * (nt + 1) / 2, 256, 0, s>>>(A, LT, K, c0, w);
+      }
       k_jtrinv<<<(K + kPW - 1) / kPW, 1024, lds_c, s>>>(LT, keep, K, Kp, Rinv, Rinv32);
       HEF_LAUNCH_CHECK();
     }
