@@ -244,28 +244,71 @@ __device__ __forceinline__ float lb16_8(const uint4 v, const float *xs, const fl
   return lo;
 }
 
+// lower and upper bounds (running maxima lo, up) of the terms of the 8
+// float16 values of v against xs/is[q0 .. q0+8): |x - c| lies within
+// |x - h| -/+ (2^-10 |h| + 2^-24)
+__device__ __forceinline__ void bounds16_8(const uint4 v, const float *xs, const float *is,
+                                           int q0, float &lo, float &up) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const uint32_t bits = (w[u >> 1] >> (16 * (u & 1))) & 0xFFFFu;
+    const float h = float(__builtin_bit_cast(_Float16, uint16_t(bits)));
+    const float d = fabsf(xs[q0 + u] - h);
+    const float e = 0x1p-10f * fabsf(h) + 0x1p-24f;
+    float dv = d - e;
+    dv = dv > 0.0f ? dv : 0.0f;
+    const float du = d + e;
+    lo = fmaxf(lo, dv * dv * is[q0 + u]);
+    up = fmaxf(up, du * du * is[q0 + u]);
+  }
+}
+
 // Exact float64 distance d(p, C) = max_i (chi_p^(i) - c_C^(i))^2 / Q_H(i)
-// (Eqs. (13), (14) applied to a node and a centroid), no FMA; full wave.
+// (Eqs. (13), (14) applied to a node and a centroid), no FMA; full wave.  xn
+// is p's row and qd is Q_H (both in column order, zero from K on; at most
+// 512 columns); cr = crow[C].  A lane's eight centroid values are loaded
+// together, ahead of any use.
 template <int PT>
-__device__ __forceinline__ double exact_d(int64_t p, int32_t C, int lane, const int32_t *crow,
-                                          const double *cent, const void *pool, int K,
-                                          const double *qh) {
+__device__ __forceinline__ double exact_d(int32_t C, int32_t cr, int lane, const double *cent,
+                                          const void *pool, int K, const float *xn,
+                                          const double *qd) {
   constexpr int MAXC = 8;
-  const int64_t cr = crow[C];
+  // unconditional loads of in-row columns (col clamped to K - 1; qd is zero
+  // from K on, so those lanes' values are never used)
+  int cl[MAXC];
+#pragma unroll
+  for (int q = 0; q < MAXC; ++q) cl[q] = lane + 64 * q < K ? lane + 64 * q : K - 1;
+  double c[MAXC];
+  if (cr < 0 && PT == kPoolF32) {
+    const float *row = reinterpret_cast<const float *>(pool) + int64_t(C) * K;
+    float t[MAXC];
+#pragma unroll
+    for (int q = 0; q < MAXC; ++q) t[q] = row[cl[q]];
+#pragma unroll
+    for (int q = 0; q < MAXC; ++q) c[q] = double(t[q]);
+  } else if (cr < 0) {
+    const uint16_t *row = reinterpret_cast<const uint16_t *>(pool) + int64_t(C) * K;
+    uint32_t t[MAXC];
+#pragma unroll
+    for (int q = 0; q < MAXC; ++q) t[q] = row[cl[q]];
+#pragma unroll
+    for (int q = 0; q < MAXC; ++q) c[q] = double(__uint_as_float(t[q] << 16));
+  } else {
+    const double *row = cent + int64_t(cr) * K;
+#pragma unroll
+    for (int q = 0; q < MAXC; ++q) c[q] = row[cl[q]];
+  }
   double dl = 0.0;
 #pragma unroll
   for (int q = 0; q < MAXC; ++q) {
     const int col = lane + 64 * q;
-    if (col < K) {
-      const double qv = qh[col];
-      if (qv > 0.0) {
-        const double x = pool_val<PT>(pool, p * K + col);
-        const double c = cr < 0 ? pool_val<PT>(pool, int64_t(C) * K + col) : cent[cr * K + col];
-        const double diff = x - c;
-        const double sq = diff * diff;
-        const double r = sq / qv;
-        dl = r > dl ? r : dl;
-      }
+    const double qv = qd[col];
+    if (qv > 0.0) {
+      const double diff = double(xn[col]) - c[q];
+      const double sq = diff * diff;
+      const double r = sq / qv;
+      dl = r > dl ? r : dl;
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
@@ -277,19 +320,22 @@ __device__ __forceinline__ double exact_d(int64_t p, int32_t C, int lane, const 
 
 // One wave per isolated node p; its candidates are the clusters C = prov[v]
 // of the co-pins v of its hyperedges, and best(p) = (smallest exact float64
-// d(p, C), smallest label).  The wave filters the candidates with float32
-// lower bounds computed from float16 copies of the centroids in the
-// permuted column order (largest weights first):
-//   stage A  one lane per candidate, 128 columns;
-//   stage B  8 lanes per candidate, all columns;
-// and evaluates the exact distance of the candidates the bounds leave.  A
-// lower bound exceeds the exact value by at most a relative 1e-6, so a
-// candidate whose bound is above the best exact distance found times
-// (1 + 1e-5) can neither be the minimum nor tie with it.  Hyperedges of at
-// most kSeedSeg pins are visited first, and the first candidate batch seeds
-// the search with the exact distance of its smallest stage-A bound.  The
-// result is the exact argmin whatever the visiting order.
+// d(p, C), smallest label).  The wave bounds d(p, C) from float16 copies of
+// the centroids, columns in the permuted order (largest weights first):
+//   stage A  one lane per candidate: a lower bound over the first 128 columns;
+//   stage B  8 lanes per candidate: lower and upper bounds over all columns.
+// u is the smallest upper bound (or exact distance) met so far.  A candidate
+// whose lower bound exceeds u (1 + 1e-5) is farther than some other
+// candidate, so it is neither the minimum nor tied with it, and is dropped.
+// The survivors of stage B get their exact distance in ascending order of
+// their lower bound, until the smallest remaining lower bound exceeds u.
+// Float32 bounds stay within a relative 1e-6 of what they bound (upper
+// bounds are scaled by 1 + 1e-5 before use), so the result is the exact
+// argmin whatever the visiting order.  The first candidate batch seeds u
+// with stage B of its smallest stage-A bound; hyperedges of at most
+// kSeedSeg pins are visited first.
 constexpr int kQCap = 72;   // stage-B queue: 8 + one batch of 64
+constexpr int kFCap = 64;   // stage-B survivors awaiting their exact distance
 constexpr int kEB = 64;     // hyperedges of p per batch
 constexpr int kAq = 128;    // stage-A columns
 
@@ -304,16 +350,28 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
        const double *__restrict__ qh, int32_t n, int32_t *__restrict__ best_label,
        double *__restrict__ best_d) {
   constexpr int NW = kT / 64;
-  __shared__ float xs_all[NW][512];
-  __shared__ float is_all[NW][512];
+  __shared__ float is[512];                // float32 1 / Q_H, permuted order
+  __shared__ double qd[512];               // Q_H, column order
+  __shared__ int32_t pm[512];              // the permutation
+  __shared__ float xs_all[NW][512];        // p's row, permuted order
+  __shared__ float xn_all[NW][512];        // p's row, column order
   __shared__ int32_t es_all[NW][kEB];      // first pin position per hyperedge (batch order)
   __shared__ int32_t ep_all[NW][kEB + 1];  // exclusive prefix of sizes
-  __shared__ int32_t qc_all[NW][kQCap];
+  __shared__ int32_t qc_all[NW][kQCap];    // stage-B queue: candidate, stage-A bound
   __shared__ float ql_all[NW][kQCap];
+  __shared__ int32_t fc_all[NW][kFCap];    // survivors: candidate, crow, stage-B bound
+  __shared__ int32_t fr_all[NW][kFCap];
+  __shared__ float fl_all[NW][kFCap];
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int g = lane >> 3, a8 = lane & 7;
   const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
+  for (int q = threadIdx.x; q < 512; q += kT) {
+    is[q] = inv32[q];
+    qd[q] = q < K ? qh[q] : 0.0;
+    pm[q] = perm[q];
+  }
+  __syncthreads();
   const int64_t p = int64_t(blockIdx.x) * NW + w;
   if (p >= n) return;
   const int32_t v0 = vptr[p], deg = vptr[p + 1] - v0;
@@ -323,35 +381,80 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
   }
   constexpr float kMargin = 1.0f + 1e-5f;
   constexpr float kUbScale = 1.0f + 2e-6f;
+  constexpr float kUpScale = 1.0f + 1e-5f;
   float *xs = xs_all[w];
-  float *is = is_all[w];
+  float *xn = xn_all[w];
   int32_t *es = es_all[w];
   int32_t *ep = ep_all[w];
   int32_t *qc = qc_all[w];
   float *ql = ql_all[w];
-  for (int q = lane; q < Kq; q += 64) {
-    xs[q] = float(pool_val<PT>(pool, p * K + perm[q]));
-    is[q] = inv32[q];
+  int32_t *fc = fc_all[w];
+  int32_t *fr = fr_all[w];
+  float *fl = fl_all[w];
+  {
+    // p's row: unconditional loads (column clamped to K - 1), then selects
+    float t[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int q = lane + 64 * j;
+      t[j] = float(pool_val<PT>(pool, p * K + (q < K ? q : K - 1)));
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) xn[lane + 64 * j] = lane + 64 * j < K ? t[j] : 0.0f;
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int q = lane + 64 * j;
+      xs[q] = q < Kq ? xn[pm[q]] : 0.0f;
+    }
   }
   const int ka = Kq < kAq ? Kq : kAq;  // stage-A width (a multiple of 64)
   wave_sync();
 
   double bd = DBL_MAX;           // best exact distance (wave-uniform)
   int32_t bl = INT32_MAX;
-  float ub = FLT_MAX;            // float32 upper bound of bd
-  int nq = 0;                    // queue fill (wave-uniform)
-  auto consider = [&](int32_t C) {
-    const double dl = exact_d<PT>(p, C, lane, crow, cent, pool, K, qh);
+  float ub = FLT_MAX;            // u: float32 upper bound of the minimum
+  int nq = 0, nf = 0;            // queue and survivor fills (wave-uniform)
+  auto exact = [&](int32_t C, int32_t cr) {
+    const double dl = exact_d<PT>(C, cr, lane, cent, pool, K, xn, qd);
     if (dl < bd || (dl == bd && C < bl)) {
       bd = dl;
       bl = C;
-      ub = fminf(ub, float(bd) * kUbScale * kUbScale);
+    }
+    ub = fminf(ub, float(dl) * kUbScale * kUbScale);
+  };
+  // exact distances of the survivors, smallest lower bound first
+  auto resolve = [&]() {
+    while (nf > 0) {
+      float l = lane < nf ? fl[lane] : FLT_MAX;
+      int i = lane;
+      for (int off = 1; off < 64; off <<= 1) {
+        const float ol = __shfl_xor(l, off, 64);
+        const int oi = __shfl_xor(i, off, 64);
+        if (ol < l || (ol == l && oi < i)) {
+          l = ol;
+          i = oi;
+        }
+      }
+      if (l > ub * kMargin) {
+        nf = 0;
+        break;
+      }
+      const int32_t C = fc[i], cr = fr[i];
+      wave_sync();
+      if (lane == 0) {
+        fc[i] = fc[nf - 1];
+        fr[i] = fr[nf - 1];
+        fl[i] = fl[nf - 1];
+      }
+      --nf;
+      wave_sync();
+      if (C != bl) exact(C, cr);
     }
   };
-  // stage B for up to 8 queued candidates (taken from the queue's end), then
-  // the exact distance of those it leaves
-  auto batch = [&](int cnt) {
-    int32_t C = -1;
+  // stage B for the last cnt (<= 8) queue entries; survivors join the list
+  auto stage_b = [&](int cnt) {
+    int32_t C = -1, cr = -1;
     float lo = FLT_MAX;
     if (g < cnt) {
       C = qc[nq - cnt + g];
@@ -359,19 +462,55 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
     }
     nq -= cnt;
     wave_sync();
-    const bool live = C >= 0 && !(lo > ub * kMargin);
+    const bool live = C >= 0 && C != bl && !(lo > ub * kMargin);
+    float up = 0.0f;
     if (live) {
-      const _Float16 *row = cperm + int64_t(C) * Kq;
-      for (int q0 = 8 * a8; q0 < Kq; q0 += 64)
-        lo = fmaxf(lo, lb16_8(*reinterpret_cast<const uint4 *>(row + q0), xs, is, q0));
+      // lane a8 of the group takes columns 8 a8 + 64 it (Kq <= 512)
+      cr = crow[C];
+      const uint4 *row = reinterpret_cast<const uint4 *>(cperm + int64_t(C) * Kq);
+      uint4 v[8];
+#pragma unroll
+      for (int it = 0; it < 8; ++it)
+        v[it] = 8 * a8 + 64 * it < Kq ? row[a8 + 8 * it] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+      for (int it = 0; it < 8; ++it)
+        if (8 * a8 + 64 * it < Kq) bounds16_8(v[it], xs, is, 8 * a8 + 64 * it, lo, up);
     }
-    for (int off = 4; off > 0; off >>= 1) lo = fmaxf(lo, __shfl_xor(lo, off, 8));
-    for (int t = 0; t < cnt; ++t) {
-      const int32_t Ct = __shfl(C, 8 * t, 64);
-      const float lt = __shfl(lo, 8 * t, 64);
-      if (Ct < 0 || Ct == bl || lt > ub * kMargin) continue;
-      consider(Ct);
+    for (int off = 4; off > 0; off >>= 1) {
+      lo = fmaxf(lo, __shfl_xor(lo, off, 8));
+      up = fmaxf(up, __shfl_xor(up, off, 8));
     }
+    float um = live ? up * kUpScale : FLT_MAX;
+    for (int off = 8; off < 64; off <<= 1) um = fminf(um, __shfl_xor(um, off, 64));
+    ub = fminf(ub, um);
+    const bool keep = live && a8 == 0 && !(lo > ub * kMargin);
+    const uint64_t m = __ballot(keep);
+    const int nk = __popcll(m);
+    if (nf + nk > kFCap) {
+      // drop the survivors u now excludes, then resolve if still full
+      const bool k2 = lane < nf && !(fl[lane] > ub * kMargin);
+      const int32_t c2 = k2 ? fc[lane] : 0, r2 = k2 ? fr[lane] : 0;
+      const float l2 = k2 ? fl[lane] : 0.0f;
+      const uint64_t m2 = __ballot(k2);
+      wave_sync();
+      if (k2) {
+        const int at = __popcll(m2 & lt_mask);
+        fc[at] = c2;
+        fr[at] = r2;
+        fl[at] = l2;
+      }
+      nf = __popcll(m2);
+      wave_sync();
+      if (nf + nk > kFCap) resolve();
+    }
+    if (keep) {
+      const int at = nf + __popcll(m & lt_mask);
+      fc[at] = C;
+      fr[at] = cr;
+      fl[at] = lo;
+    }
+    nf += nk;
+    wave_sync();
   };
 
   for (int32_t e0 = 0; e0 < deg; e0 += kEB) {
@@ -417,13 +556,20 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
         if (v != p) C = prov[v];
       }
       if (C >= 0) {
+        // 64 columns (one 128-byte line) per round, loads ahead of use
         lo = 0.0f;
-        const _Float16 *row = cperm + int64_t(C) * Kq;
-        for (int q0 = 0; q0 < ka; q0 += 8)
-          lo = fmaxf(lo, lb16_8(*reinterpret_cast<const uint4 *>(row + q0), xs, is, q0));
+        const uint4 *row = reinterpret_cast<const uint4 *>(cperm + int64_t(C) * Kq);
+        for (int q0 = 0; q0 < ka; q0 += 64) {
+          uint4 v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = row[q0 / 8 + u];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) lo = fmaxf(lo, lb16_8(v[u], xs, is, q0 + 8 * u));
+        }
       }
-      if (bl == INT32_MAX) {
-        // seed: the candidate with the smallest (bound, label) of this batch
+      int32_t seed = -1;
+      if (ub == FLT_MAX) {
+        // seed u: stage B of the smallest (bound, label) of this batch
         float sl = lo;
         int32_t sc = C >= 0 ? C : INT32_MAX;
         for (int off = 1; off < 64; off <<= 1) {
@@ -434,9 +580,18 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
             sc = oc;
           }
         }
-        if (sc != INT32_MAX) consider(sc);
+        if (sc != INT32_MAX) {
+          if (lane == 0) {
+            qc[nq] = sc;
+            ql[nq] = sl;
+          }
+          ++nq;
+          wave_sync();
+          stage_b(1);
+          seed = sc;
+        }
       }
-      const bool ok = C >= 0 && C != bl && !(lo > ub * kMargin);
+      const bool ok = C >= 0 && C != bl && C != seed && !(lo > ub * kMargin);
       const uint64_t m = __ballot(ok);
       if (ok) {
         const int at2 = nq + __popcll(m & lt_mask);
@@ -445,11 +600,12 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
       }
       nq += __popcll(m);
       wave_sync();
-      while (nq >= 8) batch(8);
+      while (nq >= 8) stage_b(8);
     }
     wave_sync();
   }
-  if (nq > 0) batch(nq);
+  if (nq > 0) stage_b(nq);
+  resolve();
   if (lane == 0) {
     best_label[p] = bl == INT32_MAX ? -1 : bl;
     best_d[p] = bd;
