@@ -57,19 +57,27 @@ __device__ __forceinline__ void load_cols(const void *pool, int64_t p, int K, in
   }
 }
 
+// Spread of hyperedge [a, b) of pins over this lane's columns.  Pins go in
+// chunks of 4 (ids first, then rows, so the loads overlap); a chunk past the
+// end repeats the last pin, which leaves max and min unchanged.
 template <int CPL, int PT>
-__device__ __forceinline__ void edge_spread(const int32_t *__restrict__ eptr,
-                                            const int32_t *__restrict__ pins, const void *pool,
-                                            int K, int c0, int64_t e, double (&s)[CPL]) {
+__device__ __forceinline__ void edge_spread(const int32_t *__restrict__ pins, const void *pool,
+                                            int K, int c0, int32_t a, int32_t b,
+                                            double (&s)[CPL]) {
   float mx[CPL], mn[CPL];
 #pragma unroll
   for (int q = 0; q < CPL; ++q) { mx[q] = -FLT_MAX; mn[q] = FLT_MAX; }
-  const int32_t a = eptr[e], b = eptr[e + 1];
-  for (int32_t j = a; j < b; ++j) {
-    float v[CPL];
-    load_cols<CPL, PT>(pool, pins[j], K, c0, v);
+  for (int32_t j0 = a; j0 < b; j0 += 4) {
+    int32_t pp[4];
 #pragma unroll
-    for (int q = 0; q < CPL; ++q) { mx[q] = fmaxf(mx[q], v[q]); mn[q] = fminf(mn[q], v[q]); }
+    for (int u = 0; u < 4; ++u) pp[u] = pins[j0 + u < b ? j0 + u : b - 1];
+    float v[4][CPL];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) load_cols<CPL, PT>(pool, pp[u], K, c0, v[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) { mx[q] = fmaxf(mx[q], v[u][q]); mn[q] = fminf(mn[q], v[u][q]); }
   }
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
@@ -78,6 +86,9 @@ __device__ __forceinline__ void edge_spread(const int32_t *__restrict__ eptr,
   }
 }
 
+// A workgroup takes kEdgesPerBlk = kThreads consecutive hyperedges; group
+// grp (LPR lanes) takes e0 + grp + ngrp k for k < LPR, and lane k of the
+// group fetches that hyperedge's pin range up front.
 template <int CPL, int PT>
 __global__ void __launch_bounds__(kThreads)
 k_score_qh(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
@@ -87,18 +98,30 @@ k_score_qh(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
   const int tid = threadIdx.x;
   const int ngrp = kThreads / LPR;
   const int grp = tid / LPR;
-  const int c0 = (tid % LPR) * CPL;
+  const int sub = tid % LPR;
+  const int c0 = sub * CPL;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t e0 = blk * kEdgesPerBlk;
   const int64_t e1 = e0 + kEdgesPerBlk < m ? e0 + kEdgesPerBlk : m;
+  int32_t ea = 0, eb = 0;
+  float ew = 0.0f;
+  {
+    const int64_t e = e0 + grp + int64_t(ngrp) * sub;
+    if (e < e1) {
+      ea = eptr[e];
+      eb = eptr[e + 1];
+      ew = w ? w[e] : 1.0f;
+    }
+  }
   double acc[CPL];
 #pragma unroll
   for (int q = 0; q < CPL; ++q) acc[q] = 0.0;
-  if (c0 < K) {
-    for (int64_t e = e0 + grp; e < e1; e += ngrp) {
+  for (int k = 0; k < LPR && e0 + grp + int64_t(ngrp) * k < e1; ++k) {
+    const int32_t a = __shfl(ea, k, LPR), b = __shfl(eb, k, LPR);
+    const double we = double(__shfl(ew, k, LPR));
+    if (c0 < K) {
       double s[CPL];
-      edge_spread<CPL, PT>(eptr, pins, pool, K, c0, e, s);
-      const double we = w ? double(w[e]) : 1.0;
+      edge_spread<CPL, PT>(pins, pool, K, c0, a, b, s);
 #pragma unroll
       for (int q = 0; q < CPL; ++q) acc[q] = fma(we, s[q], acc[q]);
     }
@@ -122,7 +145,8 @@ k_score_r(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
   const int tid = threadIdx.x;
   const int ngrp = kThreads / LPR;
   const int grp = tid / LPR;
-  const int c0 = (tid % LPR) * CPL;
+  const int sub = tid % LPR;
+  const int c0 = sub * CPL;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t e0 = blk * kEdgesPerBlk;
   const int64_t e1 = e0 + kEdgesPerBlk < m ? e0 + kEdgesPerBlk : m;
@@ -132,16 +156,26 @@ k_score_r(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
     const double qv = (c0 + q < K) ? qh[c0 + q] : 0.0;
     inv[q] = qv > 0.0 ? 1.0 / qv : 0.0;
   }
-  for (int64_t e = e0 + grp; e < e1; e += ngrp) {
+  int32_t ea = 0, eb = 0;
+  {
+    const int64_t e = e0 + grp + int64_t(ngrp) * sub;
+    if (e < e1) {
+      ea = eptr[e];
+      eb = eptr[e + 1];
+    }
+  }
+  for (int k = 0; k < LPR && e0 + grp + int64_t(ngrp) * k < e1; ++k) {
+    const int64_t e = e0 + grp + int64_t(ngrp) * k;
+    const int32_t a = __shfl(ea, k, LPR), b = __shfl(eb, k, LPR);
     double best = 0.0;
     if (c0 < K) {
       double s[CPL];
-      edge_spread<CPL, PT>(eptr, pins, pool, K, c0, e, s);
+      edge_spread<CPL, PT>(pins, pool, K, c0, a, b, s);
 #pragma unroll
       for (int q = 0; q < CPL; ++q) best = fmax(best, s[q] * inv[q]);
     }
     for (int off = LPR / 2; off > 0; off >>= 1) best = fmax(best, __shfl_xor(best, off, LPR));
-    if (tid % LPR == 0) R[e] = float(best);
+    if (sub == 0) R[e] = float(best);
   }
 }
 
