@@ -160,60 +160,91 @@ __global__ void k_lgram_sym(double *__restrict__ G, int C, int S) {
 }
 
 // Cholesky of G with column dropping, then the Y-block columns of R^-1.
-// One 64-thread workgroup per expansion.  Column c is dropped when its
-// reference length is 0 or its Schur pivot d_c <= tau^2 * G_cc.
+// One wave per expansion; lane t holds row t of the C x C Gram (registers),
+// so the factorisation needs no barriers: column k's pivot and the entries
+// L_jk come from lane shuffles.  Column c is dropped when its reference
+// length is 0 or its Schur pivot d_c <= tau^2 * G_cc.  L goes to LDS; lane c
+// then forms column c of R^-1 = L^-T by back substitution.
+template <int C>
 __global__ void __launch_bounds__(64)
-k_lsolve(const double *__restrict__ Gall, int C, int B, double tau,
-         double *__restrict__ Tall, int32_t *__restrict__ drops,
-         double *__restrict__ Rall) {
-  __shared__ double A[48 * 48];
-  __shared__ double Lm[48 * 48];
-  __shared__ int keep[48];
+k_lsolve(const double *__restrict__ Gall, int B, double tau, double *__restrict__ Tall,
+         int32_t *__restrict__ drops, double *__restrict__ Rall) {
+  __shared__ double Ls[C * C];
   const double *G = Gall + blockIdx.x * C * C;
   double *T = Tall + blockIdx.x * C * B;
   const int t = threadIdx.x;
-  for (int e = t; e < C * C; e += 64) { A[e] = G[e]; Lm[e] = 0.0; }
-  __syncthreads();
-  for (int k = 0; k < C; ++k) {
-    if (t == 0) {
-      const double d = A[k * C + k];
-      const double ref = G[k * C + k];
-      keep[k] = (ref > 0.0 && d > tau * tau * ref) ? 1 : 0;
-      if (keep[k]) Lm[k * C + k] = sqrt(d);
-    }
-    __syncthreads();
-    if (keep[k] && t > k && t < C) Lm[t * C + k] = A[t * C + k] / Lm[k * C + k];
-    __syncthreads();
-    if (keep[k] && t > k && t < C) {
-      const double lik = Lm[t * C + k];
-      for (int j = k + 1; j <= t; ++j) A[t * C + j] -= lik * Lm[j * C + k];
-    }
-    __syncthreads();
+  double a[C], l[C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    a[j] = t < C ? G[t * C + j] : 0.0;
+    l[j] = 0.0;
   }
-  // column c of R^-1 (R = L^T): L^T x = e_c by back substitution, one
-  // thread per column, the vectors in LDS
-  __shared__ double X[48 * 49];
-  if (t < C) {
-    const int c = t;
-    for (int i = 0; i < C; ++i) X[i * 49 + c] = 0.0;
-    if (keep[c]) {
-      X[c * 49 + c] = 1.0 / Lm[c * C + c];
-      for (int i = c - 1; i >= 0; --i) {
-        if (!keep[i]) continue;
-        double acc = 0.0;
-        for (int l = i + 1; l <= c; ++l) acc += Lm[l * C + i] * X[l * 49 + c];
-        X[i * 49 + c] = -acc / Lm[i * C + i];
+  double gref = 0.0;
+#pragma unroll
+  for (int j = 0; j < C; ++j)
+    if (j == t) gref = a[j];
+  uint64_t keep = 0;
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    const double d = __shfl(a[k], k, 64);
+    const double ref = __shfl(gref, k, 64);
+    if (ref > 0.0 && d > tau * tau * ref) {
+      keep |= uint64_t(1) << k;
+      const double lkk = sqrt(d);
+      const double lk = t == k ? lkk : (t > k ? a[k] / lkk : 0.0);
+      l[k] = lk;
+#pragma unroll
+      for (int j = k + 1; j < C; ++j) {
+        const double ljk = __shfl(lk, j, 64);
+        if (j <= t) a[j] -= lk * ljk;
       }
     }
   }
-  __syncthreads();
-  for (int e = t; e < C * B; e += 64) T[e] = X[(e / B) * 49 + 2 * B + e % B];
-  if (t < B && !keep[2 * B + t]) atomicAdd(&drops[blockIdx.x], 1);
-  // optionally the whole R^-1 (row-major C x C), zero rows/columns for drops
-  if (Rall) {
-    double *Rf = Rall + blockIdx.x * C * C;
-    for (int e = t; e < C * C; e += 64) Rf[e] = X[(e / C) * 49 + e % C];
+  if (t < C) {
+#pragma unroll
+    for (int j = 0; j < C; ++j) Ls[t * C + j] = l[j];
   }
+  __syncthreads();
+  // column c of R^-1 (R = L^T): L^T x = e_c, rows c, c-1, ..., 0
+  const int c = t;
+  const bool kc = c < C && ((keep >> c) & 1);
+  double x[C];
+#pragma unroll
+  for (int i = C - 1; i >= 0; --i) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = i + 1; q < C; ++q) acc += Ls[q * C + i] * x[q];
+    const bool ki = (keep >> i) & 1;
+    double xi = 0.0;
+    if (kc && ki) xi = i == c ? 1.0 / Ls[i * C + i] : (i < c ? -acc / Ls[i * C + i] : 0.0);
+    x[i] = xi;
+  }
+  if (c >= 2 * B && c < C) {
+#pragma unroll
+    for (int i = 0; i < C; ++i) T[i * B + (c - 2 * B)] = x[i];
+  }
+  if (t < B && !((keep >> (2 * B + t)) & 1)) atomicAdd(&drops[blockIdx.x], 1);
+  // optionally the whole R^-1 (row-major C x C), zero rows/columns for drops
+  if (Rall && c < C) {
+    double *Rf = Rall + blockIdx.x * C * C;
+#pragma unroll
+    for (int i = 0; i < C; ++i) Rf[i * C + c] = x[i];
+  }
+}
+
+// the solve for C = 3B columns (B in {1, 2, 4, 8, 16})
+hef_status lsolve_launch(const double *G, int B, double tau, double *T, int32_t *drops,
+                         double *R, hipStream_t s) {
+  switch (B) {
+    case 1: k_lsolve<3><<<2, 64, 0, s>>>(G, B, tau, T, drops, R); break;
+    case 2: k_lsolve<6><<<2, 64, 0, s>>>(G, B, tau, T, drops, R); break;
+    case 4: k_lsolve<12><<<2, 64, 0, s>>>(G, B, tau, T, drops, R); break;
+    case 8: k_lsolve<24><<<2, 64, 0, s>>>(G, B, tau, T, drops, R); break;
+    case 16: k_lsolve<48><<<2, 64, 0, s>>>(G, B, tau, T, drops, R); break;
+    default: return HEF_ERR_UNSUPPORTED;
+  }
+  HEF_LAUNCH_CHECK();
+  return HEF_OK;
 }
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -423,9 +454,7 @@ hef_status lanczos_gram(const float *v0, const float *v1, const float *y, int64_
 hef_status lanczos_solve(const double *G2, int B, double tau, double *T2, int32_t *drops,
                          double *R2, hipStream_t s) {
   TimedScope ts(kStLanczosSolve, s);
-  k_lsolve<<<2, 64, 0, s>>>(G2, 3 * B, B, tau, T2, drops, R2);
-  HEF_LAUNCH_CHECK();
-  return HEF_OK;
+  return lsolve_launch(G2, B, tau, T2, drops, R2, s);
 }
 
 hef_status lanczos_apply(int B, const float *v0, const float *v1, const float *y, const double *T,
@@ -518,9 +547,8 @@ hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double
   }
   {
     TimedScope ts(kStLanczosSolve, s);
-    k_lsolve<<<2, 64, 0, s>>>(G, C, B, tau, t_of(0), drops, r_of(0));
+    HEF_TRY(lsolve_launch(G, B, tau, t_of(0), drops, r_of(0), s));
   }
-  HEF_LAUNCH_CHECK();
   if (use_star) HEF_TRY(lapply(B, nullptr, nullptr, sb[iy], t_of(0), sb[in], Ns, nullptr, 0, 0, K, 0, s));
   if (use_clique) HEF_TRY(lapply(B, nullptr, nullptr, cb[iy], t_of(0) + C * B, cb[in], n, nullptr, 0, 0, K, 0, s));
   HEF_TRY(checkpoint(0, nullptr, sb[in], nullptr, cb[in]));
@@ -538,9 +566,8 @@ hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double
     double *Tj = t_of(j);
     {
       TimedScope ts(kStLanczosSolve, s);
-      k_lsolve<<<2, 64, 0, s>>>(G, C, B, tau, Tj, drops, r_of(j));
+      HEF_TRY(lsolve_launch(G, B, tau, Tj, drops, r_of(j), s));
     }
-    HEF_LAUNCH_CHECK();
     const int64_t col_s = (j - 1) * int64_t(B);
     const int64_t col_c = (use_star ? bk : 0) + (j - 1) * int64_t(B);
     if (use_star)
