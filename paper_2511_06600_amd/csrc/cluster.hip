@@ -220,47 +220,27 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Safe float32 lower bound of one column's term (x - c)^2 / Q_H from the
-// float16 copy h of c: |h - c| <= 2^-10 |h| + 2^-24 (float16 rounding of the
-// float32 rounding of c, subnormals included; |c| <= 1 for an orthonormal
-// basis).
-__device__ __forceinline__ float lb16_term(float x, float h, float iq) {
-  float dev = fabsf(x - h) - (0x1p-10f * fabsf(h) + 0x1p-24f);
-  dev = dev > 0.0f ? dev : 0.0f;
-  return dev * dev * iq;
-}
-
-// max over the 8 float16 values of v against xs/is[q0 .. q0+8)
-__device__ __forceinline__ float lb16_8(const uint4 v, const float *xs, const float *is, int q0) {
-  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-  float lo = 0.0f;
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const float h0 = float(__builtin_bit_cast(_Float16, uint16_t(w[u] & 0xFFFFu)));
-    const float h1 = float(__builtin_bit_cast(_Float16, uint16_t(w[u] >> 16)));
-    lo = fmaxf(lo, lb16_term(xs[q0 + 2 * u], h0, is[q0 + 2 * u]));
-    lo = fmaxf(lo, lb16_term(xs[q0 + 2 * u + 1], h1, is[q0 + 2 * u + 1]));
-  }
-  return lo;
-}
-
-// lower and upper bounds (running maxima lo, up) of the terms of the 8
-// float16 values of v against xs/is[q0 .. q0+8): |x - c| lies within
-// |x - h| -/+ (2^-10 |h| + 2^-24)
-__device__ __forceinline__ void bounds16_8(const uint4 v, const float *xs, const float *is,
-                                           int q0, float &lo, float &up) {
+// Bounds of one column's term (x - c)^2 / Q_H from the float16 copy h of c:
+// |h - c| <= 2^-10 |h| + 2^-24 (float16 rounding of the float32 rounding of
+// c, subnormals included; |c| <= 1 for an orthonormal basis; the factor
+// 2^-10 is twice the rounding bound, which leaves room for the float32
+// rounding below), so |x - c| sqrt(1 / Q_H) lies within
+// |x - h| sv -/+ (|h| e1 + e0) with sv = sqrt(1 / Q_H), e1 = 2^-10 sv,
+// e0 = 2^-24 sv.  The running maxima lo, up over the 8 float16 values of v
+// (columns q0 .. q0+8) are kept in this square-root scale; their squares
+// bound the term from below and above to within a relative 1e-6.
+__device__ __forceinline__ void bounds16_8(const uint4 v, const float *xs, const float *sv,
+                                           const float *e1, const float *e0, int q0, float &lo,
+                                           float &up) {
   const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     const uint32_t bits = (w[u >> 1] >> (16 * (u & 1))) & 0xFFFFu;
     const float h = float(__builtin_bit_cast(_Float16, uint16_t(bits)));
-    const float d = fabsf(xs[q0 + u] - h);
-    const float e = 0x1p-10f * fabsf(h) + 0x1p-24f;
-    float dv = d - e;
-    dv = dv > 0.0f ? dv : 0.0f;
-    const float du = d + e;
-    lo = fmaxf(lo, dv * dv * is[q0 + u]);
-    up = fmaxf(up, du * du * is[q0 + u]);
+    const float a = fabsf(xs[q0 + u] - h);
+    const float es = __builtin_fmaf(fabsf(h), e1[q0 + u], e0[q0 + u]);
+    lo = fmaxf(lo, __builtin_fmaf(a, sv[q0 + u], -es));
+    up = fmaxf(up, __builtin_fmaf(a, sv[q0 + u], es));
   }
 }
 
@@ -321,23 +301,29 @@ __device__ __forceinline__ double exact_d(int32_t C, int32_t cr, int lane, const
 // One wave per isolated node p; its candidates are the clusters C = prov[v]
 // of the co-pins v of its hyperedges, and best(p) = (smallest exact float64
 // d(p, C), smallest label).  The wave bounds d(p, C) from float16 copies of
-// the centroids, columns in the permuted order (largest weights first):
-//   stage A  one lane per candidate: a lower bound over the first 128 columns;
-//   stage B  8 lanes per candidate: lower and upper bounds over all columns.
-// u is the smallest upper bound (or exact distance) met so far.  A candidate
-// whose lower bound exceeds u (1 + 1e-5) is farther than some other
-// candidate, so it is neither the minimum nor tied with it, and is dropped.
-// The survivors of stage B get their exact distance in ascending order of
-// their lower bound, until the smallest remaining lower bound exceeds u.
-// Float32 bounds stay within a relative 1e-6 of what they bound (upper
-// bounds are scaled by 1 + 1e-5 before use), so the result is the exact
-// argmin whatever the visiting order.  The first candidate batch seeds u
-// with stage B of its smallest stage-A bound; hyperedges of at most
-// kSeedSeg pins are visited first.
+// the centroids, columns in the permuted order (largest weights first), in
+// stages over growing column ranges, each stage keeping running lower and
+// upper bounds:
+//   stage A  one lane per candidate, columns [0, 128);
+//   stage B  8 lanes per candidate, columns [128, 256);
+//   stage C  8 lanes per candidate, columns [256, Kq): the upper bound now
+//            covers every column.
+// u is the smallest complete upper bound (or exact distance) met so far.  A
+// candidate whose lower bound exceeds u (1 + 1e-5) is farther than some other
+// candidate, so it is neither the minimum nor tied with it, and is dropped
+// at any stage.  The survivors of stage C get their exact distance in
+// ascending order of their lower bound, until the smallest remaining lower
+// bound exceeds u.  Float32 bounds stay within a relative 1e-6 of what they
+// bound (upper bounds are scaled by 1 + 1e-5 before use), so the result is
+// the exact argmin whatever the visiting order.  The first candidate batch
+// seeds u with stages B and C of its smallest stage-A bound; hyperedges of
+// at most kSeedSeg pins are visited first.
 constexpr int kQCap = 72;   // stage-B queue: 8 + one batch of 64
-constexpr int kFCap = 64;   // stage-B survivors awaiting their exact distance
+constexpr int kQ2Cap = 16;  // stage-C queue: 8 + one stage-B batch
+constexpr int kFCap = 64;   // stage-C survivors awaiting their exact distance
 constexpr int kEB = 64;     // hyperedges of p per batch
 constexpr int kAq = 128;    // stage-A columns
+constexpr int kBq = 256;    // end of the stage-B columns
 
 template <int PT>
 __global__ void __launch_bounds__(kT)
@@ -350,16 +336,22 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
        const double *__restrict__ qh, int32_t n, int32_t *__restrict__ best_label,
        double *__restrict__ best_d) {
   constexpr int NW = kT / 64;
-  __shared__ float is[512];                // float32 1 / Q_H, permuted order
+  __shared__ float sv[512];                // sqrt(1 / Q_H), 2^-10 and 2^-24 times
+  __shared__ float s10[512];               // it, permuted order (zero for unused
+  __shared__ float s24[512];               // columns)
   __shared__ double qd[512];               // Q_H, column order
   __shared__ int32_t pm[512];              // the permutation
   __shared__ float xs_all[NW][512];        // p's row, permuted order
   __shared__ float xn_all[NW][512];        // p's row, column order
   __shared__ int32_t es_all[NW][kEB];      // first pin position per hyperedge (batch order)
   __shared__ int32_t ep_all[NW][kEB + 1];  // exclusive prefix of sizes
-  __shared__ int32_t qc_all[NW][kQCap];    // stage-B queue: candidate, stage-A bound
+  __shared__ int32_t qc_all[NW][kQCap];    // stage-B queue: candidate, bounds
   __shared__ float ql_all[NW][kQCap];
-  __shared__ int32_t fc_all[NW][kFCap];    // survivors: candidate, crow, stage-B bound
+  __shared__ float qu_all[NW][kQCap];
+  __shared__ int32_t rc_all[NW][kQ2Cap];   // stage-C queue: candidate, bounds
+  __shared__ float rl_all[NW][kQ2Cap];
+  __shared__ float ru_all[NW][kQ2Cap];
+  __shared__ int32_t fc_all[NW][kFCap];    // survivors: candidate, crow, lower bound
   __shared__ int32_t fr_all[NW][kFCap];
   __shared__ float fl_all[NW][kFCap];
   const int w = threadIdx.x >> 6;
@@ -367,7 +359,10 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
   const int g = lane >> 3, a8 = lane & 7;
   const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
   for (int q = threadIdx.x; q < 512; q += kT) {
-    is[q] = inv32[q];
+    const float r = sqrtf(inv32[q]);
+    sv[q] = r;
+    s10[q] = 0x1p-10f * r;
+    s24[q] = 0x1p-24f * r;
     qd[q] = q < K ? qh[q] : 0.0;
     pm[q] = perm[q];
   }
@@ -388,6 +383,10 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
   int32_t *ep = ep_all[w];
   int32_t *qc = qc_all[w];
   float *ql = ql_all[w];
+  float *qu = qu_all[w];
+  int32_t *rc = rc_all[w];
+  float *rl = rl_all[w];
+  float *ru = ru_all[w];
   int32_t *fc = fc_all[w];
   int32_t *fr = fr_all[w];
   float *fl = fl_all[w];
@@ -414,8 +413,8 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
   double bd = DBL_MAX;           // best exact distance (wave-uniform)
   int32_t bl = INT32_MAX;
   float ub = FLT_MAX;            // u: float32 upper bound of the minimum
-  int nq = 0, nf = 0;            // queue and survivor fills (wave-uniform)
-  auto exact = [&](int32_t C, int32_t cr) {
+  int nq = 0, nr = 0, nf = 0;    // queue, stage-C queue, survivor fills (wave-uniform)
+  auto exact = [&](int32_t C, int32_t cr) __attribute__((always_inline)) {
     const double dl = exact_d<PT>(C, cr, lane, cent, pool, K, xn, qd);
     if (dl < bd || (dl == bd && C < bl)) {
       bd = dl;
@@ -424,7 +423,7 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
     ub = fminf(ub, float(dl) * kUbScale * kUbScale);
   };
   // exact distances of the survivors, smallest lower bound first
-  auto resolve = [&]() {
+  auto resolve = [&]() __attribute__((always_inline)) {
     while (nf > 0) {
       float l = lane < nf ? fl[lane] : FLT_MAX;
       int i = lane;
@@ -436,7 +435,7 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
           i = oi;
         }
       }
-      if (l > ub * kMargin) {
+      if (l * l > ub * kMargin) {
         nf = 0;
         break;
       }
@@ -452,43 +451,48 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
       if (C != bl) exact(C, cr);
     }
   };
-  // stage B for the last cnt (<= 8) queue entries; survivors join the list
-  auto stage_b = [&](int cnt) {
+  // stage C for the last cnt (<= 8) stage-C queue entries; survivors join
+  // the list, and their complete upper bounds tighten u
+  auto stage_c = [&](int cnt) __attribute__((always_inline)) {
     int32_t C = -1, cr = -1;
-    float lo = FLT_MAX;
+    float lo = FLT_MAX, up = 0.0f;
     if (g < cnt) {
-      C = qc[nq - cnt + g];
-      lo = ql[nq - cnt + g];
+      C = rc[nr - cnt + g];
+      lo = rl[nr - cnt + g];
+      up = ru[nr - cnt + g];
     }
-    nq -= cnt;
+    nr -= cnt;
     wave_sync();
-    const bool live = C >= 0 && C != bl && !(lo > ub * kMargin);
-    float up = 0.0f;
+    const bool live = C >= 0 && C != bl && !(lo * lo > ub * kMargin);
     if (live) {
-      // lane a8 of the group takes columns 8 a8 + 64 it (Kq <= 512)
+      // lane a8 of the group takes columns kBq + 8 a8 + 64 it (Kq <= 512)
       cr = crow[C];
       const uint4 *row = reinterpret_cast<const uint4 *>(cperm + int64_t(C) * Kq);
-      uint4 v[8];
+      uint4 v[4];
 #pragma unroll
-      for (int it = 0; it < 8; ++it)
-        v[it] = 8 * a8 + 64 * it < Kq ? row[a8 + 8 * it] : make_uint4(0u, 0u, 0u, 0u);
+      for (int it = 0; it < 4; ++it) {
+        const int q0 = kBq + 8 * a8 + 64 * it;
+        v[it] = q0 < Kq ? row[q0 / 8] : make_uint4(0u, 0u, 0u, 0u);
+      }
 #pragma unroll
-      for (int it = 0; it < 8; ++it)
-        if (8 * a8 + 64 * it < Kq) bounds16_8(v[it], xs, is, 8 * a8 + 64 * it, lo, up);
+      for (int it = 0; it < 4; ++it) {
+        const int q0 = kBq + 8 * a8 + 64 * it;
+        if (q0 < Kq) bounds16_8(v[it], xs, sv, s10, s24, q0, lo, up);
+      }
     }
     for (int off = 4; off > 0; off >>= 1) {
       lo = fmaxf(lo, __shfl_xor(lo, off, 8));
       up = fmaxf(up, __shfl_xor(up, off, 8));
     }
-    float um = live ? up * kUpScale : FLT_MAX;
+    float um = live ? up * up * kUpScale : FLT_MAX;
     for (int off = 8; off < 64; off <<= 1) um = fminf(um, __shfl_xor(um, off, 64));
     ub = fminf(ub, um);
-    const bool keep = live && a8 == 0 && !(lo > ub * kMargin);
+    const bool keep = live && a8 == 0 && !(lo * lo > ub * kMargin);
     const uint64_t m = __ballot(keep);
     const int nk = __popcll(m);
     if (nf + nk > kFCap) {
       // drop the survivors u now excludes, then resolve if still full
-      const bool k2 = lane < nf && !(fl[lane] > ub * kMargin);
+      const bool k2 = lane < nf && !(fl[lane] * fl[lane] > ub * kMargin);
       const int32_t c2 = k2 ? fc[lane] : 0, r2 = k2 ? fr[lane] : 0;
       const float l2 = k2 ? fl[lane] : 0.0f;
       const uint64_t m2 = __ballot(k2);
@@ -511,6 +515,50 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
     }
     nf += nk;
     wave_sync();
+  };
+  // stage B for the last cnt (<= 8) queue entries; survivors join the
+  // stage-C queue, which is drained in batches of 8
+  auto stage_b = [&](int cnt) __attribute__((always_inline)) {
+    int32_t C = -1;
+    float lo = FLT_MAX, up = 0.0f;
+    if (g < cnt) {
+      C = qc[nq - cnt + g];
+      lo = ql[nq - cnt + g];
+      up = qu[nq - cnt + g];
+    }
+    nq -= cnt;
+    wave_sync();
+    const bool live = C >= 0 && C != bl && !(lo * lo > ub * kMargin);
+    if (live) {
+      // lane a8 of the group takes columns kAq + 8 a8 + 64 it
+      const uint4 *row = reinterpret_cast<const uint4 *>(cperm + int64_t(C) * Kq);
+      uint4 v[2];
+#pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        const int q0 = kAq + 8 * a8 + 64 * it;
+        v[it] = q0 < Kq ? row[q0 / 8] : make_uint4(0u, 0u, 0u, 0u);
+      }
+#pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        const int q0 = kAq + 8 * a8 + 64 * it;
+        if (q0 < Kq) bounds16_8(v[it], xs, sv, s10, s24, q0, lo, up);
+      }
+    }
+    for (int off = 4; off > 0; off >>= 1) {
+      lo = fmaxf(lo, __shfl_xor(lo, off, 8));
+      up = fmaxf(up, __shfl_xor(up, off, 8));
+    }
+    const bool keep = live && a8 == 0 && !(lo * lo > ub * kMargin);
+    const uint64_t m = __ballot(keep);
+    if (keep) {
+      const int at = nr + __popcll(m & lt_mask);
+      rc[at] = C;
+      rl[at] = lo;
+      ru[at] = up;
+    }
+    nr += __popcll(m);
+    wave_sync();
+    while (nr >= 8) stage_c(8);
   };
 
   for (int32_t e0 = 0; e0 < deg; e0 += kEB) {
@@ -545,7 +593,7 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
     for (int32_t t0 = 0; t0 < total; t0 += 64) {
       const int32_t t = t0 + lane;
       int32_t C = -1;
-      float lo = FLT_MAX;
+      float lo = FLT_MAX, up = 0.0f;
       if (t < total) {
         int lo_i = 0, hi_i = nb;  // last i with ep[i] <= t
         while (hi_i - lo_i > 1) {
@@ -564,19 +612,21 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
 #pragma unroll
           for (int u = 0; u < 8; ++u) v[u] = row[q0 / 8 + u];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) lo = fmaxf(lo, lb16_8(v[u], xs, is, q0 + 8 * u));
+          for (int u = 0; u < 8; ++u) bounds16_8(v[u], xs, sv, s10, s24, q0 + 8 * u, lo, up);
         }
       }
       int32_t seed = -1;
       if (ub == FLT_MAX) {
-        // seed u: stage B of the smallest (bound, label) of this batch
-        float sl = lo;
+        // seed u: stages B and C of the smallest (bound, label) of this batch
+        float sl = lo, su = up;
         int32_t sc = C >= 0 ? C : INT32_MAX;
         for (int off = 1; off < 64; off <<= 1) {
           const float ol = __shfl_xor(sl, off, 64);
+          const float ou = __shfl_xor(su, off, 64);
           const int32_t oc = __shfl_xor(sc, off, 64);
           if (ol < sl || (ol == sl && oc < sc)) {
             sl = ol;
+            su = ou;
             sc = oc;
           }
         }
@@ -584,19 +634,22 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
           if (lane == 0) {
             qc[nq] = sc;
             ql[nq] = sl;
+            qu[nq] = su;
           }
           ++nq;
           wave_sync();
           stage_b(1);
+          while (nr > 0) stage_c(nr < 8 ? nr : 8);
           seed = sc;
         }
       }
-      const bool ok = C >= 0 && C != bl && C != seed && !(lo > ub * kMargin);
+      const bool ok = C >= 0 && C != bl && C != seed && !(lo * lo > ub * kMargin);
       const uint64_t m = __ballot(ok);
       if (ok) {
         const int at2 = nq + __popcll(m & lt_mask);
         qc[at2] = C;
         ql[at2] = lo;
+        qu[at2] = up;
       }
       nq += __popcll(m);
       wave_sync();
@@ -605,6 +658,7 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
     wave_sync();
   }
   if (nq > 0) stage_b(nq);
+  while (nr > 0) stage_c(nr < 8 ? nr : 8);
   resolve();
   if (lane == 0) {
     best_label[p] = bl == INT32_MAX ? -1 : bl;
