@@ -148,20 +148,38 @@ __device__ __forceinline__ double pool_val(const void *pool, int64_t idx) {
   return double(__uint_as_float(uint32_t(h) << 16));
 }
 
+// One wave per contracted cluster (grid-stride), lane j of the wave takes
+// columns j, j + 64, ... (K <= 512); members summed in CSR order.
 template <int PT>
-__global__ void k_centroids(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
-                            const int32_t *__restrict__ in_list, const int32_t *__restrict__ n_in,
-                            const void *__restrict__ pool, int K, double *__restrict__ cent) {
+__global__ void __launch_bounds__(kT)
+k_centroids(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
+            const int32_t *__restrict__ in_list, const int32_t *__restrict__ n_in,
+            const void *__restrict__ pool, int K, double *__restrict__ cent) {
   const int32_t cnt = *n_in;
-  for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < int64_t(cnt) * K;
-       idx += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t c = idx / K;
-    const int col = int(idx % K);
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = int64_t(gridDim.x) * (kT / 64);
+  for (int64_t c = int64_t(blockIdx.x) * (kT / 64) + (threadIdx.x >> 6); c < cnt; c += nw) {
     const int32_t e = in_list[c];
     const int32_t a = eptr[e], b = eptr[e + 1];
-    double acc = 0.0;
-    for (int32_t j = a; j < b; ++j) acc = acc + pool_val<PT>(pool, int64_t(pins[j]) * K + col);
-    cent[c * K + col] = acc / double(b - a);
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    for (int32_t j = a; j < b; ++j) {
+      const int64_t base = int64_t(pins[j]) * K;
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int col = lane + 64 * q;
+        v[q] = pool_val<PT>(pool, base + (col < K ? col : K - 1));
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] = acc[q] + v[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int col = lane + 64 * q;
+      if (col < K) cent[c * K + col] = acc[q] / double(b - a);
+    }
   }
 }
 
@@ -190,29 +208,40 @@ k_qh_order(const double *__restrict__ qh, int K, int32_t *__restrict__ perm,
 
 // cperm[C][q] = float16 of cluster C's centroid in column perm[q] (zero for
 // q >= nuse), for every cluster id C (a node that is its cluster's smallest
-// member).  Row width Kq = K rounded up to 64.  crow[C] = the row of C's
-// float64 centroid (-1: singleton, the centroid is its pool row).
+// member).  Row width Kq = K rounded up to 64 (<= 512).  crow[C] = the row of
+// C's float64 centroid (-1: singleton, the centroid is its pool row).  One
+// wave per node, lane j takes q = j, j + 64, ...
 template <int PT>
-__global__ void k_cperm(const int32_t *__restrict__ prov, const int32_t *__restrict__ owner,
-                        const int32_t *__restrict__ in_index, const double *__restrict__ cent,
-                        const void *__restrict__ pool, int K, int Kq,
-                        const int32_t *__restrict__ perm, const int32_t *__restrict__ nuse,
-                        _Float16 *__restrict__ cperm, int32_t *__restrict__ crow, int32_t n) {
-  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= int64_t(n) * Kq) return;
-  const int64_t v = idx / Kq;
-  const int q = int(idx % Kq);
-  if (prov[v] != v) return;
-  // row of the cluster's float64 centroid, or -1 for a singleton (its pool row)
-  if (q == 0) crow[v] = owner[v] < 0 ? -1 : in_index[owner[v]];
-  float val = 0.0f;
-  if (q < *nuse) {
-    const int col = perm[q];
-    const int32_t ow = owner[v];
-    val = ow < 0 ? float(pool_val<PT>(pool, v * K + col))
-                 : float(cent[int64_t(in_index[ow]) * K + col]);
+__global__ void __launch_bounds__(kT)
+k_cperm(const int32_t *__restrict__ prov, const int32_t *__restrict__ owner,
+        const int32_t *__restrict__ in_index, const double *__restrict__ cent,
+        const void *__restrict__ pool, int K, int Kq, const int32_t *__restrict__ perm,
+        const int32_t *__restrict__ nuse, _Float16 *__restrict__ cperm,
+        int32_t *__restrict__ crow, int32_t n) {
+  const int64_t v = int64_t(blockIdx.x) * (kT / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (v >= n || prov[v] != v) return;
+  const int32_t ow = owner[v];
+  const int64_t cr = ow < 0 ? -1 : in_index[ow];
+  if (lane == 0) crow[v] = int32_t(cr);
+  const int nu = *nuse;
+  // perm has 512 entries (zero from nuse on), so every load is in bounds
+  int col[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) col[j] = perm[lane + 64 * j];
+  float val[8];
+  if (cr < 0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) val[j] = float(pool_val<PT>(pool, v * K + col[j]));
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) val[j] = float(cent[cr * K + col[j]]);
   }
-  cperm[v * Kq + q] = _Float16(val);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int q = lane + 64 * j;
+    if (q < Kq) cperm[v * Kq + q] = _Float16(q < nu ? val[j] : 0.0f);
+  }
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -1015,7 +1044,7 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
       k_qh_order<<<1, 512, 0, s>>>(qh, K, w.perm, w.inv32, w.small + 3);
       if (pool_type == kPoolF32) {
         k_centroids<kPoolF32><<<2048, kT, 0, s>>>(L.eptr, L.pins, w.in_list, w.small + 1, pool, K, w.cent);
-        k_cperm<kPoolF32><<<g1(n * Kq), kT, 0, s>>>(w.prov, w.owner, w.in_index, w.cent, pool, K, Kq,
+        k_cperm<kPoolF32><<<cdiv(n, kT / 64), kT, 0, s>>>(w.prov, w.owner, w.in_index, w.cent, pool, K, Kq,
                                                    w.perm, w.small + 3, w.cperm, w.crow, int32_t(n));
         {
           TimedScope tb(kStClusterBest, s);
@@ -1026,7 +1055,7 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
         }
       } else {
         k_centroids<kPoolBF16><<<2048, kT, 0, s>>>(L.eptr, L.pins, w.in_list, w.small + 1, pool, K, w.cent);
-        k_cperm<kPoolBF16><<<g1(n * Kq), kT, 0, s>>>(w.prov, w.owner, w.in_index, w.cent, pool, K, Kq,
+        k_cperm<kPoolBF16><<<cdiv(n, kT / 64), kT, 0, s>>>(w.prov, w.owner, w.in_index, w.cent, pool, K, Kq,
                                                    w.perm, w.small + 3, w.cperm, w.crow, int32_t(n));
         {
           TimedScope tb(kStClusterBest, s);
