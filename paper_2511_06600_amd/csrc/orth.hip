@@ -48,6 +48,8 @@ k_chol_panel(const double *__restrict__ A, const double *__restrict__ G, int K, 
              const int32_t *__restrict__ force_keep) {
   extern __shared__ double pan[];  // [K - c0][kPS]
   __shared__ int s_keep;
+  __shared__ double s_ref[kPW];     // G_jj of the panel's columns
+  __shared__ int s_force[kPW];
   const int t = threadIdx.x;
   const int w = K - c0 < kPW ? K - c0 : kPW;
   const int nr = K - c0;
@@ -55,13 +57,17 @@ k_chol_panel(const double *__restrict__ A, const double *__restrict__ G, int K, 
     const int i = e / w, j = e % w;
     pan[i * kPS + j] = i >= j ? A[int64_t(c0 + i) * K + c0 + j] : 0.0;
   }
+  if (t < w) {
+    s_ref[t] = G[int64_t(c0 + t) * K + c0 + t];
+    s_force[t] = force_keep ? force_keep[c0 + t] : 1;
+  }
   __syncthreads();
   for (int jj = 0; jj < w; ++jj) {
     if (t == 0) {
       const double d = pan[jj * kPS + jj];
-      const double ref = G[int64_t(c0 + jj) * K + c0 + jj];
+      const double ref = s_ref[jj];
       int kp = (ref > 0.0 && d > tau * tau * ref) ? 1 : 0;
-      if (force_keep && !force_keep[c0 + jj]) kp = 0;
+      if (!s_force[jj]) kp = 0;
       keep[c0 + jj] = kp;
       s_keep = kp;
       pan[jj * kPS + jj] = kp ? sqrt(d) : 0.0;
@@ -130,6 +136,7 @@ k_jtrinv(const double *__restrict__ LT, const int32_t *__restrict__ keep, int K,
   extern __shared__ double X[];  // [K][kPS]: rows of the column block J
   __shared__ double T[kPW * kPS];
   __shared__ double Lb[kPW * kPS];
+  __shared__ int kr[kPW], kc[kPW];
   const int t = threadIdx.x;
   const int J = blockIdx.x;
   const int j0 = J * kPW;
@@ -159,18 +166,30 @@ k_jtrinv(const double *__restrict__ LT, const int32_t *__restrict__ keep, int K,
       T[i * kPS + j] = acc;
     }
     __syncthreads();
-    // solve L_II X_IJ = T by forward substitution, one column per thread
-    if (t < wj) {
-      const int j = t;
-      const bool colkeep = keep[j0 + j] != 0;
-      for (int i = 0; i < wi; ++i) {
-        double x = 0.0;
-        if (colkeep && keep[i0 + i]) {
-          double acc = T[i * kPS + j];
-          for (int l = 0; l < i; ++l) acc -= LT[int64_t(i0 + l) * K + i0 + i] * X[(i0 + l) * kPS + j];
-          x = acc / LT[int64_t(i0 + i) * K + i0 + i];
+    // solve L_II X_IJ = T by forward substitution: L_II staged in LDS,
+    // thread (i, j) keeps row i of column j; step l fixes x_l and removes
+    // it from the rows below (the same products, subtracted in the same
+    // ascending order as a row-by-row substitution)
+    {
+      const int mm = t / kPW, ii = t % kPW;
+      Lb[ii * kPS + mm] = (ii < wi && mm < wi) ? LT[int64_t(i0 + mm) * K + i0 + ii] : 0.0;
+      if (t < kPW) {
+        kr[t] = t < wi ? keep[i0 + t] : 0;
+        kc[t] = t < wj ? keep[j0 + t] : 0;
+      }
+    }
+    __syncthreads();
+    {
+      const int i = t / kPW, j = t % kPW;
+      double acc = T[i * kPS + j];
+      for (int l = 0; l < wi; ++l) {
+        if (i == l) {
+          const double x = (kc[j] && kr[l]) ? acc / Lb[l * kPS + l] : 0.0;
+          if (j < wj) X[(i0 + l) * kPS + j] = x;
+          T[l * kPS + j] = x;
         }
-        X[(i0 + i) * kPS + j] = x;
+        __syncthreads();
+        if (i > l) acc -= Lb[i * kPS + l] * T[l * kPS + j];
       }
     }
     __syncthreads();
