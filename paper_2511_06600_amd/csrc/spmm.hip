@@ -78,27 +78,46 @@ k_prep(int64_t n, const float *__restrict__ s, const float *__restrict__ xs,
 // ---- CSR pass: per hyperedge e (lane sub < NCH: star, else clique) -------
 //   star:   yE[e] = alpha_e * sum_{p in e} U_star[p];  W_star[e] = alpha_e xE[e]
 //   clique: W_T[e] = T_e = beta_e * sum_{p in e} U_clique[p]
+// The per-hyperedge inputs of the finish (alpha_e and this lane's chunk of
+// xE[e], or beta_e), loaded before the gather so their latency overlaps it.
+template <int B>
+struct CsrIn {
+  float f;
+  float xv[Geo<B>::CH];
+  __device__ __forceinline__ void load(int64_t e, int sub, const float *__restrict__ alpha,
+                                       const float *__restrict__ beta,
+                                       const float *__restrict__ xE) {
+    using G = Geo<B>;
+    const int vec = sub / G::NCH, ch = sub % G::NCH;
+    if (vec == 0) {
+      f = alpha[e];
+      load_ch<G::CH>(xE + e * B + ch * G::CH, xv);
+    } else {
+      f = beta[e];
+#pragma unroll
+      for (int c = 0; c < G::CH; ++c) xv[c] = 0.0f;
+    }
+  }
+};
+
 template <int B>
 __device__ __forceinline__ void csr_finish(int64_t e, int sub, const float (&acc)[Geo<B>::CH],
-                                           const float *__restrict__ alpha,
-                                           const float *__restrict__ beta,
-                                           const float *__restrict__ xE, float *__restrict__ yE,
+                                           const CsrIn<B> &in, float *__restrict__ yE,
                                            float *__restrict__ W) {
   using G = Geo<B>;
   const int vec = sub / G::NCH, ch = sub % G::NCH;
   float out[G::CH];
   if (vec == 0) {
-    const float a = alpha[e];
+    const float a = in.f;
 #pragma unroll
     for (int c = 0; c < G::CH; ++c) out[c] = a * acc[c];
     store_ch<G::CH>(yE + e * B + ch * G::CH, out);
     float xv[G::CH];
-    load_ch<G::CH>(xE + e * B + ch * G::CH, xv);
 #pragma unroll
-    for (int c = 0; c < G::CH; ++c) xv[c] *= a;
+    for (int c = 0; c < G::CH; ++c) xv[c] = in.xv[c] * a;
     store_ch<G::CH>(W + e * G::RW + ch * G::CH, xv);
   } else {
-    const float bt = beta[e];
+    const float bt = in.f;
 #pragma unroll
     for (int c = 0; c < G::CH; ++c) out[c] = bt * acc[c];
     store_ch<G::CH>(W + e * G::RW + B + ch * G::CH, out);
@@ -120,6 +139,8 @@ k_csr_small(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
   if (!((on_mask >> (sub / G::NCH)) & 1)) return;
   const int32_t a = eptr[e], b = eptr[e + 1];
   if (b - a > kSmallSeg) return;
+  CsrIn<B> in;
+  in.load(e, sub, alpha, beta, xE);
   float acc[G::CH];
 #pragma unroll
   for (int c = 0; c < G::CH; ++c) acc[c] = 0.0f;
@@ -143,7 +164,7 @@ k_csr_small(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
 #pragma unroll
       for (int c = 0; c < G::CH; ++c) acc[c] += v[u][c];
   }
-  csr_finish<B>(e, sub, acc, alpha, beta, xE, yE, W);
+  csr_finish<B>(e, sub, acc, in, yE, W);
 }
 
 // One wave per long hyperedge: 64/LPS slots stride over its pins, then a
@@ -166,6 +187,8 @@ k_csr_big(const int32_t *__restrict__ list, const int32_t *__restrict__ count,
        bi += gridDim.x * kWaves) {
     const int32_t e = list[bi];
     const int32_t a = eptr[e], b = eptr[e + 1];
+    CsrIn<B> in;
+    if (slot == 0 && on) in.load(e, sub, alpha, beta, xE);
     float acc[G::CH];
 #pragma unroll
     for (int c = 0; c < G::CH; ++c) acc[c] = 0.0f;
@@ -195,33 +218,52 @@ k_csr_big(const int32_t *__restrict__ list, const int32_t *__restrict__ count,
     for (int off = 32; off >= G::LPS; off >>= 1)
 #pragma unroll
       for (int c = 0; c < G::CH; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
-    if (slot == 0 && on) csr_finish<B>(e, sub, acc, alpha, beta, xE, yE, W);
+    if (slot == 0 && on) csr_finish<B>(e, sub, acc, in, yE, W);
   }
 }
 
 // ---- CSC pass: per node u ---------------------------------------------------
 //   star:   yV[u] = s_u * sum_{e ∋ u} W_star[e]
 //   clique: yc[u] = s_u * sum_{e ∋ u} W_T[e] - gam_u xc[u]
+// The per-node inputs of the finish (s_u, and gamma_u with this lane's chunk
+// of xc[u] for the clique half), loaded before the gather.
+template <int B>
+struct CscIn {
+  float su, gu;
+  float own[Geo<B>::CH];
+  __device__ __forceinline__ void load(int64_t u, int sub, const float *__restrict__ s,
+                                       const float *__restrict__ gam,
+                                       const float *__restrict__ xc) {
+    using G = Geo<B>;
+    const int vec = sub / G::NCH, ch = sub % G::NCH;
+    su = s[u];
+    if (vec == 0) {
+      gu = 0.0f;
+#pragma unroll
+      for (int c = 0; c < G::CH; ++c) own[c] = 0.0f;
+    } else {
+      gu = gam[u];
+      load_ch<G::CH>(xc + u * B + ch * G::CH, own);
+    }
+  }
+};
+
 template <int B>
 __device__ __forceinline__ void csc_finish(int64_t u, int sub, const float (&acc)[Geo<B>::CH],
-                                           const float *__restrict__ s,
-                                           const float *__restrict__ gam,
-                                           const float *__restrict__ xc, float *__restrict__ yV,
+                                           const CscIn<B> &in, float *__restrict__ yV,
                                            float *__restrict__ yc) {
   using G = Geo<B>;
   const int vec = sub / G::NCH, ch = sub % G::NCH;
-  const float su = s[u];
+  const float su = in.su;
   float out[G::CH];
   if (vec == 0) {
 #pragma unroll
     for (int c = 0; c < G::CH; ++c) out[c] = su * acc[c];
     store_ch<G::CH>(yV + u * B + ch * G::CH, out);
   } else {
-    const float gu = gam[u];
-    float own[G::CH];
-    load_ch<G::CH>(xc + u * B + ch * G::CH, own);
+    const float gu = in.gu;
 #pragma unroll
-    for (int c = 0; c < G::CH; ++c) out[c] = su * acc[c] - gu * own[c];
+    for (int c = 0; c < G::CH; ++c) out[c] = su * acc[c] - gu * in.own[c];
     store_ch<G::CH>(yc + u * B + ch * G::CH, out);
   }
 }
@@ -241,6 +283,8 @@ k_csc_small(const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
   if (!((on_mask >> (sub / G::NCH)) & 1)) return;
   const int32_t a = vptr[u], b = vptr[u + 1];
   if (b - a > kSmallSeg) return;
+  CscIn<B> in;
+  in.load(u, sub, s, gam, xc);
   float acc[G::CH];
 #pragma unroll
   for (int c = 0; c < G::CH; ++c) acc[c] = 0.0f;
@@ -264,7 +308,7 @@ k_csc_small(const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
 #pragma unroll
       for (int c = 0; c < G::CH; ++c) acc[c] += v[q][c];
   }
-  csc_finish<B>(u, sub, acc, s, gam, xc, yV, yc);
+  csc_finish<B>(u, sub, acc, in, yV, yc);
 }
 
 template <int B>
@@ -285,6 +329,8 @@ k_csc_big(const int32_t *__restrict__ list, const int32_t *__restrict__ count,
        bi += gridDim.x * kWaves) {
     const int32_t u = list[bi];
     const int32_t a = vptr[u], b = vptr[u + 1];
+    CscIn<B> in;
+    if (slot == 0 && on) in.load(u, sub, s, gam, xc);
     float acc[G::CH];
 #pragma unroll
     for (int c = 0; c < G::CH; ++c) acc[c] = 0.0f;
@@ -313,7 +359,7 @@ k_csc_big(const int32_t *__restrict__ list, const int32_t *__restrict__ count,
     for (int off = 32; off >= G::LPS; off >>= 1)
 #pragma unroll
       for (int c = 0; c < G::CH; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
-    if (slot == 0 && on) csc_finish<B>(u, sub, acc, s, gam, xc, yV, yc);
+    if (slot == 0 && on) csc_finish<B>(u, sub, acc, in, yV, yc);
   }
 }
 
