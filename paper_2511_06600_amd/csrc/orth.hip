@@ -417,7 +417,8 @@ __global__ void k_jgram_scatter(const double *__restrict__ sums, int nsb, int np
 // Q = V Rinv (n x K times upper-triangular K x K), out of place.  Block =
 // 128 x 128 output tile; 4 waves of 64 x 64 (2 x 2 MFMA tiles).  The k
 // loop runs over 32-wide chunks up to the tile's last column (Rinv is zero
-// below its diagonal); both operand chunks are staged in LDS.
+// below its diagonal); both operand chunks are staged in LDS, the next one
+// fetched into registers during the current chunk's products.
 constexpr int kAT = 256;
 constexpr int kAM = 128, kAN = 128, kAK = 32;
 constexpr int kALDA = kAK + 1;   // A chunk [128][33]
@@ -446,33 +447,60 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oc
       for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
   // Rinv is upper triangular: rows past the tile's last column are zero
   const int kend = (!full && col0 + kAN < K) ? col0 + kAN : K;
-  for (int k0 = 0; k0 < kend; k0 += kAK) {
-    __syncthreads();
-    // A chunk: rows row0..+127, cols k0..k0+31 of V (512 groups of 8 values)
-    for (int g = tid; g < kAM * (kAK / 8); g += kAT) {
-      float v[8];
+  // the next k chunk is fetched into registers while the current one is
+  // multiplied: A = 128 rows x 32 columns of V (2 groups of 8 values per
+  // thread), B = 32 rows x 128 columns of Rinv32 (4 float4 per thread)
+  float ra[2][8];
+  float4 rb[4];
+  auto fetch = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int g = tid + kAT * h;
       if (oct) {
         const int o = g / kAK, c = g % kAK;
-        load8oct(V, pool_type, row0 + 8 * o, n, k0 + c, K, v);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) As[(8 * o + q) * kALDA + c] = (k0 + c < kend) ? v[q] : 0.0f;
+        load8oct(V, pool_type, row0 + 8 * o, n, k0 + c, K, ra[h]);
       } else {
         const int r = g / (kAK / 8), c8 = (g % (kAK / 8)) * 8;
-        load8(V, pool_type, row0 + r, n, k0 + c8, K, v);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) As[r * kALDA + c8 + q] = (k0 + c8 + q < kend) ? v[q] : 0.0f;
+        load8(V, pool_type, row0 + r, n, k0 + c8, K, ra[h]);
       }
     }
-    // B chunk: rows k0..k0+31, cols col0..col0+127 of Rinv32 (row stride Kp)
-    for (int g = tid; g < kAK * (kAN / 4); g += kAT) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int g = tid + kAT * h;
       const int r = g / (kAN / 4), c4 = (g % (kAN / 4)) * 4;
       const int kk = k0 + r, cc = col0 + c4;
-      float4 t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (kk < kend && cc < Kp) t = *reinterpret_cast<const float4 *>(Rinv32 + int64_t(kk) * Kp + cc);
-      float *d = Bs + r * kALDB + c4;
-      d[0] = t.x; d[1] = t.y; d[2] = t.z; d[3] = t.w;
+      rb[h] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (kk < kend && cc < Kp) rb[h] = *reinterpret_cast<const float4 *>(Rinv32 + int64_t(kk) * Kp + cc);
     }
+  };
+  auto stash = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int g = tid + kAT * h;
+      if (oct) {
+        const int o = g / kAK, c = g % kAK;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) As[(8 * o + q) * kALDA + c] = (k0 + c < kend) ? ra[h][q] : 0.0f;
+      } else {
+        const int r = g / (kAK / 8), c8 = (g % (kAK / 8)) * 8;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) As[r * kALDA + c8 + q] = (k0 + c8 + q < kend) ? ra[h][q] : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int g = tid + kAT * h;
+      const int r = g / (kAN / 4), c4 = (g % (kAN / 4)) * 4;
+      float *d = Bs + r * kALDB + c4;
+      d[0] = rb[h].x; d[1] = rb[h].y; d[2] = rb[h].z; d[3] = rb[h].w;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < kend; k0 += kAK) {
     __syncthreads();
+    stash(k0);
+    __syncthreads();
+    if (k0 + kAK < kend) fetch(k0 + kAK);
 #pragma unroll 4
     for (int s = 0; s < kAK / 2; ++s) {
       const int kk = 2 * s + (lane >> 5);
