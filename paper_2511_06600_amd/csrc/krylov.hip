@@ -3,8 +3,8 @@
 // Per expansion, b start vectors and k steps of the block three-term
 // recurrence: Y = A V_j, then V_{j+1} is the Gram-Schmidt of Y against
 // [V_{j-1}, V_j] and within itself.  The Gram-Schmidt is carried out in the
-// Gram metric of M = [V_{j-1} | V_j | Y]: G = M^T M is accumulated with
-// FP32 matrix cores in row chunks and summed across chunks in float64, its
+// Gram metric of M = [V_{j-1} | V_j | Y]: G = M^T M is accumulated in FP32
+// register blocks over row chunks and summed across chunks in float64, its
 // Cholesky factor R (float64) gives V_{j+1} = M R^-1[:, Y columns].  A
 // column whose Gram-Schmidt residual falls below tau times its length is a
 // breakdown and becomes zero.  V_0 = X R^-1 starts the sequence and is not
@@ -93,8 +93,9 @@ k_lgram(const float *__restrict__ v0, const float *__restrict__ v1,
   constexpr int RG = 256 / NT;
   constexpr int SLAB = 128;
   constexpr int LD = C + 1;
-  __shared__ float sh[SLAB * LD];
-  __shared__ double comb[C * C];
+  // slab buffer, reused for the row groups' sums at the end
+  constexpr int SH = SLAB * LD > RG * NT * S * S ? SLAB * LD : RG * NT * S * S;
+  __shared__ float sh[SH];
   const int tid = threadIdx.x;
   const int g = tid / NT;
   const int blk = tid % NT;
@@ -137,18 +138,29 @@ k_lgram(const float *__restrict__ v0, const float *__restrict__ v1,
       }
     }
   }
-  for (int e = tid; e < C * C; e += 256) comb[e] = 0.0;
+  // every row group's sums go to LDS (the slab buffer is free now); each
+  // entry is then summed over the row groups in ascending order, in float64
   __syncthreads();
-  for (int gg = 0; gg < RG; ++gg) {
-    if (active && g == gg) {
+  float *red = sh;
+  if (active) {
 #pragma unroll
-      for (int a = 0; a < S; ++a)
+    for (int a = 0; a < S; ++a)
 #pragma unroll
-        for (int b = 0; b < S; ++b) comb[(bi * S + a) * C + bj * S + b] += double(acc[a][b]);
-    }
-    __syncthreads();
+      for (int b = 0; b < S; ++b) red[(g * NT + blk) * S * S + a * S + b] = acc[a][b];
   }
-  for (int e = tid; e < C * C; e += 256) partial[int64_t(blockIdx.x) * C * C + e] = comb[e];
+  __syncthreads();
+  for (int e = tid; e < C * C; e += 256) {
+    const int i = e / C, j = e % C;
+    const int ri = i / S, rj = j / S;
+    double t = 0.0;
+    if (ri <= rj) {
+      int id = rj - ri;
+      for (int a = 0; a < ri; ++a) id += NB - a;
+      const int off = id * S * S + (i % S) * S + (j % S);
+      for (int gg = 0; gg < RG; ++gg) t += double(red[gg * NT * S * S + off]);
+    }
+    partial[int64_t(blockIdx.x) * C * C + e] = t;
+  }
 }
 
 // Entries in blocks below the diagonal are copied from their mirror.
