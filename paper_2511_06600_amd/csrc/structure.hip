@@ -36,15 +36,24 @@ __global__ void k_validate(const int32_t *eptr, const int32_t *pins, const float
   if (bad) atomicOr(flag, bad);
 }
 
-__global__ void k_edge_ids(const int32_t *eptr, uint32_t *eid, int32_t m) {
+__global__ void k_edge_ids(const int32_t *__restrict__ eptr, uint32_t *__restrict__ eid,
+                           int32_t m) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= m) return;
-  for (int32_t j = eptr[e]; j < eptr[e + 1]; ++j) eid[j] = uint32_t(e);
+  const int32_t a = eptr[e], b = eptr[e + 1];
+  for (int32_t j = a; j < b; ++j) eid[j] = uint32_t(e);
 }
 
-__global__ void k_degree(const int32_t *pins, int32_t *deg, int64_t nnz) {
+// vptr[v] = first position of a key >= v in the sorted pin keys (v <= n):
+// position j writes the nodes in (key[j-1], key[j]] (key[-1] = -1,
+// key[nnz] = n).
+__global__ void k_seg_bounds(const uint32_t *__restrict__ key, int64_t nnz, int32_t n,
+                             int32_t *__restrict__ vptr) {
   const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j < nnz) atomicAdd(&deg[pins[j]], 1);
+  if (j > nnz) return;
+  const int64_t cur = j < nnz ? int64_t(key[j]) : int64_t(n);
+  const int64_t prev = j > 0 ? int64_t(key[j - 1]) : -1;
+  for (int64_t v = prev + 1; v <= cur; ++v) vptr[v] = int32_t(j);
 }
 
 __global__ void k_copy_pins(const int32_t *pins, uint32_t *keys, int64_t nnz) {
@@ -52,9 +61,12 @@ __global__ void k_copy_pins(const int32_t *pins, uint32_t *keys, int64_t nnz) {
   if (j < nnz) keys[j] = uint32_t(pins[j]);
 }
 
-// Per hyperedge: alpha_e = sqrt(w_e)/|e|, beta_e = w_e/(|e|(|e|-1)); flag big.
-__global__ void k_edge_scales(const int32_t *eptr, const float *w, float *alpha,
-                              float *beta, int32_t *big, int32_t m) {
+// Per hyperedge: alpha_e = sqrt(w_e)/|e|, beta_e = w_e/(|e|(|e|-1)); flag
+// big; the float64 terms w_e/|e| and beta_e of the node sums.
+__global__ void k_edge_scales(const int32_t *__restrict__ eptr, const float *__restrict__ w,
+                              float *__restrict__ alpha, float *__restrict__ beta,
+                              int32_t *__restrict__ big, double *__restrict__ tdb,
+                              double *__restrict__ tcb, int32_t m) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= m) return;
   const int32_t sz = eptr[e + 1] - eptr[e];
@@ -63,23 +75,24 @@ __global__ void k_edge_scales(const int32_t *eptr, const float *w, float *alpha,
   alpha[e] = float(sqrt(we) / k);
   beta[e] = float(we / (k * (k - 1.0)));
   big[e] = sz > kSmallSeg ? 1 : 0;
+  tdb[e] = we / k;
+  tcb[e] = we / (k * (k - 1.0));
 }
 
 // Per node, over its hyperedges in ascending order, in float64:
 // d_b = sum w_e/|e|, cb = sum beta_e; s = d_b^-1/2, gam = s^2 cb.
-__global__ void k_node_scales(const int32_t *vptr, const int32_t *eids,
-                              const int32_t *eptr, const float *w, float *s_out,
-                              float *gam, int32_t *big, int32_t n) {
+__global__ void k_node_scales(const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
+                              const double *__restrict__ tdb, const double *__restrict__ tcb,
+                              float *__restrict__ s_out, float *__restrict__ gam,
+                              int32_t *__restrict__ big, int32_t n) {
   const int64_t u = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (u >= n) return;
   double db = 0.0, cb = 0.0;
   const int32_t a = vptr[u], b = vptr[u + 1];
   for (int32_t j = a; j < b; ++j) {
     const int32_t e = eids[j];
-    const double k = double(eptr[e + 1] - eptr[e]);
-    const double we = w ? double(w[e]) : 1.0;
-    db += we / k;
-    cb += we / (k * (k - 1.0));
+    db += tdb[e];
+    cb += tcb[e];
   }
   const double sv = db > 0.0 ? 1.0 / sqrt(db) : 0.0;
   s_out[u] = float(sv);
@@ -108,6 +121,8 @@ size_t structure_build_ws(int64_t n, int64_t m, int64_t nnz) {
   a.take<uint32_t>(nnz);  // keys out
   a.take<int32_t>(std::max(n, m) + 1);  // flags
   a.take<int32_t>(std::max(n, m) + 1);  // compaction scratch
+  a.take<double>(std::max<int64_t>(m, 1));  // per-edge node-sum terms
+  a.take<double>(std::max<int64_t>(m, 1));
   return a.mark() + radix_ws_bytes(nnz) + scan_ws_bytes(std::max(n, m) + 1) + 4096;
 }
 
@@ -131,32 +146,33 @@ hef_status structure_build(const Level &L, Structure &st, Arena &ws, hipStream_t
   uint32_t *keys_out = ws.take<uint32_t>(nnz);
   int32_t *flags = ws.take<int32_t>(std::max(n, m) + 1);
   int32_t *scratch = ws.take<int32_t>(std::max(n, m) + 1);
+  double *tdb = ws.take<double>(std::max<int64_t>(m, 1));
+  double *tcb = ws.take<double>(std::max<int64_t>(m, 1));
   if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
 
-  // node degrees -> vptr
-  HEF_HIP(hipMemsetAsync(st.vptr, 0, (n + 1) * sizeof(int32_t), s));
-  if (nnz > 0) k_degree<<<cdiv(nnz, 256), 256, 0, s>>>(L.pins, st.vptr, nnz);
-  HEF_LAUNCH_CHECK();
-  HEF_TRY(exclusive_scan_i32(st.vptr, st.vptr, n, ws, s));
-
   // eids: stable sort of (pin, edge) by pin; input is in edge order, so
-  // each node's hyperedges come out ascending.
+  // each node's hyperedges come out ascending.  vptr from the sorted pins.
   if (nnz > 0) {
     k_copy_pins<<<cdiv(nnz, 256), 256, 0, s>>>(L.pins, keys, nnz);
     k_edge_ids<<<cdiv(m, 256), 256, 0, s>>>(L.eptr, vals, int32_t(m));
     HEF_LAUNCH_CHECK();
     HEF_TRY(radix_sort_pairs(keys, vals, keys_out, reinterpret_cast<uint32_t *>(st.eids),
                              nnz, bits_for(n > 0 ? n - 1 : 0), ws, s));
+    k_seg_bounds<<<cdiv(nnz + 1, 256), 256, 0, s>>>(keys_out, nnz, int32_t(n), st.vptr);
+    HEF_LAUNCH_CHECK();
+  } else {
+    HEF_HIP(hipMemsetAsync(st.vptr, 0, (n + 1) * sizeof(int32_t), s));
   }
 
   // scales and big-segment lists
   if (m > 0) {
-    k_edge_scales<<<cdiv(m, 256), 256, 0, s>>>(L.eptr, L.w, st.alpha, st.beta, flags, int32_t(m));
+    k_edge_scales<<<cdiv(m, 256), 256, 0, s>>>(L.eptr, L.w, st.alpha, st.beta, flags, tdb, tcb,
+                                               int32_t(m));
     HEF_LAUNCH_CHECK();
   }
   HEF_TRY(compact_flags(flags, scratch, st.big_e, st.n_big, m, ws, s));
   if (n > 0) {
-    k_node_scales<<<cdiv(n, 256), 256, 0, s>>>(st.vptr, st.eids, L.eptr, L.w, st.s, st.gam,
+    k_node_scales<<<cdiv(n, 256), 256, 0, s>>>(st.vptr, st.eids, tdb, tcb, st.s, st.gam,
                                               flags, int32_t(n));
     HEF_LAUNCH_CHECK();
   }
