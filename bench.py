@@ -97,12 +97,12 @@ def read_traffic():
 
 def cpu_baseline(cfg_name):
     """The FP64 oracle (as it stands) on a bounded sample of the workload:
-    the same recipe (size law, locality, weights, k, b, levels) at 1% of
-    the node and hyperedge counts."""
+    the same recipe (size law, locality, weights, k, b, levels) at 2% of
+    the node and hyperedge counts (about 15 s of host time)."""
     from oracle import coarsen as oco
     from synth import generate, get_config, start_block
     cfg = get_config(cfg_name)
-    n, m = cfg["n"] // 100, cfg["m"] // 100
+    n, m = cfg["n"] // 50, cfg["m"] // 50
     h = generate(n, m, cfg["lo"], cfg["hi"], cfg["alpha"], cfg["p_loc"],
                  weights=cfg["weights"], seed=20251106 + cfg["index"])
     start = lambda lev, x, rows, b: start_block(7, lev, x, rows, b)  # noqa: E731
@@ -117,7 +117,7 @@ def cpu_baseline(cfg_name):
     dt = time.perf_counter() - t0
     est = sum(lv[1] for lv in out.levels)
     return {"value": est / dt, "unit": "estimates/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{cfg_name} recipe at n={h.n}, m={h.m} (1% of the nodes and nets), "
+            "sample": f"{cfg_name} recipe at n={h.n}, m={h.m} (2% of the nodes and nets), "
                       f"k={cfg['k']}, b={cfg['b']}, {cfg['levels']} levels: {est} estimates "
                       f"in {dt:.1f} s"}
 

@@ -47,7 +47,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kEdgesPerBlk = 256;
-constexpr int kXBlocks = 512;  // workgroups of the step cross products
+constexpr int kXBlocks = 2048;  // workgroups of the step cross products
 
 // ------------------------------------------------------------ pool loads
 template <int CPL>
@@ -111,11 +111,20 @@ k_sadj_a(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
     float mx[CPL], mn[CPL];
 #pragma unroll
     for (int q = 0; q < CPL; ++q) { mx[q] = -FLT_MAX; mn[q] = FLT_MAX; }
-    for (int32_t j = eptr[e]; j < eptr[e + 1]; ++j) {
-      float v[CPL];
-      load_row<CPL>(chi, pins[j], K, c0, v);
+    // pins in chunks of 4 (ids first, then rows); a chunk past the end
+    // repeats the last pin, which leaves max and min unchanged
+    const int32_t a = eptr[e], b = eptr[e + 1];
+    for (int32_t j0 = a; j0 < b; j0 += 4) {
+      int32_t pp[4];
 #pragma unroll
-      for (int q = 0; q < CPL; ++q) { mx[q] = fmaxf(mx[q], v[q]); mn[q] = fminf(mn[q], v[q]); }
+      for (int u = 0; u < 4; ++u) pp[u] = pins[j0 + u < b ? j0 + u : b - 1];
+      float v[4][CPL];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) load_row<CPL>(chi, pp[u], K, c0, v[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) { mx[q] = fmaxf(mx[q], v[u][q]); mn[q] = fminf(mn[q], v[u][q]); }
     }
     double best = 0.0;
     int bi = INT_MAX;
@@ -186,13 +195,23 @@ k_sadj_b(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
 #pragma unroll
       for (int q = 0; q < CPL; ++q) { mx[q] = v[q]; mn[q] = v[q]; ja[q] = a; jb[q] = a; }
     }
-    for (int32_t j = a + 1; j < b; ++j) {
-      float v[CPL];
-      load_row<CPL>(chi, pins[j], K, c0, v);
+    // pins in chunks of 4 in CSR order (ids first, then rows); a chunk past
+    // the end repeats the last pin, which never beats it strictly
+    for (int32_t j0 = a + 1; j0 < b; j0 += 4) {
+      int32_t pp[4];
 #pragma unroll
-      for (int q = 0; q < CPL; ++q) {
-        if (v[q] > mx[q]) { mx[q] = v[q]; ja[q] = j; }
-        if (v[q] < mn[q]) { mn[q] = v[q]; jb[q] = j; }
+      for (int u = 0; u < 4; ++u) pp[u] = pins[j0 + u < b ? j0 + u : b - 1];
+      float v[4][CPL];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) load_row<CPL>(chi, pp[u], K, c0, v[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int32_t j = j0 + u < b ? j0 + u : b - 1;
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+          if (v[u][q] > mx[q]) { mx[q] = v[u][q]; ja[q] = j; }
+          if (v[u][q] < mn[q]) { mn[q] = v[u][q]; jb[q] = j; }
+        }
       }
     }
     const int is = istar[e];
@@ -298,6 +317,31 @@ __global__ void k_vbar(float *__restrict__ abar, const float *__restrict__ pbar,
 // X3 = [v0 | v1 | y]^T vbar (3B x B, float64): per workgroup a row range in
 // 64-row LDS slabs, one output entry (or a few) per thread, FP32 per slab,
 // float64 across slabs; partial[blk][3B*B].
+// One SL-row slab of [v0 | v1 | y | vb] into registers (element g of the
+// slab: row g / (C + B), column g % (C + B)); zeros past r1.
+template <int B, int SL, int PF>
+__device__ __forceinline__ void xgram_fetch(float (&pre)[PF], int tid, int64_t rs, int64_t r1,
+                                            const float *v0, const float *v1, const float *y,
+                                            const float *vb) {
+  constexpr int C = 3 * B;
+#pragma unroll
+  for (int i = 0; i < PF; ++i) {
+    const int g = tid + i * kThreads;
+    const int r = g / (C + B), c = g % (C + B);
+    const int64_t row = rs + r;
+    float v = 0.0f;
+    if (g < SL * (C + B) && row < r1) {
+      if (c < C) {
+        const float *sp = c < B ? v0 : (c < 2 * B ? v1 : y);
+        v = sp ? sp[row * B + (c % B)] : 0.0f;
+      } else {
+        v = vb[row * B + (c - C)];
+      }
+    }
+    pre[i] = v;
+  }
+}
+
 template <int B>
 __global__ void __launch_bounds__(kThreads)
 k_xgram(const float *__restrict__ v0, const float *__restrict__ v1, const float *__restrict__ y,
@@ -306,47 +350,71 @@ k_xgram(const float *__restrict__ v0, const float *__restrict__ v1, const float 
   constexpr int C = 3 * B;
   constexpr int NE = C * B;
   constexpr int EPT = (NE + kThreads - 1) / kThreads;
+  // with few entries, RG row groups split each slab's rows (entry e of group
+  // g takes rows g, g + RG, ...); their float64 sums are added in group order
+  constexpr int RG = NE >= kThreads ? 1 : kThreads / NE;
   constexpr int SL = 64;
   __shared__ float sm[SL][C + 1];
   __shared__ float sv[SL][B + 1];
+  __shared__ double gsum[RG > 1 ? RG * NE : 1];
   const int tid = threadIdx.x;
+  const int grp = RG > 1 ? tid / NE : 0;
   const int64_t r0 = int64_t(blockIdx.x) * rows_per_blk;
   const int64_t r1 = r0 + rows_per_blk < rows ? r0 + rows_per_blk : rows;
   double acc[EPT];
 #pragma unroll
   for (int u = 0; u < EPT; ++u) acc[u] = 0.0;
+  // the next slab is fetched into registers while the current one is used
+  constexpr int PF = (SL * (C + B) + kThreads - 1) / kThreads;
+  float pre[PF];
+  if (r0 < r1) xgram_fetch<B, SL, PF>(pre, tid, r0, r1, v0, v1, y, vb);
   for (int64_t rs = r0; rs < r1; rs += SL) {
     __syncthreads();
-    for (int g = tid; g < SL * (C + B); g += kThreads) {
-      const int r = g / (C + B), c = g % (C + B);
-      const int64_t row = rs + r;
-      float v = 0.0f;
-      if (row < r1) {
-        if (c < C) {
-          const float *sp = c < B ? v0 : (c < 2 * B ? v1 : y);
-          v = sp ? sp[row * B + (c % B)] : 0.0f;
-        } else {
-          v = vb[row * B + (c - C)];
-        }
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int g = tid + i * kThreads;
+      if (g < SL * (C + B)) {
+        const int r = g / (C + B), c = g % (C + B);
+        if (c < C) sm[r][c] = pre[i]; else sv[r][c - C] = pre[i];
       }
-      if (c < C) sm[r][c] = v; else sv[r][c - C] = v;
     }
     __syncthreads();
-#pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-      const int e = tid + u * kThreads;
-      if (e < NE) {
+    if (rs + SL < r1) xgram_fetch<B, SL, PF>(pre, tid, rs + SL, r1, v0, v1, y, vb);
+    if (RG > 1) {
+      if (grp < RG) {
+        const int e = tid - grp * NE;
         const int a = e / B, c = e % B;
-        float s = 0.0f;
-        for (int r = 0; r < SL; ++r) s = fmaf(sm[r][a], sv[r][c], s);
-        acc[u] += double(s);
+        float sacc = 0.0f;
+        for (int r = grp; r < SL; r += RG) sacc = fmaf(sm[r][a], sv[r][c], sacc);
+        acc[0] += double(sacc);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) {
+        const int e = tid + u * kThreads;
+        if (e < NE) {
+          const int a = e / B, c = e % B;
+          float sacc = 0.0f;
+          for (int r = 0; r < SL; ++r) sacc = fmaf(sm[r][a], sv[r][c], sacc);
+          acc[u] += double(sacc);
+        }
       }
     }
   }
+  if (RG > 1) {
+    if (grp < RG) gsum[tid] = acc[0];
+    __syncthreads();
+    if (tid < NE) {
+      double t = gsum[tid];
+      for (int g = 1; g < RG; ++g) t += gsum[g * NE + tid];
+      partial[int64_t(blockIdx.x) * NE + tid] = t;
+    }
+  } else {
 #pragma unroll
-  for (int u = 0; u < EPT; ++u) {
-    const int e = tid + u * kThreads;
-    if (e < NE) partial[int64_t(blockIdx.x) * NE + e] = acc[u];
+    for (int u = 0; u < EPT; ++u) {
+      const int e = tid + u * kThreads;
+      if (e < NE) partial[int64_t(blockIdx.x) * NE + e] = acc[u];
+    }
   }
 }
 
@@ -521,7 +589,24 @@ __global__ void k_wfinal(const int32_t *__restrict__ eptr, const int32_t *__rest
   if (e >= m) return;
   const int32_t a = eptr[e], b = eptr[e + 1];
   double gz = 0.0, gh = 0.0;
-  for (int32_t j = a; j < b; ++j) { gz += znode[pins[j]]; gh += hnode[pins[j]]; }
+  // pins in chunks of 8 (loads first), added in CSR order
+  for (int32_t j0 = a; j0 < b; j0 += 8) {
+    int32_t pp[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) pp[u] = pins[j0 + u < b ? j0 + u : b - 1];
+    double z[8], hv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      z[u] = znode[pp[u]];
+      hv[u] = hnode[pp[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (j0 + u < b) {
+        gz += z[u];
+        gh += hv[u];
+      }
+  }
   const double k = double(b - a);
   dw[e] = float(eacc[e] - gz / (2.0 * k) - gh / (k * (k - 1.0)) + wdirect[e]);
 }
