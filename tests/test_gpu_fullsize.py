@@ -1,11 +1,12 @@
 """Parity at the full configuration sizes, in the launch configuration the
 benchmark times.
 
-* netlist200k (200k nodes, 210k hyperedges, k = 20, b = 4): the FP32
-  estimate against the float64 oracle on 8192 sampled hyperedges and every
-  Q_H value (stored by tests/golden/make_fullsize_samples.py, which calls
-  only the oracle), within the FP32 bars (1e-4 norm-relative and at the
-  99.9th percentile over R >= 1e-3 max R; Q_H 1e-5).
+* netlist200k (200k nodes, 210k hyperedges, k = 20, b = 4) and large2m
+  (2M nodes, 2.2M hyperedges, k = 30, b = 8): the FP32 estimate against the
+  float64 oracle on 8192 sampled hyperedges and every Q_H value (stored by
+  tests/golden/make_fullsize_samples.py, which calls only the oracle),
+  within the FP32 bars (1e-4 norm-relative and at the 99.9th percentile
+  over R >= 1e-3 max R; Q_H 1e-5).
 * large2m (2M nodes, 2.2M hyperedges, k = 30, b = 8, 3 levels, the
   benchmark workload): properties that hold at any size -- the weighted
   ratios of every pool column sum to one (Eqs. (9), (13)), the pool is
@@ -51,11 +52,12 @@ def _spread_sums(h, dh, chi, qh, chunk=32):
     return out.cpu().numpy()
 
 
-def test_netlist200k_matches_oracle_sample():
-    cfg = get_config("netlist200k")
-    h = make_hypergraph("netlist200k")
-    ref = np.load(os.path.join(GOLD, "netlist200k_R_sample.npz"))
-    say(f"case: resistance netlist200k n={h.n} m={h.m} k={cfg['k']} b={cfg['b']}")
+@pytest.mark.parametrize("name", ["netlist200k", "large2m"])
+def test_matches_oracle_sample(name):
+    cfg = get_config(name)
+    h = make_hypergraph(name)
+    ref = np.load(os.path.join(GOLD, f"{name}_R_sample.npz"))
+    say(f"case: resistance {name} n={h.n} m={h.m} k={cfg['k']} b={cfg['b']}")
     dh = to_device(h)
     R, qh, _ = hef.resistance(dh, hef.Params(k=cfg["k"], b=cfg["b"], assume_valid=True))
     R = R.cpu().numpy().astype(np.float64)[ref["idx"]]
