@@ -46,7 +46,7 @@ namespace {
 
 constexpr int kT = 256;
 constexpr int kSeedSeg = 64;  // hyperedges this short seed the best-first search
-constexpr int kRoundsPerSync = 16;
+constexpr int kRoundsPerSync = 4;
 constexpr int32_t kStUndecided = 0, kStIn = 1, kStOut = 2, kStNone = 3;
 
 // ---- a6: Eq. (15) -----------------------------------------------------------
@@ -81,6 +81,9 @@ __global__ void k_rank(const uint32_t *__restrict__ order, const float *__restri
 // ---- a7: contraction rounds --------------------------------------------------
 // packed[p] = max over undecided candidates e ∋ p of (round << 32 | ~rank[e])
 // = the newest round's smallest rank.  First checks whether e is blocked.
+// `undecided` becomes nonzero while candidates remain: a plain store of 1 by
+// one lane per wave (a same-address counter updated by every wave serialises
+// at the memory side and dominated the round).
 __global__ void k_round_propose(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
                                 const int32_t *__restrict__ rank, int32_t *__restrict__ state,
                                 const int32_t *__restrict__ owner,
@@ -97,7 +100,8 @@ __global__ void k_round_propose(const int32_t *__restrict__ eptr, const int32_t 
   const unsigned long long key =
       (static_cast<unsigned long long>(round) << 32) | uint32_t(~uint32_t(rank[e]));
   for (int32_t j = a; j < b; ++j) atomicMax(&packed[pins[j]], key);
-  atomicAdd(undecided, 1);
+  const uint64_t act = __ballot(1);
+  if ((threadIdx.x & 63) == __ffsll(static_cast<long long>(act)) - 1) *undecided = 1;
 }
 
 __global__ void k_round_select(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
