@@ -312,6 +312,26 @@ __device__ __forceinline__ void slab_store(float *S, bool oct, int tid, const fl
   }
 }
 
+// The products of one LDS slab for the wave's tiles (ti, tj0) and
+// (ti, tj0 + 1), those switched off skipped at compile time.
+template <bool ON0, bool ON1>
+__device__ __forceinline__ void gram_slab(const float *A, const float *Bm, int lane, int ti,
+                                          int tj0, floatx16 &acc0, floatx16 &acc1) {
+#pragma unroll 8
+  for (int s = 0; s < kSlab / 2; ++s) {
+    const int row = 2 * s + (lane >> 5);
+    const float a_op = A[row * kSB + 32 * ti + (lane & 31)];
+    if (ON0) {
+      const float b0 = Bm[row * kSB + 32 * tj0 + (lane & 31)];
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op, b0, acc0, 0, 0, 0);
+    }
+    if (ON1) {
+      const float b1 = Bm[row * kSB + 32 * (tj0 + 1) + (lane & 31)];
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op, b1, acc1, 0, 0, 0);
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kGT)
 k_jgram(const void *__restrict__ pool, const void *__restrict__ poolB, int pool_type, int oct,
         int64_t n, int K, int nsb, int npairs, int64_t rows_per_chunk,
@@ -356,19 +376,10 @@ k_jgram(const void *__restrict__ pool, const void *__restrict__ poolB, int pool_
     }
     const float *A = As[buf];
     const float *Bm = diag ? As[buf] : Bs[buf];
-#pragma unroll 4
-    for (int s = 0; s < kSlab / 2; ++s) {
-      const int row = 2 * s + (lane >> 5);
-      const float a_op = A[row * kSB + 32 * ti + (lane & 31)];
-      if (on0) {
-        const float b0 = Bm[row * kSB + 32 * tj0 + (lane & 31)];
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op, b0, acc0, 0, 0, 0);
-      }
-      if (on1) {
-        const float b1 = Bm[row * kSB + 32 * (tj0 + 1) + (lane & 31)];
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op, b1, acc1, 0, 0, 0);
-      }
-    }
+    // the wave's tile set is fixed per block: one branch-free loop per set
+    if (on0 && on1) gram_slab<true, true>(A, Bm, lane, ti, tj0, acc0, acc1);
+    else if (on1) gram_slab<false, true>(A, Bm, lane, ti, tj0, acc0, acc1);
+    else if (on0) gram_slab<true, false>(A, Bm, lane, ti, tj0, acc0, acc1);
     if (++slabs == kFlushSlabs) {
       slabs = 0;
 #pragma unroll
