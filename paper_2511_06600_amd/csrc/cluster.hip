@@ -782,13 +782,19 @@ __global__ void k_group_eta(const int32_t *__restrict__ cl_ptr, const int32_t *_
 }
 
 // segment starts of a sorted key array: ptr[k] = first index with key >= k
+// ptr[k] = the first position of a key >= k in the ascending keys[0, cnt),
+// for k = 0 .. nseg (one binary search per segment, so a long run of empty
+// segments costs no single thread more than another)
 __global__ void k_seg_ptr(const uint32_t *__restrict__ keys, int64_t cnt, int32_t nseg,
                           int32_t *__restrict__ ptr) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i > cnt) return;
-  const int64_t prev = i == 0 ? -1 : int64_t(keys[i - 1]);
-  const int64_t cur = i == cnt ? int64_t(nseg) : int64_t(keys[i]);
-  for (int64_t k = prev + 1; k <= cur; ++k) ptr[k] = int32_t(i);
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k > nseg) return;
+  int64_t lo = 0, hi = cnt;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (int64_t(keys[mid]) < k) lo = mid + 1; else hi = mid;
+  }
+  ptr[k] = int32_t(lo);
 }
 
 // gather helpers for the sorts
@@ -964,6 +970,13 @@ size_t level_ws_bytes(int64_t n, int64_t m, int64_t nnz, int K) {
          scan_ws_bytes(std::max(std::max(n, m), nnz) + 1) + 4096;
 }
 
+__global__ void k_counts3(const int32_t *__restrict__ a, const int32_t *__restrict__ b,
+                          const int32_t *__restrict__ c, int64_t n, int32_t *__restrict__ out) {
+  out[0] = a[n];
+  out[1] = b[n];
+  out[2] = c[n];
+}
+
 hef_status read_i32(const int32_t *dev, int32_t *host, hipStream_t s) {
   HEF_HIP(hipMemcpyAsync(host, dev, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HEF_HIP(hipStreamSynchronize(s));
@@ -1094,33 +1107,43 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
   int32_t ngroups = 0;
   {
     TimedScope ts(kStClusterRebuild, s);
+    // three scans (group roots, clusters, attach pairs), one host read of
+    // their totals; the cluster and pair positions live in ibuf and in the
+    // contraction's key buffer, both free at this point
+    int32_t *pos_cl = w.ibuf;
+    int32_t *pos_pr = reinterpret_cast<int32_t *>(w.packed);
+    int32_t ncl = 0, npr = 0;
     if (n > 0) {
       k_root_flags<<<g1(n), kT, 0, s>>>(w.prov, w.parent, w.flag, int32_t(n));
       HEF_LAUNCH_CHECK();
       HEF_TRY(exclusive_scan_i32(w.flag, w.pos, n, ws, s));
       k_labels<<<g1(n), kT, 0, s>>>(w.prov, w.parent, w.pos, label_out, int32_t(n));
+      k_cluster_flags<<<g1(n), kT, 0, s>>>(w.prov, w.flag, int32_t(n));
       HEF_LAUNCH_CHECK();
-      HEF_TRY(read_i32(w.pos + n, &ngroups, s));
+      HEF_TRY(exclusive_scan_i32(w.flag, pos_cl, n, ws, s));
+      k_pair_flags<<<g1(n), kT, 0, s>>>(w.best_label, w.owner, w.flag, int32_t(n));
+      HEF_LAUNCH_CHECK();
+      HEF_TRY(exclusive_scan_i32(w.flag, pos_pr, n, ws, s));
+      k_counts3<<<1, 1, 0, s>>>(w.pos, pos_cl, pos_pr, n, w.small + 4);
+      HEF_LAUNCH_CHECK();
+      int32_t c3[3] = {0, 0, 0};
+      HEF_HIP(hipMemcpyAsync(c3, w.small + 4, sizeof(c3), hipMemcpyDeviceToHost, s));
+      HEF_HIP(hipStreamSynchronize(s));
+      ngroups = c3[0];
+      ncl = c3[1];
+      npr = c3[2];
     }
     *n_groups_out = ngroups;
     if (n > 0 && ngroups > 0) {
       // cluster contributions sorted by (group, label)
-      k_cluster_flags<<<g1(n), kT, 0, s>>>(w.prov, w.flag, int32_t(n));
-      HEF_TRY(exclusive_scan_i32(w.flag, w.pos, n, ws, s));
-      int32_t ncl = 0;
-      HEF_TRY(read_i32(w.pos + n, &ncl, s));
-      k_items_clusters<<<g1(n), kT, 0, s>>>(w.prov, label_out, w.pos, w.k0, w.v0, int32_t(n));
+      k_items_clusters<<<g1(n), kT, 0, s>>>(w.prov, label_out, pos_cl, w.k0, w.v0, int32_t(n));
       HEF_LAUNCH_CHECK();
       HEF_TRY(radix_sort_pairs(w.k0, w.v0, w.k1, w.v1, ncl, bits_for(ngroups), ws, s));
-      k_seg_ptr<<<g1(int64_t(ncl) + 1), kT, 0, s>>>(w.k1, ncl, ngroups, w.cl_ptr);
+      k_seg_ptr<<<g1(int64_t(ngroups) + 1), kT, 0, s>>>(w.k1, ncl, ngroups, w.cl_ptr);
       HEF_HIP(hipMemcpyAsync(w.ibuf, w.v1, sizeof(int32_t) * std::max(ncl, 1), hipMemcpyDeviceToDevice, s));
       // pair contributions sorted by (group, min, max)
-      k_pair_flags<<<g1(n), kT, 0, s>>>(w.best_label, w.owner, w.flag, int32_t(n));
-      HEF_TRY(exclusive_scan_i32(w.flag, w.pos, n, ws, s));
-      int32_t npr = 0;
-      HEF_TRY(read_i32(w.pos + n, &npr, s));
       if (npr > 0) {
-        k_items_pairs<<<g1(n), kT, 0, s>>>(w.best_label, w.flag, w.pos, w.k0, w.v0, int32_t(n));
+        k_items_pairs<<<g1(n), kT, 0, s>>>(w.best_label, w.flag, pos_pr, w.k0, w.v0, int32_t(n));
         HEF_LAUNCH_CHECK();
         HEF_TRY(radix_sort_pairs(w.k0, w.v0, w.k1, w.v1, npr, bits_for(n), ws, s));      // by max
         k_rekey_min<<<g1(npr), kT, 0, s>>>(w.best_label, w.v1, w.k1, npr);
@@ -1129,7 +1152,7 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
         HEF_TRY(radix_sort_pairs(w.k0, w.v0, w.k1, w.v1, npr, bits_for(ngroups), ws, s)); // by group
         HEF_LAUNCH_CHECK();
       }
-      k_seg_ptr<<<g1(int64_t(npr) + 1), kT, 0, s>>>(w.k1, npr, ngroups, w.pr_ptr);
+      k_seg_ptr<<<g1(int64_t(ngroups) + 1), kT, 0, s>>>(w.k1, npr, ngroups, w.pr_ptr);
       k_group_eta<<<g1(ngroups), kT, 0, s>>>(w.cl_ptr, w.ibuf, w.prov_eta, w.pr_ptr,
                                              reinterpret_cast<const int32_t *>(w.v1), w.best_d,
                                              ngroups, eta_out);
