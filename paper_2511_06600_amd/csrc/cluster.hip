@@ -860,6 +860,138 @@ __global__ void k_gather_u32(const uint32_t *__restrict__ src, const uint32_t *_
 }
 
 // after sorting slots by (edge, label): count distinct labels per edge
+// ---- a9: per-hyperedge sorted labels -----------------------------------------
+// lab_sorted[eptr[e] .. eptr[e+1]) = the labels of e's pins in ascending order
+// and cnt[e] = their number of distinct values (0 when below 2).  Hyperedges
+// of at most kSmallSeg pins: one thread each, a bitonic network in
+// registers; larger ones (the structure's big list): one workgroup each, a
+// bitonic sort in LDS of up to kEdgeSortCap labels (a larger hyperedge
+// raises *overflow and the level takes the global sort instead).
+constexpr int kEdgeSortCap = 16384;
+
+template <int N>
+__device__ __forceinline__ void bitonic_regs(uint32_t (&x)[N]) {
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int l = i ^ j;
+        if (l > i) {
+          const uint32_t a = x[i], b = x[l];
+          const bool asc = (i & k) == 0;
+          x[i] = asc ? min(a, b) : max(a, b);
+          x[l] = asc ? max(a, b) : min(a, b);
+        }
+      }
+}
+
+template <int N>
+__device__ __forceinline__ void elab_regs(const int32_t *__restrict__ pins,
+                                          const int32_t *__restrict__ label, int32_t a,
+                                          int32_t sz, uint32_t *__restrict__ out, int32_t &c) {
+  uint32_t x[N];
+  // unconditional loads (position clamped into the segment), then padding
+#pragma unroll
+  for (int u = 0; u < N; ++u) x[u] = uint32_t(pins[a + (u < sz ? u : sz - 1)]);
+#pragma unroll
+  for (int u = 0; u < N; ++u) x[u] = uint32_t(label[x[u]]);
+#pragma unroll
+  for (int u = 0; u < N; ++u) x[u] = u < sz ? x[u] : 0xFFFFFFFFu;
+  bitonic_regs<N>(x);
+  c = 0;
+#pragma unroll
+  for (int u = 0; u < N; ++u)
+    if (u < sz) {
+      out[a + u] = x[u];
+      c += (u == 0 || x[u] != x[u - 1]) ? 1 : 0;
+    }
+}
+
+__global__ void __launch_bounds__(kT)
+k_elab_small(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
+             const int32_t *__restrict__ label, int32_t m, uint32_t *__restrict__ lab_sorted,
+             int32_t *__restrict__ cnt) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  const int32_t a = eptr[e], sz = eptr[e + 1] - a;
+  if (sz > kSmallSeg) return;
+  if (sz == 0) {
+    cnt[e] = 0;
+    return;
+  }
+  int32_t c = 0;
+  if (sz <= 8)
+    elab_regs<8>(pins, label, a, sz, lab_sorted, c);
+  else
+    elab_regs<32>(pins, label, a, sz, lab_sorted, c);
+  cnt[e] = c >= 2 ? c : 0;
+}
+
+__global__ void __launch_bounds__(kT)
+k_elab_big(const int32_t *__restrict__ list, const int32_t *__restrict__ count,
+           const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
+           const int32_t *__restrict__ label, uint32_t *__restrict__ lab_sorted,
+           int32_t *__restrict__ cnt, int32_t *__restrict__ overflow) {
+  __shared__ uint32_t buf[kEdgeSortCap];
+  __shared__ int32_t wsum[kT / 64];
+  const int tid = threadIdx.x;
+  const int32_t nb = *count;
+  for (int32_t bi = blockIdx.x; bi < nb; bi += gridDim.x) {
+    const int32_t e = list[bi];
+    const int32_t a = eptr[e], sz = eptr[e + 1] - a;
+    if (sz > kEdgeSortCap) {
+      if (tid == 0) *overflow = 1;
+      continue;
+    }
+    int32_t P = 1;
+    while (P < sz) P <<= 1;
+    for (int32_t i = tid; i < P; i += kT) buf[i] = i < sz ? uint32_t(label[pins[a + i]]) : 0xFFFFFFFFu;
+    __syncthreads();
+    for (int32_t k = 2; k <= P; k <<= 1)
+      for (int32_t j = k >> 1; j > 0; j >>= 1) {
+        for (int32_t i = tid; i < P; i += kT) {
+          const int32_t l = i ^ j;
+          if (l > i) {
+            const uint32_t x = buf[i], y = buf[l];
+            const bool asc = (i & k) == 0;
+            if ((x > y) == asc) {
+              buf[i] = y;
+              buf[l] = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    int32_t c = 0;
+    for (int32_t i = tid; i < sz; i += kT) {
+      lab_sorted[a + i] = buf[i];
+      c += (i == 0 || buf[i] != buf[i - 1]) ? 1 : 0;
+    }
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((tid & 63) == 0) wsum[tid >> 6] = c;
+    __syncthreads();
+    if (tid == 0) {
+      int32_t t = 0;
+      for (int q = 0; q < kT / 64; ++q) t += wsum[q];
+      cnt[e] = t >= 2 ? t : 0;
+    }
+    __syncthreads();
+  }
+}
+
+// eptr2[m2] = nnz2 and (m2, nnz2, overflow) for the host, in one place
+__global__ void k_rebuild_tail(const int32_t *__restrict__ kpos, const int32_t *__restrict__ nptr,
+                               int64_t m, const int32_t *__restrict__ overflow,
+                               int32_t *__restrict__ eptr2, int32_t *__restrict__ out3) {
+  const int32_t m2 = kpos[m], nnz2 = nptr[m];
+  eptr2[m2] = nnz2;
+  out3[0] = m2;
+  out3[1] = nnz2;
+  out3[2] = overflow ? *overflow : 0;
+}
+
 __global__ void k_distinct(const int32_t *__restrict__ eptr, const uint32_t *__restrict__ lab_sorted,
                            int32_t *__restrict__ cnt, int32_t m) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1165,9 +1297,9 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
 
 // Coarse hypergraph: pins mapped to labels, per-hyperedge sorted distinct
 // labels, hyperedges with fewer than two kept (order and weight kept).
-hef_status rebuild_level(const Level &L, const int32_t *label, int32_t n2, int32_t *eptr2,
-                         int32_t *pins2, float *w2, int32_t *m2_host, int64_t *nnz2_host,
-                         Arena &ws, hipStream_t s) {
+hef_status rebuild_level(const Level &L, const Structure &st, const int32_t *label, int32_t n2,
+                         int32_t *eptr2, int32_t *pins2, float *w2, int32_t *m2_host,
+                         int64_t *nnz2_host, Arena &ws, hipStream_t s) {
   const int64_t m = L.m, nnz = L.nnz;
   TimedScope ts(kStClusterRebuild, s);
   const size_t mk = ws.mark();
@@ -1176,6 +1308,7 @@ hef_status rebuild_level(const Level &L, const int32_t *label, int32_t n2, int32
   uint32_t *eid = ws.take<uint32_t>(nnz + 1);
   int32_t *cnt = ws.take<int32_t>(m + 1), *nptr = ws.take<int32_t>(m + 1);
   int32_t *flag = ws.take<int32_t>(m + 1), *kpos = ws.take<int32_t>(m + 1);
+  int32_t *misc = ws.take<int32_t>(8);  // overflow flag, (m2, nnz2, overflow)
   if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
   *m2_host = 0;
   *nnz2_host = 0;
@@ -1184,7 +1317,33 @@ hef_status rebuild_level(const Level &L, const int32_t *label, int32_t n2, int32
     ws.reset(mk);
     return HEF_OK;
   }
-  // sort slots by label, then stably by hyperedge: (edge, label) order
+  // the compacted hyperedges: counts, positions, emission, totals
+  auto emit = [&](const int32_t *ovf) -> hef_status {
+    HEF_TRY(exclusive_scan_i32(cnt, nptr, m, ws, s));
+    k_flag_pos<<<g1(m), kT, 0, s>>>(cnt, flag, int32_t(m));
+    HEF_LAUNCH_CHECK();
+    HEF_TRY(exclusive_scan_i32(flag, kpos, m, ws, s));
+    k_emit<<<g1(m), kT, 0, s>>>(L.eptr, k0, cnt, nptr, kpos, L.w, eptr2, pins2, w2, int32_t(m));
+    k_rebuild_tail<<<1, 1, 0, s>>>(kpos, nptr, m, ovf, eptr2, misc + 4);
+    HEF_LAUNCH_CHECK();
+    int32_t t3[3] = {0, 0, 0};
+    HEF_HIP(hipMemcpyAsync(t3, misc + 4, sizeof(t3), hipMemcpyDeviceToHost, s));
+    HEF_HIP(hipStreamSynchronize(s));
+    *m2_host = t3[0];
+    *nnz2_host = t3[1];
+    return t3[2] ? HEF_ERR_UNSUPPORTED : HEF_OK;
+  };
+  // per-hyperedge sorts
+  HEF_HIP(hipMemsetAsync(misc, 0, sizeof(int32_t), s));
+  k_elab_small<<<g1(m), kT, 0, s>>>(L.eptr, L.pins, label, int32_t(m), k0, cnt);
+  k_elab_big<<<1024, kT, 0, s>>>(st.big_e, st.n_big, L.eptr, L.pins, label, k0, cnt, misc);
+  HEF_LAUNCH_CHECK();
+  if (emit(misc) == HEF_OK) {
+    ws.reset(mk);
+    return HEF_OK;
+  }
+  // a hyperedge beyond the LDS sort: global sorts of the slots by label,
+  // then stably by hyperedge, i.e. (edge, label) order
   k_pin_labels<<<g1(nnz), kT, 0, s>>>(L.pins, label, k0, v0, nnz);
   HEF_LAUNCH_CHECK();
   HEF_TRY(radix_sort_pairs(k0, v0, k1, v1, nnz, bits_for(std::max<int32_t>(n2 - 1, 0)), ws, s));
@@ -1198,19 +1357,7 @@ hef_status rebuild_level(const Level &L, const int32_t *label, int32_t n2, int32
   HEF_LAUNCH_CHECK();
   k_distinct<<<g1(m), kT, 0, s>>>(L.eptr, k0, cnt, int32_t(m));
   HEF_LAUNCH_CHECK();
-  HEF_TRY(exclusive_scan_i32(cnt, nptr, m, ws, s));
-  k_flag_pos<<<g1(m), kT, 0, s>>>(cnt, flag, int32_t(m));
-  HEF_LAUNCH_CHECK();
-  HEF_TRY(exclusive_scan_i32(flag, kpos, m, ws, s));
-  k_emit<<<g1(m), kT, 0, s>>>(L.eptr, k0, cnt, nptr, kpos, L.w, eptr2, pins2, w2, int32_t(m));
-  HEF_LAUNCH_CHECK();
-  int32_t m2 = 0, nnz2 = 0;
-  HEF_TRY(read_i32(kpos + m, &m2, s));
-  HEF_TRY(read_i32(nptr + m, &nnz2, s));
-  HEF_HIP(hipMemcpyAsync(eptr2 + m2, &nnz2, sizeof(int32_t), hipMemcpyHostToDevice, s));
-  HEF_HIP(hipStreamSynchronize(s));
-  *m2_host = m2;
-  *nnz2_host = nnz2;
+  HEF_TRY(emit(nullptr));
   ws.reset(mk);
   return HEF_OK;
 }
@@ -1219,6 +1366,7 @@ size_t rebuild_ws_bytes(int64_t n, int64_t m, int64_t nnz) {
   Arena a;
   for (int i = 0; i < 5; ++i) a.take<uint32_t>(nnz + 1);
   for (int i = 0; i < 4; ++i) a.take<int32_t>(m + 1);
+  a.take<int32_t>(8);
   return a.mark() + radix_ws_bytes(nnz) + scan_ws_bytes(std::max(n, m) + 1) + 4096;
 }
 
@@ -1379,7 +1527,8 @@ hef_status hef_coarsen(const hef_hypergraph *hg, const hef_params *p, int32_t *c
     }
     int32_t m2 = 0;
     int64_t nnz2 = 0;
-    HEF_TRY(rebuild_level(L, c.label, ng, c.eptr[cur], c.pins[cur], c.w[cur], &m2, &nnz2, a, stream));
+    HEF_TRY(rebuild_level(L, c.st, c.label, ng, c.eptr[cur], c.pins[cur], c.w[cur], &m2, &nnz2,
+                          a, stream));
     L.n = ng;
     L.m = m2;
     L.nnz = nnz2;

@@ -134,3 +134,32 @@ def test_coarsen_netlist_invariants_and_determinism():
     assert torch.equal(a[3], b[3])
     assert cl.min() == 0 and cl.max() == nc - 1 and np.unique(cl).size == nc
     assert nc < h.n
+
+
+def _with_giant_edge(h, size):
+    """h plus one more hyperedge over nodes 0 .. size-1 (weight 1)."""
+    from synth.hypergraph import Hypergraph
+    eptr = np.concatenate([h.eptr, [h.eptr[-1] + size]]).astype(h.eptr.dtype)
+    pins = np.concatenate([h.pins, np.arange(size, dtype=h.pins.dtype)])
+    w = np.concatenate([h.w, np.ones(1, h.w.dtype)])
+    return Hypergraph(n=h.n, m=h.m + 1, eptr=eptr, pins=pins, w=w)
+
+
+@pytest.mark.parametrize("giant", [0, 17000], ids=["sorted_per_hyperedge", "global_sort"])
+def test_rebuild_matches_oracle_counts(giant):
+    """Alg. 2 step 6 on the GPU's own level-0 map: the coarse hypergraph the
+    library builds for level 1 has the node, hyperedge and pin counts of the
+    oracle's rebuild of the same map.  Hyperedges up to 16384 pins are sorted
+    one per workgroup; the 17000-pin one sends the level to the global
+    sort."""
+    h = generate(40000, 30000, 2, 2000, 2.5, p_loc=0.6, win=300, weights="lognormal", seed=61)
+    if giant:
+        h = _with_giant_edge(h, giant)
+    say(f"case: rebuild counts n={h.n} m={h.m} max|e|={h.sizes().max()}")
+    dh = to_device(h)
+    cl1, nc1, _, _ = hef.coarsen(dh, hef.Params(k=8, b=2, levels=1))
+    m1, eptr1, pins1, _, _ = ocl.rebuild(h.m, h.eptr, h.pins, h.w, cl1.cpu().numpy())
+    hef.coarsen(dh, hef.Params(k=8, b=2, levels=2))
+    lev = hef.last_coarsen_levels()
+    say(f"  level 1: gpu {lev[1]} oracle {(nc1, m1, int(eptr1[-1]))}")
+    assert tuple(lev[1]) == (nc1, m1, int(eptr1[-1]))
