@@ -1220,7 +1220,12 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
     if (n > 0) {
       k_uf_init<<<g1(n), kT, 0, s>>>(w.parent, int32_t(n));
       HEF_LAUNCH_CHECK();
-      for (int it = 0; it < 64; ++it) {
+      // two hook + compress rounds per host check (a settled forest is
+      // left unchanged by further rounds)
+      for (int it = 0; it < 64; it += 2) {
+        HEF_HIP(hipMemsetAsync(w.small + 2, 0, sizeof(int32_t), s));
+        k_uf_hook<<<g1(n), kT, 0, s>>>(w.best_label, w.parent, int32_t(n), w.small + 2);
+        k_uf_compress<<<g1(n), kT, 0, s>>>(w.parent, int32_t(n));
         HEF_HIP(hipMemsetAsync(w.small + 2, 0, sizeof(int32_t), s));
         k_uf_hook<<<g1(n), kT, 0, s>>>(w.best_label, w.parent, int32_t(n), w.small + 2);
         k_uf_compress<<<g1(n), kT, 0, s>>>(w.parent, int32_t(n));
@@ -1228,7 +1233,7 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
         int32_t ch = 0;
         HEF_TRY(read_i32(w.small + 2, &ch, s));
         if (!ch) break;
-        if (it == 63) {
+        if (it == 62) {
           set_error("union-find did not settle");
           return HEF_ERR_NUMERICAL;
         }
