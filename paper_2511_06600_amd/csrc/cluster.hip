@@ -57,8 +57,23 @@ __global__ void k_eta_update(const int32_t *__restrict__ eptr, const int32_t *__
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= m) return;
   double acc = 0.0;
-  if (eta)
-    for (int32_t j = eptr[e]; j < eptr[e + 1]; ++j) acc = acc + double(eta[pins[j]]);
+  if (eta) {
+    const int32_t a = eptr[e], b = eptr[e + 1];
+    // pins loaded four at a time ahead of the dependent loads; the terms are
+    // added in pin order
+    int32_t j = a;
+    for (; j + 4 <= b; j += 4) {
+      int32_t p[4];
+      float t[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) p[q] = pins[j + q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) t[q] = eta[p[q]];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc = acc + double(t[q]);
+    }
+    for (; j < b; ++j) acc = acc + double(eta[pins[j]]);
+  }
   const float r = float(acc + double(R[e]));
   R_upd[e] = r;
   keys[e] = __float_as_uint(r);  // r >= 0: bit order = numeric order

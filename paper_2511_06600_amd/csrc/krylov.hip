@@ -163,12 +163,38 @@ k_lgram(const float *__restrict__ v0, const float *__restrict__ v1,
   }
 }
 
-// Entries in blocks below the diagonal are copied from their mirror.
-__global__ void k_lgram_sym(double *__restrict__ G, int C, int S) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= C * C) return;
-  const int i = e / C, j = e % C;
-  if (i / S > j / S) G[e] = G[j * C + i];
+// G = the column sums of the partials (float64: 32 row lanes of two
+// accumulators each, then a fixed tree), written for the entries in blocks
+// on or above the diagonal and mirrored into the blocks below it.
+// 256 threads = 8 columns x 32 row lanes.
+__global__ void __launch_bounds__(256)
+k_gram_reduce(const double *__restrict__ in, int64_t nrows, int C, int S,
+              double *__restrict__ G) {
+  __shared__ double red[32][9];
+  const int cl = threadIdx.x & 7, rl = threadIdx.x >> 3;
+  const int64_t c = int64_t(blockIdx.x) * 8 + cl;
+  const int64_t ncols = int64_t(C) * C;
+  const int i = int(c / C), j = int(c % C);
+  const bool upper = c < ncols && i / S <= j / S;
+  double a0 = 0.0, a1 = 0.0;
+  if (upper) {
+    int64_t r = rl;
+    for (; r + 32 < nrows; r += 64) {
+      a0 += in[r * ncols + c];
+      a1 += in[(r + 32) * ncols + c];
+    }
+    if (r < nrows) a0 += in[r * ncols + c];
+  }
+  red[rl][cl] = a0 + a1;
+  __syncthreads();
+  for (int off = 16; off > 0; off >>= 1) {
+    if (rl < off) red[rl][cl] += red[rl + off][cl];
+    __syncthreads();
+  }
+  if (rl == 0 && upper) {
+    G[int64_t(i) * C + j] = red[0][cl];
+    if (i / S < j / S) G[int64_t(j) * C + i] = red[0][cl];
+  }
 }
 
 // Cholesky of G with column dropping, then the Y-block columns of R^-1.
@@ -448,8 +474,7 @@ hef_status lgram(const float *v0, const float *v1, const float *y, int64_t rows,
   HEF_LAUNCH_CHECK();
   }
   TimedScope ts(kStLanczosReduce, s);
-  HEF_TRY(reduce_cols_f64(partial, nblk, int64_t(C) * C, G, s));
-  k_lgram_sym<<<cdiv(C * C, 256), 256, 0, s>>>(G, C, S);
+  k_gram_reduce<<<cdiv(int64_t(C) * C, 8), 256, 0, s>>>(partial, nblk, C, S, G);
   HEF_LAUNCH_CHECK();
   return HEF_OK;
 }

@@ -89,7 +89,26 @@ __global__ void k_node_scales(const int32_t *__restrict__ vptr, const int32_t *_
   if (u >= n) return;
   double db = 0.0, cb = 0.0;
   const int32_t a = vptr[u], b = vptr[u + 1];
-  for (int32_t j = a; j < b; ++j) {
+  // Incidence ids are loaded four at a time before the dependent loads, and
+  // the terms are added in incidence order.
+  int32_t j = a;
+  for (; j + 4 <= b; j += 4) {
+    int32_t e[4];
+    double td[4], tc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) e[q] = eids[j + q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      td[q] = tdb[e[q]];
+      tc[q] = tcb[e[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      db += td[q];
+      cb += tc[q];
+    }
+  }
+  for (; j < b; ++j) {
     const int32_t e = eids[j];
     db += tdb[e];
     cb += tcb[e];
