@@ -163,7 +163,7 @@ k_lgram(const float *__restrict__ v0, const float *__restrict__ v1,
   }
 }
 
-// G = the column sums of the partials (float64: 32 row lanes of two
+// G = the column sums of the partials (float64: 32 row lanes of eight
 // accumulators each, then a fixed tree), written for the entries in blocks
 // on or above the diagonal and mirrored into the blocks below it.
 // 256 threads = 8 columns x 32 row lanes.
@@ -176,16 +176,21 @@ k_gram_reduce(const double *__restrict__ in, int64_t nrows, int C, int S,
   const int64_t ncols = int64_t(C) * C;
   const int i = int(c / C), j = int(c % C);
   const bool upper = c < ncols && i / S <= j / S;
-  double a0 = 0.0, a1 = 0.0;
+  double acc[8] = {};
   if (upper) {
     int64_t r = rl;
-    for (; r + 32 < nrows; r += 64) {
-      a0 += in[r * ncols + c];
-      a1 += in[(r + 32) * ncols + c];
+    for (; r + 7 * 32 < nrows; r += 8 * 32) {
+      double t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[q] = in[(r + 32 * q) * ncols + c];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] += t[q];
     }
-    if (r < nrows) a0 += in[r * ncols + c];
+#pragma unroll
+    for (int q = 0; q < 7; ++q)
+      if (r + 32 * q < nrows) acc[q] += in[(r + 32 * q) * ncols + c];
   }
-  red[rl][cl] = a0 + a1;
+  red[rl][cl] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   __syncthreads();
   for (int off = 16; off > 0; off >>= 1) {
     if (rl < off) red[rl][cl] += red[rl + off][cl];
