@@ -206,15 +206,16 @@ k_jtrinv(const double *__restrict__ LT, const int32_t *__restrict__ keep, int K,
 
 // ---------------------------------------------------------------- Gram
 // G = V^T V.  Block = (row chunk, super-tile pair (a <= b) of 128-column
-// super blocks).  8 waves; wave w owns the 32x32 tiles (w/2, 2(w%2)) and
-// (w/2, 2(w%2)+1) of the 128x128 super tile (tiles below the diagonal of a
-// diagonal super tile are skipped).  32-row slabs of both super blocks are
-// double-buffered in LDS; FP32 MFMA accumulators are flushed to float64
+// super blocks).  FP32 pool: 16 waves, one 32x32 tile of the 128x128 super
+// tile each (tiles below the diagonal of a diagonal super tile are skipped).
+// BF16 pool: 8 waves of two tiles each.  32-row slabs of both super blocks
+// are double-buffered in LDS; FP32 MFMA accumulators are flushed to float64
 // registers every 128 rows.
 constexpr int kSB = 128;        // super-block width (4 MFMA tiles)
 constexpr int kSlab = 32;       // rows per LDS slab
 constexpr int kFlushSlabs = 4;  // FP32 accumulation over 128 rows
-constexpr int kGT = 512;        // Gram workgroup size
+constexpr int kGT = 512;        // BF16 Gram workgroup size
+constexpr int kGT32 = 1024;     // FP32 Gram workgroup size: one wave per tile
 
 __device__ __forceinline__ int2 pair_of(int p, int nsb) {
   for (int a = 0; a < nsb; ++a) {
@@ -312,27 +313,19 @@ __device__ __forceinline__ void slab_store(float *S, bool oct, int tid, const fl
   }
 }
 
-// The products of one LDS slab for the wave's tiles (ti, tj0) and
-// (ti, tj0 + 1), those switched off skipped at compile time.
-template <bool ON0, bool ON1>
-__device__ __forceinline__ void gram_slab(const float *A, const float *Bm, int lane, int ti,
-                                          int tj0, floatx16 &acc0, floatx16 &acc1) {
+// The 32x32 tile (ti, tj) of one LDS slab's products.
+__device__ __forceinline__ void gram_tile(const float *A, const float *Bm, int lane, int ti, int tj,
+                                          floatx16 &acc) {
 #pragma unroll 8
   for (int s = 0; s < kSlab / 2; ++s) {
     const int row = 2 * s + (lane >> 5);
     const float a_op = A[row * kSB + 32 * ti + (lane & 31)];
-    if (ON0) {
-      const float b0 = Bm[row * kSB + 32 * tj0 + (lane & 31)];
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op, b0, acc0, 0, 0, 0);
-    }
-    if (ON1) {
-      const float b1 = Bm[row * kSB + 32 * (tj0 + 1) + (lane & 31)];
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op, b1, acc1, 0, 0, 0);
-    }
+    const float b_op = Bm[row * kSB + 32 * tj + (lane & 31)];
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op, b_op, acc, 0, 0, 0);
   }
 }
 
-__global__ void __launch_bounds__(kGT)
+__global__ void __launch_bounds__(kGT32)
 k_jgram(const void *__restrict__ pool, const void *__restrict__ poolB, int pool_type, int oct,
         int64_t n, int K, int nsb, int npairs, int64_t rows_per_chunk,
         double *__restrict__ partial) {
@@ -346,52 +339,55 @@ k_jgram(const void *__restrict__ pool, const void *__restrict__ poolB, int pool_
   const bool cross = poolB != nullptr;
   const int2 ab = cross ? make_int2(pair / nsb, pair % nsb) : pair_of(pair, nsb);
   const bool diag = !cross && ab.x == ab.y;
-  const void *srcB = cross ? poolB : pool;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = tid >> 6;
-  const int ti = w >> 1;                // tile row
-  const int tj0 = 2 * (w & 1);          // first of two tile columns
-  const bool on0 = !diag || tj0 >= ti;
-  const bool on1 = !diag || tj0 + 1 >= ti;
+  // Off-diagonal pairs: wave w owns tile (w / 4, w % 4).  Diagonal pairs:
+  // waves 0..9 own the ten tiles on or above the diagonal, row by row, and
+  // waves 10..15 only write zeros for the six tiles below it.
+  int ti = w >> 2, tj = w & 3;
+  bool on = true;
+  if (diag) {
+    const int t = w < 10 ? w : w - 10;
+    const int r = w < 10 ? (t < 4 ? 0 : t < 7 ? 1 : t < 9 ? 2 : 3)
+                         : (t < 1 ? 1 : t < 3 ? 2 : 3);
+    const int first = w < 10 ? (r == 0 ? 0 : r == 1 ? 4 : r == 2 ? 7 : 9)
+                             : (r == 1 ? 0 : r == 2 ? 1 : 3);
+    ti = r;
+    tj = w < 10 ? r + (t - first) : t - first;
+    on = w < 10;
+  }
+  // the first half of the block stages super block a, the second half b
+  // (a diagonal pair stages one super block)
+  const bool loader = !diag || tid < kGT32 / 2;
+  const void *src = tid < kGT32 / 2 ? pool : (cross ? poolB : pool);
+  const int cb = (tid < kGT32 / 2 ? ab.x : ab.y) * kSB;
+  const int lt = tid & (kGT32 / 2 - 1);
   const int64_t r0 = chunk * rows_per_chunk;
   const int64_t r1 = r0 + rows_per_chunk < n ? r0 + rows_per_chunk : n;
-  // loader: 32 rows x 128 cols = 512 groups of 8 values per thread
-  floatx16 acc0, acc1;
-  double d0[16], d1[16];
+  floatx16 acc;
+  double d[16];
 #pragma unroll
-  for (int v = 0; v < 16; ++v) { acc0[v] = 0.0f; acc1[v] = 0.0f; d0[v] = 0.0; d1[v] = 0.0; }
-  float ra[8], rb[8];
-  slab_load(pool, pool_type, oct, r0, r1, ab.x * kSB, K, tid, ra);
-  if (!diag) slab_load(srcB, pool_type, oct, r0, r1, ab.y * kSB, K, tid, rb);
-  slab_store(As[0], oct, tid, ra);
-  if (!diag) slab_store(Bs[0], oct, tid, rb);
+  for (int v = 0; v < 16; ++v) { acc[v] = 0.0f; d[v] = 0.0; }
+  float rv[8];
+  if (loader) {
+    slab_load(src, pool_type, oct, r0, r1, cb, K, lt, rv);
+    slab_store(tid < kGT32 / 2 ? As[0] : Bs[0], oct, lt, rv);
+  }
   __syncthreads();
   int buf = 0, slabs = 0;
   for (int64_t r = r0; r < r1; r += kSlab) {
     const bool more = r + kSlab < r1;
-    if (more) {
-      slab_load(pool, pool_type, oct, r + kSlab, r1, ab.x * kSB, K, tid, ra);
-      if (!diag) slab_load(srcB, pool_type, oct, r + kSlab, r1, ab.y * kSB, K, tid, rb);
-    }
+    if (more && loader) slab_load(src, pool_type, oct, r + kSlab, r1, cb, K, lt, rv);
     const float *A = As[buf];
     const float *Bm = diag ? As[buf] : Bs[buf];
-    // the wave's tile set is fixed per block: one branch-free loop per set
-    if (on0 && on1) gram_slab<true, true>(A, Bm, lane, ti, tj0, acc0, acc1);
-    else if (on1) gram_slab<false, true>(A, Bm, lane, ti, tj0, acc0, acc1);
-    else if (on0) gram_slab<true, false>(A, Bm, lane, ti, tj0, acc0, acc1);
+    if (on) gram_tile(A, Bm, lane, ti, tj, acc);
     if (++slabs == kFlushSlabs) {
       slabs = 0;
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        d0[v] += double(acc0[v]); acc0[v] = 0.0f;
-        d1[v] += double(acc1[v]); acc1[v] = 0.0f;
-      }
+      for (int v = 0; v < 16; ++v) { d[v] += double(acc[v]); acc[v] = 0.0f; }
     }
-    if (more) {
-      slab_store(As[buf ^ 1], oct, tid, ra);
-      if (!diag) slab_store(Bs[buf ^ 1], oct, tid, rb);
-    }
+    if (more && loader) slab_store(tid < kGT32 / 2 ? As[buf ^ 1] : Bs[buf ^ 1], oct, lt, rv);
     __syncthreads();
     buf ^= 1;
   }
@@ -400,8 +396,7 @@ k_jgram(const void *__restrict__ pool, const void *__restrict__ poolB, int pool_
   for (int v = 0; v < 16; ++v) {
     const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
     const int j = lane & 31;
-    out[(ti * 4 + tj0) * 1024 + i * 32 + j] = on0 ? d0[v] + double(acc0[v]) : 0.0;
-    out[(ti * 4 + tj0 + 1) * 1024 + i * 32 + j] = on1 ? d1[v] + double(acc1[v]) : 0.0;
+    out[(ti * 4 + tj) * 1024 + i * 32 + j] = on ? d[v] + double(acc[v]) : 0.0;
   }
 }
 
@@ -851,7 +846,7 @@ hef_status gram_run(const void *pool, const void *poolB, int pool_type, int64_t 
         reinterpret_cast<const uint16_t *>(pool), oct, n, K, p.nsb, p.npairs, p.rows_per_chunk,
         partial);
   else
-    k_jgram<<<int64_t(p.npairs) * p.nchunks, kGT, 0, s>>>(pool, poolB, pool_type, oct, n, K, p.nsb,
+    k_jgram<<<int64_t(p.npairs) * p.nchunks, kGT32, 0, s>>>(pool, poolB, pool_type, oct, n, K, p.nsb,
                                                           p.npairs, p.rows_per_chunk, partial);
   HEF_LAUNCH_CHECK();
   }
