@@ -212,8 +212,8 @@ k_jtrinv(const double *__restrict__ LT, const int32_t *__restrict__ keep, int K,
 // are double-buffered in LDS; FP32 MFMA accumulators are flushed to float64
 // registers every 128 rows.
 constexpr int kSB = 128;        // super-block width (4 MFMA tiles)
-constexpr int kSlab = 32;       // rows per LDS slab
-constexpr int kFlushSlabs = 4;  // FP32 accumulation over 128 rows
+constexpr int kSlab = 64;       // rows per LDS slab
+constexpr int kFlushSlabs = 2;  // FP32 accumulation over 128 rows
 constexpr int kGT = 512;        // BF16 Gram workgroup size
 constexpr int kGT32 = 1024;     // FP32 Gram workgroup size: one wave per tile
 
@@ -369,16 +369,26 @@ k_jgram(const void *__restrict__ pool, const void *__restrict__ poolB, int pool_
   double d[16];
 #pragma unroll
   for (int v = 0; v < 16; ++v) { acc[v] = 0.0f; d[v] = 0.0; }
-  float rv[8];
+  // a slab is staged as 32-row halves
+  float rv[kSlab / 32][8];
+  auto fetch = [&](int64_t r) __attribute__((always_inline)) {
+#pragma unroll
+    for (int h = 0; h < kSlab / 32; ++h) slab_load(src, pool_type, oct, r + 32 * h, r1, cb, K, lt, rv[h]);
+  };
+  auto stash = [&](int b) __attribute__((always_inline)) {
+    float *S = tid < kGT32 / 2 ? As[b] : Bs[b];
+#pragma unroll
+    for (int h = 0; h < kSlab / 32; ++h) slab_store(S + 32 * h * kSB, oct, lt, rv[h]);
+  };
   if (loader) {
-    slab_load(src, pool_type, oct, r0, r1, cb, K, lt, rv);
-    slab_store(tid < kGT32 / 2 ? As[0] : Bs[0], oct, lt, rv);
+    fetch(r0);
+    stash(0);
   }
   __syncthreads();
   int buf = 0, slabs = 0;
   for (int64_t r = r0; r < r1; r += kSlab) {
     const bool more = r + kSlab < r1;
-    if (more && loader) slab_load(src, pool_type, oct, r + kSlab, r1, cb, K, lt, rv);
+    if (more && loader) fetch(r + kSlab);
     const float *A = As[buf];
     const float *Bm = diag ? As[buf] : Bs[buf];
     if (on) gram_tile(A, Bm, lane, ti, tj, acc);
@@ -387,7 +397,7 @@ k_jgram(const void *__restrict__ pool, const void *__restrict__ poolB, int pool_
 #pragma unroll
       for (int v = 0; v < 16; ++v) { d[v] += double(acc[v]); acc[v] = 0.0f; }
     }
-    if (more && loader) slab_store(tid < kGT32 / 2 ? As[buf ^ 1] : Bs[buf ^ 1], oct, lt, rv);
+    if (more && loader) stash(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
