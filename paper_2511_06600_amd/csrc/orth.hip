@@ -213,6 +213,7 @@ k_jtrinv(const double *__restrict__ LT, const int32_t *__restrict__ keep, int K,
 // registers every 128 rows.
 constexpr int kSB = 128;        // super-block width (4 MFMA tiles)
 constexpr int kSlab = 64;       // rows per LDS slab
+constexpr int kSLd = kSlab + 4; // LDS column stride (floats) of a slab
 constexpr int kFlushSlabs = 2;  // FP32 accumulation over 128 rows
 constexpr int kGT = 512;        // BF16 Gram workgroup size
 constexpr int kGT32 = 1024;     // FP32 Gram workgroup size: one wave per tile
@@ -296,7 +297,8 @@ __device__ __forceinline__ void load8oct(const void *pool, int pool_type, int64_
 
 // One 32-row slab of a 128-column super block into registers: row-major
 // input (thread -> row, 8 columns) or row-octet input (thread -> octet of
-// rows, 1 column); the store puts it row-major in LDS.
+// rows, 1 column); the store puts it column-major in LDS (column c at
+// S + c * kSLd, rows contiguous), where an octet is two 16-byte stores.
 __device__ __forceinline__ void slab_load(const void *pool, int pool_type, bool oct, int64_t r,
                                           int64_t r1, int cbase, int K, int tid, float (&v)[8]) {
   if (oct) load8oct(pool, pool_type, r + 8 * (tid >> 7), r1, cbase + (tid & 127), K, v);
@@ -305,23 +307,30 @@ __device__ __forceinline__ void slab_load(const void *pool, int pool_type, bool 
 
 __device__ __forceinline__ void slab_store(float *S, bool oct, int tid, const float (&v)[8]) {
   if (oct) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) S[(8 * (tid >> 7) + u) * kSB + (tid & 127)] = v[u];
+    float *d = S + (tid & 127) * kSLd + 8 * (tid >> 7);
+    *reinterpret_cast<float4 *>(d) = make_float4(v[0], v[1], v[2], v[3]);
+    *reinterpret_cast<float4 *>(d + 4) = make_float4(v[4], v[5], v[6], v[7]);
   } else {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) S[(tid >> 4) * kSB + (tid & 15) * 8 + q] = v[q];
+    for (int q = 0; q < 8; ++q) S[((tid & 15) * 8 + q) * kSLd + (tid >> 4)] = v[q];
   }
 }
 
-// The 32x32 tile (ti, tj) of one LDS slab's products.
+// The 32x32 tile (ti, tj) of one LDS slab's products.  The slab's rows are
+// split between the two lane halves (half h takes rows h kSlab/2 ...), so
+// that each lane reads four consecutive rows of its column at once.
 __device__ __forceinline__ void gram_tile(const float *A, const float *Bm, int lane, int ti, int tj,
                                           floatx16 &acc) {
-#pragma unroll 8
-  for (int s = 0; s < kSlab / 2; ++s) {
-    const int row = 2 * s + (lane >> 5);
-    const float a_op = A[row * kSB + 32 * ti + (lane & 31)];
-    const float b_op = Bm[row * kSB + 32 * tj + (lane & 31)];
-    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op, b_op, acc, 0, 0, 0);
+  const float *pa = A + (32 * ti + (lane & 31)) * kSLd + (lane >> 5) * (kSlab / 2);
+  const float *pb = Bm + (32 * tj + (lane & 31)) * kSLd + (lane >> 5) * (kSlab / 2);
+#pragma unroll
+  for (int s = 0; s < kSlab / 2; s += 4) {
+    const float4 a = *reinterpret_cast<const float4 *>(pa + s);
+    const float4 b = *reinterpret_cast<const float4 *>(pb + s);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, acc, 0, 0, 0);
   }
 }
 
@@ -329,8 +338,8 @@ __global__ void __launch_bounds__(kGT32)
 k_jgram(const void *__restrict__ pool, const void *__restrict__ poolB, int pool_type, int oct,
         int64_t n, int K, int nsb, int npairs, int64_t rows_per_chunk,
         double *__restrict__ partial) {
-  __shared__ float As[2][kSlab * kSB];
-  __shared__ float Bs[2][kSlab * kSB];
+  __shared__ __attribute__((aligned(16))) float As[2][kSB * kSLd];
+  __shared__ __attribute__((aligned(16))) float Bs[2][kSB * kSLd];
   const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
   const int pair = int(lb % npairs);
   const int64_t chunk = lb / npairs;
@@ -378,7 +387,7 @@ k_jgram(const void *__restrict__ pool, const void *__restrict__ poolB, int pool_
   auto stash = [&](int b) __attribute__((always_inline)) {
     float *S = tid < kGT32 / 2 ? As[b] : Bs[b];
 #pragma unroll
-    for (int h = 0; h < kSlab / 32; ++h) slab_store(S + 32 * h * kSB, oct, lt, rv[h]);
+    for (int h = 0; h < kSlab / 32; ++h) slab_store(S + 32 * h, oct, lt, rv[h]);
   };
   if (loader) {
     fetch(r0);
