@@ -444,12 +444,13 @@ __global__ void k_jgram_scatter(const double *__restrict__ sums, int nsb, int np
 // loop runs over 32-wide chunks up to the tile's last column (Rinv is zero
 // below its diagonal); both operand chunks are staged in LDS, the next one
 // fetched into registers during the current chunk's products.
-constexpr int kAT = 256;
+constexpr int kAT = 256;         // BF16 apply workgroup size
+constexpr int kAT32 = 512;       // FP32 apply workgroup size
 constexpr int kAM = 128, kAN = 128, kAK = 32;
 constexpr int kALDA = kAK + 1;   // A chunk [128][33]
 constexpr int kALDB = kAN + 1;   // B chunk [32][129]
 
-__global__ void __launch_bounds__(kAT)
+__global__ void __launch_bounds__(kAT32)
 k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oct, int64_t n,
          int K, int Kp, const float *__restrict__ Rinv32, int ncb, int full, int accumulate) {
   __shared__ float As[kAM * kALDA];
@@ -462,12 +463,12 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oc
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = tid >> 6;
-  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
-  floatx16 acc[2][2];
+  const int wr = (w >> 2) * 64, wc = (w & 3) * 32;
+  floatx16 acc[2][1];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 1; ++b)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
   // Rinv is upper triangular: rows past the tile's last column are zero
@@ -475,12 +476,12 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oc
   // the next k chunk is fetched into registers while the current one is
   // multiplied: A = 128 rows x 32 columns of V (2 groups of 8 values per
   // thread), B = 32 rows x 128 columns of Rinv32 (4 float4 per thread)
-  float ra[2][8];
-  float4 rb[4];
+  float ra[1][8];
+  float4 rb[2];
   auto fetch = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int g = tid + kAT * h;
+    for (int h = 0; h < 1; ++h) {
+      const int g = tid + kAT32 * h;
       if (oct) {
         const int o = g / kAK, c = g % kAK;
         load8oct(V, pool_type, row0 + 8 * o, n, k0 + c, K, ra[h]);
@@ -490,8 +491,8 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oc
       }
     }
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const int g = tid + kAT * h;
+    for (int h = 0; h < 2; ++h) {
+      const int g = tid + kAT32 * h;
       const int r = g / (kAN / 4), c4 = (g % (kAN / 4)) * 4;
       const int kk = k0 + r, cc = col0 + c4;
       rb[h] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -500,8 +501,8 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oc
   };
   auto stash = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int g = tid + kAT * h;
+    for (int h = 0; h < 1; ++h) {
+      const int g = tid + kAT32 * h;
       if (oct) {
         const int o = g / kAK, c = g % kAK;
 #pragma unroll
@@ -513,8 +514,8 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oc
       }
     }
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const int g = tid + kAT * h;
+    for (int h = 0; h < 2; ++h) {
+      const int g = tid + kAT32 * h;
       const int r = g / (kAN / 4), c4 = (g % (kAN / 4)) * 4;
       float *d = Bs + r * kALDB + c4;
       d[0] = rb[h].x; d[1] = rb[h].y; d[2] = rb[h].z; d[3] = rb[h].w;
@@ -529,22 +530,22 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oc
 #pragma unroll 4
     for (int s = 0; s < kAK / 2; ++s) {
       const int kk = 2 * s + (lane >> 5);
-      float a_op[2], b_op[2];
+      float a_op[2], b_op[1];
 #pragma unroll
       for (int a = 0; a < 2; ++a) a_op[a] = As[(wr + 32 * a + (lane & 31)) * kALDA + kk];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) b_op[b] = Bs[kk * kALDB + wc + 32 * b + (lane & 31)];
+      for (int b = 0; b < 1; ++b) b_op[b] = Bs[kk * kALDB + wc + 32 * b + (lane & 31)];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < 1; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[a], b_op[b], acc[a][b], 0, 0, 0);
     }
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 1; ++b)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int64_t row = row0 + wr + 32 * a + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
@@ -883,7 +884,7 @@ hef_status apply_run(const void *V, void *Q, int pool_type, int64_t n, int K, in
   if (n == 0) return HEF_OK;
   TimedScope ts(kStOrthApply, s);
   const int ncb = (K + kAN - 1) / kAN;
-  k_japply<<<cdiv(n, kAM) * ncb, kAT, 0, s>>>(V, Q, pool_type, oct, n, K, Kp, Rinv32, ncb, full,
+  k_japply<<<cdiv(n, kAM) * ncb, kAT32, 0, s>>>(V, Q, pool_type, oct, n, K, Kp, Rinv32, ncb, full,
                                               accumulate);
   HEF_LAUNCH_CHECK();
   return HEF_OK;
