@@ -21,7 +21,7 @@ namespace hef {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kEdgesPerBlk = 256;
+constexpr int kEdgesPerBlk = 128;
 
 template <int CPL, int PT>
 __device__ __forceinline__ void load_cols(const void *pool, int64_t p, int K, int c0,
@@ -86,9 +86,9 @@ __device__ __forceinline__ void edge_spread(const int32_t *__restrict__ pins, co
   }
 }
 
-// A workgroup takes kEdgesPerBlk = kThreads consecutive hyperedges; group
-// grp (LPR lanes) takes e0 + grp + ngrp k for k < LPR, and lane k of the
-// group fetches that hyperedge's pin range up front.
+// A workgroup takes kEdgesPerBlk consecutive hyperedges [e0, e1); group grp
+// (LPR lanes, ngrp groups) takes e0 + grp + ngrp k, in rounds of LPR: lane j
+// of the group fetches the pin range of the round's j-th hyperedge up front.
 template <int CPL, int PT>
 __global__ void __launch_bounds__(kThreads)
 k_score_qh(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
@@ -103,27 +103,29 @@ k_score_qh(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t e0 = blk * kEdgesPerBlk;
   const int64_t e1 = e0 + kEdgesPerBlk < m ? e0 + kEdgesPerBlk : m;
-  int32_t ea = 0, eb = 0;
-  float ew = 0.0f;
-  {
-    const int64_t e = e0 + grp + int64_t(ngrp) * sub;
-    if (e < e1) {
-      ea = eptr[e];
-      eb = eptr[e + 1];
-      ew = w ? w[e] : 1.0f;
-    }
-  }
   double acc[CPL];
 #pragma unroll
   for (int q = 0; q < CPL; ++q) acc[q] = 0.0;
-  for (int k = 0; k < LPR && e0 + grp + int64_t(ngrp) * k < e1; ++k) {
-    const int32_t a = __shfl(ea, k, LPR), b = __shfl(eb, k, LPR);
-    const double we = double(__shfl(ew, k, LPR));
-    if (c0 < K) {
-      double s[CPL];
-      edge_spread<CPL, PT>(pins, pool, K, c0, a, b, s);
+  for (int k0 = 0; k0 < kEdgesPerBlk / ngrp && e0 + grp + int64_t(ngrp) * k0 < e1; k0 += LPR) {
+    int32_t ea = 0, eb = 0;
+    float ew = 0.0f;
+    {
+      const int64_t e = e0 + grp + int64_t(ngrp) * (k0 + sub);
+      if (e < e1) {
+        ea = eptr[e];
+        eb = eptr[e + 1];
+        ew = w ? w[e] : 1.0f;
+      }
+    }
+    for (int k = 0; k < LPR && e0 + grp + int64_t(ngrp) * (k0 + k) < e1; ++k) {
+      const int32_t a = __shfl(ea, k, LPR), b = __shfl(eb, k, LPR);
+      const double we = double(__shfl(ew, k, LPR));
+      if (c0 < K) {
+        double s[CPL];
+        edge_spread<CPL, PT>(pins, pool, K, c0, a, b, s);
 #pragma unroll
-      for (int q = 0; q < CPL; ++q) acc[q] = fma(we, s[q], acc[q]);
+        for (int q = 0; q < CPL; ++q) acc[q] = fma(we, s[q], acc[q]);
+      }
     }
   }
   for (int g = 0; g < ngrp; ++g) {
@@ -156,26 +158,28 @@ k_score_r(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
     const double qv = (c0 + q < K) ? qh[c0 + q] : 0.0;
     inv[q] = qv > 0.0 ? 1.0 / qv : 0.0;
   }
-  int32_t ea = 0, eb = 0;
-  {
-    const int64_t e = e0 + grp + int64_t(ngrp) * sub;
-    if (e < e1) {
-      ea = eptr[e];
-      eb = eptr[e + 1];
+  for (int k0 = 0; k0 < kEdgesPerBlk / ngrp && e0 + grp + int64_t(ngrp) * k0 < e1; k0 += LPR) {
+    int32_t ea = 0, eb = 0;
+    {
+      const int64_t e = e0 + grp + int64_t(ngrp) * (k0 + sub);
+      if (e < e1) {
+        ea = eptr[e];
+        eb = eptr[e + 1];
+      }
     }
-  }
-  for (int k = 0; k < LPR && e0 + grp + int64_t(ngrp) * k < e1; ++k) {
-    const int64_t e = e0 + grp + int64_t(ngrp) * k;
-    const int32_t a = __shfl(ea, k, LPR), b = __shfl(eb, k, LPR);
-    double best = 0.0;
-    if (c0 < K) {
-      double s[CPL];
-      edge_spread<CPL, PT>(pins, pool, K, c0, a, b, s);
+    for (int k = 0; k < LPR && e0 + grp + int64_t(ngrp) * (k0 + k) < e1; ++k) {
+      const int64_t e = e0 + grp + int64_t(ngrp) * (k0 + k);
+      const int32_t a = __shfl(ea, k, LPR), b = __shfl(eb, k, LPR);
+      double best = 0.0;
+      if (c0 < K) {
+        double s[CPL];
+        edge_spread<CPL, PT>(pins, pool, K, c0, a, b, s);
 #pragma unroll
-      for (int q = 0; q < CPL; ++q) best = fmax(best, s[q] * inv[q]);
+        for (int q = 0; q < CPL; ++q) best = fmax(best, s[q] * inv[q]);
+      }
+      for (int off = LPR / 2; off > 0; off >>= 1) best = fmax(best, __shfl_xor(best, off, LPR));
+      if (sub == 0) R[e] = float(best);
     }
-    for (int off = LPR / 2; off > 0; off >>= 1) best = fmax(best, __shfl_xor(best, off, LPR));
-    if (sub == 0) R[e] = float(best);
   }
 }
 
