@@ -328,22 +328,40 @@ k_lapply(const float *__restrict__ v0, const float *__restrict__ v1,
   __shared__ double Ts[C * B];
   __shared__ float sm[3][RB * LDR];
   const int tid = threadIdx.x;
-  for (int e = tid; e < C * B; e += 256) Ts[e] = Tm[e];
   const int64_t row0 = int64_t(xcd_block(blockIdx.x, gridDim.x)) * RB;
   const int nrow = int(rows - row0 < RB ? rows - row0 : RB);
   const float *src[3] = {v0, v1, y};
-  // coalesced loads of the workgroup's rows into LDS
+  // coalesced loads of the workgroup's rows into LDS, all of a thread's
+  // loads issued before the first is stored
+  if constexpr (B >= 4) {
+    constexpr int NL = (RB * B / 4 + 255) / 256;  // float4 per thread and array
+    float4 t[3][NL];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    if (src[a] == nullptr) continue;
-    const float *base = src[a] + row0 * B;
-    if constexpr (B >= 4) {
-      for (int i = tid; i < nrow * B / 4; i += 256) {
-        const float4 t = reinterpret_cast<const float4 *>(base)[i];
-        float *d = &sm[a][(4 * i / B) * LDR + (4 * i) % B];
-        d[0] = t.x; d[1] = t.y; d[2] = t.z; d[3] = t.w;
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int u = 0; u < NL; ++u) {
+        const int i = tid + 256 * u;
+        t[a][u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (src[a] != nullptr && i < nrow * B / 4)
+          t[a][u] = reinterpret_cast<const float4 *>(src[a] + row0 * B)[i];
       }
-    } else {
+    for (int e = tid; e < C * B; e += 256) Ts[e] = Tm[e];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int u = 0; u < NL; ++u) {
+        const int i = tid + 256 * u;
+        if (src[a] != nullptr && i < nrow * B / 4) {
+          float *d = &sm[a][(4 * i / B) * LDR + (4 * i) % B];
+          d[0] = t[a][u].x; d[1] = t[a][u].y; d[2] = t[a][u].z; d[3] = t[a][u].w;
+        }
+      }
+  } else {
+    for (int e = tid; e < C * B; e += 256) Ts[e] = Tm[e];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (src[a] == nullptr) continue;
+      const float *base = src[a] + row0 * B;
       for (int i = tid; i < nrow * B; i += 256) sm[a][(i / B) * LDR + i % B] = base[i];
     }
   }
