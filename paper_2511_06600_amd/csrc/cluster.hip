@@ -183,7 +183,21 @@ k_centroids(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
     double acc[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    for (int32_t j = a; j < b; ++j) {
+    // two pins' rows in flight at a time; the sums run in pin order
+    int32_t j = a;
+    for (; j + 2 <= b; j += 2) {
+      const int64_t base0 = int64_t(pins[j]) * K, base1 = int64_t(pins[j + 1]) * K;
+      double v0[8], v1[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int col = lane + 64 * q;
+        v0[q] = pool_val<PT>(pool, base0 + (col < K ? col : K - 1));
+        v1[q] = pool_val<PT>(pool, base1 + (col < K ? col : K - 1));
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] = (acc[q] + v0[q]) + v1[q];
+    }
+    if (j < b) {
       const int64_t base = int64_t(pins[j]) * K;
       double v[8];
 #pragma unroll
@@ -200,6 +214,11 @@ k_centroids(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
       if (col < K) cent[c * K + col] = acc[q] / double(b - a);
     }
   }
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 // ---- a8: best neighbouring cluster of every isolated node --------------------
@@ -237,6 +256,7 @@ k_cperm(const int32_t *__restrict__ prov, const int32_t *__restrict__ owner,
         const void *__restrict__ pool, int K, int Kq, const int32_t *__restrict__ perm,
         const int32_t *__restrict__ nuse, _Float16 *__restrict__ cperm,
         int32_t *__restrict__ crow, int32_t n) {
+  __shared__ float rows[kT / 64][512];
   const int64_t v = int64_t(blockIdx.x) * (kT / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (v >= n || prov[v] != v) return;
@@ -244,28 +264,33 @@ k_cperm(const int32_t *__restrict__ prov, const int32_t *__restrict__ owner,
   const int64_t cr = ow < 0 ? -1 : in_index[ow];
   if (lane == 0) crow[v] = int32_t(cr);
   const int nu = *nuse;
-  // perm has 512 entries (zero from nuse on), so every load is in bounds
+  // the row (or its cluster's centroid) is read in column order into LDS,
+  // then permuted from there; perm has 512 entries (zero from nuse on)
+  float *row = rows[threadIdx.x >> 6];
+  if (cr < 0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c = lane + 64 * j;
+      const float x = float(pool_val<PT>(pool, v * K + (c < K ? c : K - 1)));
+      row[c] = c < K ? x : 0.0f;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c = lane + 64 * j;
+      const float x = float(cent[cr * K + (c < K ? c : K - 1)]);
+      row[c] = c < K ? x : 0.0f;
+    }
+  }
   int col[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) col[j] = perm[lane + 64 * j];
-  float val[8];
-  if (cr < 0) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) val[j] = float(pool_val<PT>(pool, v * K + col[j]));
-  } else {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) val[j] = float(cent[cr * K + col[j]]);
-  }
+  wave_sync();
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int q = lane + 64 * j;
-    if (q < Kq) cperm[v * Kq + q] = _Float16(q < nu ? val[j] : 0.0f);
+    if (q < Kq) cperm[v * Kq + q] = _Float16(q < nu ? row[col[j]] : 0.0f);
   }
-}
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
 }
 
 // Bounds of one column's term (x - c)^2 / Q_H from the float16 copy h of c:
