@@ -208,9 +208,9 @@ k_jtrinv(const double *__restrict__ LT, const int32_t *__restrict__ keep, int K,
 // G = V^T V.  Block = (row chunk, super-tile pair (a <= b) of 128-column
 // super blocks).  FP32 pool: 16 waves, one 32x32 tile of the 128x128 super
 // tile each (tiles below the diagonal of a diagonal super tile are skipped).
-// BF16 pool: 8 waves of two tiles each.  32-row slabs of both super blocks
-// are double-buffered in LDS; FP32 MFMA accumulators are flushed to float64
-// registers every 128 rows.
+// BF16 pool: 8 waves of two tiles each.  Row slabs of both super blocks are
+// double-buffered in LDS (64 rows, column-major, for the FP32 pool); FP32
+// MFMA accumulators are flushed to float64 registers every 128 rows.
 constexpr int kSB = 128;        // super-block width (4 MFMA tiles)
 constexpr int kSlab = 64;       // rows per LDS slab
 constexpr int kSLd = kSlab + 4; // LDS column stride (floats) of a slab
@@ -295,7 +295,7 @@ __device__ __forceinline__ void load8oct(const void *pool, int pool_type, int64_
     if (rb + q >= rows) v[q] = 0.0f;
 }
 
-// One 32-row slab of a 128-column super block into registers: row-major
+// 32 rows of a 128-column super block into registers: row-major
 // input (thread -> row, 8 columns) or row-octet input (thread -> octet of
 // rows, 1 column); the store puts it column-major in LDS (column c at
 // S + c * kSLd, rows contiguous), where an octet is two 16-byte stores.
@@ -440,10 +440,11 @@ __global__ void k_jgram_scatter(const double *__restrict__ sums, int nsb, int np
 
 // ---------------------------------------------------------------- apply
 // Q = V Rinv (n x K times upper-triangular K x K), out of place.  Block =
-// 128 x 128 output tile; 4 waves of 64 x 64 (2 x 2 MFMA tiles).  The k
-// loop runs over 32-wide chunks up to the tile's last column (Rinv is zero
-// below its diagonal); both operand chunks are staged in LDS, the next one
-// fetched into registers during the current chunk's products.
+// 128 x 128 output tile; 8 waves of 64 x 32 (2 x 1 MFMA tiles) for the FP32
+// pool, 4 waves of 64 x 64 for the BF16 pool.  The k loop runs over 32-wide
+// chunks up to the tile's last column (Rinv is zero below its diagonal);
+// both operand chunks are staged in LDS, the next one fetched into
+// registers during the current chunk's products.
 constexpr int kAT = 256;         // BF16 apply workgroup size
 constexpr int kAT32 = 512;       // FP32 apply workgroup size
 constexpr int kAM = 128, kAN = 128, kAK = 32;
