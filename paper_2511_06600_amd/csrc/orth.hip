@@ -36,6 +36,7 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 // its column of L is zero.
 constexpr int kPW = 32;
 constexpr int kPS = kPW + 1;  // LDS row stride of a panel
+constexpr int kMaxPB = 16;    // 32-column blocks of the widest pool (K <= 512)
 
 // Right-looking: A holds G minus the contributions of the finished panels
 // (lower triangle).  Panel [c0, c0+w) is factored by one workgroup in LDS
@@ -53,10 +54,11 @@ k_chol_panel(const double *__restrict__ A, const double *__restrict__ G, int K, 
   const int t = threadIdx.x;
   const int w = K - c0 < kPW ? K - c0 : kPW;
   const int nr = K - c0;
-  for (int e = t; e < nr * w; e += 1024) {
-    const int i = e / w, j = e % w;
-    pan[i * kPS + j] = i >= j ? A[int64_t(c0 + i) * K + c0 + j] : 0.0;
-  }
+  // thread t works on panel column t % 32 and rows t / 32 + 32 k
+  const int tc = t & (kPW - 1), tr = t >> 5;
+  if (tc < w)
+    for (int i = tr; i < nr; i += 1024 / kPW)
+      pan[i * kPS + tc] = i >= tc ? A[int64_t(c0 + i) * K + c0 + tc] : 0.0;
   if (t < w) {
     s_ref[t] = G[int64_t(c0 + t) * K + c0 + t];
     s_force[t] = force_keep ? force_keep[c0 + t] : 1;
@@ -78,21 +80,16 @@ k_chol_panel(const double *__restrict__ A, const double *__restrict__ G, int K, 
     for (int i = jj + 1 + t; i < nr; i += 1024)
       pan[i * kPS + jj] = kp ? pan[i * kPS + jj] / piv : 0.0;
     __syncthreads();
-    if (kp) {
-      const int wc = w - jj - 1;
-      if (wc > 0) {
-        for (int e = t; e < (nr - jj - 1) * wc; e += 1024) {
-          const int i = jj + 1 + e / wc, q = jj + 1 + e % wc;
-          if (q <= i) pan[i * kPS + q] -= pan[i * kPS + jj] * pan[q * kPS + jj];
-        }
-      }
+    if (kp && tc > jj && tc < w) {
+      const double lq = pan[tc * kPS + jj];
+      for (int i = tr; i < nr; i += 1024 / kPW)
+        if (i >= tc) pan[i * kPS + tc] -= pan[i * kPS + jj] * lq;
     }
     __syncthreads();
   }
-  for (int e = t; e < nr * w; e += 1024) {
-    const int i = e / w, j = e % w;
-    if (i >= j) LT[int64_t(c0 + j) * K + c0 + i] = pan[i * kPS + j];
-  }
+  if (tc < w)
+    for (int i = tr; i < nr; i += 1024 / kPW)
+      if (i >= tc) LT[int64_t(c0 + tc) * K + c0 + i] = pan[i * kPS + tc];
 }
 
 // A[i][q] -= sum_{l in [c0, c0+w)} L[i][l] L[q][l] for c0+w <= q <= i < K:
@@ -148,19 +145,26 @@ k_jtrinv(const double *__restrict__ LT, const int32_t *__restrict__ keep, int K,
     const int i0 = I * kPW;
     const int wi = K - i0 < kPW ? K - i0 : kPW;
     // T = -sum_{m in [j0, i0)} L[i0+i][m] X[m][j]   (zero for I == J), the
-    // rows of L staged in LDS one 32 x 32 block at a time
+    // rows of L staged in LDS one 32 x 32 block at a time; every block of
+    // the row is loaded into registers up front (K <= 512: at most 16)
     {
       const int i = t / kPW, j = t % kPW;
+      const int mm = t / kPW, ii = t % kPW;
       double acc = (I == J && i == j) ? 1.0 : 0.0;
-      for (int M0 = j0; M0 < i0; M0 += kPW) {
-        __syncthreads();
-        {
-          const int mm = t / kPW, ii = t % kPW;
-          Lb[ii * kPS + mm] = ii < wi ? LT[int64_t(M0 + mm) * K + i0 + ii] : 0.0;
-        }
-        __syncthreads();
-        if (i < wi && j < wj) {
-          for (int mm = 0; mm < kPW; ++mm) acc -= Lb[i * kPS + mm] * X[(M0 + mm) * kPS + j];
+      double lreg[kMaxPB];
+#pragma unroll
+      for (int bb = 0; bb < kMaxPB; ++bb)
+        if (bb < I - J) lreg[bb] = ii < wi ? LT[int64_t(j0 + bb * kPW + mm) * K + i0 + ii] : 0.0;
+#pragma unroll
+      for (int bb = 0; bb < kMaxPB; ++bb) {
+        if (bb < I - J) {
+          const int M0 = j0 + bb * kPW;
+          __syncthreads();
+          Lb[ii * kPS + mm] = lreg[bb];
+          __syncthreads();
+          if (i < wi && j < wj) {
+            for (int m2 = 0; m2 < kPW; ++m2) acc -= Lb[i * kPS + m2] * X[(M0 + m2) * kPS + j];
+          }
         }
       }
       T[i * kPS + j] = acc;
