@@ -216,11 +216,6 @@ k_centroids(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
   }
 }
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
 // ---- a8: best neighbouring cluster of every isolated node --------------------
 // Columns with Q_H > 0 sorted by ascending Q_H (largest weights first).
 __global__ void __launch_bounds__(512)

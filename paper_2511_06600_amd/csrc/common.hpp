@@ -67,6 +67,13 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // padded to oct_rows(n) (padding rows are zero).
 inline int64_t oct_rows(int64_t n) { return (n + 7) / 8 * 8; }
 
+// Orders the LDS accesses of one wave: what a lane wrote before the call is
+// seen by the wave's other lanes after it.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Map a launched block index to a logical one so that each of the 8 XCDs of
 // an MI355X (which receive blocks round-robin) walks a contiguous range of
 // logical blocks; neighbouring work then shares its XCD's L2.

@@ -148,7 +148,7 @@ k_jtrinv(const double *__restrict__ LT, const int32_t *__restrict__ keep, int K,
     // rows of L staged in LDS one 32 x 32 block at a time; every block of
     // the row is loaded into registers up front (K <= 512: at most 16)
     {
-      const int i = t / kPW, j = t % kPW;
+      const int j = t / kPW, i = t % kPW;
       const int mm = t / kPW, ii = t % kPW;
       double acc = (I == J && i == j) ? 1.0 : 0.0;
       double lreg[kMaxPB];
@@ -171,9 +171,10 @@ k_jtrinv(const double *__restrict__ LT, const int32_t *__restrict__ keep, int K,
     }
     __syncthreads();
     // solve L_II X_IJ = T by forward substitution: L_II staged in LDS,
-    // thread (i, j) keeps row i of column j; step l fixes x_l and removes
-    // it from the rows below (the same products, subtracted in the same
-    // ascending order as a row-by-row substitution)
+    // thread (i, j) keeps row i of column j, a column's 32 rows in one wave;
+    // step l fixes x_l and removes it from the rows below (the same
+    // products, subtracted in the same ascending order as a row-by-row
+    // substitution)
     {
       const int mm = t / kPW, ii = t % kPW;
       Lb[ii * kPS + mm] = (ii < wi && mm < wi) ? LT[int64_t(i0 + mm) * K + i0 + ii] : 0.0;
@@ -184,7 +185,7 @@ k_jtrinv(const double *__restrict__ LT, const int32_t *__restrict__ keep, int K,
     }
     __syncthreads();
     {
-      const int i = t / kPW, j = t % kPW;
+      const int j = t / kPW, i = t % kPW;
       double acc = T[i * kPS + j];
       for (int l = 0; l < wi; ++l) {
         if (i == l) {
@@ -192,7 +193,7 @@ k_jtrinv(const double *__restrict__ LT, const int32_t *__restrict__ keep, int K,
           if (j < wj) X[(i0 + l) * kPS + j] = x;
           T[l * kPS + j] = x;
         }
-        __syncthreads();
+        wave_sync();
         if (i > l) acc -= Lb[i * kPS + l] * T[l * kPS + j];
       }
     }
