@@ -46,7 +46,7 @@ namespace hef {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kEdgesPerBlk = 256;
+constexpr int kEdgesPerBlk = 64;
 constexpr int kXBlocks = 2048;  // workgroups of the step cross products
 
 // ------------------------------------------------------------ pool loads

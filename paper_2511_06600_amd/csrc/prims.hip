@@ -155,16 +155,22 @@ k_reduce_cols(const double *__restrict__ in, int64_t nrows, int64_t ncols,
   __shared__ double red[32][9];
   const int cl = threadIdx.x & 7, rl = threadIdx.x >> 3;
   const int64_t c = int64_t(blockIdx.x) * 8 + cl;
-  double a0 = 0.0, a1 = 0.0;
+  // eight independent loads in flight per row lane
+  double acc[8] = {};
   if (c < ncols) {
     int64_t r = rl;
-    for (; r + 32 < nrows; r += 64) {
-      a0 += in[r * ncols + c];
-      a1 += in[(r + 32) * ncols + c];
+    for (; r + 7 * 32 < nrows; r += 8 * 32) {
+      double t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[q] = in[(r + 32 * q) * ncols + c];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] += t[q];
     }
-    if (r < nrows) a0 += in[r * ncols + c];
+#pragma unroll
+    for (int q = 0; q < 7; ++q)
+      if (r + 32 * q < nrows) acc[q] += in[(r + 32 * q) * ncols + c];
   }
-  red[rl][cl] = a0 + a1;
+  red[rl][cl] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   __syncthreads();
   for (int off = 16; off > 0; off >>= 1) {
     if (rl < off) red[rl][cl] += red[rl + off][cl];

@@ -28,7 +28,7 @@ hef_status compact_flags(const int32_t *flag, int32_t *scratch, int32_t *idx_out
                          int32_t *count_dev, int64_t n, Arena &ws, hipStream_t s);
 
 // out[c] = sum_r in[r * ncols + c] (float64) in a fixed order that does not
-// depend on timing: 32 row lanes per column each sum every 32nd row (two
+// depend on timing: 32 row lanes per column each sum every 32nd row (eight
 // interleaved accumulators), then a fixed tree over the lanes.
 hef_status reduce_cols_f64(const double *in, int64_t nrows, int64_t ncols, double *out,
                            hipStream_t s);
