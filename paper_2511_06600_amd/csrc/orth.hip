@@ -469,7 +469,9 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oc
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = tid >> 6;
-  const int wr = (w >> 2) * 64, wc = (w & 3) * 32;
+  // the column quarter of wave w rotates with the block, so that the waves
+  // which stop early (below) fall on every SIMD in turn
+  const int wr = (w >> 2) * 64, wc = int(((w & 3) + lb) & 3) * 32;
   floatx16 acc[2][1];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -479,6 +481,8 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oc
       for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
   // Rinv is upper triangular: rows past the tile's last column are zero
   const int kend = (!full && col0 + kAN < K) ? col0 + kAN : K;
+  // ... and the wave's own columns need rows k < col0 + wc + 32 only
+  const int kw = (!full && col0 + wc + 32 < kend) ? col0 + wc + 32 : kend;
   // the next k chunk is fetched into registers while the current one is
   // multiplied: A = 128 rows x 32 columns of V (2 groups of 8 values per
   // thread), B = 32 rows x 128 columns of Rinv32 (4 float4 per thread)
@@ -533,6 +537,7 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oc
     stash(k0);
     __syncthreads();
     if (k0 + kAK < kend) fetch(k0 + kAK);
+    if (k0 >= kw) continue;
 #pragma unroll 4
     for (int s = 0; s < kAK / 2; ++s) {
       const int kk = 2 * s + (lane >> 5);
