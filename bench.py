@@ -221,10 +221,10 @@ def main():
                        nfused)),
         "k_lgram": roofline_entry("hbm", lg_b, ms_of("lanczos_gram"), per.get("lanczos_gram", (0, 0))[1],
                                   PEAK_HBM_GBS, "GB/s", ["k_lgram"],
-                                  traffic_of(["k_lgram"], 2 * (k + 1) * len(levels))),
+                                  traffic_of(["k_lgram"], (k + 1) * len(levels))),
         "k_lapply": roofline_entry("hbm", la_b, ms_of("lanczos_apply"), per.get("lanczos_apply", (0, 0))[1],
                                    PEAK_HBM_GBS, "GB/s", ["k_lapply"],
-                                   traffic_of(["k_lapply"], 2 * (k + 1) * len(levels))),
+                                   traffic_of(["k_lapply"], (k + 1) * len(levels))),
         "k_jgram": roofline_entry("mfma", jg_f, ms_of("orth_gram"), per.get("orth_gram", (0, 0))[1],
                                   PEAK_FP32_MFMA, "TFLOP/s", ["k_jgram"],
                                   traffic_of(["k_jgram"], len(levels))),

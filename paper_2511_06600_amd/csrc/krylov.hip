@@ -81,11 +81,29 @@ struct GramSlab {
 // groups split each slab's rows.  Per-thread FP32 sums (a few hundred rows)
 // are combined in float64 in row-group order; partial[blk][C*C].  The next
 // slab is loaded into registers while the current one is consumed.
+// Operands of one expansion's Gram.  A launch covers two expansions:
+// workgroups [0, nb0) take side 0, the rest side 1.
+struct GramSide {
+  const float *v0, *v1, *y;
+  int64_t rows, rows_per_blk;
+  double *partial;
+};
+struct GramPair {
+  GramSide s[2];
+  int nb0;
+};
+
 template <int B>
 __global__ void __launch_bounds__(256)
-k_lgram(const float *__restrict__ v0, const float *__restrict__ v1,
-        const float *__restrict__ y, int64_t rows, int64_t rows_per_blk,
-        double *__restrict__ partial) {
+k_lgram(const GramPair P) {
+  const bool second = int(blockIdx.x) >= P.nb0;
+  const int bid = int(blockIdx.x) - (second ? P.nb0 : 0);
+  const float *__restrict__ v0 = second ? P.s[1].v0 : P.s[0].v0;
+  const float *__restrict__ v1 = second ? P.s[1].v1 : P.s[0].v1;
+  const float *__restrict__ y = second ? P.s[1].y : P.s[0].y;
+  const int64_t rows = second ? P.s[1].rows : P.s[0].rows;
+  const int64_t rows_per_blk = second ? P.s[1].rows_per_blk : P.s[0].rows_per_blk;
+  double *__restrict__ partial = second ? P.s[1].partial : P.s[0].partial;
   constexpr int C = 3 * B;
   constexpr int S = (C % 6 == 0) ? 6 : 3;
   constexpr int NB = C / S;
@@ -113,7 +131,7 @@ k_lgram(const float *__restrict__ v0, const float *__restrict__ v1,
   for (int a = 0; a < S; ++a)
 #pragma unroll
     for (int b = 0; b < S; ++b) acc[a][b] = 0.0f;
-  const int64_t r0 = int64_t(blockIdx.x) * rows_per_blk;
+  const int64_t r0 = int64_t(bid) * rows_per_blk;
   const int64_t r1 = r0 + rows_per_blk < rows ? r0 + rows_per_blk : rows;
   // the next slab is fetched into registers while the current one is used
   using SL = GramSlab<B, SLAB>;
@@ -159,7 +177,7 @@ k_lgram(const float *__restrict__ v0, const float *__restrict__ v1,
       const int off = id * S * S + (i % S) * S + (j % S);
       for (int gg = 0; gg < RG; ++gg) t += double(red[gg * NT * S * S + off]);
     }
-    partial[int64_t(blockIdx.x) * C * C + e] = t;
+    partial[int64_t(bid) * C * C + e] = t;
   }
 }
 
@@ -167,12 +185,19 @@ k_lgram(const float *__restrict__ v0, const float *__restrict__ v1,
 // accumulators each, then a fixed tree), written for the entries in blocks
 // on or above the diagonal and mirrored into the blocks below it.
 // 256 threads = 8 columns x 32 row lanes.
+// Two expansions per launch: workgroups [0, nbh) reduce (in0, nrows0) into
+// G0, the rest (in1, nrows1) into G1.
 __global__ void __launch_bounds__(256)
-k_gram_reduce(const double *__restrict__ in, int64_t nrows, int C, int S,
-              double *__restrict__ G) {
+k_gram_reduce(const double *__restrict__ in0, int64_t nrows0, double *__restrict__ G0,
+              const double *__restrict__ in1, int64_t nrows1, double *__restrict__ G1, int nbh,
+              int C, int S) {
   __shared__ double red[32][9];
+  const bool second = int(blockIdx.x) >= nbh;
+  const double *__restrict__ in = second ? in1 : in0;
+  const int64_t nrows = second ? nrows1 : nrows0;
+  double *__restrict__ G = second ? G1 : G0;
   const int cl = threadIdx.x & 7, rl = threadIdx.x >> 3;
-  const int64_t c = int64_t(blockIdx.x) * 8 + cl;
+  const int64_t c = int64_t(int(blockIdx.x) - (second ? nbh : 0)) * 8 + cl;
   const int64_t ncols = int64_t(C) * C;
   const int i = int(c / C), j = int(c % C);
   const bool upper = c < ncols && i / S <= j / S;
@@ -314,12 +339,23 @@ __device__ __forceinline__ void ld(const float *p, float (&v)[CH]) {
   }
 }
 
+// Operands of one expansion's apply.  A launch covers two expansions:
+// logical workgroups [0, nb0) take side 0, the rest side 1.
+struct ApplySide {
+  const float *v0, *v1, *y;
+  const double *T;
+  float *vn;
+  int64_t rows;
+  int col0;
+};
+struct ApplyPair {
+  ApplySide s[2];
+  int64_t nb0;
+};
+
 template <int B>
 __global__ void __launch_bounds__(256)
-k_lapply(const float *__restrict__ v0, const float *__restrict__ v1,
-         const float *__restrict__ y, const double *__restrict__ Tm, float *__restrict__ vn,
-         int64_t rows, void *__restrict__ pool, int pool_type, int64_t pool_rows, int K,
-         int col0) {
+k_lapply(const ApplyPair P, void *__restrict__ pool, int pool_type, int64_t pool_rows, int K) {
   constexpr int C = 3 * B;
   constexpr int RB = B <= 8 ? 256 : 128;  // rows per workgroup
   constexpr int NSPL = 256 / RB;          // threads per row
@@ -328,7 +364,16 @@ k_lapply(const float *__restrict__ v0, const float *__restrict__ v1,
   __shared__ double Ts[C * B];
   __shared__ float sm[3][RB * LDR];
   const int tid = threadIdx.x;
-  const int64_t row0 = int64_t(xcd_block(blockIdx.x, gridDim.x)) * RB;
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const bool second = lb >= P.nb0;
+  const float *__restrict__ v0 = second ? P.s[1].v0 : P.s[0].v0;
+  const float *__restrict__ v1 = second ? P.s[1].v1 : P.s[0].v1;
+  const float *__restrict__ y = second ? P.s[1].y : P.s[0].y;
+  const double *__restrict__ Tm = second ? P.s[1].T : P.s[0].T;
+  float *__restrict__ vn = second ? P.s[1].vn : P.s[0].vn;
+  const int64_t rows = second ? P.s[1].rows : P.s[0].rows;
+  const int col0 = second ? P.s[1].col0 : P.s[0].col0;
+  const int64_t row0 = (lb - (second ? P.nb0 : 0)) * RB;
   const int nrow = int(rows - row0 < RB ? rows - row0 : RB);
   const float *src[3] = {v0, v1, y};
   // coalesced loads of the workgroup's rows into LDS, all of a thread's
@@ -452,54 +497,90 @@ __global__ void k_start(uint64_t h, int64_t total, float *out) {
   out[i] = float(sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2));
 }
 
+// Sides with zero rows launch nothing.
 template <int B>
-hef_status apply_t(const float *v0, const float *v1, const float *y, const double *T, float *vn,
-                   int64_t rows, void *pool, int pool_type, int64_t pool_rows, int K, int col0,
-                   hipStream_t s) {
-  if (rows == 0) return HEF_OK;
-  TimedScope ts(kStLanczosApply, s);
+hef_status apply_t(const ApplySide &a, const ApplySide &b, void *pool, int pool_type,
+                   int64_t pool_rows, int K, hipStream_t s) {
   constexpr int RB = B <= 8 ? 256 : 128;
-  k_lapply<B><<<cdiv(rows, RB), 256, 0, s>>>(v0, v1, y, T, vn, rows, pool, pool_type, pool_rows,
-                                            K, col0);
+  ApplyPair P;
+  P.s[0] = a;
+  P.s[1] = b;
+  P.nb0 = cdiv(a.rows, RB);
+  const int64_t nblk = P.nb0 + cdiv(b.rows, RB);
+  if (nblk == 0) return HEF_OK;
+  TimedScope ts(kStLanczosApply, s);
+  k_lapply<B><<<nblk, 256, 0, s>>>(P, pool, pool_type, pool_rows, K);
   HEF_LAUNCH_CHECK();
   return HEF_OK;
+}
+
+hef_status lapply2(int B, const ApplySide &a, const ApplySide &b, void *pool, int pool_type,
+                   int64_t pool_rows, int K, hipStream_t s) {
+  switch (B) {
+    case 1: return apply_t<1>(a, b, pool, pool_type, pool_rows, K, s);
+    case 2: return apply_t<2>(a, b, pool, pool_type, pool_rows, K, s);
+    case 4: return apply_t<4>(a, b, pool, pool_type, pool_rows, K, s);
+    case 8: return apply_t<8>(a, b, pool, pool_type, pool_rows, K, s);
+    case 16: return apply_t<16>(a, b, pool, pool_type, pool_rows, K, s);
+    default: return HEF_ERR_UNSUPPORTED;
+  }
 }
 
 hef_status lapply(int B, const float *v0, const float *v1, const float *y, const double *T,
                   float *vn, int64_t rows, void *pool, int pool_type, int64_t pool_rows, int K,
                   int col0, hipStream_t s) {
-  switch (B) {
-    case 1: return apply_t<1>(v0, v1, y, T, vn, rows, pool, pool_type, pool_rows, K, col0, s);
-    case 2: return apply_t<2>(v0, v1, y, T, vn, rows, pool, pool_type, pool_rows, K, col0, s);
-    case 4: return apply_t<4>(v0, v1, y, T, vn, rows, pool, pool_type, pool_rows, K, col0, s);
-    case 8: return apply_t<8>(v0, v1, y, T, vn, rows, pool, pool_type, pool_rows, K, col0, s);
-    case 16: return apply_t<16>(v0, v1, y, T, vn, rows, pool, pool_type, pool_rows, K, col0, s);
-    default: return HEF_ERR_UNSUPPORTED;
-  }
+  const ApplySide a{v0, v1, y, T, vn, rows, col0};
+  const ApplySide none{nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0};
+  return lapply2(B, a, none, pool, pool_type, pool_rows, K, s);
 }
 
-hef_status lgram(const float *v0, const float *v1, const float *y, int64_t rows, int B,
-                 double *partial, double *G, hipStream_t s) {
+// The Grams of up to two expansions (a side with y == nullptr is skipped),
+// each over its own rows, in one Gram launch and one reduce launch.
+hef_status lgram2(int B, const float *v0a, const float *v1a, const float *ya, int64_t rowsa,
+                  double *partiala, double *Ga, const float *v0b, const float *v1b,
+                  const float *yb, int64_t rowsb, double *partialb, double *Gb, hipStream_t s) {
   const int C = 3 * B;
   const int S = (C % 6 == 0) ? 6 : 3;
-  const int64_t per = std::max<int64_t>(64, cdiv(cdiv(rows, kGramBlocks), 64) * 64);
-  const int nblk = int(std::max<int64_t>(1, cdiv(rows, per)));
+  GramPair P;
+  int nb[2] = {0, 0};
+  const float *v0[2] = {v0a, v0b}, *v1[2] = {v1a, v1b}, *y[2] = {ya, yb};
+  const int64_t rows[2] = {rowsa, rowsb};
+  double *part[2] = {partiala, partialb};
+  for (int i = 0; i < 2; ++i) {
+    const int64_t per = std::max<int64_t>(64, cdiv(cdiv(rows[i], kGramBlocks), 64) * 64);
+    nb[i] = y[i] ? int(std::max<int64_t>(1, cdiv(rows[i], per))) : 0;
+    P.s[i] = GramSide{v0[i], v1[i], y[i], rows[i], per, part[i]};
+  }
+  P.nb0 = nb[0];
+  const int nblk = nb[0] + nb[1];
+  if (nblk == 0) return HEF_OK;
   {
   TimedScope ts(kStLanczosGram, s);
   switch (B) {
-    case 1: k_lgram<1><<<nblk, 256, 0, s>>>(v0, v1, y, rows, per, partial); break;
-    case 2: k_lgram<2><<<nblk, 256, 0, s>>>(v0, v1, y, rows, per, partial); break;
-    case 4: k_lgram<4><<<nblk, 256, 0, s>>>(v0, v1, y, rows, per, partial); break;
-    case 8: k_lgram<8><<<nblk, 256, 0, s>>>(v0, v1, y, rows, per, partial); break;
-    case 16: k_lgram<16><<<nblk, 256, 0, s>>>(v0, v1, y, rows, per, partial); break;
+    case 1: k_lgram<1><<<nblk, 256, 0, s>>>(P); break;
+    case 2: k_lgram<2><<<nblk, 256, 0, s>>>(P); break;
+    case 4: k_lgram<4><<<nblk, 256, 0, s>>>(P); break;
+    case 8: k_lgram<8><<<nblk, 256, 0, s>>>(P); break;
+    case 16: k_lgram<16><<<nblk, 256, 0, s>>>(P); break;
     default: return HEF_ERR_UNSUPPORTED;
   }
   HEF_LAUNCH_CHECK();
   }
   TimedScope ts(kStLanczosReduce, s);
-  k_gram_reduce<<<cdiv(int64_t(C) * C, 8), 256, 0, s>>>(partial, nblk, C, S, G);
+  const int nbh = int(cdiv(int64_t(C) * C, 8));
+  if (nb[0] > 0 && nb[1] > 0)
+    k_gram_reduce<<<2 * nbh, 256, 0, s>>>(partiala, nb[0], Ga, partialb, nb[1], Gb, nbh, C, S);
+  else if (nb[0] > 0)
+    k_gram_reduce<<<nbh, 256, 0, s>>>(partiala, nb[0], Ga, nullptr, 0, nullptr, nbh, C, S);
+  else
+    k_gram_reduce<<<nbh, 256, 0, s>>>(partialb, nb[1], Gb, nullptr, 0, nullptr, nbh, C, S);
   HEF_LAUNCH_CHECK();
   return HEF_OK;
+}
+
+hef_status lgram(const float *v0, const float *v1, const float *y, int64_t rows, int B,
+                 double *partial, double *G, hipStream_t s) {
+  return lgram2(B, v0, v1, y, rows, partial, G, nullptr, nullptr, nullptr, 0, nullptr, nullptr, s);
 }
 
 }  // namespace
@@ -597,20 +678,21 @@ hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double
   const int K = out.K;
   const int64_t bk = int64_t(B) * k;
   // V_0 = X R^-1 (no pool write)
-  if (use_star) {
+  if (use_star)
     HEF_HIP(hipMemcpyAsync(sb[iy], start_star, Ns * B * sizeof(float), hipMemcpyDeviceToDevice, s));
-    HEF_TRY(lgram(nullptr, nullptr, sb[iy], Ns, B, ps, Gs, s));
-  }
-  if (use_clique) {
+  if (use_clique)
     HEF_HIP(hipMemcpyAsync(cb[iy], start_clique, n * B * sizeof(float), hipMemcpyDeviceToDevice, s));
-    HEF_TRY(lgram(nullptr, nullptr, cb[iy], n, B, pc, Gc, s));
-  }
+  HEF_TRY(lgram2(B, nullptr, nullptr, use_star ? sb[iy] : nullptr, Ns, ps, Gs, nullptr, nullptr,
+                 use_clique ? cb[iy] : nullptr, n, pc, Gc, s));
   {
     TimedScope ts(kStLanczosSolve, s);
     HEF_TRY(lsolve_launch(G, B, tau, t_of(0), drops, r_of(0), s));
   }
-  if (use_star) HEF_TRY(lapply(B, nullptr, nullptr, sb[iy], t_of(0), sb[in], Ns, nullptr, 0, 0, K, 0, s));
-  if (use_clique) HEF_TRY(lapply(B, nullptr, nullptr, cb[iy], t_of(0) + C * B, cb[in], n, nullptr, 0, 0, K, 0, s));
+  {
+    const ApplySide as{nullptr, nullptr, sb[iy], t_of(0), sb[in], use_star ? Ns : 0, 0};
+    const ApplySide ac{nullptr, nullptr, cb[iy], t_of(0) + C * B, cb[in], use_clique ? n : 0, 0};
+    HEF_TRY(lapply2(B, as, ac, nullptr, 0, 0, K, s));
+  }
   HEF_TRY(checkpoint(0, nullptr, sb[in], nullptr, cb[in]));
   // rotate: cur <- next; prev stays "absent" for step 1
   std::swap(ic, in);
@@ -619,10 +701,9 @@ hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double
   for (int j = 1; j <= k; ++j) {
     HEF_TRY(spmm_apply(L, st, B, use_star ? sb[ic] : nullptr, use_star ? sb[iy] : nullptr,
                        use_clique ? cb[ic] : nullptr, use_clique ? cb[iy] : nullptr, tb, s));
-    if (use_star)
-      HEF_TRY(lgram(have_prev ? sb[ip] : nullptr, sb[ic], sb[iy], Ns, B, ps, Gs, s));
-    if (use_clique)
-      HEF_TRY(lgram(have_prev ? cb[ip] : nullptr, cb[ic], cb[iy], n, B, pc, Gc, s));
+    HEF_TRY(lgram2(B, have_prev ? sb[ip] : nullptr, sb[ic], use_star ? sb[iy] : nullptr, Ns, ps,
+                   Gs, have_prev ? cb[ip] : nullptr, cb[ic], use_clique ? cb[iy] : nullptr, n, pc,
+                   Gc, s));
     double *Tj = t_of(j);
     {
       TimedScope ts(kStLanczosSolve, s);
@@ -630,12 +711,13 @@ hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double
     }
     const int64_t col_s = (j - 1) * int64_t(B);
     const int64_t col_c = (use_star ? bk : 0) + (j - 1) * int64_t(B);
-    if (use_star)
-      HEF_TRY(lapply(B, have_prev ? sb[ip] : nullptr, sb[ic], sb[iy], Tj, sb[in], Ns, out.pool,
-                     out.pool_type, n, K, int(col_s), s));
-    if (use_clique)
-      HEF_TRY(lapply(B, have_prev ? cb[ip] : nullptr, cb[ic], cb[iy], Tj + C * B, cb[in], n, out.pool,
-                     out.pool_type, n, K, int(col_c), s));
+    {
+      const ApplySide as{have_prev ? sb[ip] : nullptr, sb[ic], sb[iy], Tj, sb[in],
+                         use_star ? Ns : 0, int(col_s)};
+      const ApplySide ac{have_prev ? cb[ip] : nullptr, cb[ic], cb[iy], Tj + C * B, cb[in],
+                         use_clique ? n : 0, int(col_c)};
+      HEF_TRY(lapply2(B, as, ac, out.pool, out.pool_type, n, K, s));
+    }
     HEF_TRY(checkpoint(j, sb[ic], sb[in], cb[ic], cb[in]));
     // rotate prev <- cur <- next, next <- old prev
     const int old_prev = ip;
