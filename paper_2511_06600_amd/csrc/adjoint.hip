@@ -300,29 +300,25 @@ __global__ void k_qradj_w(const double *__restrict__ Rinv, const double *__restr
 }
 
 // ------------------------------------------------------------ 3. Lanczos steps
-// vbar = abar + (pool rows) pbar[:, col .. col+B); abar is cleared for reuse.
-template <int B>
-__global__ void k_vbar(float *__restrict__ abar, const float *__restrict__ pbar, int K, int col,
-                       int64_t pool_rows, int64_t rows, float *__restrict__ vbar) {
-  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (g >= rows * B) return;
-  const int64_t r = g / B;
-  const int c = int(g % B);
-  float v = abar[g];
-  if (r < pool_rows) v += pbar[r * K + col + c];
-  vbar[g] = v;
-  abar[g] = 0.0f;
-}
-
 // X3 = [v0 | v1 | y]^T vbar (3B x B, float64): per workgroup a row range in
 // 64-row LDS slabs, one output entry (or a few) per thread, FP32 per slab,
 // float64 across slabs; partial[blk][3B*B].
-// One SL-row slab of [v0 | v1 | y | vb] into registers (element g of the
+// vbar = abar + pbar[:, col .. col + B) on the first pool_rows rows, formed
+// while the cross products read it; abar is cleared for the next step.
+struct VbarIn {
+  float *abar;
+  const float *pbar;
+  int K, col;
+  int64_t pool_rows;
+  float *vbar;
+};
+
+// One SL-row slab of [v0 | v1 | y | vbar] into registers (element g of the
 // slab: row g / (C + B), column g % (C + B)); zeros past r1.
 template <int B, int SL, int PF>
 __device__ __forceinline__ void xgram_fetch(float (&pre)[PF], int tid, int64_t rs, int64_t r1,
                                             const float *v0, const float *v1, const float *y,
-                                            const float *vb) {
+                                            const VbarIn &vi) {
   constexpr int C = 3 * B;
 #pragma unroll
   for (int i = 0; i < PF; ++i) {
@@ -335,7 +331,13 @@ __device__ __forceinline__ void xgram_fetch(float (&pre)[PF], int tid, int64_t r
         const float *sp = c < B ? v0 : (c < 2 * B ? v1 : y);
         v = sp ? sp[row * B + (c % B)] : 0.0f;
       } else {
-        v = vb[row * B + (c - C)];
+        // vbar = abar + the pool adjoint's columns, written out (and abar
+        // cleared) here: every row is fetched exactly once
+        const int64_t gi = row * B + (c - C);
+        v = vi.abar[gi];
+        if (row < vi.pool_rows) v += vi.pbar[row * vi.K + vi.col + (c - C)];
+        vi.vbar[gi] = v;
+        vi.abar[gi] = 0.0f;
       }
     }
     pre[i] = v;
@@ -345,8 +347,7 @@ __device__ __forceinline__ void xgram_fetch(float (&pre)[PF], int tid, int64_t r
 template <int B>
 __global__ void __launch_bounds__(kThreads)
 k_xgram(const float *__restrict__ v0, const float *__restrict__ v1, const float *__restrict__ y,
-        const float *__restrict__ vb, int64_t rows, int64_t rows_per_blk,
-        double *__restrict__ partial) {
+        const VbarIn vi, int64_t rows, int64_t rows_per_blk, double *__restrict__ partial) {
   constexpr int C = 3 * B;
   constexpr int NE = C * B;
   constexpr int EPT = (NE + kThreads - 1) / kThreads;
@@ -367,7 +368,7 @@ k_xgram(const float *__restrict__ v0, const float *__restrict__ v1, const float 
   // the next slab is fetched into registers while the current one is used
   constexpr int PF = (SL * (C + B) + kThreads - 1) / kThreads;
   float pre[PF];
-  if (r0 < r1) xgram_fetch<B, SL, PF>(pre, tid, r0, r1, v0, v1, y, vb);
+  if (r0 < r1) xgram_fetch<B, SL, PF>(pre, tid, r0, r1, v0, v1, y, vi);
   for (int64_t rs = r0; rs < r1; rs += SL) {
     __syncthreads();
 #pragma unroll
@@ -379,7 +380,7 @@ k_xgram(const float *__restrict__ v0, const float *__restrict__ v1, const float 
       }
     }
     __syncthreads();
-    if (rs + SL < r1) xgram_fetch<B, SL, PF>(pre, tid, rs + SL, r1, v0, v1, y, vb);
+    if (rs + SL < r1) xgram_fetch<B, SL, PF>(pre, tid, rs + SL, r1, v0, v1, y, vi);
     if (RG > 1) {
       if (grp < RG) {
         const int e = tid - grp * NE;
@@ -474,16 +475,38 @@ k_tadj(const double *__restrict__ X3all, const double *__restrict__ Rall, int B,
 
 // Mbar = [v0 | v1 | y | vbar] Tadj; one thread per (row, output block g):
 // g = 0 -> accP += (Vbar_{j-2}), g = 1 -> accC += (Vbar_{j-1}), g = 2 -> ybar.
+// Both expansions in one launch: logical workgroups [0, nb0) take side 0,
+// the rest side 1.
+struct AapplySide {
+  const float *v0, *v1, *y, *vb;
+  const double *Tadj;
+  int64_t rows;
+  float *accP, *accC, *ybar;
+};
+struct AapplyPair {
+  AapplySide s[2];
+  int64_t nb0;
+};
+
 template <int B>
 __global__ void __launch_bounds__(kThreads)
-k_aapply(const float *__restrict__ v0, const float *__restrict__ v1, const float *__restrict__ y,
-         const float *__restrict__ vb, const double *__restrict__ Tadj, int64_t rows,
-         float *__restrict__ accP, float *__restrict__ accC, float *__restrict__ ybar) {
+k_aapply(const AapplyPair P) {
   constexpr int C = 3 * B;
   __shared__ float Ts[(C + B) * C];
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const bool second = lb >= P.nb0;
+  const float *__restrict__ v0 = second ? P.s[1].v0 : P.s[0].v0;
+  const float *__restrict__ v1 = second ? P.s[1].v1 : P.s[0].v1;
+  const float *__restrict__ y = second ? P.s[1].y : P.s[0].y;
+  const float *__restrict__ vb = second ? P.s[1].vb : P.s[0].vb;
+  const double *__restrict__ Tadj = second ? P.s[1].Tadj : P.s[0].Tadj;
+  const int64_t rows = second ? P.s[1].rows : P.s[0].rows;
+  float *__restrict__ accP = second ? P.s[1].accP : P.s[0].accP;
+  float *__restrict__ accC = second ? P.s[1].accC : P.s[0].accC;
+  float *__restrict__ ybar = second ? P.s[1].ybar : P.s[0].ybar;
   for (int e = threadIdx.x; e < (C + B) * C; e += kThreads) Ts[e] = float(Tadj[e]);
   __syncthreads();
-  const int64_t gid = int64_t(xcd_block(blockIdx.x, gridDim.x)) * kThreads + threadIdx.x;
+  const int64_t gid = (lb - (second ? P.nb0 : 0)) * kThreads + threadIdx.x;
   const int64_t r = gid / 3;
   const int g = int(gid % 3);
   if (r >= rows) return;
@@ -718,11 +741,10 @@ hef_status step_kernels_t(int64_t rows, int64_t pool_rows, float *abar, const fl
                           int col, float *vbar, const float *v0, const float *v1, const float *y,
                           double *xpart, double *X3, hipStream_t s) {
   constexpr int C = 3 * B;
-  k_vbar<B><<<cdiv(rows * B, 256), 256, 0, s>>>(abar, pbar, K, col, pool_rows, rows, vbar);
-  HEF_LAUNCH_CHECK();
   const int64_t per = std::max<int64_t>(64, cdiv(cdiv(rows, kXBlocks), 64) * 64);
   const int nblk = int(std::max<int64_t>(1, cdiv(rows, per)));
-  k_xgram<B><<<nblk, kThreads, 0, s>>>(v0, v1, y, vbar, rows, per, xpart);
+  const VbarIn vi{abar, pbar, K, col, pool_rows, vbar};
+  k_xgram<B><<<nblk, kThreads, 0, s>>>(v0, v1, y, vi, rows, per, xpart);
   HEF_LAUNCH_CHECK();
   return reduce_cols_f64(xpart, nblk, int64_t(C) * B, X3, s);
 }
@@ -740,25 +762,27 @@ hef_status step_kernels(int B, int64_t rows, int64_t pool_rows, float *abar, con
   }
 }
 
+// Sides with zero rows launch nothing.
 template <int B>
-hef_status aapply_t(const float *v0, const float *v1, const float *y, const float *vb,
-                    const double *Tadj, int64_t rows, float *accP, float *accC, float *ybar,
-                    hipStream_t s) {
-  k_aapply<B><<<cdiv(rows * 3, kThreads), kThreads, 0, s>>>(v0, v1, y, vb, Tadj, rows, accP,
-                                                            accC, ybar);
+hef_status aapply_t(const AapplySide &a, const AapplySide &b, hipStream_t s) {
+  AapplyPair P;
+  P.s[0] = a;
+  P.s[1] = b;
+  P.nb0 = cdiv(a.rows * 3, kThreads);
+  const int64_t nblk = P.nb0 + cdiv(b.rows * 3, kThreads);
+  if (nblk == 0) return HEF_OK;
+  k_aapply<B><<<nblk, kThreads, 0, s>>>(P);
   HEF_LAUNCH_CHECK();
   return HEF_OK;
 }
 
-hef_status aapply(int B, const float *v0, const float *v1, const float *y, const float *vb,
-                  const double *Tadj, int64_t rows, float *accP, float *accC, float *ybar,
-                  hipStream_t s) {
+hef_status aapply(int B, const AapplySide &a, const AapplySide &b, hipStream_t s) {
   switch (B) {
-    case 1: return aapply_t<1>(v0, v1, y, vb, Tadj, rows, accP, accC, ybar, s);
-    case 2: return aapply_t<2>(v0, v1, y, vb, Tadj, rows, accP, accC, ybar, s);
-    case 4: return aapply_t<4>(v0, v1, y, vb, Tadj, rows, accP, accC, ybar, s);
-    case 8: return aapply_t<8>(v0, v1, y, vb, Tadj, rows, accP, accC, ybar, s);
-    case 16: return aapply_t<16>(v0, v1, y, vb, Tadj, rows, accP, accC, ybar, s);
+    case 1: return aapply_t<1>(a, b, s);
+    case 2: return aapply_t<2>(a, b, s);
+    case 4: return aapply_t<4>(a, b, s);
+    case 8: return aapply_t<8>(a, b, s);
+    case 16: return aapply_t<16>(a, b, s);
     default: return HEF_ERR_UNSUPPORTED;
   }
 }
@@ -933,12 +957,10 @@ hef_status reverse_sweep(const Level &L, const hef_params &p, const float *dR, f
                          use_clique ? vc(j - 1) : nullptr, use_clique ? ycj : nullptr, tj, s));
       if (j < j1) {
         const double *Tj = w.tape.T + size_t(j) * 2 * C * B;
-        if (use_star)
-          HEF_TRY(lanczos_apply(B, j >= 2 ? vs(j - 2) : nullptr, vs(j - 1), ysj, Tj,
-                                w.vseg_s + size_t(t) * Ns * B, Ns, nullptr, 0, 0, K, 0, s));
-        if (use_clique)
-          HEF_TRY(lanczos_apply(B, j >= 2 ? vc(j - 2) : nullptr, vc(j - 1), ycj, Tj + C * B,
-                                w.vseg_c + size_t(t) * n * B, n, nullptr, 0, 0, K, 0, s));
+        HEF_TRY(lanczos_apply_pair(B, j >= 2 ? vs(j - 2) : nullptr, vs(j - 1), ysj, Tj,
+                                   w.vseg_s + size_t(t) * Ns * B, use_star ? Ns : 0,
+                                   j >= 2 ? vc(j - 2) : nullptr, vc(j - 1), ycj, Tj + C * B,
+                                   w.vseg_c + size_t(t) * n * B, use_clique ? n : 0, K, s));
       }
     }
     for (int j = j1; j > j0; --j) {
@@ -963,11 +985,13 @@ hef_status reverse_sweep(const Level &L, const hef_params &p, const float *dR, f
                              w.xpart + size_t(kXBlocks) * C * B, w.X3 + C * B, s));
       k_tadj<<<2, kThreads, 0, s>>>(w.X3, w.tape.Rinv + size_t(j) * 2 * C * C, B, mask, w.Tadj);
       HEF_LAUNCH_CHECK();
-      if (use_star)
-        HEF_TRY(aapply(B, ps, vs(j - 1), ysj, w.vb_s, w.Tadj, Ns, as_2, as_1, w.yb_s, s));
-      if (use_clique)
-        HEF_TRY(aapply(B, pc, vc(j - 1), ycj, w.vb_c, w.Tadj + (C + B) * C, n, ac_2, ac_1,
-                       w.yb_c, s));
+      {
+        const AapplySide sa{ps, vs(j - 1), ysj, w.vb_s, w.Tadj, use_star ? Ns : 0, as_2, as_1,
+                            w.yb_s};
+        const AapplySide sc{pc, vc(j - 1), ycj, w.vb_c, w.Tadj + (C + B) * C, use_clique ? n : 0,
+                            ac_2, ac_1, w.yb_c};
+        HEF_TRY(aapply(B, sa, sc, s));
+      }
       HEF_TRY(spmm_apply(L, st, B, use_star ? w.yb_s : nullptr, use_star ? w.ay_s : nullptr,
                          use_clique ? w.yb_c : nullptr, use_clique ? w.ay_c : nullptr, w.tbar, s));
       HEF_TRY(weights(B, L, st, use_star ? w.yb_s : nullptr, ysj, vs(j - 1), w.ay_s,

@@ -604,6 +604,15 @@ hef_status lanczos_apply(int B, const float *v0, const float *v1, const float *y
   return lapply(B, v0, v1, y, T, vn, rows, pool, pool_type, pool_rows, K, col0, s);
 }
 
+hef_status lanczos_apply_pair(int B, const float *v0a, const float *v1a, const float *ya,
+                              const double *Ta, float *vna, int64_t rowsa, const float *v0b,
+                              const float *v1b, const float *yb, const double *Tb, float *vnb,
+                              int64_t rowsb, int K, hipStream_t s) {
+  const ApplySide a{v0a, v1a, ya, Ta, vna, rowsa, 0};
+  const ApplySide b{v0b, v1b, yb, Tb, vnb, rowsb, 0};
+  return lapply2(B, a, b, nullptr, 0, 0, K, s);
+}
+
 size_t krylov_ws_bytes(int64_t n, int64_t m, int B) {
   Arena a;
   for (int i = 0; i < 4; ++i) a.take<float>((n + m) * B);

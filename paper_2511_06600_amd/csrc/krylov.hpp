@@ -75,7 +75,9 @@ hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double
 //    (C x C each, C = 3B, consecutive), Cholesky with the drop rule and
 //    T2 = [T_star | T_clique], T = R^-1[:, y columns] (C x B each); R2
 //    (nullable) receives both whole R^-1 (C x C each, consecutive);
-//  * lanczos_apply: vn = M T (float64 arithmetic), optional pool write.
+//  * lanczos_apply: vn = M T (float64 arithmetic), optional pool write;
+//  * lanczos_apply_pair: two lanczos_apply without pool writes (sides a and
+//    b, a side with zero rows skipped) in one launch.
 size_t lanczos_partial_elems(int B);
 hef_status lanczos_gram(const float *v0, const float *v1, const float *y, int64_t rows, int B,
                         double *partial, double *G, hipStream_t s);
@@ -84,6 +86,10 @@ hef_status lanczos_solve(const double *G2, int B, double tau, double *T2, int32_
 hef_status lanczos_apply(int B, const float *v0, const float *v1, const float *y, const double *T,
                          float *vn, int64_t rows, void *pool, int pool_type, int64_t pool_rows,
                          int K, int col0, hipStream_t s);
+hef_status lanczos_apply_pair(int B, const float *v0a, const float *v1a, const float *ya,
+                              const double *Ta, float *vna, int64_t rowsa, const float *v0b,
+                              const float *v1b, const float *yb, const double *Tb, float *vnb,
+                              int64_t rowsb, int K, hipStream_t s);
 
 // Counter-based N(0,1) start block (splitmix64 + Box-Muller in float64).
 hef_status start_block(uint64_t seed, int level, int expansion, int64_t rows, int B,
