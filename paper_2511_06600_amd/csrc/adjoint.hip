@@ -313,6 +313,18 @@ struct VbarIn {
   float *vbar;
 };
 
+// One expansion's operands of the step cross products; a launch covers two.
+struct XgramSide {
+  const float *v0, *v1, *y;
+  VbarIn vi;
+  int64_t rows, rows_per_blk;
+  double *partial;
+};
+struct XgramPair {
+  XgramSide s[2];
+  int nb0;
+};
+
 // One SL-row slab of [v0 | v1 | y | vbar] into registers (element g of the
 // slab: row g / (C + B), column g % (C + B)); zeros past r1.
 template <int B, int SL, int PF>
@@ -346,8 +358,17 @@ __device__ __forceinline__ void xgram_fetch(float (&pre)[PF], int tid, int64_t r
 
 template <int B>
 __global__ void __launch_bounds__(kThreads)
-k_xgram(const float *__restrict__ v0, const float *__restrict__ v1, const float *__restrict__ y,
-        const VbarIn vi, int64_t rows, int64_t rows_per_blk, double *__restrict__ partial) {
+k_xgram(const XgramPair P) {
+  // workgroups [0, nb0) take side 0, the rest side 1
+  const bool second = int(blockIdx.x) >= P.nb0;
+  const XgramSide &S = second ? P.s[1] : P.s[0];
+  const float *__restrict__ v0 = S.v0;
+  const float *__restrict__ v1 = S.v1;
+  const float *__restrict__ y = S.y;
+  const VbarIn vi = S.vi;
+  const int64_t rows = S.rows, rows_per_blk = S.rows_per_blk;
+  double *__restrict__ partial = S.partial;
+  const int bid = int(blockIdx.x) - (second ? P.nb0 : 0);
   constexpr int C = 3 * B;
   constexpr int NE = C * B;
   constexpr int EPT = (NE + kThreads - 1) / kThreads;
@@ -360,7 +381,7 @@ k_xgram(const float *__restrict__ v0, const float *__restrict__ v1, const float 
   __shared__ double gsum[RG > 1 ? RG * NE : 1];
   const int tid = threadIdx.x;
   const int grp = RG > 1 ? tid / NE : 0;
-  const int64_t r0 = int64_t(blockIdx.x) * rows_per_blk;
+  const int64_t r0 = int64_t(bid) * rows_per_blk;
   const int64_t r1 = r0 + rows_per_blk < rows ? r0 + rows_per_blk : rows;
   double acc[EPT];
 #pragma unroll
@@ -408,13 +429,13 @@ k_xgram(const float *__restrict__ v0, const float *__restrict__ v1, const float 
     if (tid < NE) {
       double t = gsum[tid];
       for (int g = 1; g < RG; ++g) t += gsum[g * NE + tid];
-      partial[int64_t(blockIdx.x) * NE + tid] = t;
+      partial[int64_t(bid) * NE + tid] = t;
     }
   } else {
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
       const int e = tid + u * kThreads;
-      if (e < NE) partial[int64_t(blockIdx.x) * NE + e] = acc[u];
+      if (e < NE) partial[int64_t(bid) * NE + e] = acc[u];
     }
   }
 }
@@ -736,33 +757,49 @@ size_t transient_bytes(int64_t n, int64_t m, int64_t nnz, const hef_params &p) {
   return need + 4096;
 }
 
+// The step cross products X3 of both expansions (a side with zero rows
+// contributes a zero X3), in one launch and one reduce.
+struct StepSide {
+  int64_t rows, pool_rows;
+  float *abar;
+  int col;
+  float *vbar;
+  const float *v0, *v1, *y;
+  double *xpart, *X3;
+};
+
 template <int B>
-hef_status step_kernels_t(int64_t rows, int64_t pool_rows, float *abar, const float *pbar, int K,
-                          int col, float *vbar, const float *v0, const float *v1, const float *y,
-                          double *xpart, double *X3, hipStream_t s) {
+hef_status step_kernels_t(const StepSide &a, const StepSide &b, const float *pbar, int K,
+                          hipStream_t s) {
   constexpr int C = 3 * B;
-  const int64_t per = std::max<int64_t>(64, cdiv(cdiv(rows, kXBlocks), 64) * 64);
-  const int nblk = int(std::max<int64_t>(1, cdiv(rows, per)));
-  const VbarIn vi{abar, pbar, K, col, pool_rows, vbar};
-  k_xgram<B><<<nblk, kThreads, 0, s>>>(v0, v1, y, vi, rows, per, xpart);
+  XgramPair P;
+  int nb[2];
+  const StepSide *sd[2] = {&a, &b};
+  for (int i = 0; i < 2; ++i) {
+    const StepSide &t = *sd[i];
+    const int64_t per = std::max<int64_t>(64, cdiv(cdiv(t.rows, kXBlocks), 64) * 64);
+    nb[i] = int(std::max<int64_t>(1, cdiv(t.rows, per)));
+    P.s[i] = XgramSide{t.v0, t.v1, t.y, VbarIn{t.abar, pbar, K, t.col, t.pool_rows, t.vbar},
+                       t.rows, per, t.xpart};
+  }
+  P.nb0 = nb[0];
+  k_xgram<B><<<nb[0] + nb[1], kThreads, 0, s>>>(P);
   HEF_LAUNCH_CHECK();
-  return reduce_cols_f64(xpart, nblk, int64_t(C) * B, X3, s);
+  return reduce_cols_f64_pair(a.xpart, nb[0], a.X3, b.xpart, nb[1], b.X3, int64_t(C) * B, s);
 }
 
-hef_status step_kernels(int B, int64_t rows, int64_t pool_rows, float *abar, const float *pbar,
-                        int K, int col, float *vbar, const float *v0, const float *v1,
-                        const float *y, double *xpart, double *X3, hipStream_t s) {
+hef_status step_kernels(int B, const StepSide &a, const StepSide &b, const float *pbar, int K,
+                        hipStream_t s) {
   switch (B) {
-    case 1: return step_kernels_t<1>(rows, pool_rows, abar, pbar, K, col, vbar, v0, v1, y, xpart, X3, s);
-    case 2: return step_kernels_t<2>(rows, pool_rows, abar, pbar, K, col, vbar, v0, v1, y, xpart, X3, s);
-    case 4: return step_kernels_t<4>(rows, pool_rows, abar, pbar, K, col, vbar, v0, v1, y, xpart, X3, s);
-    case 8: return step_kernels_t<8>(rows, pool_rows, abar, pbar, K, col, vbar, v0, v1, y, xpart, X3, s);
-    case 16: return step_kernels_t<16>(rows, pool_rows, abar, pbar, K, col, vbar, v0, v1, y, xpart, X3, s);
+    case 1: return step_kernels_t<1>(a, b, pbar, K, s);
+    case 2: return step_kernels_t<2>(a, b, pbar, K, s);
+    case 4: return step_kernels_t<4>(a, b, pbar, K, s);
+    case 8: return step_kernels_t<8>(a, b, pbar, K, s);
+    case 16: return step_kernels_t<16>(a, b, pbar, K, s);
     default: return HEF_ERR_UNSUPPORTED;
   }
 }
 
-// Sides with zero rows launch nothing.
 template <int B>
 hef_status aapply_t(const AapplySide &a, const AapplySide &b, hipStream_t s) {
   AapplyPair P;
@@ -977,12 +1014,13 @@ hef_status reverse_sweep(const Level &L, const hef_params &p, const float *dR, f
       float *ac_2 = j >= 3 ? w.abar_c + size_t((j - 2) % 3) * n * B : nullptr;
       const int col_s = int((j - 1) * int64_t(B));
       const int col_c = int((use_star ? bk : 0) + (j - 1) * int64_t(B));
-      if (use_star)
-        HEF_TRY(step_kernels(B, Ns, n, as_j, pbar, K, col_s, w.vb_s, ps, vs(j - 1), ysj,
-                             w.xpart, w.X3, s));
-      if (use_clique)
-        HEF_TRY(step_kernels(B, n, n, ac_j, pbar, K, col_c, w.vb_c, pc, vc(j - 1), ycj,
-                             w.xpart + size_t(kXBlocks) * C * B, w.X3 + C * B, s));
+      {
+        const StepSide ss{use_star ? Ns : 0, n, as_j, col_s, w.vb_s, ps, vs(j - 1), ysj,
+                          w.xpart, w.X3};
+        const StepSide sc{use_clique ? n : 0, n, ac_j, col_c, w.vb_c, pc, vc(j - 1), ycj,
+                          w.xpart + size_t(kXBlocks) * C * B, w.X3 + C * B};
+        HEF_TRY(step_kernels(B, ss, sc, pbar, K, s));
+      }
       k_tadj<<<2, kThreads, 0, s>>>(w.X3, w.tape.Rinv + size_t(j) * 2 * C * C, B, mask, w.Tadj);
       HEF_LAUNCH_CHECK();
       {

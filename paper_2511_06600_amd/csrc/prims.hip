@@ -150,11 +150,17 @@ __global__ void k_compact(const int32_t *flag, const int32_t *pos, int32_t *idx_
 
 // 256 threads = 8 columns x 32 row lanes.
 __global__ void __launch_bounds__(256)
-k_reduce_cols(const double *__restrict__ in, int64_t nrows, int64_t ncols,
-              double *__restrict__ out) {
+k_reduce_cols(const double *__restrict__ in0, int64_t nrows0, double *__restrict__ out0,
+              const double *__restrict__ in1, int64_t nrows1, double *__restrict__ out1,
+              int64_t nbc, int64_t ncols) {
   __shared__ double red[32][9];
+  // workgroups [0, nbc) reduce side 0, the rest side 1
+  const bool second = int64_t(blockIdx.x) >= nbc;
+  const double *__restrict__ in = second ? in1 : in0;
+  const int64_t nrows = second ? nrows1 : nrows0;
+  double *__restrict__ out = second ? out1 : out0;
   const int cl = threadIdx.x & 7, rl = threadIdx.x >> 3;
-  const int64_t c = int64_t(blockIdx.x) * 8 + cl;
+  const int64_t c = (int64_t(blockIdx.x) - (second ? nbc : 0)) * 8 + cl;
   // eight independent loads in flight per row lane
   double acc[8] = {};
   if (c < ncols) {
@@ -189,7 +195,18 @@ __global__ void k_flag_copy(const int32_t *flag, int32_t *out, int64_t n) {
 hef_status reduce_cols_f64(const double *in, int64_t nrows, int64_t ncols, double *out,
                            hipStream_t s) {
   if (ncols <= 0) return HEF_OK;
-  k_reduce_cols<<<cdiv(ncols, 8), 256, 0, s>>>(in, nrows, ncols, out);
+  k_reduce_cols<<<cdiv(ncols, 8), 256, 0, s>>>(in, nrows, out, nullptr, 0, nullptr,
+                                                cdiv(ncols, 8), ncols);
+  HEF_LAUNCH_CHECK();
+  return HEF_OK;
+}
+
+hef_status reduce_cols_f64_pair(const double *in0, int64_t nrows0, double *out0,
+                                const double *in1, int64_t nrows1, double *out1, int64_t ncols,
+                                hipStream_t s) {
+  if (ncols <= 0) return HEF_OK;
+  const int64_t nbc = cdiv(ncols, 8);
+  k_reduce_cols<<<2 * nbc, 256, 0, s>>>(in0, nrows0, out0, in1, nrows1, out1, nbc, ncols);
   HEF_LAUNCH_CHECK();
   return HEF_OK;
 }

@@ -32,6 +32,10 @@ hef_status compact_flags(const int32_t *flag, int32_t *scratch, int32_t *idx_out
 // interleaved accumulators), then a fixed tree over the lanes.
 hef_status reduce_cols_f64(const double *in, int64_t nrows, int64_t ncols, double *out,
                            hipStream_t s);
+// Two independent reduce_cols_f64 (same ncols) in one launch.
+hef_status reduce_cols_f64_pair(const double *in0, int64_t nrows0, double *out0,
+                                const double *in1, int64_t nrows1, double *out1, int64_t ncols,
+                                hipStream_t s);
 
 inline int bits_for(int64_t maxval) {
   int b = 1;
