@@ -212,12 +212,12 @@ def main():
         tot = sum(traffic[kk][0] + traffic[kk][1] for kk in kernels)
         return tot / launches
 
-    spmm_stages = ("spmm_prep", "spmm_csr", "spmm_csr_big", "spmm_csc", "spmm_csc_big")
+    spmm_stages = ("spmm_prep", "spmm_csr", "spmm_csc")
     rooflines = {
         "a2_spmm": roofline_entry(
             "hbm", spmm_b, ms_of(*spmm_stages), nfused * S, PEAK_HBM_GBS, "GB/s",
-            ["k_prep", "k_csr_small", "k_csr_big", "k_csc_small", "k_csc_big"],
-            traffic_of(["k_prep", "k_csr_small", "k_csr_big", "k_csc_small", "k_csc_big"],
+            ["k_prep", "k_csr", "k_csc"],
+            traffic_of(["k_prep", "k_csr", "k_csc"],
                        nfused)),
         "k_lgram": roofline_entry("hbm", lg_b, ms_of("lanczos_gram"), per.get("lanczos_gram", (0, 0))[1],
                                   PEAK_HBM_GBS, "GB/s", ["k_lgram"],

@@ -124,8 +124,6 @@ enum Stage : int {
   kStClusterRebuild,
   kStAdjoint,
   kStStart,
-  kStSpmmCsrBig,
-  kStSpmmCscBig,
   kStSpmmPrep,
   kStLanczosReduce,
   kStOrthReduce,

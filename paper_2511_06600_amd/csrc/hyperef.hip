@@ -50,7 +50,7 @@ static const char *kStageNames[kStageCount] = {
     "structure", "spmm_csr", "spmm_csc", "lanczos_gram", "lanczos_solve", "lanczos_apply",
     "orth_gram", "orth_chol", "orth_apply", "score_qh", "score_r", "cluster_update",
     "cluster_contract", "cluster_local", "cluster_rebuild", "adjoint", "start_block",
-    "spmm_csr_big", "spmm_csc_big", "spmm_prep", "lanczos_reduce", "orth_reduce",
+    "spmm_prep", "lanczos_reduce", "orth_reduce",
     "score_reduce", "cluster_best"};
 
 namespace {

@@ -125,13 +125,12 @@ __device__ __forceinline__ void csr_finish(int64_t e, int sub, const float (&acc
 }
 
 template <int B>
-__global__ void __launch_bounds__(kThreads)
-k_csr_small(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
-            const float *__restrict__ U, const float *__restrict__ alpha,
-            const float *__restrict__ beta, const float *__restrict__ xE,
-            float *__restrict__ yE, float *__restrict__ W, int32_t m, int on_mask) {
+__device__ __forceinline__ void
+csr_small(int64_t blk, const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
+          const float *__restrict__ U, const float *__restrict__ alpha,
+          const float *__restrict__ beta, const float *__restrict__ xE,
+          float *__restrict__ yE, float *__restrict__ W, int32_t m, int on_mask) {
   using G = Geo<B>;
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t g = blk * kThreads + threadIdx.x;
   const int64_t e = g / G::LPS;
   const int sub = int(g % G::LPS);
@@ -170,12 +169,12 @@ k_csr_small(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
 // One wave per long hyperedge: 64/LPS slots stride over its pins, then a
 // fixed xor tree across slots.
 template <int B>
-__global__ void __launch_bounds__(kThreads)
-k_csr_big(const int32_t *__restrict__ list, const int32_t *__restrict__ count,
-          const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
-          const float *__restrict__ U, const float *__restrict__ alpha,
-          const float *__restrict__ beta, const float *__restrict__ xE,
-          float *__restrict__ yE, float *__restrict__ W, int on_mask) {
+__device__ __forceinline__ void
+csr_big(int bx, int nbx, const int32_t *__restrict__ list, const int32_t *__restrict__ count,
+        const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
+        const float *__restrict__ U, const float *__restrict__ alpha,
+        const float *__restrict__ beta, const float *__restrict__ xE,
+        float *__restrict__ yE, float *__restrict__ W, int on_mask) {
   using G = Geo<B>;
   constexpr int SLOTS = 64 / G::LPS;
   const int lane = threadIdx.x & 63;
@@ -183,8 +182,7 @@ k_csr_big(const int32_t *__restrict__ list, const int32_t *__restrict__ count,
   const int sub = lane % G::LPS;
   const bool on = (on_mask >> (sub / G::NCH)) & 1;
   const int32_t cnt = *count;
-  for (int32_t bi = blockIdx.x * kWaves + (threadIdx.x >> 6); bi < cnt;
-       bi += gridDim.x * kWaves) {
+  for (int32_t bi = bx * kWaves + (threadIdx.x >> 6); bi < cnt; bi += nbx * kWaves) {
     const int32_t e = list[bi];
     const int32_t a = eptr[e], b = eptr[e + 1];
     CsrIn<B> in;
@@ -269,13 +267,12 @@ __device__ __forceinline__ void csc_finish(int64_t u, int sub, const float (&acc
 }
 
 template <int B>
-__global__ void __launch_bounds__(kThreads)
-k_csc_small(const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
-            const float *__restrict__ W, const float *__restrict__ s,
-            const float *__restrict__ gam, const float *__restrict__ xc,
-            float *__restrict__ yV, float *__restrict__ yc, int32_t n, int on_mask) {
+__device__ __forceinline__ void
+csc_small(int64_t blk, const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
+          const float *__restrict__ W, const float *__restrict__ s,
+          const float *__restrict__ gam, const float *__restrict__ xc,
+          float *__restrict__ yV, float *__restrict__ yc, int32_t n, int on_mask) {
   using G = Geo<B>;
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t g = blk * kThreads + threadIdx.x;
   const int64_t u = g / G::LPS;
   const int sub = int(g % G::LPS);
@@ -312,12 +309,12 @@ k_csc_small(const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
 }
 
 template <int B>
-__global__ void __launch_bounds__(kThreads)
-k_csc_big(const int32_t *__restrict__ list, const int32_t *__restrict__ count,
-          const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
-          const float *__restrict__ W, const float *__restrict__ s,
-          const float *__restrict__ gam, const float *__restrict__ xc,
-          float *__restrict__ yV, float *__restrict__ yc, int on_mask) {
+__device__ __forceinline__ void
+csc_big(int bx, int nbx, const int32_t *__restrict__ list, const int32_t *__restrict__ count,
+        const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
+        const float *__restrict__ W, const float *__restrict__ s,
+        const float *__restrict__ gam, const float *__restrict__ xc,
+        float *__restrict__ yV, float *__restrict__ yc, int on_mask) {
   using G = Geo<B>;
   constexpr int SLOTS = 64 / G::LPS;
   const int lane = threadIdx.x & 63;
@@ -325,8 +322,7 @@ k_csc_big(const int32_t *__restrict__ list, const int32_t *__restrict__ count,
   const int sub = lane % G::LPS;
   const bool on = (on_mask >> (sub / G::NCH)) & 1;
   const int32_t cnt = *count;
-  for (int32_t bi = blockIdx.x * kWaves + (threadIdx.x >> 6); bi < cnt;
-       bi += gridDim.x * kWaves) {
+  for (int32_t bi = bx * kWaves + (threadIdx.x >> 6); bi < cnt; bi += nbx * kWaves) {
     const int32_t u = list[bi];
     const int32_t a = vptr[u], b = vptr[u + 1];
     CscIn<B> in;
@@ -363,6 +359,45 @@ k_csc_big(const int32_t *__restrict__ list, const int32_t *__restrict__ count,
   }
 }
 
+// One launch per pass: workgroups [0, kBigGrid) walk the long segments (one
+// wave each), the rest take the short ones (kBigGrid is a multiple of 8, so
+// a workgroup's XCD is the same in both numberings).
+template <int B>
+__global__ void __launch_bounds__(kThreads)
+k_csr(const int32_t *__restrict__ big_e, const int32_t *__restrict__ n_big,
+      const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
+      const float *__restrict__ U, const float *__restrict__ alpha,
+      const float *__restrict__ beta, const float *__restrict__ xE, float *__restrict__ yE,
+      float *__restrict__ W, int32_t m, int on_mask) {
+  if (int(blockIdx.x) < kBigGrid) {
+    csr_big<B>(int(blockIdx.x), kBigGrid, big_e, n_big, eptr, pins, U, alpha, beta, xE, yE, W,
+               on_mask);
+  } else {
+    const int64_t nsmall = int64_t(gridDim.x) - kBigGrid;
+    csr_small<B>(xcd_block(int64_t(blockIdx.x) - kBigGrid, nsmall), eptr, pins, U, alpha, beta,
+                 xE, yE, W, m, on_mask);
+  }
+}
+
+template <int B>
+__global__ void __launch_bounds__(kThreads)
+k_csc(const int32_t *__restrict__ big_v, const int32_t *__restrict__ n_big_v,
+      const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
+      const float *__restrict__ W, const float *__restrict__ s, const float *__restrict__ gam,
+      const float *__restrict__ xc, float *__restrict__ yV, float *__restrict__ yc, int32_t n,
+      int on_mask) {
+  if (int(blockIdx.x) < kBigGrid) {
+    csc_big<B>(int(blockIdx.x), kBigGrid, big_v, n_big_v, vptr, eids, W, s, gam, xc, yV, yc,
+               on_mask);
+  } else {
+    const int64_t nsmall = int64_t(gridDim.x) - kBigGrid;
+    csc_small<B>(xcd_block(int64_t(blockIdx.x) - kBigGrid, nsmall), vptr, eids, W, s, gam, xc,
+                 yV, yc, n, on_mask);
+  }
+}
+
+static_assert(kBigGrid % 8 == 0, "the XCD of a workgroup must not depend on its role");
+
 template <int B>
 hef_status spmm_t(const Level &L, const Structure &st, const float *xs, float *ys,
                   const float *xc, float *yc, float *scratch, hipStream_t s) {
@@ -380,30 +415,16 @@ hef_status spmm_t(const Level &L, const Structure &st, const float *xs, float *y
   }
   if (m > 0) {
     const int64_t nb = cdiv(m * G::LPS, kThreads);
-    {
-      TimedScope ts(kStSpmmCsr, s);
-      k_csr_small<B><<<nb, kThreads, 0, s>>>(L.eptr, L.pins, U, st.alpha, st.beta, xE, yE, W,
-                                             int32_t(m), on);
-    }
-    {
-      TimedScope ts(kStSpmmCsrBig, s);
-      k_csr_big<B><<<kBigGrid, kThreads, 0, s>>>(st.big_e, st.n_big, L.eptr, L.pins, U,
-                                                 st.alpha, st.beta, xE, yE, W, on);
-    }
+    TimedScope ts(kStSpmmCsr, s);
+    k_csr<B><<<kBigGrid + nb, kThreads, 0, s>>>(st.big_e, st.n_big, L.eptr, L.pins, U, st.alpha,
+                                                st.beta, xE, yE, W, int32_t(m), on);
     HEF_LAUNCH_CHECK();
   }
   if (n > 0) {
     const int64_t nb = cdiv(n * G::LPS, kThreads);
-    {
-      TimedScope ts(kStSpmmCsc, s);
-      k_csc_small<B><<<nb, kThreads, 0, s>>>(st.vptr, st.eids, W, st.s, st.gam, xc, ys, yc,
-                                             int32_t(n), on);
-    }
-    {
-      TimedScope ts(kStSpmmCscBig, s);
-      k_csc_big<B><<<kBigGrid, kThreads, 0, s>>>(st.big_v, st.n_big + 1, st.vptr, st.eids, W,
-                                                 st.s, st.gam, xc, ys, yc, on);
-    }
+    TimedScope ts(kStSpmmCsc, s);
+    k_csc<B><<<kBigGrid + nb, kThreads, 0, s>>>(st.big_v, st.n_big + 1, st.vptr, st.eids, W, st.s,
+                                                st.gam, xc, ys, yc, int32_t(n), on);
     HEF_LAUNCH_CHECK();
   }
   return HEF_OK;
