@@ -217,6 +217,15 @@ k_centroids(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
 }
 
 // ---- a8: best neighbouring cluster of every isolated node --------------------
+// flag[p] = 1 for the nodes the search runs on: not in a contracted cluster,
+// at least one hyperedge
+__global__ void k_single_flag(const int32_t *__restrict__ owner, const int32_t *__restrict__ vptr,
+                              int32_t n, int32_t *__restrict__ flag) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  flag[p] = (owner[p] < 0 && vptr[p + 1] > vptr[p]) ? 1 : 0;
+}
+
 // Columns with Q_H > 0 sorted by ascending Q_H (largest weights first).
 __global__ void __launch_bounds__(512)
 k_qh_order(const double *__restrict__ qh, int K, int32_t *__restrict__ perm,
@@ -401,9 +410,13 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
        const int32_t *__restrict__ crow, const double *__restrict__ cent,
        const _Float16 *__restrict__ cperm, int Kq, const int32_t *__restrict__ perm,
        const float *__restrict__ inv32, const void *__restrict__ pool, int K,
-       const double *__restrict__ qh, int32_t n, int32_t *__restrict__ best_label,
+       const double *__restrict__ qh, const int32_t *__restrict__ list,
+       const int32_t *__restrict__ count, int32_t *__restrict__ best_label,
        double *__restrict__ best_d) {
   constexpr int NW = kT / 64;
+  // one wave per listed isolated node; workgroups past the list leave at once
+  const int32_t cnt = *count;
+  if (int64_t(blockIdx.x) * NW >= cnt) return;
   __shared__ float sv[512];                // sqrt(1 / Q_H), 2^-10 and 2^-24 times
   __shared__ float s10[512];               // it, permuted order (zero for unused
   __shared__ float s24[512];               // columns)
@@ -435,8 +448,9 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
     pm[q] = perm[q];
   }
   __syncthreads();
-  const int64_t p = int64_t(blockIdx.x) * NW + w;
-  if (p >= n) return;
+  const int64_t i = int64_t(blockIdx.x) * NW + w;
+  if (i >= cnt) return;
+  const int64_t p = list[i];
   const int32_t v0 = vptr[p], deg = vptr[p + 1] - v0;
   if (owner[p] >= 0 || deg == 0) {
     if (lane == 0) best_label[p] = -1;
@@ -1226,6 +1240,12 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
     if (local && n > 0 && m > 0 && K > 0) {
       const int Kq = (K + 63) / 64 * 64;
       k_qh_order<<<1, 512, 0, s>>>(qh, K, w.perm, w.inv32, w.small + 3);
+      // the isolated nodes, listed in node order (sort buffers are free here)
+      int32_t *sflag = reinterpret_cast<int32_t *>(w.k1);
+      int32_t *slist = reinterpret_cast<int32_t *>(w.v0);
+      k_single_flag<<<g1(n), kT, 0, s>>>(w.owner, st.vptr, int32_t(n), sflag);
+      HEF_LAUNCH_CHECK();
+      HEF_TRY(compact_flags(sflag, reinterpret_cast<int32_t *>(w.k0), slist, w.small + 7, n, ws, s));
       if (pool_type == kPoolF32) {
         k_centroids<kPoolF32><<<2048, kT, 0, s>>>(L.eptr, L.pins, w.in_list, w.small + 1, pool, K, w.cent);
         k_cperm<kPoolF32><<<cdiv(n, kT / 64), kT, 0, s>>>(w.prov, w.owner, w.in_index, w.cent, pool, K, Kq,
@@ -1234,8 +1254,8 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
           TimedScope tb(kStClusterBest, s);
           k_best<kPoolF32><<<cdiv(n, kT / 64), kT, 0, s>>>(L.eptr, L.pins, st.vptr, st.eids,
                                                      w.owner, w.prov, w.crow, w.cent, w.cperm, Kq,
-                                                     w.perm, w.inv32, pool, K, qh, int32_t(n),
-                                                     w.best_label, w.best_d);
+                                                     w.perm, w.inv32, pool, K, qh, slist,
+                                                     w.small + 7, w.best_label, w.best_d);
         }
       } else {
         k_centroids<kPoolBF16><<<2048, kT, 0, s>>>(L.eptr, L.pins, w.in_list, w.small + 1, pool, K, w.cent);
@@ -1245,8 +1265,8 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
           TimedScope tb(kStClusterBest, s);
           k_best<kPoolBF16><<<cdiv(n, kT / 64), kT, 0, s>>>(L.eptr, L.pins, st.vptr, st.eids,
                                                      w.owner, w.prov, w.crow, w.cent, w.cperm, Kq,
-                                                     w.perm, w.inv32, pool, K, qh, int32_t(n),
-                                                     w.best_label, w.best_d);
+                                                     w.perm, w.inv32, pool, K, qh, slist,
+                                                     w.small + 7, w.best_label, w.best_d);
         }
       }
       HEF_LAUNCH_CHECK();
