@@ -402,8 +402,10 @@ constexpr int kEB = 64;     // hyperedges of p per batch
 constexpr int kAq = 128;    // stage-A columns
 constexpr int kBq = 256;    // end of the stage-B columns
 
+constexpr int kBT = 128;  // best-neighbour workgroup: two waves (two nodes)
+
 template <int PT>
-__global__ void __launch_bounds__(kT)
+__global__ void __launch_bounds__(kBT)
 k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
        const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
        const int32_t *__restrict__ owner, const int32_t *__restrict__ prov,
@@ -413,7 +415,7 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
        const double *__restrict__ qh, const int32_t *__restrict__ list,
        const int32_t *__restrict__ count, int32_t *__restrict__ best_label,
        double *__restrict__ best_d) {
-  constexpr int NW = kT / 64;
+  constexpr int NW = kBT / 64;
   // one wave per listed isolated node; workgroups past the list leave at once
   const int32_t cnt = *count;
   if (int64_t(blockIdx.x) * NW >= cnt) return;
@@ -439,7 +441,7 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
   const int lane = threadIdx.x & 63;
   const int g = lane >> 3, a8 = lane & 7;
   const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
-  for (int q = threadIdx.x; q < 512; q += kT) {
+  for (int q = threadIdx.x; q < 512; q += kBT) {
     const float r = sqrtf(inv32[q]);
     sv[q] = r;
     s10[q] = 0x1p-10f * r;
@@ -1252,7 +1254,7 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
                                                    w.perm, w.small + 3, w.cperm, w.crow, int32_t(n));
         {
           TimedScope tb(kStClusterBest, s);
-          k_best<kPoolF32><<<cdiv(n, kT / 64), kT, 0, s>>>(L.eptr, L.pins, st.vptr, st.eids,
+          k_best<kPoolF32><<<cdiv(n, kBT / 64), kBT, 0, s>>>(L.eptr, L.pins, st.vptr, st.eids,
                                                      w.owner, w.prov, w.crow, w.cent, w.cperm, Kq,
                                                      w.perm, w.inv32, pool, K, qh, slist,
                                                      w.small + 7, w.best_label, w.best_d);
@@ -1263,7 +1265,7 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
                                                    w.perm, w.small + 3, w.cperm, w.crow, int32_t(n));
         {
           TimedScope tb(kStClusterBest, s);
-          k_best<kPoolBF16><<<cdiv(n, kT / 64), kT, 0, s>>>(L.eptr, L.pins, st.vptr, st.eids,
+          k_best<kPoolBF16><<<cdiv(n, kBT / 64), kBT, 0, s>>>(L.eptr, L.pins, st.vptr, st.eids,
                                                      w.owner, w.prov, w.crow, w.cent, w.cperm, Kq,
                                                      w.perm, w.inv32, pool, K, qh, slist,
                                                      w.small + 7, w.best_label, w.best_d);
