@@ -75,9 +75,9 @@ def apply_flops(n, K):
 
 
 def score_bytes(n, m, nnz, K, s=4):
-    """One scoring pass: the pool once, the pins, the pointers and one
-    per-hyperedge value (w read or R written)."""
-    return n * K * s + 4 * nnz + 4 * (m + 1) + 4 * m
+    """The ratio pass (k_score_r): the stored m x K float32 numerators read
+    once, Q_H read, one float32 R per hyperedge written."""
+    return 4 * m * K + 8 * K + 4 * m
 
 
 def read_traffic():

@@ -3,9 +3,11 @@
 // For every hyperedge e and pool column i the two most distant pins along
 // chi^(i) are its largest and smallest entries, so the numerator of Eq. (13)
 // is s_e^(i) = (max_{p in e} chi_p^(i) - min_{p in e} chi_p^(i))^2.
-// Pass 1 forms Q_H(chi^(i)) = sum_e w_e s_e^(i) (Eq. (9)); pass 2 forms
-// R_e = max_i s_e^(i) / Q_H(chi^(i)) (Eq. (14)).  The m x K ratio matrix is
-// never stored: both passes regather the pool rows of each hyperedge.
+// Pass 1 forms Q_H(chi^(i)) = sum_e w_e s_e^(i) (Eq. (9)) and stores the
+// m x K numerators s (float32, row e contiguous); pass 2 streams them back
+// to form R_e = max_i s_e^(i) / Q_H(chi^(i)) (Eq. (14)).  Streaming s costs
+// 8 K bytes per hyperedge; regathering the pool rows cost about 4 K bytes per
+// pin, mostly missed in L2.
 //
 // A group of LPR lanes handles one hyperedge, each lane CPL consecutive
 // columns of the gathered rows; a workgroup walks a contiguous range of
@@ -93,7 +95,7 @@ template <int CPL, int PT>
 __global__ void __launch_bounds__(kThreads)
 k_score_qh(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
            const float *__restrict__ w, const void *__restrict__ pool, int K, int LPR,
-           int64_t m, double *__restrict__ partial) {
+           int64_t m, double *__restrict__ partial, float *__restrict__ sbuf) {
   __shared__ double comb[512];
   const int tid = threadIdx.x;
   const int ngrp = kThreads / LPR;
@@ -125,6 +127,17 @@ k_score_qh(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
         edge_spread<CPL, PT>(pins, pool, K, c0, a, b, s);
 #pragma unroll
         for (int q = 0; q < CPL; ++q) acc[q] = fma(we, s[q], acc[q]);
+        float *out = sbuf + (e0 + grp + int64_t(ngrp) * (k0 + k)) * K + c0;
+        if (c0 + CPL <= K && (K & 3) == 0) {
+#pragma unroll
+          for (int q = 0; q < CPL; q += 4)
+            *reinterpret_cast<float4 *>(out + q) =
+                make_float4(float(s[q]), float(s[q + 1]), float(s[q + 2]), float(s[q + 3]));
+        } else {
+#pragma unroll
+          for (int q = 0; q < CPL; ++q)
+            if (c0 + q < K) out[q] = float(s[q]);
+        }
       }
     }
   }
@@ -139,47 +152,46 @@ k_score_qh(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
   for (int c = tid; c < K; c += kThreads) partial[blk * K + c] = comb[c];
 }
 
-template <int CPL, int PT>
+// R_e = max_i s_e^(i) / Q_H^(i) from the stored numerators: LPR lanes per
+// hyperedge, CPL columns each (ties in the maximum are irrelevant: only the
+// value is kept).
+template <int CPL>
 __global__ void __launch_bounds__(kThreads)
-k_score_r(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
-          const void *__restrict__ pool, int K, int LPR, int64_t m,
+k_score_r(const float *__restrict__ sbuf, int K, int LPR, int64_t m,
           const double *__restrict__ qh, float *__restrict__ R) {
   const int tid = threadIdx.x;
   const int ngrp = kThreads / LPR;
   const int grp = tid / LPR;
   const int sub = tid % LPR;
   const int c0 = sub * CPL;
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t e0 = blk * kEdgesPerBlk;
-  const int64_t e1 = e0 + kEdgesPerBlk < m ? e0 + kEdgesPerBlk : m;
   double inv[CPL];
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
     const double qv = (c0 + q < K) ? qh[c0 + q] : 0.0;
     inv[q] = qv > 0.0 ? 1.0 / qv : 0.0;
   }
-  for (int k0 = 0; k0 < kEdgesPerBlk / ngrp && e0 + grp + int64_t(ngrp) * k0 < e1; k0 += LPR) {
-    int32_t ea = 0, eb = 0;
-    {
-      const int64_t e = e0 + grp + int64_t(ngrp) * (k0 + sub);
-      if (e < e1) {
-        ea = eptr[e];
-        eb = eptr[e + 1];
-      }
-    }
-    for (int k = 0; k < LPR && e0 + grp + int64_t(ngrp) * (k0 + k) < e1; ++k) {
-      const int64_t e = e0 + grp + int64_t(ngrp) * (k0 + k);
-      const int32_t a = __shfl(ea, k, LPR), b = __shfl(eb, k, LPR);
-      double best = 0.0;
-      if (c0 < K) {
-        double s[CPL];
-        edge_spread<CPL, PT>(pins, pool, K, c0, a, b, s);
+  const int64_t e0 = int64_t(xcd_block(blockIdx.x, gridDim.x)) * kEdgesPerBlk;
+  const int64_t e1 = e0 + kEdgesPerBlk < m ? e0 + kEdgesPerBlk : m;
+  for (int64_t e = e0 + grp; e < e1; e += ngrp) {
+    double best = 0.0;
+    if (c0 < K) {
+      const float *row = sbuf + e * K + c0;
+      float v[CPL];
+      if (c0 + CPL <= K && (K & 3) == 0) {
 #pragma unroll
-        for (int q = 0; q < CPL; ++q) best = fmax(best, s[q] * inv[q]);
+        for (int q = 0; q < CPL; q += 4) {
+          const float4 t = *reinterpret_cast<const float4 *>(row + q);
+          v[q] = t.x; v[q + 1] = t.y; v[q + 2] = t.z; v[q + 3] = t.w;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) v[q] = c0 + q < K ? row[q] : 0.0f;
       }
-      for (int off = LPR / 2; off > 0; off >>= 1) best = fmax(best, __shfl_xor(best, off, LPR));
-      if (sub == 0) R[e] = float(best);
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) best = fmax(best, double(v[q]) * inv[q]);
     }
+    for (int off = LPR / 2; off > 0; off >>= 1) best = fmax(best, __shfl_xor(best, off, LPR));
+    if (sub == 0) R[e] = float(best);
   }
 }
 
@@ -192,11 +204,12 @@ int lanes_for(int K, int CPL) {
 
 template <int CPL, int PT>
 hef_status score_t(const Level &L, const void *pool, int K, double *qh, float *R,
-                   double *partial, int64_t nblk, hipStream_t s) {
+                   double *partial, float *sbuf, int64_t nblk, hipStream_t s) {
   const int LPR = lanes_for(K, CPL);
   {
   TimedScope ts(kStScoreQ, s);
-  k_score_qh<CPL, PT><<<nblk, kThreads, 0, s>>>(L.eptr, L.pins, L.w, pool, K, LPR, L.m, partial);
+  k_score_qh<CPL, PT><<<nblk, kThreads, 0, s>>>(L.eptr, L.pins, L.w, pool, K, LPR, L.m, partial,
+                                                sbuf);
   HEF_LAUNCH_CHECK();
   }
   {
@@ -204,7 +217,7 @@ hef_status score_t(const Level &L, const void *pool, int K, double *qh, float *R
   HEF_TRY(reduce_cols_f64(partial, nblk, K, qh, s));
   }
   TimedScope ts(kStScoreR, s);
-  k_score_r<CPL, PT><<<nblk, kThreads, 0, s>>>(L.eptr, L.pins, pool, K, LPR, L.m, qh, R);
+  k_score_r<CPL><<<nblk, kThreads, 0, s>>>(sbuf, K, LPR, L.m, qh, R);
   HEF_LAUNCH_CHECK();
   return HEF_OK;
 }
@@ -214,6 +227,7 @@ hef_status score_t(const Level &L, const void *pool, int K, double *qh, float *R
 size_t score_ws_bytes(int64_t m, int K) {
   Arena a;
   a.take<double>(cdiv(std::max<int64_t>(m, 1), kEdgesPerBlk) * K);
+  a.take<float>(std::max<int64_t>(m, 1) * K);
   return a.mark();
 }
 
@@ -224,15 +238,16 @@ hef_status score_pool(const Level &L, const void *pool, int pool_type, int K, do
   const int64_t nblk = cdiv(L.m, kEdgesPerBlk);
   const size_t mk = ws.mark();
   double *partial = ws.take<double>(nblk * K);
+  float *sbuf = ws.take<float>(L.m * K);
   if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
   hef_status st;
   const bool wide = K > 256;
   if (pool_type == kPoolF32)
-    st = wide ? score_t<8, kPoolF32>(L, pool, K, qh, R, partial, nblk, s)
-              : score_t<4, kPoolF32>(L, pool, K, qh, R, partial, nblk, s);
+    st = wide ? score_t<8, kPoolF32>(L, pool, K, qh, R, partial, sbuf, nblk, s)
+              : score_t<4, kPoolF32>(L, pool, K, qh, R, partial, sbuf, nblk, s);
   else
-    st = wide ? score_t<8, kPoolBF16>(L, pool, K, qh, R, partial, nblk, s)
-              : score_t<4, kPoolBF16>(L, pool, K, qh, R, partial, nblk, s);
+    st = wide ? score_t<8, kPoolBF16>(L, pool, K, qh, R, partial, sbuf, nblk, s)
+              : score_t<4, kPoolBF16>(L, pool, K, qh, R, partial, sbuf, nblk, s);
   ws.reset(mk);
   return st;
 }
