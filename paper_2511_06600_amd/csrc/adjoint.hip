@@ -88,8 +88,7 @@ __device__ __forceinline__ void load_row_i(const int32_t *__restrict__ X, int64_
 // column sums of c_e s_e^(i*) / Q_H(i*)^2 (fixed order).
 template <int CPL>
 __global__ void __launch_bounds__(kThreads)
-k_sadj_a(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
-         const float *__restrict__ chi, int K, int LPR, int64_t m, const double *__restrict__ qh,
+k_sadj_a(const float *__restrict__ sfwd, int K, int LPR, int64_t m, const double *__restrict__ qh,
          const float *__restrict__ dR, int32_t *__restrict__ istar, double *__restrict__ partial) {
   __shared__ double comb[512];
   const int tid = threadIdx.x;
@@ -107,31 +106,18 @@ k_sadj_a(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
     acc[q] = 0.0;
   }
   for (int64_t e = e0 + grp; e < e1; e += ngrp) {
+    // the numerators the forward ratios were formed from
     double s[CPL];
-    float mx[CPL], mn[CPL];
+    {
+      float v[CPL];
+      load_row<CPL>(sfwd, e, K, c0, v);
 #pragma unroll
-    for (int q = 0; q < CPL; ++q) { mx[q] = -FLT_MAX; mn[q] = FLT_MAX; }
-    // pins in chunks of 4 (ids first, then rows); a chunk past the end
-    // repeats the last pin, which leaves max and min unchanged
-    const int32_t a = eptr[e], b = eptr[e + 1];
-    for (int32_t j0 = a; j0 < b; j0 += 4) {
-      int32_t pp[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) pp[u] = pins[j0 + u < b ? j0 + u : b - 1];
-      float v[4][CPL];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) load_row<CPL>(chi, pp[u], K, c0, v[u]);
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int q = 0; q < CPL; ++q) { mx[q] = fmaxf(mx[q], v[u][q]); mn[q] = fminf(mn[q], v[u][q]); }
+      for (int q = 0; q < CPL; ++q) s[q] = double(v[q]);
     }
     double best = 0.0;
     int bi = INT_MAX;
 #pragma unroll
     for (int q = 0; q < CPL; ++q) {
-      const double d = double(mx[q]) - double(mn[q]);
-      s[q] = d * d;
       const double r = s[q] * inv[q];
       if (c0 + q < K && r > best) { best = r; bi = c0 + q; }
     }
@@ -674,6 +660,7 @@ struct BwdWs {
   KrylovTape tape;
   int32_t *istar = nullptr;
   double *qsum = nullptr, *wdirect = nullptr, *spart = nullptr;
+  float *sfwd = nullptr;                // the forward's numerators (m x K)
   int32_t *cslot = nullptr;
   float *chibar = nullptr;
   char *big = nullptr;                  // slot_a | slot_b | dbar, later pbar
@@ -714,6 +701,7 @@ void carve(Arena &a, int64_t n, int64_t m, int64_t nnz, const hef_params &p, Bwd
   w.qsum = a.take<double>(K);
   w.wdirect = a.take<double>(m);
   w.spart = a.take<double>(cdiv(std::max<int64_t>(m, 1), kEdgesPerBlk) * K);
+  w.sfwd = a.take<float>(std::max<int64_t>(m, 1) * K);
   w.cslot = a.take<int32_t>(nnz);
   w.chibar = a.take<float>(n * K);
   w.big = a.take<char>(std::max<int64_t>(m * K * 12, n * K * 4));
@@ -860,7 +848,7 @@ hef_status score_adjoint_t(const Level &L, const Structure &st, const float *chi
                            const double *qh, const float *dR, BwdWs &w, hipStream_t s) {
   const int LPR = lanes_for(K, CPL);
   const int64_t nblk = cdiv(L.m, kEdgesPerBlk);
-  k_sadj_a<CPL><<<nblk, kThreads, 0, s>>>(L.eptr, L.pins, chi, K, LPR, L.m, qh, dR, w.istar,
+  k_sadj_a<CPL><<<nblk, kThreads, 0, s>>>(w.sfwd, K, LPR, L.m, qh, dR, w.istar,
                                           w.spart);
   HEF_LAUNCH_CHECK();
   HEF_TRY(reduce_cols_f64(w.spart, nblk, K, w.qsum, s));
@@ -916,7 +904,7 @@ hef_status taped_forward(const Level &L, const hef_params &p, const float *start
                       use_clique, ko, a, s, &w.tape));
   HEF_TRY(orthonormalize_pool(w.P, w.chi, kPoolF32, n, K, double(p.drop_tol), 1, nullptr, a, s,
                               w.rinvJ));
-  HEF_TRY(score_pool(L, w.chi, kPoolF32, K, w.qh, w.R, a, s));
+  HEF_TRY(score_pool(L, w.chi, kPoolF32, K, w.qh, w.R, a, s, w.sfwd));
   return HEF_OK;
 }
 

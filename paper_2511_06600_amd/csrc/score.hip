@@ -232,13 +232,13 @@ size_t score_ws_bytes(int64_t m, int K) {
 }
 
 hef_status score_pool(const Level &L, const void *pool, int pool_type, int K, double *qh,
-                      float *R, Arena &ws, hipStream_t s) {
+                      float *R, Arena &ws, hipStream_t s, float *keep_s) {
   if (K > 512) return HEF_ERR_UNSUPPORTED;
   if (L.m == 0) return HEF_OK;
   const int64_t nblk = cdiv(L.m, kEdgesPerBlk);
   const size_t mk = ws.mark();
   double *partial = ws.take<double>(nblk * K);
-  float *sbuf = ws.take<float>(L.m * K);
+  float *sbuf = keep_s ? keep_s : ws.take<float>(L.m * K);
   if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
   hef_status st;
   const bool wide = K > 256;
