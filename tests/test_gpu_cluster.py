@@ -94,6 +94,24 @@ def test_ties_in_resistance_and_distance():
     _check(h, R, np.zeros(h.n, np.float32), chi, qh, percentile=0.3)
 
 
+def test_no_isolated_node_and_only_isolated_nodes():
+    # every node contracted (the best-neighbour list is empty), then a
+    # threshold below every R (no contraction: every node is on the list)
+    from synth.hypergraph import Hypergraph
+    edges = [[0, 1], [2, 3], [1, 2], [4, 5, 6, 7]]
+    eptr = np.concatenate([[0], np.cumsum([len(e) for e in edges])])
+    pins = np.array([p for e in edges for p in e], np.int32)
+    h = Hypergraph(n=8, m=len(edges), eptr=eptr, pins=pins, w=np.ones(len(edges), np.float32))
+    R = np.array([0.1, 0.2, 0.9, 0.3], np.float32)
+    rng = np.random.default_rng(5)
+    chi = rng.standard_normal((8, 3)).astype(np.float32)
+    qh = np.array([1.0, 2.0, 0.5])
+    say("case: cluster_level, all nodes contracted")
+    _check(h, R, None, chi, qh, percentile=1.0)
+    say("case: cluster_level, no contraction")
+    _check(h, R, None, chi, qh, percentile=0.01)
+
+
 def test_netlist_level_bit_exact():
     h = make_hypergraph("netlist200k")
     say(f"case: cluster_level netlist200k n={h.n} m={h.m} K=160")
