@@ -67,7 +67,8 @@ typedef enum {
   HEF_OP_COARSEN = 1,
   HEF_OP_CLUSTER_LEVEL = 2,
   HEF_OP_BACKWARD = 3,
-  HEF_OP_APPLY = 4
+  HEF_OP_APPLY = 4,
+  HEF_OP_CONDUCTANCE = 5  /* sized for n_clusters up to n; ignores params  */
 } hef_op;
 
 /* Flags for hef_params.flags. */
@@ -178,6 +179,25 @@ hef_status hef_cluster_level(const hef_hypergraph *hg, const hef_params *p,
                              int32_t *cluster, int32_t *n_clusters,
                              float *eta_out, void *ws, size_t ws_bytes,
                              hipStream_t stream);
+
+/* Cluster quality of a partition (Section II-A, Eq. (3); Section IV,
+ * Eq. (18)).  With d_v the summed weight of v's hyperedges and vol(S) the
+ * summed degree of S, a cluster S gets cut(S) = the summed weight of the
+ * hyperedges with pins both in S and outside it (each counted once), and
+ * phi(S) = cut(S) / min(vol(S), vol(V) - vol(S)), or 0 when cut(S) = 0.
+ * phi_avg is the mean of phi over the n_clusters clusters.  All in float64,
+ * deterministic (fixed summation order, no atomics).
+ *   label      DEVICE [n] int32: node -> cluster in [0, n_clusters) (a label
+ *              outside gives HEF_ERR_INVALID_ARGUMENT after the run);
+ *   n_clusters 1 <= n_clusters <= max(n, 1); clusters without nodes get 0s;
+ *   cut, vol, phi  DEVICE [n_clusters] float64 outputs;
+ *   phi_avg    DEVICE [1] float64 output;
+ *   ws         DEVICE workspace of hef_workspace_size(hg, NULL,
+ *              HEF_OP_CONDUCTANCE, .) bytes.
+ * The hypergraph is validated on the device.  Synchronises `stream`. */
+hef_status hef_conductance(const hef_hypergraph *hg, const int32_t *label, int32_t n_clusters,
+                           double *cut, double *vol, double *phi, double *phi_avg, void *ws,
+                           size_t ws_bytes, hipStream_t stream);
 
 /* Adjoint of hef_resistance with respect to the hyperedge weights (the
  * derivative of Eqs. (9), (13), (14) through the Krylov bases of

@@ -61,3 +61,19 @@ def average_conductance(phi):
     """Phi_avg of Eq. (18): the mean of the clusters' conductances."""
     phi = np.asarray(phi, dtype=np.float64)
     return float(phi.sum() / len(phi)) if len(phi) else 0.0
+
+
+def one_cluster(eptr, pins, w, label, c):
+    """(cut, vol) of the single cluster c, for sampled checks on large
+    inputs: a hyperedge with k of its |e| pins in c adds w(e) to the volume
+    k times and to the cut once when 0 < k < |e| (the same quantities as
+    cluster_conductance, one cluster at a time, vectorised)."""
+    eptr = np.asarray(eptr)
+    m = len(eptr) - 1
+    w = np.ones(m) if w is None else np.asarray(w, dtype=np.float64)
+    sizes = np.diff(eptr)
+    inside = np.add.reduceat((np.asarray(label)[pins] == c).astype(np.int64), eptr[:-1]) \
+        if m else np.zeros(0, np.int64)
+    touched = inside > 0
+    split = touched & (inside < sizes)
+    return float(w[split].sum()), float((w * inside).sum())

@@ -152,6 +152,22 @@ def cluster_level(hg: DeviceHypergraph, params: Params, R: torch.Tensor,
     return cluster, int(nc.value), eta_out[:int(nc.value)]
 
 
+def conductance(hg: DeviceHypergraph, label: torch.Tensor, n_clusters: int):
+    """Eq. (3) per cluster and Eq. (18): (cut, vol, phi [n_clusters] float64,
+    phi_avg float64 scalar tensor) for the partition label [n] int32."""
+    lib = load()
+    assert label.dtype == torch.int32 and label.shape == (hg.n,) and label.is_contiguous()
+    nc = int(n_clusters)
+    out = torch.empty(3 * max(nc, 1) + 1, dtype=torch.float64, device=hg.device)
+    cut, vol, phi = out[:nc], out[nc:2 * nc], out[2 * nc:3 * nc]
+    avg = out[3 * nc:3 * nc + 1]
+    ws = _workspace(hg, Params(), _lib.OP_CONDUCTANCE)
+    check(lib.hef_conductance(C.byref(hg.c()), _ptr(label), nc, _ptr(cut), _ptr(vol), _ptr(phi),
+                              _ptr(avg), _ptr(ws), ws.numel(), _stream(hg.device)),
+          "hef_conductance")
+    return cut, vol, phi, avg[0]
+
+
 def resistance_backward(hg: DeviceHypergraph, params: Params, dR: torch.Tensor,
                         start_star: torch.Tensor | None = None,
                         start_clique: torch.Tensor | None = None,

@@ -13,14 +13,14 @@ STATUS = {
     3: "HEF_ERR_WORKSPACE_TOO_SMALL", 4: "HEF_ERR_DEVICE", 5: "HEF_ERR_NUMERICAL",
     6: "HEF_ERR_UNSUPPORTED",
 }
-OP_RESISTANCE, OP_COARSEN, OP_CLUSTER_LEVEL, OP_BACKWARD, OP_APPLY = range(5)
+OP_RESISTANCE, OP_COARSEN, OP_CLUSTER_LEVEL, OP_BACKWARD, OP_APPLY, OP_CONDUCTANCE = range(6)
 BASIS_FP32, BASIS_BF16 = 0, 1
 FLAG_ASSUME_VALID, FLAG_STAR_ONLY, FLAG_CLIQUE_ONLY, FLAG_TAPED = 1, 2, 4, 8
 
 EXPORTS = [
     "hef_params_default", "hef_pool_width", "hef_workspace_size", "hef_validate_host",
     "hef_resistance", "hef_coarsen", "hef_cluster_level", "hef_resistance_backward",
-    "hef_resistance_taped",
+    "hef_resistance_taped", "hef_conductance",
     "hef_debug_apply", "hef_debug_gram", "hef_debug_gram_ws", "hef_start_block",
     "hef_status_string", "hef_last_error", "hef_timing_enable", "hef_timing_stage_count",
     "hef_timing_stage_name", "hef_timing_read", "hef_last_coarsen_levels",
@@ -69,6 +69,7 @@ def load() -> C.CDLL:
         "hef_cluster_level": (i32, [HG, PR, vp, vp, vp, vp, vp, C.POINTER(i32), vp, vp, sz, vp]),
         "hef_resistance_backward": (i32, [HG, PR, vp, vp, vp, vp, vp, sz, vp]),
         "hef_resistance_taped": (i32, [HG, PR, vp, vp, vp, vp, sz, vp]),
+        "hef_conductance": (i32, [HG, vp, i32, vp, vp, vp, vp, vp, sz, vp]),
         "hef_debug_apply": (i32, [HG, i32, i32, vp, vp, vp, sz, vp]),
         "hef_debug_gram": (i32, [vp, i64, i32, vp, vp, sz, vp]),
         "hef_debug_gram_ws": (sz, [i64, i32]),

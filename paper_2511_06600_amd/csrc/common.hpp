@@ -129,6 +129,7 @@ enum Stage : int {
   kStOrthReduce,
   kStScoreReduce,
   kStClusterBest,
+  kStQuality,
   kStageCount
 };
 

@@ -11,6 +11,7 @@
 
 #include "cluster.hpp"
 #include "krylov.hpp"
+#include "quality.hpp"
 #include "orth.hpp"
 #include "prims.hpp"
 #include "score.hpp"
@@ -51,7 +52,7 @@ static const char *kStageNames[kStageCount] = {
     "orth_gram", "orth_chol", "orth_apply", "score_qh", "score_r", "cluster_update",
     "cluster_contract", "cluster_local", "cluster_rebuild", "adjoint", "start_block",
     "spmm_prep", "lanczos_reduce", "orth_reduce",
-    "score_reduce", "cluster_best"};
+    "score_reduce", "cluster_best", "quality"};
 
 namespace {
 
@@ -268,6 +269,9 @@ hef_status hef_workspace_size(const hef_hypergraph *hg, const hef_params *p, int
       *bytes = a.mark() + structure_build_ws(n, m, nnz) + 1024;
       return HEF_OK;
     }
+    case HEF_OP_CONDUCTANCE:
+      *bytes = conductance_bytes(n, m, nnz);
+      return HEF_OK;
     default:
       set_error("unknown op %d", op);
       return HEF_ERR_INVALID_ARGUMENT;

@@ -103,6 +103,9 @@ def test_volume_total_bounds_and_per_edge_cut(nc):
         split = (inside > 0) & (inside < sizes)
         assert cut[c] == pytest.approx(float(h.w[split].astype(np.float64).sum()), rel=1e-13,
                                        abs=0)
+        oc, ov = oq.one_cluster(h.eptr, h.pins, h.w, label, c)
+        assert oc == pytest.approx(cut[c], rel=1e-13, abs=0)
+        assert ov == pytest.approx(vol[c], rel=1e-13, abs=0)
     if nc == 1:
         assert cut[0] == 0 and phi[0] == 0
 
