@@ -299,7 +299,28 @@ def main():
         lv = hef.last_coarsen_levels()
         extra["coarsen_bf16_estimates_per_s"] = sum(x[1] for x in lv) / dt
         extra["coarsen_bf16_ms"] = dt * 1e3
-        del dh
+        # cluster quality (Eq. (3) per cluster, Eq. (18) average) of the FP32
+        # partition of the timed configuration
+        cl, ncl, _, _ = hef.coarsen(dh, params)
+        hef.conductance(dh, cl, ncl)
+        torch.cuda.synchronize()
+        hef.timing_read(reset=True)
+        hef.timing_enable(True)
+        reps = 5
+        ta = time.perf_counter()
+        for _ in range(reps):
+            _, _, _, avg = hef.conductance(dh, cl, ncl)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - ta) / reps
+        hef.timing_enable(False)
+        stq = hef.timing_read(reset=True)
+        ms_q = stq["quality"][0] / reps
+        extra["conductance_clusters"] = ncl
+        extra["conductance_phi_avg"] = float(avg.item())
+        extra["conductance_kernels_ms"] = ms_q
+        extra["conductance_pins_per_s"] = h.nnz / (ms_q / 1e3)
+        extra["conductance_call_ms"] = dt * 1e3
+        del dh, cl
         torch.cuda.empty_cache()
         # forward + backward of Alg. 1 at the gradient workload
         gname = "grad200k"

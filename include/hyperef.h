@@ -188,7 +188,8 @@ hef_status hef_cluster_level(const hef_hypergraph *hg, const hef_params *p,
  * phi_avg is the mean of phi over the n_clusters clusters.  All in float64,
  * deterministic (fixed summation order, no atomics).
  *   label      DEVICE [n] int32: node -> cluster in [0, n_clusters) (a label
- *              outside gives HEF_ERR_INVALID_ARGUMENT after the run);
+ *              outside on a pin gives HEF_ERR_INVALID_ARGUMENT after the run;
+ *              nodes without hyperedges add nothing and are not read);
  *   n_clusters 1 <= n_clusters <= max(n, 1); clusters without nodes get 0s;
  *   cut, vol, phi  DEVICE [n_clusters] float64 outputs;
  *   phi_avg    DEVICE [1] float64 output;

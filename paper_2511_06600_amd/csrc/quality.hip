@@ -8,9 +8,10 @@
 //
 // Layout of the computation (deterministic: no atomics, fixed summation
 // order):
-//  1. every pin position j emits (label of its node, j);
-//  2. a stable radix sort by label groups each cluster's pins, in ascending
-//     pin position, so the pins a hyperedge has in one cluster are adjacent;
+//  1. every pin position j of a hyperedge e emits (label of its node, e),
+//     in pin order;
+//  2. a stable radix sort by label groups each cluster's pins with e
+//     ascending, so the pins a hyperedge has in one cluster are adjacent;
 //  3. one wave per cluster walks its pins: each adds w(e) to the volume
 //     (sum over the cluster's nodes of their degrees), and the first pin of
 //     each run of one hyperedge adds w(e) to the cut when e is split;
@@ -28,31 +29,56 @@ namespace {
 
 constexpr int kQT = 256;
 
-__global__ void k_qual_emit(const int32_t *__restrict__ pins, const int32_t *__restrict__ label,
-                            int64_t nnz, int32_t nc, uint32_t *__restrict__ keys,
-                            uint32_t *__restrict__ vals, int32_t *__restrict__ bad) {
-  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= nnz) return;
+// The hyperedge holding pin position j: the last e with eptr[e] <= j.
+__device__ __forceinline__ int32_t edge_of(const int32_t *eptr, int32_t m, int32_t j) {
+  int32_t lo = 0, hi = m;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (eptr[mid] <= j) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// One thread per pin position j, kQT consecutive positions per workgroup:
+// j emits (label of its node, its hyperedge e), and marks split[e] (zeroed
+// beforehand) when its label differs from that of e's first pin.  The
+// workgroup finds the hyperedges of its first and last positions once and
+// stages that slice of eptr in LDS (at most kQT + 1 entries, as every
+// hyperedge has a pin), where each thread finds its own hyperedge.
+__global__ void __launch_bounds__(kQT)
+k_qual_emit(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
+            const int32_t *__restrict__ label, int32_t m, int64_t nnz, int32_t nc,
+            uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+            int32_t *__restrict__ split, int32_t *__restrict__ bad) {
+  __shared__ int32_t se[kQT + 2];
+  __shared__ int32_t ends[2];
+  const int64_t j0 = int64_t(blockIdx.x) * kQT;
+  const int64_t jl = (j0 + kQT < nnz ? j0 + kQT : nnz) - 1;
+  if (threadIdx.x < 2) ends[threadIdx.x] = edge_of(eptr, m, int32_t(threadIdx.x ? jl : j0));
+  __syncthreads();
+  const int32_t e0 = ends[0];
+  int32_t ne = ends[1] - e0;  // entries e0 .. e0 + ne
+  if (ne > kQT) ne = kQT;
+  for (int i = threadIdx.x; i <= ne; i += kQT) se[i] = eptr[e0 + i];
+  __syncthreads();
+  const int64_t j = j0 + threadIdx.x;
+  if (j > jl) return;
+  int32_t lo = 0, hi = ne + 1;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (se[mid] <= j) lo = mid; else hi = mid;
+  }
+  const int32_t e = e0 + lo;
   int32_t c = label[pins[j]];
+  int32_t cf = label[pins[se[lo]]];
+  if (cf < 0 || cf >= nc) cf = 0;
   if (c < 0 || c >= nc) {
     *bad = 1;  // every writer stores the same value
     c = 0;
   }
   keys[j] = uint32_t(c);
-  vals[j] = uint32_t(j);
-}
-
-// split[e] = 1 when the pins of e do not all carry one label.
-__global__ void k_qual_split(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
-                             const int32_t *__restrict__ label, int32_t m,
-                             int32_t *__restrict__ split) {
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= m) return;
-  const int32_t a = eptr[e], b = eptr[e + 1];
-  const int32_t c0 = label[pins[a]];
-  int32_t s = 0;
-  for (int32_t j = a + 1; j < b && !s; ++j) s = label[pins[j]] != c0;
-  split[e] = s;
+  vals[j] = uint32_t(e);
+  if (c != cf) split[e] = 1;  // every writer stores the same value
 }
 
 // seg[c] = first sorted position with key >= c, c in [0, nc]
@@ -68,22 +94,10 @@ __global__ void k_qual_seg(const uint32_t *__restrict__ keys, int64_t nnz, int32
   seg[c] = int32_t(lo);
 }
 
-// The hyperedge holding pin position j: the last e with eptr[e] <= j (every
-// hyperedge has at least two pins, so that e is unique).
-__device__ __forceinline__ int32_t edge_of(const int32_t *eptr, int32_t m, int32_t j) {
-  int32_t lo = 0, hi = m;
-  while (hi - lo > 1) {
-    const int32_t mid = (lo + hi) >> 1;
-    if (eptr[mid] <= j) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
 // One wave per cluster: lane l takes the cluster's sorted pins l, l+64, ...;
 // the lane sums are combined by a fixed butterfly.
 __global__ void __launch_bounds__(kQT)
-k_qual_cluster(const int32_t *__restrict__ eptr, const float *__restrict__ w, int32_t m,
-               const uint32_t *__restrict__ vals, const int32_t *__restrict__ seg,
+k_qual_cluster(const float *__restrict__ w, const uint32_t *__restrict__ vals, const int32_t *__restrict__ seg,
                const int32_t *__restrict__ split, int32_t nc, double *__restrict__ cut,
                double *__restrict__ vol) {
   const int64_t c = (int64_t(blockIdx.x) * kQT + threadIdx.x) >> 6;
@@ -94,7 +108,7 @@ k_qual_cluster(const int32_t *__restrict__ eptr, const float *__restrict__ w, in
   int32_t carry = -1;  // hyperedge of the pin before this chunk
   for (int32_t t0 = s0; t0 < s1; t0 += 64) {
     const int32_t t = t0 + lane;
-    const int32_t e = t < s1 ? edge_of(eptr, m, int32_t(vals[t])) : -1;
+    const int32_t e = t < s1 ? int32_t(vals[t]) : -1;
     int32_t pe = __shfl_up(e, 1, 64);
     if (lane == 0) pe = carry;
     carry = __shfl(e, 63, 64);
@@ -211,15 +225,15 @@ extern "C" hef_status hef_conductance(const hef_hypergraph *hg, const int32_t *l
     return HEF_OK;
   }
   HEF_HIP(hipMemsetAsync(q.bad, 0, sizeof(int32_t), stream));
-  k_qual_emit<<<cdiv(nnz, kQT), kQT, 0, stream>>>(L.pins, label, nnz, nc, q.k0, q.v0, q.bad);
-  HEF_LAUNCH_CHECK();
-  k_qual_split<<<cdiv(m, kQT), kQT, 0, stream>>>(L.eptr, L.pins, label, int32_t(m), q.split);
+  HEF_HIP(hipMemsetAsync(q.split, 0, m * sizeof(int32_t), stream));
+  k_qual_emit<<<cdiv(nnz, kQT), kQT, 0, stream>>>(L.eptr, L.pins, label, int32_t(m), nnz, nc,
+                                                   q.k0, q.v0, q.split, q.bad);
   HEF_LAUNCH_CHECK();
   HEF_TRY(radix_sort_pairs(q.k0, q.v0, q.k1, q.v1, nnz, bits_for(nc - 1), a, stream));
   k_qual_seg<<<cdiv(int64_t(nc) + 1, kQT), kQT, 0, stream>>>(q.k1, nnz, nc, q.seg);
   HEF_LAUNCH_CHECK();
-  k_qual_cluster<<<cdiv(int64_t(nc) * 64, kQT), kQT, 0, stream>>>(L.eptr, L.w, int32_t(m), q.v1,
-                                                                 q.seg, q.split, nc, cut, vol);
+  k_qual_cluster<<<cdiv(int64_t(nc) * 64, kQT), kQT, 0, stream>>>(L.w, q.v1, q.seg, q.split, nc,
+                                                                 cut, vol);
   HEF_LAUNCH_CHECK();
   HEF_TRY(reduce_cols_f64(vol, nc, 1, q.tot, stream));
   k_qual_phi<<<cdiv(nc, kQT), kQT, 0, stream>>>(cut, vol, q.tot, nc, phi);
