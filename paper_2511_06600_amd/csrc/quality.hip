@@ -16,7 +16,7 @@
 //     (sum over the cluster's nodes of their degrees), and the first pin of
 //     each run of one hyperedge adds w(e) to the cut when e is split;
 //  4. the volume total, phi and the average come from fixed-order
-//     reductions.
+//     two-stage sums over up to 256 workgroups.
 #include <cfloat>
 #include <cstdint>
 
@@ -128,17 +128,67 @@ k_qual_cluster(const float *__restrict__ w, const uint32_t *__restrict__ vals, c
   }
 }
 
-__global__ void k_qual_phi(const double *__restrict__ cut, const double *__restrict__ vol,
-                           const double *__restrict__ total, int32_t nc,
-                           double *__restrict__ phi) {
-  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (c >= nc) return;
-  const double x = cut[c];
-  phi[c] = x != 0.0 ? x / fmin(vol[c], *total - vol[c]) : 0.0;
+// Fixed-order float64 sums over many workgroups: workgroup b of nbk takes
+// the chunk [b ch, (b + 1) ch) of the ch = ceil(n / nbk) items, each thread
+// every kQT-th item of it, then an LDS tree; a single workgroup then adds
+// the nbk partials the same way.  nbk depends on n only.
+constexpr int kSumBlocks = 256;
+
+inline int sum_blocks(int64_t n) {
+  const int64_t b = cdiv(n, 1024);
+  return int(b < 1 ? 1 : (b > kSumBlocks ? kSumBlocks : b));
 }
 
-__global__ void k_qual_avg(const double *__restrict__ sum, int32_t nc, double *__restrict__ avg) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *avg = *sum / double(nc);
+__device__ __forceinline__ double block_sum(double x, double *sh) {
+  sh[threadIdx.x] = x;
+  __syncthreads();
+  for (int h = kQT / 2; h > 0; h >>= 1) {
+    if (int(threadIdx.x) < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__global__ void __launch_bounds__(kQT)
+k_sum_part(const double *__restrict__ in, int64_t n, double *__restrict__ part) {
+  __shared__ double sh[kQT];
+  const int64_t ch = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t a = int64_t(blockIdx.x) * ch, b = a + ch < n ? a + ch : n;
+  double x = 0.0;
+  for (int64_t i = a + threadIdx.x; i < b; i += kQT) x += in[i];
+  x = block_sum(x, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = x;
+}
+
+// *out = (sum of part[0 .. nbk)) / div
+__global__ void __launch_bounds__(kQT)
+k_sum_final(const double *__restrict__ part, int nbk, double div, double *__restrict__ out) {
+  __shared__ double sh[kQT];
+  double x = 0.0;
+  for (int i = threadIdx.x; i < nbk; i += kQT) x += part[i];
+  x = block_sum(x, sh);
+  if (threadIdx.x == 0) *out = x / div;
+}
+
+// phi of each cluster, and the workgroup partial sums of phi (the chunks of
+// k_sum_part)
+__global__ void __launch_bounds__(kQT)
+k_qual_phi(const double *__restrict__ cut, const double *__restrict__ vol,
+           const double *__restrict__ total, int64_t nc, double *__restrict__ phi,
+           double *__restrict__ part) {
+  __shared__ double sh[kQT];
+  const int64_t ch = (nc + gridDim.x - 1) / gridDim.x;
+  const int64_t a = int64_t(blockIdx.x) * ch, b = a + ch < nc ? a + ch : nc;
+  const double tv = *total;
+  double x = 0.0;
+  for (int64_t c = a + threadIdx.x; c < b; c += kQT) {
+    const double k = cut[c];
+    const double f = k != 0.0 ? k / fmin(vol[c], tv - vol[c]) : 0.0;
+    phi[c] = f;
+    x += f;
+  }
+  x = block_sum(x, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = x;
 }
 
 __global__ void k_qual_zero(double *__restrict__ a, double *__restrict__ b,
@@ -155,7 +205,7 @@ __global__ void k_qual_zero(double *__restrict__ a, double *__restrict__ b,
 struct QualWs {
   uint32_t *k0, *v0, *k1, *v1;
   int32_t *split, *seg, *bad;
-  double *tot, *psum;
+  double *tot, *part;
 };
 
 void qual_carve(Arena &a, int64_t n, int64_t m, int64_t nnz, QualWs &q) {
@@ -167,7 +217,7 @@ void qual_carve(Arena &a, int64_t n, int64_t m, int64_t nnz, QualWs &q) {
   q.seg = a.take<int32_t>((n > 1 ? n : 1) + 1);
   q.bad = a.take<int32_t>(1);
   q.tot = a.take<double>(1);
-  q.psum = a.take<double>(1);
+  q.part = a.take<double>(kSumBlocks);
 }
 
 }  // namespace
@@ -235,11 +285,14 @@ extern "C" hef_status hef_conductance(const hef_hypergraph *hg, const int32_t *l
   k_qual_cluster<<<cdiv(int64_t(nc) * 64, kQT), kQT, 0, stream>>>(L.w, q.v1, q.seg, q.split, nc,
                                                                  cut, vol);
   HEF_LAUNCH_CHECK();
-  HEF_TRY(reduce_cols_f64(vol, nc, 1, q.tot, stream));
-  k_qual_phi<<<cdiv(nc, kQT), kQT, 0, stream>>>(cut, vol, q.tot, nc, phi);
+  const int nbk = sum_blocks(nc);
+  k_sum_part<<<nbk, kQT, 0, stream>>>(vol, nc, q.part);
   HEF_LAUNCH_CHECK();
-  HEF_TRY(reduce_cols_f64(phi, nc, 1, q.psum, stream));
-  k_qual_avg<<<1, 64, 0, stream>>>(q.psum, nc, phi_avg);
+  k_sum_final<<<1, kQT, 0, stream>>>(q.part, nbk, 1.0, q.tot);
+  HEF_LAUNCH_CHECK();
+  k_qual_phi<<<nbk, kQT, 0, stream>>>(cut, vol, q.tot, nc, phi, q.part);
+  HEF_LAUNCH_CHECK();
+  k_sum_final<<<1, kQT, 0, stream>>>(q.part, nbk, double(nc), phi_avg);
   HEF_LAUNCH_CHECK();
   int32_t badlab = 0;
   HEF_HIP(hipMemcpyAsync(&badlab, q.bad, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
