@@ -143,6 +143,9 @@ def main():
                     help="skip the Alg. 1-only, BF16 and adjoint side measurements")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="copy 1 GiB once before timing (the reference kernel of PMC runs)")
+    ap.add_argument("--alg1-once", action="store_true",
+                    help="profiling run: after the calibration copy, one Alg. 1 estimate "
+                         "(hef_resistance, FP32 pool) at level 0 of the workload, no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -169,6 +172,12 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
+
+    if args.alg1_once:
+        hef.resistance(dh, hef.Params(k=cfg["k"], b=cfg["b"], assume_valid=True))
+        torch.cuda.synchronize()
+        print("# alg1-once done", file=sys.stderr, flush=True)
+        return
 
     for _ in range(args.warmup):
         hef.coarsen(dh, params)

@@ -177,22 +177,31 @@ class Pool:
 
 
 def unified_pool(n, m, eptr, pins, w, X_star, X_clique, k, tau=1e-3,
-                 use_star=True, use_clique=True) -> Pool:
+                 use_star=True, use_clique=True, keep_blocks=True) -> Pool:
     """The pool chi^(1..2 rho) of Alg. 1 steps 1-4: per-expansion Krylov bases
     without the start block, star vectors restricted to the hypergraph nodes,
-    star columns first, then one joint Gram-Schmidt in R^n."""
+    star columns first, then one joint Gram-Schmidt in R^n.  With
+    keep_blocks=False the per-expansion blocks are released as soon as their
+    pool columns are taken (same arithmetic, less host memory)."""
     cols = []
     sb, cb = [], []
     if use_star:
         Ab = star_operator(n, m, eptr, pins, w)
         sb = krylov_blocks(Ab, X_star, k, tau)
-        cols += [B[:n, :] for B in sb[1:]]
+        cols += [np.ascontiguousarray(B[:n, :]) for B in sb[1:]]
+        del Ab
+        if not keep_blocks:
+            sb = []
     ns = sum(c.shape[1] for c in cols)
     if use_clique:
         Ac = clique_operator(n, m, eptr, pins, w)
         cb = krylov_blocks(Ac, X_clique, k, tau)
         cols += [B for B in cb[1:]]
+        del Ac
+        if not keep_blocks:
+            cb = []
     V = np.hstack(cols) if cols else np.zeros((n, 0))
+    del cols
     Q, kept, rdiag = orthonormalize(V, np.linalg.norm(V, axis=0), tau)
     norms = np.linalg.norm(V, axis=0)
     rho = rdiag / norms[kept] if kept.size else rdiag

@@ -853,8 +853,8 @@ hef_status score_adjoint_t(const Level &L, const Structure &st, const float *chi
   HEF_LAUNCH_CHECK();
   HEF_TRY(reduce_cols_f64(w.spart, nblk, K, w.qsum, s));
   int32_t *slot_a = reinterpret_cast<int32_t *>(w.big);
-  int32_t *slot_b = slot_a + L.m * K;
-  float *dbar = reinterpret_cast<float *>(slot_b + L.m * K);
+  int32_t *slot_b = slot_a + int64_t(L.m) * K;
+  float *dbar = reinterpret_cast<float *>(slot_b + int64_t(L.m) * K);
   k_sadj_b<CPL><<<nblk, kThreads, 0, s>>>(L.eptr, L.pins, chi, K, LPR, L.m, qh, dR, L.w, w.istar,
                                           w.qsum, slot_a, slot_b, dbar, w.wdirect);
   HEF_LAUNCH_CHECK();

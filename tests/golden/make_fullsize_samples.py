@@ -38,23 +38,11 @@ def main(names):
 
 
 def lean_resistance(h, Xs, Xc, k, tau=1e-3):
-    """orr.resistance step by step (the same oracle functions in the same
-    order), releasing each expansion's blocks once its pool columns are
-    taken, so that the 2M-node case fits in host memory."""
-    cols = []
-    A = orr.star_operator(h.n, h.m, h.eptr, h.pins, h.w)
-    blocks = orr.krylov_blocks(A, Xs, k, tau)
-    cols += [np.ascontiguousarray(B[:h.n, :]) for B in blocks[1:]]
-    del blocks, A
-    A = orr.clique_operator(h.n, h.m, h.eptr, h.pins, h.w)
-    blocks = orr.krylov_blocks(A, Xc, k, tau)
-    cols += blocks[1:]
-    del blocks, A
-    V = np.hstack(cols)
-    del cols
-    chi, _, _ = orr.orthonormalize(V, np.linalg.norm(V, axis=0), tau)
-    del V
-    return orr.resistance_from_pool(h.eptr, h.pins, h.w, chi)
+    """orr.resistance with the per-expansion blocks released as soon as
+    their pool columns are taken, so that the 2M-node case fits in host
+    memory: orr.unified_pool(keep_blocks=False), then the ratios."""
+    pool = orr.unified_pool(h.n, h.m, h.eptr, h.pins, h.w, Xs, Xc, k, tau, keep_blocks=False)
+    return orr.resistance_from_pool(h.eptr, h.pins, h.w, pool.chi)
 
 
 if __name__ == "__main__":

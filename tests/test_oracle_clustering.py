@@ -186,3 +186,57 @@ def test_multilevel_coarsening_shrinks_and_composes():
     assert out.eta.shape == (out.n_clusters,)
     assert (out.eta >= 0).all()
     assert out.R0.shape == (h.m,)
+
+
+GOLD2 = os.path.join(os.path.dirname(__file__), "golden", "coarsen_two_level_examples.json")
+
+
+@pytest.mark.parametrize("ex", json.load(open(GOLD2))["examples"], ids=lambda e: e["name"])
+def test_hand_worked_two_level_coarsening(ex, monkeypatch):
+    """The level loop of Alg. 2 with prescribed per-level resistances: the
+    composed map, the eta carried into the next level's Eq. (15), and the
+    final eta, against hand-worked values."""
+    from types import SimpleNamespace
+
+    calls = []
+
+    def fake_resistance(n, m, eptr, pins, w, Xs, Xc, k, tau=1e-3, **kw):
+        lev = ex["levels"][len(calls)]
+        calls.append((n, m, int(np.asarray(eptr)[-1])))
+        assert len(lev["R"]) == m and len(lev["chi"]) == n
+        return SimpleNamespace(R=np.array(lev["R"], dtype=np.float32),
+                               qh=np.array(lev["qh"], dtype=np.float64),
+                               pool=SimpleNamespace(chi=np.array(lev["chi"], dtype=np.float64)))
+
+    monkeypatch.setattr(oco.resistance, "resistance", fake_resistance)
+    eptr, pins = _csr(ex["edges"])
+    start = lambda lev, x, rows, b: np.zeros((rows, b))  # noqa: E731
+    out = oco.coarsen(ex["n"], len(ex["edges"]), eptr, pins, np.array(ex["w"], np.float32), 1, 1,
+                      len(ex["levels"]), start, 0.5, ex["local_clustering"])
+    assert [list(c) for c in calls] == ex["expect_level_sizes"]
+    assert out.cluster.tolist() == ex["expect_cluster"]
+    assert out.n_clusters == ex["expect_n_clusters"]
+    # level-0 R_upd is R itself (eta = 0); level-1 R_upd adds the eta of the
+    # level-0 clusters in CSR pin order (float64, then float32)
+    lev0, lev1 = out.levels[0][3], out.levels[1][3]
+    assert np.array_equal(lev0.R_upd, np.array(ex["expect_R_upd"][0], dtype=np.float32))
+    eta1 = lev0.eta
+    for j, terms in enumerate(ex["expect_R_upd"][1]):
+        acc = 0.0
+        for t in terms[1:]:
+            acc += float(eta1[int(t[3:])]) if isinstance(t, str) else float(np.float32(t))
+        assert lev1.R_upd[j] == np.float32(acc), (j, lev1.R_upd[j], acc)
+    if ex.get("expect_level_eta"):
+        first = ex["expect_level_eta"][0]
+        assert lev0.eta[0] == np.float32(first[0])
+        assert lev0.eta[1] == np.float32(sum([float(np.float32(first[1][0]))] + first[1][1:]))
+    exp = ex["expect_eta"]
+    if exp and isinstance(exp[0], list):
+        # final eta as a sum of level-1 cluster etas and attach distances
+        for c, terms in enumerate(exp[0]):
+            acc = 0.0
+            for t in terms:
+                acc += float(lev0.eta[int(t[8:])]) if isinstance(t, str) else float(t)
+            assert out.eta[c] == np.float32(acc), (c, out.eta[c], acc)
+    else:
+        assert np.array_equal(out.eta, np.array(exp, dtype=np.float32))

@@ -135,6 +135,75 @@ def test_pool_matches_high_precision_gram_schmidt_of_power_basis():
         assert min(np.abs(o - joint[:, j]).max(), np.abs(o + joint[:, j]).max()) < 1e-9
 
 
+def _mp_power_gs(A, X, k, digits=60):
+    """60-digit Gram-Schmidt of the step-major power basis
+    [x_1 .. x_b, A x_1 .. A x_b, ..., A^k x_1 .. A^k x_b] (float64 out)."""
+    mpmath.mp.dps = digits
+    Am = mpmath.matrix(A.tolist())
+    b = X.shape[1]
+    cur = [mpmath.matrix(X[:, c].tolist()) for c in range(b)]
+    power = []
+    for _ in range(k + 1):
+        power += cur
+        cur = [Am * v for v in cur]
+    Q = []
+    for u0 in power:
+        u = u0
+        for q in Q:
+            u = u - (q.T * u0)[0] * q
+        Q.append(u / mpmath.norm(u))
+    return np.array([[float(q[r]) for q in Q] for r in range(A.shape[0])])
+
+
+def test_block_pool_matches_high_precision_gram_schmidt_step_major():
+    """b = 2: column c of Krylov block j equals column j*b + c of the 60-digit
+    Gram-Schmidt of the step-major power basis (start vectors of one step
+    first, then their images), for both expansions; the joint pool is then
+    the 60-digit Gram-Schmidt of [star node parts | clique], each part in
+    step-major order.  A block laid out expansion-major or column-major
+    (x_1, A x_1, ..., x_2, A x_2, ...) fails this."""
+    h = make_hypergraph("pinv50")
+    k, b = 4, 2
+    Xs = start_block(7, 0, 0, h.n + h.m, b)
+    Xc = start_block(7, 0, 1, h.n, b)
+    est = orr.resistance(h.n, h.m, h.eptr, h.pins, h.w, Xs, Xc, k)
+    assert est.pool.chi.shape[1] == 2 * b * k
+    cols = []
+    for A, X, blocks, rows in ((orr.star_operator(h.n, h.m, h.eptr, h.pins, h.w), Xs,
+                                est.pool.star_blocks, h.n),
+                               (orr.clique_operator(h.n, h.m, h.eptr, h.pins, h.w), Xc,
+                                est.pool.clique_blocks, h.n)):
+        Qn = _mp_power_gs(A.toarray(), X, k)
+        assert len(blocks) == k + 1
+        for j in range(k + 1):
+            assert blocks[j].shape[1] == b
+            for c in range(b):
+                o, ref = blocks[j][:, c], Qn[:, j * b + c]
+                assert min(np.abs(o - ref).max(), np.abs(o + ref).max()) < 1e-9, (j, c)
+        cols.append(Qn[:rows, b:])
+    joint = _mp_gs(np.hstack(cols))
+    for j in range(joint.shape[1]):
+        o = est.pool.chi[:, j]
+        assert min(np.abs(o - joint[:, j]).max(), np.abs(o + joint[:, j]).max()) < 1e-9, j
+
+
+def test_fullsize_golden_script_equals_the_oracle():
+    """The script that writes the full-size oracle samples computes exactly
+    orr.resistance (it only frees each expansion's blocks early)."""
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "make_fullsize_samples.py")
+    spec = importlib.util.spec_from_file_location("make_fullsize_samples", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    h = make_hypergraph("tiny2k")
+    Xs = start_block(7, 0, 0, h.n + h.m, 2)
+    Xc = start_block(7, 0, 1, h.n, 2)
+    R, qh = mod.lean_resistance(h, Xs, Xc, 5)
+    ref = orr.resistance(h.n, h.m, h.eptr, h.pins, h.w, Xs, Xc, 5)
+    assert np.array_equal(R, ref.R) and np.array_equal(qh, ref.qh)
+
+
 def test_pool_orthonormal_and_well_conditioned():
     h = make_hypergraph("tiny2k")
     est = _est(h, k=10, b=1)
