@@ -152,3 +152,28 @@ def test_full_size_gradient_matches_oracle():
     say(f"  L gpu {L:.9e} oracle {float(ref['L']):.9e}; dw norm-rel err vs oracle {err:.2e}")
     assert abs(L - float(ref["L"])) <= 1e-4 * abs(float(ref["L"]))
     assert err < 1e-3
+
+
+def test_wide_pool_with_more_than_2_31_score_entries():
+    """m x K above 2^31 (4.25M hyperedges, K = 512): the score adjoint's
+    per-(e, i) slices and the forward's stored numerators sit past 2^31
+    entries of the workspace.  Euler's identity w . dL/dw = -L (R is
+    homogeneous of degree -1 in w) holds at any size; c_e > 0 keeps L free of
+    cancellation."""
+    n, m = 1_000_000, 4_250_000
+    h = generate(n, m, 2, 6, 2.5, p_loc=0.7, win=200, weights="lognormal", seed=77)
+    p = hef.Params(k=32, b=16, star_only=True, assume_valid=True)
+    K = p.K
+    say(f"case: wide pool n={h.n} m={h.m} nnz={h.nnz} K={K} m*K={h.m * K} (2^31={2**31})")
+    assert h.m * K > 2 ** 31
+    dh = to_device(h)
+    coef = 1.0 + 0.5 * np.random.default_rng(78).random(h.m)
+    R, _, _ = hef.resistance(dh, p)
+    dw = hef.resistance_backward(dh, p, torch.as_tensor(coef.astype(np.float32), device="cuda"))
+    R = R.cpu().numpy().astype(np.float64)
+    dw = dw.cpu().numpy().astype(np.float64)
+    L = float(coef @ R)
+    euler = float(h.w.astype(np.float64) @ dw)
+    say(f"  L={L:.6e} w.dw={euler:.6e} rel {abs(euler + L) / abs(L):.2e}")
+    assert np.isfinite(R).all() and np.isfinite(dw).all() and (R >= 0).all()
+    assert abs(euler + L) <= 1e-3 * abs(L)
