@@ -142,6 +142,25 @@ hef_status hef_resistance(const hef_hypergraph *hg, const hef_params *p,
                           float *R, double *qh, void *chi,
                           void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* hef_resistance for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * It takes no workspace; its scratch is a static device array of
+ * HEF_STATIC_SCRATCH_BYTES bytes that every device the library runs on holds
+ * until the process ends, and the call itself calls no hipMalloc, hipFree or
+ * allocating library routine.  Arguments, outputs, errors and results are
+ * those of hef_resistance (bitwise identical for identical inputs); the
+ * caller still provides every input and output.  A hypergraph whose
+ * workspace (hef_workspace_size with HEF_OP_RESISTANCE, or with chi given,
+ * that size less the n x K pool) exceeds HEF_STATIC_SCRATCH_BYTES returns
+ * HEF_ERR_WORKSPACE_TOO_SMALL with nothing written.  All calls on one device
+ * share that device's scratch, which keeps the last call's contents (every
+ * call initialises what it reads): calls that overlap on one device -- on
+ * two streams or from two threads -- race and give undefined results. */
+#define HEF_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+hef_status hef_resistance_static(const hef_hypergraph *hg, const hef_params *p,
+                                 const float *start_star, const float *start_clique, float *R,
+                                 double *qh, void *chi, hipStream_t stream);
+
 /* Alg. 2 (Section III-A "Multilevel Effective Resistance Clustering",
  * Eq. (15); Section III-B, Eq. (16)): `levels` rounds of resistance
  * estimation, Eq. (15) update, threshold contraction in ascending resistance

@@ -123,6 +123,28 @@ def resistance(hg: DeviceHypergraph, params: Params, start_star: torch.Tensor | 
     return R, qh, chi
 
 
+def resistance_static(hg: DeviceHypergraph, params: Params,
+                      start_star: torch.Tensor | None = None,
+                      start_clique: torch.Tensor | None = None, return_pool: bool = False):
+    """Alg. 1 through hef_resistance_static (no workspace: the library's
+    per-device static scratch); returns what resistance() returns."""
+    lib = load()
+    K = params.K
+    R = torch.empty(hg.m, dtype=torch.float32, device=hg.device)
+    qh = torch.empty(K, dtype=torch.float64, device=hg.device)
+    chi = None
+    if return_pool:
+        dt = torch.bfloat16 if params.basis == "bf16" else torch.float32
+        chi = torch.empty((hg.n, K), dtype=dt, device=hg.device)
+    for t, rows in ((start_star, hg.n + hg.m), (start_clique, hg.n)):
+        if t is not None:
+            assert t.dtype == torch.float32 and t.is_contiguous() and t.shape == (rows, params.b)
+    check(lib.hef_resistance_static(C.byref(hg.c()), C.byref(params.c()), _ptr(start_star),
+                                    _ptr(start_clique), _ptr(R), _ptr(qh), _ptr(chi),
+                                    _stream(hg.device)), "hef_resistance_static")
+    return R, qh, chi
+
+
 def coarsen(hg: DeviceHypergraph, params: Params):
     """Alg. 2: returns (cluster [n] int32, n_clusters, R0 [m], eta [n_clusters])."""
     lib = load()

@@ -15,11 +15,12 @@ STATUS = {
 }
 OP_RESISTANCE, OP_COARSEN, OP_CLUSTER_LEVEL, OP_BACKWARD, OP_APPLY, OP_CONDUCTANCE = range(6)
 BASIS_FP32, BASIS_BF16 = 0, 1
+STATIC_SCRATCH_BYTES = 64 << 20  # HEF_STATIC_SCRATCH_BYTES
 FLAG_ASSUME_VALID, FLAG_STAR_ONLY, FLAG_CLIQUE_ONLY, FLAG_TAPED = 1, 2, 4, 8
 
 EXPORTS = [
     "hef_params_default", "hef_pool_width", "hef_workspace_size", "hef_validate_host",
-    "hef_resistance", "hef_coarsen", "hef_cluster_level", "hef_resistance_backward",
+    "hef_resistance", "hef_resistance_static", "hef_coarsen", "hef_cluster_level", "hef_resistance_backward",
     "hef_resistance_taped", "hef_conductance",
     "hef_debug_apply", "hef_debug_gram", "hef_debug_gram_ws", "hef_start_block",
     "hef_status_string", "hef_last_error", "hef_timing_enable", "hef_timing_stage_count",
@@ -65,6 +66,7 @@ def load() -> C.CDLL:
         "hef_workspace_size": (i32, [HG, PR, i32, C.POINTER(sz)]),
         "hef_validate_host": (i32, [i32, i32, vp, vp, vp]),
         "hef_resistance": (i32, [HG, PR, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "hef_resistance_static": (i32, [HG, PR, vp, vp, vp, vp, vp, vp]),
         "hef_coarsen": (i32, [HG, PR, vp, C.POINTER(i32), vp, vp, vp, sz, vp]),
         "hef_cluster_level": (i32, [HG, PR, vp, vp, vp, vp, vp, C.POINTER(i32), vp, vp, sz, vp]),
         "hef_resistance_backward": (i32, [HG, PR, vp, vp, vp, vp, vp, sz, vp]),

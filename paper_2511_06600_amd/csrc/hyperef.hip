@@ -215,6 +215,45 @@ size_t estimate_level_bytes(int64_t n, int64_t m, int64_t nnz, const hef_params 
 
 int pool_width_of(const hef_params &p) { return pool_width(p); }
 
+
+// ---- static scratch of hef_resistance_static: one array per device (each
+// device holds its own copy at its own address until the process ends).  In
+// host code `scratch` names a host-side stand-in, never device memory: the
+// device address comes from hipGetSymbolAddress, once per device with that
+// device current, and only that address is handed to kernels.
+static __device__ __align__(256) char scratch[HEF_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hef_status static_scratch(void **out) {
+  int dev = -1;
+  HEF_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device %d: the static scratch supports devices 0..%d", dev, kMaxDevices - 1);
+    return HEF_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+      set_error("hipGetSymbolAddress(scratch) on device %d failed: %s", dev, hipGetErrorString(e));
+      return HEF_ERR_DEVICE;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return HEF_OK;
+}
+
+hef_status resistance_call(const hef_hypergraph *hg, const hef_params *p, const float *start_star,
+                           const float *start_clique, float *R, double *qh, void *chi, void *ws,
+                           size_t ws_bytes, hipStream_t stream);
+
 }  // namespace hef
 
 using namespace hef;
@@ -305,6 +344,33 @@ hef_status hef_validate_host(int32_t n, int32_t m, const int32_t *eptr, const in
 hef_status hef_resistance(const hef_hypergraph *hg, const hef_params *p, const float *start_star,
                           const float *start_clique, float *R, double *qh, void *chi, void *ws,
                           size_t ws_bytes, hipStream_t stream) {
+  return hef::resistance_call(hg, p, start_star, start_clique, R, qh, chi, ws, ws_bytes, stream);
+}
+
+hef_status hef_resistance_static(const hef_hypergraph *hg, const hef_params *p,
+                                 const float *start_star, const float *start_clique, float *R,
+                                 double *qh, void *chi, hipStream_t stream) {
+  HEF_TRY(check_hg(hg));
+  HEF_TRY(check_params(p, false));
+  const size_t need = resistance_bytes(hg->n, hg->m, hg->nnz, *p, chi == nullptr);
+  if (need > HEF_STATIC_SCRATCH_BYTES) {
+    set_error("this hypergraph needs %zu bytes of scratch; the static scratch holds %zu "
+              "(use hef_resistance with a workspace)", need, size_t(HEF_STATIC_SCRATCH_BYTES));
+    return HEF_ERR_WORKSPACE_TOO_SMALL;
+  }
+  void *ws = nullptr;
+  HEF_TRY(static_scratch(&ws));
+  return hef::resistance_call(hg, p, start_star, start_clique, R, qh, chi, ws,
+                              HEF_STATIC_SCRATCH_BYTES, stream);
+}
+
+}  // extern "C"
+
+namespace hef {
+
+hef_status resistance_call(const hef_hypergraph *hg, const hef_params *p, const float *start_star,
+                           const float *start_clique, float *R, double *qh, void *chi, void *ws,
+                           size_t ws_bytes, hipStream_t stream) {
   HEF_TRY(check_hg(hg));
   HEF_TRY(check_params(p, false));
   if (!R && hg->m > 0) { set_error("R is NULL"); return HEF_ERR_INVALID_ARGUMENT; }
@@ -359,6 +425,10 @@ hef_status hef_resistance(const hef_hypergraph *hg, const hef_params *p, const f
   if (qh) HEF_HIP(hipMemcpyAsync(qh, qh_ws, K * sizeof(double), hipMemcpyDeviceToDevice, stream));
   return HEF_OK;
 }
+
+}  // namespace hef
+
+extern "C" {
 
 hef_status hef_debug_apply(const hef_hypergraph *hg, int32_t expansion, int32_t b, const float *x,
                            float *y, void *ws, size_t ws_bytes, hipStream_t stream) {
