@@ -68,7 +68,8 @@ typedef enum {
   HEF_OP_CLUSTER_LEVEL = 2,
   HEF_OP_BACKWARD = 3,
   HEF_OP_APPLY = 4,
-  HEF_OP_CONDUCTANCE = 5  /* sized for n_clusters up to n; ignores params  */
+  HEF_OP_CONDUCTANCE = 5, /* sized for n_clusters up to n; ignores params  */
+  HEF_OP_REBUILD = 6      /* hef_rebuild; ignores params                    */
 } hef_op;
 
 /* Flags for hef_params.flags. */
@@ -99,11 +100,17 @@ typedef struct {
   int32_t orth_passes;   /* joint Cholesky-QR passes, 1 or 2                */
   int32_t ckpt_every;    /* Krylov checkpoint interval of the adjoint (5)   */
   uint32_t flags;        /* HEF_FLAG_*                                      */
+  float target_nr;       /* node-reduction target of the level loop (Section
+                            IV: NR = 60 % is a 2.5x reduction): with
+                            target_nr > 0 coarsening stops before a level
+                            once n_l <= (1 - target_nr) n_0, or after a level
+                            that merged nothing; `levels` stays the cap.
+                            0 = run exactly `levels` levels.  In [0, 1).   */
 } hef_params;
 
 /* Fills *p with the defaults: k=10, b=1, levels=1, percentile=0.5,
  * local_clustering=1, basis=FP32, seed=7, drop_tol=1e-3, orth_passes=1,
- * ckpt_every=5, flags=0. */
+ * ckpt_every=5, flags=0, target_nr=0. */
 void hef_params_default(hef_params *p);
 
 /* Pool width K = 2*b*k (b*k with a single-expansion flag). */
@@ -136,7 +143,11 @@ hef_status hef_validate_host(int32_t n, int32_t m, const int32_t *eptr,
  *                column reports 0;
  *   chi          DEVICE [n x K] row-major output pool (float32, or bfloat16
  *                when basis = BF16), or NULL; dropped columns are zero.
- * HEF_ERR_NUMERICAL if every Q_H vanished or a value is not finite. */
+ * Unless HEF_FLAG_ASSUME_VALID is set, the results are checked on the device
+ * (one more stream synchronisation) and HEF_ERR_NUMERICAL is returned if
+ * every Q_H vanished or a value is not finite.  With HEF_FLAG_ASSUME_VALID
+ * the call synchronises nothing and checks neither the input nor the
+ * results: the caller vouches for both. */
 hef_status hef_resistance(const hef_hypergraph *hg, const hef_params *p,
                           const float *start_star, const float *start_clique,
                           float *R, double *qh, void *chi,
@@ -177,6 +188,43 @@ hef_status hef_coarsen(const hef_hypergraph *hg, const hef_params *p,
                        int32_t *cluster, int32_t *n_clusters, float *R0,
                        float *eta, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* What hef_coarsen_levels records of every level l < cap it runs (any
+ * pointer may be NULL; n0, m0 are the sizes of the input hypergraph and K
+ * the pool width):
+ *   n, m, nnz  HOST [cap]: sizes of level l's hypergraph (level 0 = input);
+ *   R          DEVICE [cap x m0] float32: level l's resistances (Alg. 1, before
+ *              Eq. (15)) at offset l*m0, first m_l entries;
+ *   qh         DEVICE [cap x K] float64: level l's Q_H per pool column;
+ *   rho        DEVICE [cap x K] float64: level l's relative Gram-Schmidt
+ *              residuals |R_jj| / ||V_j|| of the joint orthonormalisation
+ *              (Alg. 1 step 4; 0 for a dropped column); min over j is the
+ *              pool's conditioning margin;
+ *   label      DEVICE [cap x n0] int32: level-l node -> level-(l+1) node at
+ *              offset l*n0, first n_l entries;
+ *   eta        DEVICE [cap x n0] float32: eta of the level-(l+1) nodes (the
+ *              clusters level l formed) at offset l*n0, first n_{l+1} entries;
+ *   levels_run HOST output: the number of levels run. */
+typedef struct {
+  int32_t cap;
+  int32_t levels_run;
+  int32_t *n, *m;
+  int64_t *nnz;
+  float *R;
+  double *qh;
+  double *rho;
+  int32_t *label;
+  float *eta;
+} hef_level_trace;
+
+/* hef_coarsen with a per-level record (`trace` may be NULL): the level-l
+ * resistances and eta serve the partitioner integration of Section III-E
+ * (its Eq. (15) node weights and per-level ratings), and the per-level
+ * labels compose to the final map. */
+hef_status hef_coarsen_levels(const hef_hypergraph *hg, const hef_params *p, int32_t *cluster,
+                              int32_t *n_clusters, float *R0, float *eta,
+                              hef_level_trace *trace, void *ws, size_t ws_bytes,
+                              hipStream_t stream);
+
 /* Sizes (n, m, nnz; HOST arrays of `cap` entries, any may be NULL) of the
  * levels whose resistances the calling thread's last hef_coarsen call
  * estimated; returns the number of such levels. */
@@ -186,7 +234,11 @@ int32_t hef_last_coarsen_levels(int32_t *n, int32_t *m, int64_t *nnz, int32_t ca
  * feed the same resistances to two implementations:
  *   R        DEVICE [m] float32 resistances of this level;
  *   eta_in   DEVICE [n] float32 node weights eta (Eq. (15)), NULL = zeros;
- *   chi      DEVICE [n x K] float32 pool, K = hef_pool_width(p);
+ *   chi      DEVICE [n x K] pool, K = hef_pool_width(p): float32, or
+ *            bfloat16 when p->basis = HEF_BASIS_BF16 (as hef_resistance
+ *            writes it); with local clustering every value must be finite
+ *            and below 65504 in magnitude (the best-neighbour screen keeps
+ *            float16 copies), else HEF_ERR_INVALID_ARGUMENT;
  *   qh       DEVICE [K] float64 quadratic forms (<= 0 marks an unusable column);
  *   cluster  DEVICE [n] int32 output: node -> cluster label;
  *   n_clusters HOST int32 output;
@@ -198,6 +250,24 @@ hef_status hef_cluster_level(const hef_hypergraph *hg, const hef_params *p,
                              int32_t *cluster, int32_t *n_clusters,
                              float *eta_out, void *ws, size_t ws_bytes,
                              hipStream_t stream);
+
+/* Alg. 2 step 6, the coarse hypergraph H' of a clustering: each pin p
+ * becomes label[p], the labels of a hyperedge are sorted and deduplicated,
+ * hyperedges left with fewer than 2 pins are removed, and the kept ones keep
+ * their order and weight (w' = w).
+ *   label      DEVICE [n] int32: node -> cluster in [0, n_clusters) (a pin
+ *              whose label lies outside gives HEF_ERR_INVALID_ARGUMENT);
+ *   eptr_out   DEVICE [m+1] int32, pins_out DEVICE [nnz] int32, w_out
+ *              DEVICE [m] float32: H' in CSR (first m' + 1, nnz', m'
+ *              entries written);
+ *   kept_out   DEVICE [m] int32 or NULL: the input id of each kept hyperedge;
+ *   m_out, nnz_out  HOST: m' and nnz';
+ *   ws         DEVICE workspace of hef_workspace_size(hg, NULL, HEF_OP_REBUILD).
+ * The hypergraph is validated on the device.  Synchronises `stream`. */
+hef_status hef_rebuild(const hef_hypergraph *hg, const int32_t *label, int32_t n_clusters,
+                       int32_t *eptr_out, int32_t *pins_out, float *w_out, int32_t *kept_out,
+                       int32_t *m_out, int64_t *nnz_out, void *ws, size_t ws_bytes,
+                       hipStream_t stream);
 
 /* Cluster quality of a partition (Section II-A, Eq. (3); Section IV,
  * Eq. (18)).  With d_v the summed weight of v's hyperedges and vol(S) the

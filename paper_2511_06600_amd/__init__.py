@@ -37,6 +37,7 @@ class Params:
     assume_valid: bool = False
     star_only: bool = False
     clique_only: bool = False
+    target_nr: float = 0.0        # node-reduction target of the level loop (0 = off)
 
     def c(self) -> _lib.HefParams:
         p = _lib.HefParams()
@@ -51,6 +52,7 @@ class Params:
         p.flags = ((_lib.FLAG_ASSUME_VALID if self.assume_valid else 0)
                    | (_lib.FLAG_STAR_ONLY if self.star_only else 0)
                    | (_lib.FLAG_CLIQUE_ONLY if self.clique_only else 0))
+        p.target_nr = self.target_nr
         return p
 
     @property
@@ -159,6 +161,64 @@ def coarsen(hg: DeviceHypergraph, params: Params):
     return cluster, int(nc.value), R0, eta[:int(nc.value)]
 
 
+def coarsen_levels(hg: DeviceHypergraph, params: Params):
+    """Alg. 2 with the per-level record of hef_coarsen_levels: returns
+    (cluster, n_clusters, R0, eta, levels), levels a list of dicts with the
+    level's sizes n, m, nnz and its R [m], qh [K], rho [K], label [n] and
+    eta [n_next] (device tensors)."""
+    lib = load()
+    cap = params.levels
+    K = params.K
+    cluster = torch.empty(hg.n, dtype=torch.int32, device=hg.device)
+    R0 = torch.empty(hg.m, dtype=torch.float32, device=hg.device)
+    eta = torch.empty(max(hg.n, 1), dtype=torch.float32, device=hg.device)
+    Rl = torch.empty((cap, max(hg.m, 1)), dtype=torch.float32, device=hg.device)
+    ql = torch.empty((cap, max(K, 1)), dtype=torch.float64, device=hg.device)
+    rl = torch.empty((cap, max(K, 1)), dtype=torch.float64, device=hg.device)
+    ll = torch.empty((cap, max(hg.n, 1)), dtype=torch.int32, device=hg.device)
+    el = torch.empty((cap, max(hg.n, 1)), dtype=torch.float32, device=hg.device)
+    hn = np.zeros(cap, dtype=np.int32)
+    hm = np.zeros(cap, dtype=np.int32)
+    hz = np.zeros(cap, dtype=np.int64)
+    tr = _lib.HefLevelTrace()
+    tr.cap = cap
+    tr.n, tr.m, tr.nnz = hn.ctypes.data, hm.ctypes.data, hz.ctypes.data
+    tr.R, tr.qh, tr.rho = _ptr(Rl), _ptr(ql), _ptr(rl)
+    tr.label, tr.eta = _ptr(ll), _ptr(el)
+    nc = C.c_int32(0)
+    ws = _workspace(hg, params, _lib.OP_COARSEN)
+    check(lib.hef_coarsen_levels(C.byref(hg.c()), C.byref(params.c()), _ptr(cluster),
+                                 C.byref(nc), _ptr(R0), _ptr(eta), C.byref(tr), _ptr(ws),
+                                 ws.numel(), _stream(hg.device)), "hef_coarsen_levels")
+    levels = []
+    for lv in range(tr.levels_run):
+        n_next = int(hn[lv + 1]) if lv + 1 < tr.levels_run else int(nc.value)
+        levels.append(dict(n=int(hn[lv]), m=int(hm[lv]), nnz=int(hz[lv]),
+                           R=Rl[lv, :int(hm[lv])], qh=ql[lv, :K], rho=rl[lv, :K],
+                           label=ll[lv, :int(hn[lv])], eta=el[lv, :n_next]))
+    return cluster, int(nc.value), R0, eta[:int(nc.value)], levels
+
+
+def rebuild(hg: DeviceHypergraph, label: torch.Tensor, n_clusters: int):
+    """Alg. 2 step 6: the coarse hypergraph of a clustering, as
+    (DeviceHypergraph over n_clusters nodes, kept [m'] int32 input ids)."""
+    lib = load()
+    assert label.dtype == torch.int32 and label.shape == (hg.n,) and label.is_contiguous()
+    eptr = torch.empty(hg.m + 1, dtype=torch.int32, device=hg.device)
+    pins = torch.empty(max(hg.nnz, 1), dtype=torch.int32, device=hg.device)
+    w = torch.empty(max(hg.m, 1), dtype=torch.float32, device=hg.device)
+    kept = torch.empty(max(hg.m, 1), dtype=torch.int32, device=hg.device)
+    m2 = C.c_int32(0)
+    nnz2 = C.c_int64(0)
+    ws = _workspace(hg, Params(), _lib.OP_REBUILD)
+    check(lib.hef_rebuild(C.byref(hg.c()), _ptr(label), int(n_clusters), _ptr(eptr), _ptr(pins),
+                          _ptr(w), _ptr(kept), C.byref(m2), C.byref(nnz2), _ptr(ws), ws.numel(),
+                          _stream(hg.device)), "hef_rebuild")
+    m2, nnz2 = int(m2.value), int(nnz2.value)
+    out = DeviceHypergraph(int(n_clusters), m2, eptr[:m2 + 1], pins[:nnz2], w[:m2])
+    return out, kept[:m2]
+
+
 def cluster_level(hg: DeviceHypergraph, params: Params, R: torch.Tensor,
                   eta: torch.Tensor | None, chi: torch.Tensor, qh: torch.Tensor):
     """One level of Alg. 2 from given inputs: (cluster [n], n_clusters, eta_out)."""
@@ -167,7 +227,8 @@ def cluster_level(hg: DeviceHypergraph, params: Params, R: torch.Tensor,
     eta_out = torch.empty(max(hg.n, 1), dtype=torch.float32, device=hg.device)
     nc = C.c_int32(0)
     ws = _workspace(hg, params, _lib.OP_CLUSTER_LEVEL)
-    assert chi.dtype == torch.float32 and chi.shape == (hg.n, params.K) and chi.is_contiguous()
+    want = torch.bfloat16 if params.basis == "bf16" else torch.float32
+    assert chi.dtype == want and chi.shape == (hg.n, params.K) and chi.is_contiguous()
     check(lib.hef_cluster_level(C.byref(hg.c()), C.byref(params.c()), _ptr(R), _ptr(eta),
                                 _ptr(chi), _ptr(qh), _ptr(cluster), C.byref(nc), _ptr(eta_out),
                                 _ptr(ws), ws.numel(), _stream(hg.device)), "hef_cluster_level")

@@ -13,7 +13,8 @@ STATUS = {
     3: "HEF_ERR_WORKSPACE_TOO_SMALL", 4: "HEF_ERR_DEVICE", 5: "HEF_ERR_NUMERICAL",
     6: "HEF_ERR_UNSUPPORTED",
 }
-OP_RESISTANCE, OP_COARSEN, OP_CLUSTER_LEVEL, OP_BACKWARD, OP_APPLY, OP_CONDUCTANCE = range(6)
+(OP_RESISTANCE, OP_COARSEN, OP_CLUSTER_LEVEL, OP_BACKWARD, OP_APPLY, OP_CONDUCTANCE,
+ OP_REBUILD) = range(7)
 BASIS_FP32, BASIS_BF16 = 0, 1
 STATIC_SCRATCH_BYTES = 64 << 20  # HEF_STATIC_SCRATCH_BYTES
 FLAG_ASSUME_VALID, FLAG_STAR_ONLY, FLAG_CLIQUE_ONLY, FLAG_TAPED = 1, 2, 4, 8
@@ -21,7 +22,7 @@ FLAG_ASSUME_VALID, FLAG_STAR_ONLY, FLAG_CLIQUE_ONLY, FLAG_TAPED = 1, 2, 4, 8
 EXPORTS = [
     "hef_params_default", "hef_pool_width", "hef_workspace_size", "hef_validate_host",
     "hef_resistance", "hef_resistance_static", "hef_coarsen", "hef_cluster_level", "hef_resistance_backward",
-    "hef_resistance_taped", "hef_conductance",
+    "hef_resistance_taped", "hef_conductance", "hef_coarsen_levels", "hef_rebuild",
     "hef_debug_apply", "hef_debug_gram", "hef_debug_gram_ws", "hef_start_block",
     "hef_status_string", "hef_last_error", "hef_timing_enable", "hef_timing_stage_count",
     "hef_timing_stage_name", "hef_timing_read", "hef_last_coarsen_levels",
@@ -37,7 +38,15 @@ class HefParams(C.Structure):
     _fields_ = [("k", C.c_int32), ("b", C.c_int32), ("levels", C.c_int32),
                 ("percentile", C.c_float), ("local_clustering", C.c_int32),
                 ("basis", C.c_int32), ("seed", C.c_uint64), ("drop_tol", C.c_float),
-                ("orth_passes", C.c_int32), ("ckpt_every", C.c_int32), ("flags", C.c_uint32)]
+                ("orth_passes", C.c_int32), ("ckpt_every", C.c_int32), ("flags", C.c_uint32),
+                ("target_nr", C.c_float)]
+
+
+class HefLevelTrace(C.Structure):
+    _fields_ = [("cap", C.c_int32), ("levels_run", C.c_int32),
+                ("n", C.c_void_p), ("m", C.c_void_p), ("nnz", C.c_void_p),
+                ("R", C.c_void_p), ("qh", C.c_void_p), ("rho", C.c_void_p),
+                ("label", C.c_void_p), ("eta", C.c_void_p)]
 
 
 class HefError(RuntimeError):
@@ -68,6 +77,10 @@ def load() -> C.CDLL:
         "hef_resistance": (i32, [HG, PR, vp, vp, vp, vp, vp, vp, sz, vp]),
         "hef_resistance_static": (i32, [HG, PR, vp, vp, vp, vp, vp, vp]),
         "hef_coarsen": (i32, [HG, PR, vp, C.POINTER(i32), vp, vp, vp, sz, vp]),
+        "hef_coarsen_levels": (i32, [HG, PR, vp, C.POINTER(i32), vp, vp,
+                                     C.POINTER(HefLevelTrace), vp, sz, vp]),
+        "hef_rebuild": (i32, [HG, vp, i32, vp, vp, vp, vp, C.POINTER(i32), C.POINTER(i64), vp,
+                              sz, vp]),
         "hef_cluster_level": (i32, [HG, PR, vp, vp, vp, vp, vp, C.POINTER(i32), vp, vp, sz, vp]),
         "hef_resistance_backward": (i32, [HG, PR, vp, vp, vp, vp, vp, sz, vp]),
         "hef_resistance_taped": (i32, [HG, PR, vp, vp, vp, vp, sz, vp]),

@@ -926,7 +926,7 @@ hef_status reverse_sweep(const Level &L, const hef_params &p, const float *dR, f
     uint32_t *keys = a.take<uint32_t>(nnz);
     uint32_t *vals = a.take<uint32_t>(nnz);
     uint32_t *keys_out = a.take<uint32_t>(nnz);
-    if (a.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+    HEF_WS_CHECK(a);
     k_pos_pairs<<<cdiv(nnz, 256), 256, 0, s>>>(L.pins, keys, vals, nnz);
     HEF_LAUNCH_CHECK();
     HEF_TRY(radix_sort_pairs(keys, vals, keys_out, reinterpret_cast<uint32_t *>(w.cslot), nnz,
@@ -1078,7 +1078,7 @@ hef_status hef_resistance_backward(const hef_hypergraph *hg, const hef_params *p
   }
   BwdWs w;
   carve(a, L.n, L.m, L.nnz, *p, w);
-  if (a.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+  HEF_WS_CHECK(a);
   if (!(p->flags & HEF_FLAG_TAPED))
     HEF_TRY(taped_forward(L, *p, start_star, start_clique, w, a, stream));
   return reverse_sweep(L, *p, dR, dw, w, a, stream);
@@ -1121,7 +1121,7 @@ hef_status hef_resistance_taped(const hef_hypergraph *hg, const hef_params *p,
   }
   BwdWs w;
   carve(a, L.n, L.m, L.nnz, *p, w);
-  if (a.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+  HEF_WS_CHECK(a);
   HEF_TRY(taped_forward(L, *p, start_star, start_clique, w, a, stream));
   HEF_HIP(hipMemcpyAsync(R, w.R, sizeof(float) * L.m, hipMemcpyDeviceToDevice, stream));
   return HEF_OK;

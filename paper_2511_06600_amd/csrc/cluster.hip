@@ -1057,13 +1057,14 @@ __global__ void k_emit(const int32_t *__restrict__ eptr, const uint32_t *__restr
                        const int32_t *__restrict__ cnt, const int32_t *__restrict__ new_ptr,
                        const int32_t *__restrict__ keep_pos, const float *__restrict__ w,
                        int32_t *__restrict__ eptr2, int32_t *__restrict__ pins2,
-                       float *__restrict__ w2, int32_t m) {
+                       float *__restrict__ w2, int32_t *__restrict__ kept2, int32_t m) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= m || cnt[e] == 0) return;
   const int32_t k = keep_pos[e];
   int32_t o = new_ptr[e];
   eptr2[k] = o;
   w2[k] = w ? w[e] : 1.0f;
+  if (kept2) kept2[k] = int32_t(e);
   for (int32_t j = eptr[e]; j < eptr[e + 1]; ++j)
     if (j == eptr[e] || lab_sorted[j] != lab_sorted[j - 1]) pins2[o++] = int32_t(lab_sorted[j]);
 }
@@ -1091,6 +1092,32 @@ __global__ void k_set_i32(int32_t *__restrict__ p, int32_t v, int64_t n) {
 __global__ void k_zero_u64(unsigned long long *__restrict__ p, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0ull;
+}
+
+// flag |= 1 if the label of a pin lies outside [0, nc)
+__global__ void k_label_range(const int32_t *__restrict__ pins, const int32_t *__restrict__ label,
+                              int64_t nnz, int32_t nc, int32_t *__restrict__ flag) {
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j < nnz) {
+    const int32_t l = label[pins[j]];
+    if (l < 0 || l >= nc) atomicOr(flag, 1);
+  }
+}
+
+// flag |= 1 if a pool value is not finite or not below the largest float16
+// (the local-clustering screen keeps float16 copies of pool rows)
+template <int PT>
+__global__ void k_pool_range(const void *__restrict__ pool, int64_t count,
+                             int32_t *__restrict__ flag) {
+  int bad = 0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const float x = PT == kPoolF32
+        ? reinterpret_cast<const float *>(pool)[i]
+        : __uint_as_float(uint32_t(reinterpret_cast<const uint16_t *>(pool)[i]) << 16);
+    if (!(fabsf(x) < 65504.0f)) bad = 1;
+  }
+  if (bad) atomicOr(flag, 1);
 }
 
 inline unsigned g1(int64_t n) { return unsigned(std::max<int64_t>(1, cdiv(n, kT))); }
@@ -1178,7 +1205,7 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
   const size_t mk = ws.mark();
   LevelWs w;
   carve_level(ws, n, m, nnz, K, w);
-  if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+  HEF_WS_CHECK(ws);
 
   // ---- a6: Eq. (15), order and threshold
   {
@@ -1361,7 +1388,7 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
 // labels, hyperedges with fewer than two kept (order and weight kept).
 hef_status rebuild_level(const Level &L, const Structure &st, const int32_t *label, int32_t n2,
                          int32_t *eptr2, int32_t *pins2, float *w2, int32_t *m2_host,
-                         int64_t *nnz2_host, Arena &ws, hipStream_t s) {
+                         int64_t *nnz2_host, Arena &ws, hipStream_t s, int32_t *kept2 = nullptr) {
   const int64_t m = L.m, nnz = L.nnz;
   TimedScope ts(kStClusterRebuild, s);
   const size_t mk = ws.mark();
@@ -1371,7 +1398,7 @@ hef_status rebuild_level(const Level &L, const Structure &st, const int32_t *lab
   int32_t *cnt = ws.take<int32_t>(m + 1), *nptr = ws.take<int32_t>(m + 1);
   int32_t *flag = ws.take<int32_t>(m + 1), *kpos = ws.take<int32_t>(m + 1);
   int32_t *misc = ws.take<int32_t>(8);  // overflow flag, (m2, nnz2, overflow)
-  if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+  HEF_WS_CHECK(ws);
   *m2_host = 0;
   *nnz2_host = 0;
   if (m == 0 || nnz == 0) {
@@ -1385,7 +1412,8 @@ hef_status rebuild_level(const Level &L, const Structure &st, const int32_t *lab
     k_flag_pos<<<g1(m), kT, 0, s>>>(cnt, flag, int32_t(m));
     HEF_LAUNCH_CHECK();
     HEF_TRY(exclusive_scan_i32(flag, kpos, m, ws, s));
-    k_emit<<<g1(m), kT, 0, s>>>(L.eptr, k0, cnt, nptr, kpos, L.w, eptr2, pins2, w2, int32_t(m));
+    k_emit<<<g1(m), kT, 0, s>>>(L.eptr, k0, cnt, nptr, kpos, L.w, eptr2, pins2, w2, kept2,
+                                int32_t(m));
     k_rebuild_tail<<<1, 1, 0, s>>>(kpos, nptr, m, ovf, eptr2, misc + 4);
     HEF_LAUNCH_CHECK();
     int32_t t3[3] = {0, 0, 0};
@@ -1430,6 +1458,14 @@ size_t rebuild_ws_bytes(int64_t n, int64_t m, int64_t nnz) {
   for (int i = 0; i < 4; ++i) a.take<int32_t>(m + 1);
   a.take<int32_t>(8);
   return a.mark() + radix_ws_bytes(nnz) + scan_ws_bytes(std::max(n, m) + 1) + 4096;
+}
+
+size_t rebuild_call_bytes(int64_t n, int64_t m, int64_t nnz) {
+  Arena a;
+  Structure st;
+  structure_carve(a, n, m, nnz, st);
+  a.take<int32_t>(4);
+  return a.mark() + std::max(structure_build_ws(n, m, nnz), rebuild_ws_bytes(n, m, nnz)) + 4096;
 }
 
 size_t cluster_level_bytes(int64_t n, int64_t m, int64_t nnz, int K) {
@@ -1526,20 +1562,96 @@ hef_status hef_cluster_level(const hef_hypergraph *hg, const hef_params *p, cons
     HEF_TRY(validate_device(L, flags, &bad, stream));
     if (bad) { set_error("invalid hypergraph (code %d)", bad); return HEF_ERR_INVALID_HYPERGRAPH; }
   }
+  const int pt = p->basis == HEF_BASIS_BF16 ? kPoolBF16 : kPoolF32;
+  if (p->local_clustering && hg->n > 0 && K > 0) {
+    HEF_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t), stream));
+    const int64_t cnt = int64_t(hg->n) * K;
+    const unsigned nb = unsigned(std::min<int64_t>(cdiv(cnt, kT), 4096));
+    if (pt == kPoolF32) k_pool_range<kPoolF32><<<nb, kT, 0, stream>>>(chi, cnt, flags);
+    else k_pool_range<kPoolBF16><<<nb, kT, 0, stream>>>(chi, cnt, flags);
+    HEF_LAUNCH_CHECK();
+    int32_t f = 0;
+    HEF_TRY(read_i32(flags, &f, stream));
+    if (f) {
+      set_error("a pool value is not finite or its magnitude reaches 65504 (float16 range)");
+      return HEF_ERR_INVALID_ARGUMENT;
+    }
+  }
   HEF_TRY(structure_build(L, st, a, stream));
   int32_t ng = 0;
-  HEF_TRY(cluster_one_level(L, st, R, eta_in, chi, kPoolF32, K, qh, p->percentile,
+  HEF_TRY(cluster_one_level(L, st, R, eta_in, chi, pt, K, qh, p->percentile,
                             p->local_clustering != 0, cluster, &ng, eta_out, a, stream));
   HEF_HIP(hipStreamSynchronize(stream));
   *n_clusters = ng;
   return HEF_OK;
 }
 
+hef_status hef_rebuild(const hef_hypergraph *hg, const int32_t *label, int32_t n_clusters,
+                       int32_t *eptr_out, int32_t *pins_out, float *w_out, int32_t *kept_out,
+                       int32_t *m_out, int64_t *nnz_out, void *ws, size_t ws_bytes,
+                       hipStream_t stream) {
+  if (!hg || !m_out || !nnz_out || !ws || !eptr_out || (hg->n > 0 && !label) ||
+      (hg->m > 0 && (!pins_out || !w_out))) {
+    set_error("NULL argument");
+    return HEF_ERR_INVALID_ARGUMENT;
+  }
+  if (hg->n < 0 || hg->m < 0 || hg->nnz < 0 || hg->nnz > INT32_MAX || !hg->eptr ||
+      (hg->nnz > 0 && !hg->pins)) {
+    set_error("bad hypergraph sizes or pointers");
+    return HEF_ERR_INVALID_ARGUMENT;
+  }
+  if (n_clusters < 0 || (hg->n > 0 && n_clusters < 1) || n_clusters > std::max(hg->n, 1)) {
+    set_error("n_clusters=%d out of range for n=%d", n_clusters, hg->n);
+    return HEF_ERR_INVALID_ARGUMENT;
+  }
+  const size_t need = rebuild_call_bytes(hg->n, hg->m, hg->nnz);
+  if (ws_bytes < need) { set_error("workspace too small (%zu < %zu)", ws_bytes, need); return HEF_ERR_WORKSPACE_TOO_SMALL; }
+  Arena a;
+  a.base = static_cast<char *>(ws);
+  a.cap = ws_bytes;
+  Structure st;
+  structure_carve(a, hg->n, hg->m, hg->nnz, st);
+  int32_t *flags = a.take<int32_t>(4);
+  if (a.overflow) { set_error("workspace carve overflow"); return HEF_ERR_WORKSPACE_TOO_SMALL; }
+  Level L;
+  L.n = hg->n; L.m = hg->m; L.nnz = hg->nnz; L.eptr = hg->eptr; L.pins = hg->pins; L.w = hg->w;
+  int32_t bad = 0;
+  HEF_TRY(validate_device(L, flags, &bad, stream));
+  if (bad) { set_error("invalid hypergraph (code %d)", bad); return HEF_ERR_INVALID_HYPERGRAPH; }
+  if (hg->n > 0 && hg->nnz > 0) {
+    HEF_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t), stream));
+    k_label_range<<<g1(hg->nnz), kT, 0, stream>>>(hg->pins, label, hg->nnz, n_clusters, flags);
+    HEF_LAUNCH_CHECK();
+    int32_t f = 0;
+    HEF_TRY(read_i32(flags, &f, stream));
+    if (f) { set_error("a pin's label lies outside [0, n_clusters)"); return HEF_ERR_INVALID_ARGUMENT; }
+  }
+  HEF_TRY(structure_build(L, st, a, stream));
+  int32_t m2 = 0;
+  int64_t nnz2 = 0;
+  HEF_TRY(rebuild_level(L, st, label, n_clusters, eptr_out, pins_out, w_out, &m2, &nnz2, a, stream,
+                        kept_out));
+  *m_out = m2;
+  *nnz_out = nnz2;
+  return HEF_OK;
+}
+
 hef_status hef_coarsen(const hef_hypergraph *hg, const hef_params *p, int32_t *cluster,
                        int32_t *n_clusters, float *R0, float *eta, void *ws, size_t ws_bytes,
                        hipStream_t stream) {
+  return hef_coarsen_levels(hg, p, cluster, n_clusters, R0, eta, nullptr, ws, ws_bytes, stream);
+}
+
+hef_status hef_coarsen_levels(const hef_hypergraph *hg, const hef_params *p, int32_t *cluster,
+                              int32_t *n_clusters, float *R0, float *eta,
+                              hef_level_trace *trace, void *ws, size_t ws_bytes,
+                              hipStream_t stream) {
   if (!hg || !p || !n_clusters || !ws || (hg->n > 0 && !cluster)) {
     set_error("NULL argument");
+    return HEF_ERR_INVALID_ARGUMENT;
+  }
+  if (trace && trace->cap < 0) {
+    set_error("trace capacity is negative");
     return HEF_ERR_INVALID_ARGUMENT;
   }
   size_t need = 0;
@@ -1568,21 +1680,45 @@ hef_status hef_coarsen(const hef_hypergraph *hg, const hef_params *p, int32_t *c
   const float *eta_cur = nullptr;
   int cur = 0;
   g_levels_run = 0;
+  if (trace) trace->levels_run = 0;
+  // node-reduction target: stop once n_l <= (1 - target_nr) n_0 (0 = off)
+  const double n_goal = (1.0 - double(p->target_nr)) * double(n0);
   for (int lev = 0; lev < p->levels && L.m > 0; ++lev) {
+    if (p->target_nr > 0.0f && double(L.n) <= n_goal) break;
     if (lev < kMaxLevelLog) {
       g_level_n[lev] = L.n;
       g_level_m[lev] = L.m;
       g_level_nnz[lev] = L.nnz;
       g_levels_run = lev + 1;
     }
+    const bool tr = trace && lev < trace->cap;
+    if (tr) {
+      if (trace->n) trace->n[lev] = L.n;
+      if (trace->m) trace->m[lev] = L.m;
+      if (trace->nnz) trace->nnz[lev] = L.nnz;
+      trace->levels_run = lev + 1;
+    }
     HEF_TRY(estimate_level(L, *p, p->seed, lev, nullptr, nullptr, c.st, c.pool, c.pool2, c.qh,
-                           c.R, a, stream));
+                           c.R, a, stream, (tr && trace->rho) ? trace->rho + int64_t(lev) * K
+                                                               : nullptr));
     if (lev == 0 && R0)
       HEF_HIP(hipMemcpyAsync(R0, c.R, sizeof(float) * L.m, hipMemcpyDeviceToDevice, stream));
+    if (tr && trace->R && L.m > 0)
+      HEF_HIP(hipMemcpyAsync(trace->R + int64_t(lev) * hg->m, c.R, sizeof(float) * L.m,
+                             hipMemcpyDeviceToDevice, stream));
+    if (tr && trace->qh && K > 0)
+      HEF_HIP(hipMemcpyAsync(trace->qh + int64_t(lev) * K, c.qh, sizeof(double) * K,
+                             hipMemcpyDeviceToDevice, stream));
     int32_t ng = 0;
     float *eta_next = c.eta[cur];
     HEF_TRY(cluster_one_level(L, c.st, c.R, eta_cur, c.pool, pt, K, c.qh, p->percentile,
                               p->local_clustering != 0, c.label, &ng, eta_next, a, stream));
+    if (tr && trace->label && L.n > 0)
+      HEF_HIP(hipMemcpyAsync(trace->label + int64_t(lev) * n0, c.label, sizeof(int32_t) * L.n,
+                             hipMemcpyDeviceToDevice, stream));
+    if (tr && trace->eta && ng > 0)
+      HEF_HIP(hipMemcpyAsync(trace->eta + int64_t(lev) * n0, eta_next, sizeof(float) * ng,
+                             hipMemcpyDeviceToDevice, stream));
     if (n0 > 0) {
       k_compose<<<g1(n0), kT, 0, stream>>>(cluster, c.label, n0);
       HEF_LAUNCH_CHECK();
@@ -1591,6 +1727,7 @@ hef_status hef_coarsen(const hef_hypergraph *hg, const hef_params *p, int32_t *c
     int64_t nnz2 = 0;
     HEF_TRY(rebuild_level(L, c.st, c.label, ng, c.eptr[cur], c.pins[cur], c.w[cur], &m2, &nnz2,
                           a, stream));
+    const bool stalled = ng == L.n;  // nothing merged: no further reduction
     L.n = ng;
     L.m = m2;
     L.nnz = nnz2;
@@ -1599,6 +1736,7 @@ hef_status hef_coarsen(const hef_hypergraph *hg, const hef_params *p, int32_t *c
     L.w = c.w[cur];
     eta_cur = eta_next;
     cur ^= 1;
+    if (stalled && p->target_nr > 0.0f) break;
   }
   if (eta && L.n > 0) {
     if (eta_cur)

@@ -34,6 +34,15 @@ const char *last_error();
 
 #define HEF_LAUNCH_CHECK() HEF_HIP(hipGetLastError())
 
+// A workspace carve that ran past the caller's workspace.
+#define HEF_WS_CHECK(arena)                                                       \
+  do {                                                                            \
+    if ((arena).overflow) {                                                       \
+      ::hef::set_error("workspace overflow in %s (%s:%d)", __func__, __FILE__, __LINE__); \
+      return HEF_ERR_WORKSPACE_TOO_SMALL;                                         \
+    }                                                                             \
+  } while (0)
+
 // ------------------------------------------------------------- workspace
 // Bump allocator over the caller's workspace.  With base == nullptr it only
 // measures, so the planner and the runtime carve the workspace identically.

@@ -106,6 +106,10 @@ hef_status check_params(const hef_params *p, bool need_levels) {
   }
   if (need_levels) {
     if (p->levels < 1 || p->levels > 64) { set_error("levels out of range"); return HEF_ERR_INVALID_ARGUMENT; }
+    if (!(p->target_nr >= 0.0f && p->target_nr < 1.0f)) {
+      set_error("target_nr must lie in [0, 1)");
+      return HEF_ERR_INVALID_ARGUMENT;
+    }
     if (!(p->percentile > 0.0f && p->percentile <= 1.0f)) {
       set_error("percentile must lie in (0, 1]");
       return HEF_ERR_INVALID_ARGUMENT;
@@ -174,7 +178,7 @@ __global__ void k_check_finite(const float *R, int64_t m, const double *qh, int 
 hef_status estimate_level(const Level &L, const hef_params &p, uint64_t seed, int level,
                           const float *start_star, const float *start_clique, Structure &st,
                           void *pool, void *pool2, double *qh, float *R, Arena &ws,
-                          hipStream_t s) {
+                          hipStream_t s, double *rho) {
   const int64_t n = L.n, m = L.m;
   const int K = pool_width(p);
   const int B = p.b;
@@ -185,13 +189,13 @@ hef_status estimate_level(const Level &L, const hef_params &p, uint64_t seed, in
   float *xs = nullptr, *xc = nullptr;
   if (use_star && !start_star) {
     xs = ws.take<float>((n + m) * B);
-    if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+    HEF_WS_CHECK(ws);
     HEF_TRY(start_block(seed, level, 0, n + m, B, xs, s));
     start_star = xs;
   }
   if (use_clique && !start_clique) {
     xc = ws.take<float>(n * B);
-    if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+    HEF_WS_CHECK(ws);
     HEF_TRY(start_block(seed, level, 1, n, B, xc, s));
     start_clique = xc;
   }
@@ -204,7 +208,7 @@ hef_status estimate_level(const Level &L, const hef_params &p, uint64_t seed, in
                       use_clique, ko, ws, s));
   ws.reset(mk);
   HEF_TRY(orthonormalize_pool(pool2, pool, ko.pool_type, n, K, double(p.drop_tol),
-                              p.orth_passes, nullptr, ws, s));
+                              p.orth_passes, nullptr, ws, s, nullptr, rho));
   HEF_TRY(score_pool(L, pool, ko.pool_type, K, qh, R, ws, s));
   return HEF_OK;
 }
@@ -274,6 +278,7 @@ void hef_params_default(hef_params *p) {
   p->orth_passes = 1;
   p->ckpt_every = 5;
   p->flags = 0;
+  p->target_nr = 0.0f;
 }
 
 int32_t hef_pool_width(const hef_params *p) { return p ? pool_width(*p) : 0; }
@@ -310,6 +315,9 @@ hef_status hef_workspace_size(const hef_hypergraph *hg, const hef_params *p, int
     }
     case HEF_OP_CONDUCTANCE:
       *bytes = conductance_bytes(n, m, nnz);
+      return HEF_OK;
+    case HEF_OP_REBUILD:
+      *bytes = rebuild_call_bytes(n, m, nnz);
       return HEF_OK;
     default:
       set_error("unknown op %d", op);

@@ -652,7 +652,7 @@ hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double
   double *G = ws.take<double>(2 * 48 * 48);
   double *Tm = ws.take<double>(2 * 48 * 16);
   int32_t *drops = ws.take<int32_t>(2);
-  if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+  HEF_WS_CHECK(ws);
   const int C = 3 * B;
   double *Gs = G, *Gc = G + C * C;
   double *ps = partial, *pc = partial + size_t(kGramBlocks) * 9 * B * B;

@@ -46,7 +46,7 @@ constexpr int kMaxPB = 16;    // 32-column blocks of the widest pool (K <= 512)
 __global__ void __launch_bounds__(1024)
 k_chol_panel(const double *__restrict__ A, const double *__restrict__ G, int K, int c0,
              double tau, double *__restrict__ LT, int32_t *__restrict__ keep,
-             const int32_t *__restrict__ force_keep) {
+             const int32_t *__restrict__ force_keep, double *__restrict__ rho) {
   extern __shared__ double pan[];  // [K - c0][kPS]
   __shared__ int s_keep;
   __shared__ double s_ref[kPW];     // G_jj of the panel's columns
@@ -71,6 +71,8 @@ k_chol_panel(const double *__restrict__ A, const double *__restrict__ G, int K, 
       int kp = (ref > 0.0 && d > tau * tau * ref) ? 1 : 0;
       if (!s_force[jj]) kp = 0;
       keep[c0 + jj] = kp;
+      // relative Gram-Schmidt residual |R_jj| / ||V_j|| of a kept column
+      if (rho) rho[c0 + jj] = kp ? sqrt(d / ref) : 0.0;
       s_keep = kp;
       pan[jj * kPS + jj] = kp ? sqrt(d) : 0.0;
     }
@@ -868,7 +870,7 @@ hef_status gram_run(const void *pool, const void *poolB, int pool_type, int64_t 
   double *partial = ws.take<double>(size_t(p.nchunks) * p.npairs * 16 * 1024);
   const int64_t tot = int64_t(p.npairs) * 16 * 1024;
   double *sums = ws.take<double>(tot);
-  if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+  HEF_WS_CHECK(ws);
   HEF_HIP(hipMemsetAsync(G, 0, sizeof(double) * K * K, s));
   {
   TimedScope ts(kStOrthGram, s);
@@ -903,9 +905,20 @@ hef_status apply_run(const void *V, void *Q, int pool_type, int64_t n, int K, in
 
 }  // namespace
 
+// The most row chunks the Gram plan takes for any row count up to n: a
+// chunk holds at least 128 rows and the plan never exceeds `want` chunks,
+// but the count is not monotone in n, so a coarser level (fewer rows) can
+// need more partials than the finest.
+int64_t gram_max_chunks(int64_t n, int K, bool cross) {
+  const GramPlan p = gram_plan(n, K, cross);
+  const int64_t want = std::max<int64_t>(1, 512 / p.npairs);
+  return std::max<int64_t>(1, std::min<int64_t>(want, cdiv(std::max<int64_t>(n, 1), 128)));
+}
+
 size_t orth_ws_bytes(int64_t n, int K) {
   const int Kp = (K + 31) / 32 * 32;
-  const GramPlan p = gram_plan(n, K);
+  GramPlan p = gram_plan(n, K);
+  p.nchunks = int(gram_max_chunks(n, K, false));
   Arena a;
   a.take<double>(int64_t(K) * K);    // G
   a.take<double>(int64_t(K) * K);    // LT
@@ -926,7 +939,8 @@ hef_status gram_f32(const float *X, int64_t n, int K, double *G, Arena &ws, hipS
 }
 
 size_t gram_cross_ws_bytes(int64_t n, int K) {
-  const GramPlan p = gram_plan(n, K, true);
+  GramPlan p = gram_plan(n, K, true);
+  p.nchunks = int(gram_max_chunks(n, K, true));
   Arena a;
   a.take<double>(size_t(p.nchunks) * p.npairs * 16 * 1024);
   a.take<double>(size_t(p.npairs) * 16 * 1024);
@@ -947,7 +961,7 @@ hef_status gemm_f32(const float *X, int64_t n, int K, const float *W, int Kp, fl
 
 hef_status orthonormalize_pool(void *P, void *out, int pool_type, int64_t n, int K, double tau,
                                int passes, int32_t *keep_out, Arena &ws, hipStream_t s,
-                               double *rinv_out) {
+                               double *rinv_out, double *rho_out) {
   if (K <= 0) return HEF_OK;
   if (K > 512) {
     set_error("pool width %d exceeds 512", K);
@@ -963,7 +977,7 @@ hef_status orthonormalize_pool(void *P, void *out, int pool_type, int64_t n, int
   uint16_t *RhT = ws.take<uint16_t>(int64_t(Kp) * Kp);
   uint16_t *RlT = ws.take<uint16_t>(int64_t(Kp) * Kp);
   int32_t *keep = ws.take<int32_t>(K);
-  if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+  HEF_WS_CHECK(ws);
   for (int pass = 0; pass < passes; ++pass) {
     // pass 0: P (row-octet layout) -> out; pass 1: out -> P (reused,
     // row-major), copied back to out
@@ -985,7 +999,8 @@ hef_status orthonormalize_pool(void *P, void *out, int pool_type, int64_t n, int
       for (int c0 = 0; c0 < K; c0 += kPW) {
         const int w = K - c0 < kPW ? K - c0 : kPW;
         k_chol_panel<<<1, 1024, size_t(K - c0) * kPS * sizeof(double), s>>>(
-            A, G, K, c0, tau, LT, keep, pass == 0 ? nullptr : keep);
+            A, G, K, c0, tau, LT, keep, pass == 0 ? nullptr : keep,
+            pass == 0 ? rho_out : nullptr);
         const int nt = (K - c0 - w + kPW - 1) / kPW;
         if (nt > 0) k_chol_update<<<nt * (nt + 1) / 2, 256, 0, s>>>(A, LT, K, c0, w);
       }

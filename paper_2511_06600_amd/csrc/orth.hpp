@@ -16,10 +16,12 @@ size_t orth_ws_bytes(int64_t n, int K);
 // drops), using P as scratch.  `keep_out` (device int32 [K], may be null)
 // receives 1 for kept and 0 for dropped columns; `rinv_out` (device float64
 // [Kp x Kp], Kp = K rounded up to 32, may be null) the last pass's R^-1
-// (row-major, upper triangular, zero rows and columns for drops).
+// (row-major, upper triangular, zero rows and columns for drops); `rho_out`
+// (device float64 [K], may be null) the first pass's relative residuals
+// rho_j = |R_jj| / ||V_j|| (0 for dropped columns).
 hef_status orthonormalize_pool(void *P, void *out, int pool_type, int64_t n, int K, double tau,
                                int passes, int32_t *keep_out, Arena &ws, hipStream_t s,
-                               double *rinv_out = nullptr);
+                               double *rinv_out = nullptr, double *rho_out = nullptr);
 
 // Test hook: G = X^T X (float64, K x K) of a row-major n x K float32 matrix,
 // through the same matrix-core Gram kernels.

@@ -222,7 +222,7 @@ hef_status exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, Arena 
   const int64_t ntiles = cdiv(n, kScanTile);
   const size_t mk = ws.mark();
   int32_t *sums = ws.take<int32_t>(ntiles + 1);
-  if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+  HEF_WS_CHECK(ws);
   if (n == 0) {
     HEF_HIP(hipMemsetAsync(out, 0, sizeof(int32_t), s));
     ws.reset(mk);
@@ -250,7 +250,7 @@ hef_status radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_out,
   const int64_t nb = cdiv(n, kRadixTile);
   const size_t mk = ws.mark();
   int32_t *hist = ws.take<int32_t>(nb * kBins + 1);
-  if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+  HEF_WS_CHECK(ws);
   const int passes = (bits + kRadixBits - 1) / kRadixBits;
   uint32_t *ka = keys, *va = vals, *kb = keys_out, *vb = vals_out;
   for (int p = 0; p < passes; ++p) {

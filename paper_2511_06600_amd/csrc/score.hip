@@ -239,7 +239,7 @@ hef_status score_pool(const Level &L, const void *pool, int pool_type, int K, do
   const size_t mk = ws.mark();
   double *partial = ws.take<double>(nblk * K);
   float *sbuf = keep_s ? keep_s : ws.take<float>(int64_t(L.m) * K);
-  if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+  HEF_WS_CHECK(ws);
   hef_status st;
   const bool wide = K > 256;
   if (pool_type == kPoolF32)

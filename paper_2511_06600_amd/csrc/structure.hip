@@ -167,7 +167,7 @@ hef_status structure_build(const Level &L, Structure &st, Arena &ws, hipStream_t
   int32_t *scratch = ws.take<int32_t>(std::max(n, m) + 1);
   double *tdb = ws.take<double>(std::max<int64_t>(m, 1));
   double *tcb = ws.take<double>(std::max<int64_t>(m, 1));
-  if (ws.overflow) return HEF_ERR_WORKSPACE_TOO_SMALL;
+  HEF_WS_CHECK(ws);
 
   // eids: stable sort of (pin, edge) by pin; input is in edge order, so
   // each node's hyperedges come out ascending.  vptr from the sorted pins.

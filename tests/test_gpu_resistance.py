@@ -27,7 +27,8 @@ def test_start_block_generator_matches_counter_definition():
 
 @pytest.mark.parametrize("b", [1, 4, 8, 16])
 def test_expansion_operators_match_oracle(b):
-    # hyperedges up to 300 pins and hub nodes exercise the long-segment kernels
+    # hyperedges up to 300 pins exercise the long-segment CSR kernel (csr_big);
+    # node degrees stay below 32 here: test_long_node_segments covers csc_big
     h = generate(6000, 6400, 2, 300, 2.2, p_loc=0.7, win=400, weights="lognormal", seed=31)
     say(f"case: debug_apply n={h.n} m={h.m} b={b} maxsize={h.sizes().max()}")
     dh = to_device(h)
@@ -171,3 +172,38 @@ def test_degenerate_single_hyperedge():
     dh = hef.DeviceHypergraph.from_arrays(n, 1, eptr, pins, np.array([0.25], np.float32))
     R, qh, _ = hef.resistance(dh, hef.Params(k=3, b=1))
     assert abs(float(R[0]) - 4.0) < 1e-4
+
+
+@pytest.mark.parametrize("b", [1, 4, 8, 16])
+def test_long_node_segments(b):
+    """Nodes in hundreds of hyperedges (degree >> 32) go to the CSC pass's
+    wave-per-node path: six hub nodes are added as pins to 400-900 random
+    hyperedges each."""
+    base = generate(5000, 6000, 2, 40, 2.5, p_loc=0.7, win=300, weights="lognormal", seed=71)
+    rng = np.random.default_rng(72)
+    hubs = np.array([3, 777, 1500, 2501, 3999, 4998])
+    edges = [list(base.pins[base.eptr[e]:base.eptr[e + 1]]) for e in range(base.m)]
+    for i, hub in enumerate(hubs):
+        for e in rng.choice(base.m, size=400 + 100 * i, replace=False):
+            if hub not in edges[e]:
+                edges[e].append(int(hub))
+    edges = [sorted(e) for e in edges]
+    eptr = np.concatenate([[0], np.cumsum([len(e) for e in edges])]).astype(np.int64)
+    pins = np.array([p for e in edges for p in e], dtype=np.int32)
+    from synth.hypergraph import Hypergraph
+    h = Hypergraph(n=base.n, m=base.m, eptr=eptr, pins=pins, w=base.w)
+    deg = np.bincount(pins, minlength=h.n)
+    say(f"case: debug_apply hub nodes b={b}: max degree {deg.max()}, "
+        f"{int((deg > 32).sum())} nodes above 32")
+    assert (deg > 32).sum() >= 6 and deg.max() > 400
+    dh = to_device(h)
+    rng = np.random.default_rng(b)
+    for expansion, A in ((0, orr.star_operator(h.n, h.m, h.eptr, h.pins, h.w)),
+                         (1, orr.clique_operator(h.n, h.m, h.eptr, h.pins, h.w))):
+        x = rng.standard_normal((A.shape[0], b)).astype(np.float32)
+        y = hef.debug_apply(dh, expansion, torch.as_tensor(x, device="cuda")).cpu().numpy()
+        ref = A @ x.astype(np.float64)
+        err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+        hub_err = np.abs(y[hubs] - ref[hubs]).max() / np.abs(ref[hubs]).max()
+        say(f"  expansion {expansion}: rel err {err:.2e}, hub rows {hub_err:.2e}")
+        assert err < 1e-6 and hub_err < 1e-6

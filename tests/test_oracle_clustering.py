@@ -240,3 +240,38 @@ def test_hand_worked_two_level_coarsening(ex, monkeypatch):
             assert out.eta[c] == np.float32(acc), (c, out.eta[c], acc)
     else:
         assert np.array_equal(out.eta, np.array(exp, dtype=np.float32))
+
+
+def test_node_reduction_target_stops_the_level_loop(monkeypatch):
+    """Section IV's NR target on the hand-worked two-level example: level 0
+    takes 6 nodes to 4.  NR = 0.3 (goal 4.2 nodes) stops after level 0;
+    NR = 0.5 (goal 3) runs level 1 (4 -> 3 nodes) and stops there, below the
+    cap of 5 levels; NR = 0.9 (goal 0.6) runs on until a level merges
+    nothing.  Levels past the second reuse the second level's R prefix."""
+    from types import SimpleNamespace
+    ex = json.load(open(GOLD2))["examples"][0]
+
+    def fake_resistance(n, m, eptr, pins, w, Xs, Xc, k, tau=1e-3, **kw):
+        lev = ex["levels"][min(len(calls), 1)]
+        calls.append(n)
+        R = np.array(lev["R"][:m] + [0.5] * max(0, m - len(lev["R"])), dtype=np.float32)
+        return SimpleNamespace(R=R, qh=np.ones(1), pool=SimpleNamespace(chi=np.zeros((n, 1))))
+
+    monkeypatch.setattr(oco.resistance, "resistance", fake_resistance)
+    eptr, pins = _csr(ex["edges"])
+    start = lambda lev, x, rows, b: np.zeros((rows, b))  # noqa: E731
+    run = lambda nr: oco.coarsen(ex["n"], len(ex["edges"]), eptr, pins,  # noqa: E731
+                                 np.ones(len(ex["edges"]), np.float32), 1, 1, 5, start, 0.5,
+                                 False, target_nr=nr)
+    calls = []
+    out = run(0.3)
+    assert calls == [6] and out.n_clusters == 4
+    calls = []
+    out = run(0.5)
+    assert calls == [6, 4] and out.n_clusters == 3
+    # NR = 0.9: level 2 (edges {0,1} {1,2} {0,2}, R_upd 0.31 0.26 0.41,
+    # delta 0.31) merges {1,2}; level 3 (two copies of {0,1}, R_upd 0.37
+    # 0.41, delta 0.37) merges nothing, and the loop stops there
+    calls = []
+    out = run(0.9)
+    assert calls == [6, 4, 3, 2] and out.n_clusters == 2
