@@ -131,7 +131,7 @@ k_chol_update(double *__restrict__ A, const double *__restrict__ LT, int K, int 
 // (row-major, Kp x Kp, float64 and float32; entries outside stay as set).
 __global__ void __launch_bounds__(1024)
 k_jtrinv(const double *__restrict__ LT, const int32_t *__restrict__ keep, int K, int Kp,
-         double *__restrict__ Rinv, float *__restrict__ Rinv32) {
+         double *__restrict__ Rinv, float *__restrict__ Rinv32, float *__restrict__ RinvT32) {
   extern __shared__ double X[];  // [K][kPS]: rows of the column block J
   __shared__ double T[kPW * kPS];
   __shared__ double Lb[kPW * kPS];
@@ -207,6 +207,7 @@ k_jtrinv(const double *__restrict__ LT, const int32_t *__restrict__ keep, int K,
     const double x = X[i * kPS + j];
     Rinv[int64_t(j0 + j) * Kp + i] = x;
     Rinv32[int64_t(j0 + j) * Kp + i] = float(x);
+    if (RinvT32) RinvT32[int64_t(i) * Kp + j0 + j] = float(x);
   }
 }
 
@@ -574,6 +575,151 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oc
       }
 }
 
+// Q = V Rinv for the float32 pool, Rinv upper triangular (Kp x Kp, zero
+// outside K x K), read through its transpose RT (RT[c][k] = Rinv[k][c]): no
+// LDS and no barriers.  A workgroup of four waves takes 64 rows; the
+// 32-column output tiles are dealt to the waves in snake order of their work
+// (tile c needs the c + 1 leading 32-row chunks of Rinv), so the waves'
+// shares of the triangle are about equal, at most 4 tiles each.  Operands
+// come straight from global memory into registers, kA2G k steps at a time,
+// the next group loaded while the current one is multiplied:
+//  * MFMA step s of a 32-wide k chunk pairs k = 32 kc + s (lanes 0-31) with
+//    32 kc + 16 + s (lanes 32-63), so a lane's B values for kA2G steps are
+//    kA2G consecutive entries of one row of RT (one 16-byte load);
+//  * the wave's two row tiles interleave: lane i of row tile r holds local
+//    row 2i + r, so in the row-octet layout one 8-byte load gives a lane its
+//    A values of both row tiles.
+constexpr int kA2T = 256;
+constexpr int kA2Rows = 64;
+constexpr int kA2G = 4;  // k steps per register group (4 groups per 32-wide chunk)
+
+template <bool OCT, int NA>
+__device__ __forceinline__ void tri_chunks(const float *__restrict__ Vw,
+                                           const float *__restrict__ RT, uint32_t vo,
+                                           uint32_t vo1, const bool (&vrow)[2], int K, int Kp,
+                                           const uint32_t (&rb)[4], int h, int kc0, int kc1,
+                                           floatx16 (&acc)[2][4]) {
+  constexpr int GPC = 16 / kA2G;  // register groups per 32-wide chunk
+  const int g0 = kc0 * GPC, g1 = kc1 * GPC;
+  if (g0 >= g1) return;
+  float a[2][kA2G][2];
+  float4 b[2][NA];
+  const char *vb = reinterpret_cast<const char *>(Vw);
+  const char *rt = reinterpret_cast<const char *>(RT);
+  auto load = [&](int g, int buf) __attribute__((always_inline)) {
+    const int kb = 32 * (g / GPC) + 16 * h + kA2G * (g % GPC);  // first k of the group
+#pragma unroll
+    for (int s = 0; s < kA2G; ++s) {
+      const int k = kb + s;
+      const bool kin = k < K;
+      const uint32_t kk = kin ? uint32_t(k) : 0u;
+      float x0, x1;
+      if constexpr (OCT) {
+        // rows 2i and 2i + 1 sit side by side in their octet
+        const float2 t = *reinterpret_cast<const float2 *>(vb + 4u * (vo + 8u * kk));
+        x0 = t.x;
+        x1 = t.y;
+      } else {
+        x0 = *reinterpret_cast<const float *>(vb + 4u * (vo + kk));
+        x1 = *reinterpret_cast<const float *>(vb + 4u * (vo1 + kk));
+      }
+      a[buf][s][0] = (kin && vrow[0]) ? x0 : 0.0f;
+      a[buf][s][1] = (kin && vrow[1]) ? x1 : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < NA; ++j)
+      b[buf][j] = *reinterpret_cast<const float4 *>(rt + 4u * (rb[j] + uint32_t(kb)));
+  };
+  auto mul = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int s = 0; s < kA2G; ++s)
+#pragma unroll
+      for (int j = 0; j < NA; ++j) {
+        const float bv = s == 0 ? b[buf][j].x : s == 1 ? b[buf][j].y : s == 2 ? b[buf][j].z
+                                                                              : b[buf][j].w;
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+          acc[r][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[buf][s][r], bv, acc[r][j], 0, 0, 0);
+      }
+  };
+  // two register groups in flight: the next group's loads are issued before
+  // the current group's products
+  load(g0, 0);
+  int g = g0;
+  for (; g + 2 <= g1; g += 2) {
+    load(g + 1, 1);
+    mul(0);
+    if (g + 2 < g1) load(g + 2, 0);
+    mul(1);
+  }
+  if (g < g1) mul(0);
+}
+
+template <bool OCT>
+__global__ void __launch_bounds__(kA2T) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_japply_tri(const float *__restrict__ V, float *__restrict__ Q, int64_t n, int K, int Kp,
+             const float *__restrict__ RT) {
+  static_assert(kA2G == 4, "a group's B values are one float4");
+  const int64_t row0 = int64_t(xcd_block(blockIdx.x, gridDim.x)) * kA2Rows;
+  // the wave index and everything derived from it are wave-uniform (scalar)
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 31, h = lane >> 5;
+  const int nct = Kp / 32;
+  // this wave's tiles, in descending order of their column (and work): in
+  // the snake, wave w takes positions t with t % 8 in {w, 7 - w}
+  int ct[4] = {0, 0, 0, 0};
+  int nt = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int t = 8 * (q >> 1) + ((q & 1) ? 7 - w : w);
+    if (t < nct) ct[nt++] = nct - 1 - t;
+  }
+  if (nt == 0) return;
+  // the workgroup's rows of V from a uniform base (row0 is a multiple of 8)
+  const float *Vw = OCT ? V + (row0 >> 3) * int64_t(K) * 8 : V + row0 * int64_t(K);
+  const int64_t last = n - 1 - row0;  // the last valid local row
+  const bool vrow[2] = {2 * li <= last, 2 * li + 1 <= last};
+  // a valid row pair to read (masked out above when past the end)
+  const uint32_t r0 = uint32_t(2 * li <= last ? 2 * li : (last & ~int64_t(1)));
+  const uint32_t r1 = uint32_t(2 * li + 1 <= last ? 2 * li + 1 : last);
+  const uint32_t vo = OCT ? ((r0 >> 3) * uint32_t(K)) * 8u + (r0 & 7u) : r0 * uint32_t(K);
+  const uint32_t vo1 = r1 * uint32_t(K);
+  uint32_t rb[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) rb[j] = uint32_t(32 * ct[j] + li) * uint32_t(Kp);
+  floatx16 acc[2][4];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[r][j][v] = 0.0f;
+  // k chunks 0 .. ct[nt-1] with all nt tiles, then one tile fewer after each
+  // tile's diagonal chunk
+  const int e3 = nt >= 4 ? ct[3] + 1 : 0;
+  const int e2 = nt >= 3 ? ct[2] + 1 : 0;
+  const int e1 = nt >= 2 ? ct[1] + 1 : 0;
+  const int e0 = ct[0] + 1;
+  if (nt >= 4) tri_chunks<OCT, 4>(Vw, RT, vo, vo1, vrow, K, Kp, rb, h, 0, e3, acc);
+  if (nt >= 3) tri_chunks<OCT, 3>(Vw, RT, vo, vo1, vrow, K, Kp, rb, h, e3, e2, acc);
+  if (nt >= 2) tri_chunks<OCT, 2>(Vw, RT, vo, vo1, vrow, K, Kp, rb, h, e2, e1, acc);
+  tri_chunks<OCT, 1>(Vw, RT, vo, vo1, vrow, K, Kp, rb, h, e1, e0, acc);
+  float *Qw = Q + row0 * int64_t(K);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (j >= nt) continue;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int rl = 2 * (8 * (v >> 2) + 4 * h + (v & 3)) + r;
+        const int col = 32 * ct[j] + li;
+        if (rl <= last && col < K) Qw[uint32_t(rl) * uint32_t(K) + uint32_t(col)] = acc[r][j][v];
+      }
+  }
+}
+
 // ---------------------------------------------------------------- bf16 pool
 // With the pool stored as bfloat16 its values are exact bf16 numbers, so the
 // Gram runs on bf16 matrix cores (v_mfma_f32_32x32x16_bf16: exact products,
@@ -893,9 +1039,20 @@ hef_status gram_run(const void *pool, const void *poolB, int pool_type, int64_t 
 
 hef_status apply_run(const void *V, void *Q, int pool_type, int64_t n, int K, int Kp,
                      const float *Rinv32, hipStream_t s, bool full = false,
-                     bool accumulate = false, bool oct = false) {
+                     bool accumulate = false, bool oct = false, const float *RinvT32 = nullptr) {
   if (n == 0) return HEF_OK;
   TimedScope ts(kStOrthApply, s);
+  if (!full && !accumulate && pool_type == kPoolF32 && RinvT32) {
+    const int64_t nb = cdiv(n, kA2Rows);
+    if (oct)
+      k_japply_tri<true><<<nb, kA2T, 0, s>>>(reinterpret_cast<const float *>(V),
+                                             reinterpret_cast<float *>(Q), n, K, Kp, RinvT32);
+    else
+      k_japply_tri<false><<<nb, kA2T, 0, s>>>(reinterpret_cast<const float *>(V),
+                                              reinterpret_cast<float *>(Q), n, K, Kp, RinvT32);
+    HEF_LAUNCH_CHECK();
+    return HEF_OK;
+  }
   const int ncb = (K + kAN - 1) / kAN;
   k_japply<<<cdiv(n, kAM) * ncb, kAT32, 0, s>>>(V, Q, pool_type, oct, n, K, Kp, Rinv32, ncb, full,
                                               accumulate);
@@ -925,6 +1082,7 @@ size_t orth_ws_bytes(int64_t n, int K) {
   a.take<double>(int64_t(K) * K);    // trailing matrix of the Cholesky
   a.take<double>(int64_t(Kp) * Kp);  // Rinv
   a.take<float>(int64_t(Kp) * Kp);   // Rinv32
+  a.take<float>(int64_t(Kp) * Kp);   // its transpose
   a.take<uint16_t>(int64_t(Kp) * Kp);  // RhT
   a.take<uint16_t>(int64_t(Kp) * Kp);  // RlT
   a.take<int32_t>(K);                // keep
@@ -974,6 +1132,7 @@ hef_status orthonormalize_pool(void *P, void *out, int pool_type, int64_t n, int
   double *A = ws.take<double>(int64_t(K) * K);
   double *Rinv = ws.take<double>(int64_t(Kp) * Kp);
   float *Rinv32 = ws.take<float>(int64_t(Kp) * Kp);
+  float *RinvT32 = ws.take<float>(int64_t(Kp) * Kp);
   uint16_t *RhT = ws.take<uint16_t>(int64_t(Kp) * Kp);
   uint16_t *RlT = ws.take<uint16_t>(int64_t(Kp) * Kp);
   int32_t *keep = ws.take<int32_t>(K);
@@ -992,6 +1151,7 @@ hef_status orthonormalize_pool(void *P, void *out, int pool_type, int64_t n, int
                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_c)));
       HEF_HIP(hipMemsetAsync(Rinv, 0, sizeof(double) * Kp * Kp, s));
       HEF_HIP(hipMemsetAsync(Rinv32, 0, sizeof(float) * Kp * Kp, s));
+      HEF_HIP(hipMemsetAsync(RinvT32, 0, sizeof(float) * Kp * Kp, s));
       HEF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_chol_panel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_c)));
       HEF_HIP(hipMemcpyAsync(A, G, sizeof(double) * K * K, hipMemcpyDeviceToDevice, s));
@@ -1004,7 +1164,7 @@ hef_status orthonormalize_pool(void *P, void *out, int pool_type, int64_t n, int
         const int nt = (K - c0 - w + kPW - 1) / kPW;
         if (nt > 0) k_chol_update<<<nt * (nt + 1) / 2, 256, 0, s>>>(A, LT, K, c0, w);
       }
-      k_jtrinv<<<(K + kPW - 1) / kPW, 1024, lds_c, s>>>(LT, keep, K, Kp, Rinv, Rinv32);
+      k_jtrinv<<<(K + kPW - 1) / kPW, 1024, lds_c, s>>>(LT, keep, K, Kp, Rinv, Rinv32, RinvT32);
       HEF_LAUNCH_CHECK();
     }
     if (pool_type == kPoolBF16) {
@@ -1020,7 +1180,7 @@ hef_status orthonormalize_pool(void *P, void *out, int pool_type, int64_t n, int
             Kp, RhT, RlT, ncb);
       HEF_LAUNCH_CHECK();
     } else {
-      HEF_TRY(apply_run(src, dst, pool_type, n, K, Kp, Rinv32, s, false, false, oct));
+      HEF_TRY(apply_run(src, dst, pool_type, n, K, Kp, Rinv32, s, false, false, oct, RinvT32));
     }
     if (pass == 1)
       HEF_HIP(hipMemcpyAsync(out, P, size_t(n) * K * (pool_type == kPoolBF16 ? 2 : 4),
