@@ -69,7 +69,8 @@ typedef enum {
   HEF_OP_BACKWARD = 3,
   HEF_OP_APPLY = 4,
   HEF_OP_CONDUCTANCE = 5, /* sized for n_clusters up to n; ignores params  */
-  HEF_OP_REBUILD = 6      /* hef_rebuild; ignores params                    */
+  HEF_OP_REBUILD = 6,     /* hef_rebuild; ignores params                    */
+  HEF_OP_RATING = 7       /* hef_rating; ignores params                     */
 } hef_op;
 
 /* Flags for hef_params.flags. */
@@ -268,6 +269,29 @@ hef_status hef_rebuild(const hef_hypergraph *hg, const int32_t *label, int32_t n
                        int32_t *eptr_out, int32_t *pins_out, float *w_out, int32_t *kept_out,
                        int32_t *m_out, int64_t *nnz_out, void *ws, size_t ws_bytes,
                        hipStream_t stream);
+
+/* Resistance-based vertex-pair rating for multilevel partitioning
+ * (Section III-E, Eq. (17); Alg. 3 step 3): for nodes p != q sharing
+ * hyperedges,  r(p, q) = sum over the hyperedges e holding both of
+ * w(e) / (R_e - shift), summed in float64 in ascending hyperedge order; a
+ * hyperedge with R_e - shift == 0 adds nothing.  Eq. (17) prints the
+ * denominator as R_e - 1, i.e. Eq. (7)'s cardinality term |e| - 1 with |e|
+ * replaced by R_e; since R_e <= 1/w(e) that form is negative for every
+ * hyperedge with w(e) >= 1 and rates heavy hyperedges lowest, against the
+ * stated aim (heavy, low-resistance hyperedges).  shift = 0 replaces the
+ * whole term |e| - 1 by R_e (heavy, low-resistance hyperedges rate high);
+ * shift = 1 evaluates the printed form.  With R_e = |e| and shift = 1 this is
+ * Eq. (7) itself.
+ *   R       DEVICE [m] float32 resistances (finite, else
+ *           HEF_ERR_INVALID_ARGUMENT), e.g. a level's Eq. (15) values;
+ *   best    DEVICE [n] int32 output: the neighbour q of largest r(p, q), ties
+ *           to the smallest q; -1 for a node without neighbours;
+ *   rating  DEVICE [n] float64 output: r(p, best[p]) (0 without neighbours);
+ *   ws      DEVICE workspace of hef_workspace_size(hg, NULL, HEF_OP_RATING).
+ * Work and memory are proportional to sum_e |e| (|e| - 1).  The hypergraph is
+ * validated on the device.  Synchronises `stream`. */
+hef_status hef_rating(const hef_hypergraph *hg, const float *R, float shift, int32_t *best,
+                      double *rating, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Cluster quality of a partition (Section II-A, Eq. (3); Section IV,
  * Eq. (18)).  With d_v the summed weight of v's hyperedges and vol(S) the

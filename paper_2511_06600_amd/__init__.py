@@ -219,6 +219,19 @@ def rebuild(hg: DeviceHypergraph, label: torch.Tensor, n_clusters: int):
     return out, kept[:m2]
 
 
+def rating(hg: DeviceHypergraph, R: torch.Tensor, shift: float = 0.0):
+    """Eq. (17) vertex-pair rating: (best [n] int32, rating [n] float64), the
+    neighbour of largest sum of w(e) / (R_e - shift) over shared hyperedges."""
+    lib = load()
+    assert R.dtype == torch.float32 and R.shape == (hg.m,) and R.is_contiguous()
+    best = torch.empty(max(hg.n, 1), dtype=torch.int32, device=hg.device)
+    val = torch.empty(max(hg.n, 1), dtype=torch.float64, device=hg.device)
+    ws = _workspace(hg, Params(), _lib.OP_RATING)
+    check(lib.hef_rating(C.byref(hg.c()), _ptr(R), float(shift), _ptr(best), _ptr(val), _ptr(ws),
+                         ws.numel(), _stream(hg.device)), "hef_rating")
+    return best[:hg.n], val[:hg.n]
+
+
 def cluster_level(hg: DeviceHypergraph, params: Params, R: torch.Tensor,
                   eta: torch.Tensor | None, chi: torch.Tensor, qh: torch.Tensor):
     """One level of Alg. 2 from given inputs: (cluster [n], n_clusters, eta_out)."""

@@ -14,7 +14,7 @@ STATUS = {
     6: "HEF_ERR_UNSUPPORTED",
 }
 (OP_RESISTANCE, OP_COARSEN, OP_CLUSTER_LEVEL, OP_BACKWARD, OP_APPLY, OP_CONDUCTANCE,
- OP_REBUILD) = range(7)
+ OP_REBUILD, OP_RATING) = range(8)
 BASIS_FP32, BASIS_BF16 = 0, 1
 STATIC_SCRATCH_BYTES = 64 << 20  # HEF_STATIC_SCRATCH_BYTES
 FLAG_ASSUME_VALID, FLAG_STAR_ONLY, FLAG_CLIQUE_ONLY, FLAG_TAPED = 1, 2, 4, 8
@@ -23,6 +23,7 @@ EXPORTS = [
     "hef_params_default", "hef_pool_width", "hef_workspace_size", "hef_validate_host",
     "hef_resistance", "hef_resistance_static", "hef_coarsen", "hef_cluster_level", "hef_resistance_backward",
     "hef_resistance_taped", "hef_conductance", "hef_coarsen_levels", "hef_rebuild",
+    "hef_rating",
     "hef_debug_apply", "hef_debug_gram", "hef_debug_gram_ws", "hef_start_block",
     "hef_status_string", "hef_last_error", "hef_timing_enable", "hef_timing_stage_count",
     "hef_timing_stage_name", "hef_timing_read", "hef_last_coarsen_levels",
@@ -81,6 +82,7 @@ def load() -> C.CDLL:
                                      C.POINTER(HefLevelTrace), vp, sz, vp]),
         "hef_rebuild": (i32, [HG, vp, i32, vp, vp, vp, vp, C.POINTER(i32), C.POINTER(i64), vp,
                               sz, vp]),
+        "hef_rating": (i32, [HG, vp, C.c_float, vp, vp, vp, sz, vp]),
         "hef_cluster_level": (i32, [HG, PR, vp, vp, vp, vp, vp, C.POINTER(i32), vp, vp, sz, vp]),
         "hef_resistance_backward": (i32, [HG, PR, vp, vp, vp, vp, vp, sz, vp]),
         "hef_resistance_taped": (i32, [HG, PR, vp, vp, vp, vp, sz, vp]),

@@ -139,6 +139,7 @@ enum Stage : int {
   kStScoreReduce,
   kStClusterBest,
   kStQuality,
+  kStRating,
   kStageCount
 };
 

@@ -13,6 +13,7 @@
 #include "krylov.hpp"
 #include "quality.hpp"
 #include "orth.hpp"
+#include "rating.hpp"
 #include "prims.hpp"
 #include "score.hpp"
 #include "structure.hpp"
@@ -52,7 +53,7 @@ static const char *kStageNames[kStageCount] = {
     "orth_gram", "orth_chol", "orth_apply", "score_qh", "score_r", "cluster_update",
     "cluster_contract", "cluster_local", "cluster_rebuild", "adjoint", "start_block",
     "spmm_prep", "lanczos_reduce", "orth_reduce",
-    "score_reduce", "cluster_best", "quality"};
+    "score_reduce", "cluster_best", "quality", "rating"};
 
 namespace {
 
@@ -319,6 +320,9 @@ hef_status hef_workspace_size(const hef_hypergraph *hg, const hef_params *p, int
     case HEF_OP_REBUILD:
       *bytes = rebuild_call_bytes(n, m, nnz);
       return HEF_OK;
+    case HEF_OP_RATING:
+      *bytes = rating_bytes(n, m, nnz);
+      return HEF_OK;
     default:
       set_error("unknown op %d", op);
       return HEF_ERR_INVALID_ARGUMENT;
@@ -437,6 +441,25 @@ hef_status resistance_call(const hef_hypergraph *hg, const hef_params *p, const 
 }  // namespace hef
 
 extern "C" {
+
+hef_status hef_rating(const hef_hypergraph *hg, const float *R, float shift, int32_t *best,
+                      double *rating, void *ws, size_t ws_bytes, hipStream_t stream) {
+  HEF_TRY(check_hg(hg));
+  if ((hg->m > 0 && !R) || (hg->n > 0 && (!best || !rating)) || !ws) {
+    set_error("NULL argument");
+    return HEF_ERR_INVALID_ARGUMENT;
+  }
+  if (!std::isfinite(shift)) {
+    set_error("shift must be finite");
+    return HEF_ERR_INVALID_ARGUMENT;
+  }
+  const size_t need = rating_bytes(hg->n, hg->m, hg->nnz);
+  if (ws_bytes < need) {
+    set_error("workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+    return HEF_ERR_WORKSPACE_TOO_SMALL;
+  }
+  return rating_run(level_of(hg), R, shift, best, rating, ws, ws_bytes, stream);
+}
 
 hef_status hef_debug_apply(const hef_hypergraph *hg, int32_t expansion, int32_t b, const float *x,
                            float *y, void *ws, size_t ws_bytes, hipStream_t stream) {
