@@ -30,6 +30,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from synth import get_config, make_hypergraph  # noqa: E402
+
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E, GB/s
 PEAK_FP32_MFMA = 157.3    # TFLOP/s, dense FP32 matrix
 PEAK_BF16_MFMA = 2500.0   # TFLOP/s, dense BF16 matrix
@@ -80,6 +82,40 @@ def score_bytes(n, m, nnz, K, s=4):
     return 4 * m * K + 8 * K + 4 * m
 
 
+def score_qh_bytes(n, m, nnz, K, s=4):
+    """The Q_H gather pass (k_score_qh): every pool row read once (n K s),
+    pins and the pointer and weight arrays, the m x K float32 numerators
+    written."""
+    return n * K * s + 4 * nnz + 8 * m + 4 * m * K
+
+
+def measured_copy_GBps(torch, nbytes=1 << 30, reps=5):
+    """Device-to-device copy of nbytes: (read + written bytes) / time."""
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del x, y
+    return 2 * nbytes / (ms / 1e3) / 1e9
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:  # pragma: no cover
+        pass
+    return "unknown"
+
+
 def read_traffic():
     """{kernel: (fetch bytes, write bytes) per coarsen step} from the PMC
     summary, or {} if it is absent."""
@@ -107,19 +143,35 @@ def cpu_baseline(cfg_name):
                  weights=cfg["weights"], seed=20251106 + cfg["index"])
     start = lambda lev, x, rows, b: start_block(7, lev, x, rows, b)  # noqa: E731
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
+        threadpool_limits = None
         threads = os.cpu_count() or 1
     t0 = time.perf_counter()
     out = oco.coarsen(h.n, h.m, h.eptr, h.pins, h.w, cfg["k"], cfg["b"], cfg["levels"], start,
                       cfg["percentile"], cfg["local_clustering"])
     dt = time.perf_counter() - t0
     est = sum(lv[1] for lv in out.levels)
-    return {"value": est / dt, "unit": "estimates/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{cfg_name} recipe at n={h.n}, m={h.m} (2% of the nodes and nets), "
-                      f"k={cfg['k']}, b={cfg['b']}, {cfg['levels']} levels: {est} estimates "
-                      f"in {dt:.1f} s"}
+    res = {"value": est / dt, "unit": "estimates/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{cfg_name} recipe at n={h.n}, m={h.m} (2% of the nodes and nets), "
+                     f"k={cfg['k']}, b={cfg['b']}, {cfg['levels']} levels: {est} estimates "
+                     f"in {dt:.1f} s",
+           "os_cpu_count": os.cpu_count(), "cpu_model": cpu_model()}
+    # the tiny workload (Alg. 1, 2k nodes) with one BLAS thread and with all
+    if threadpool_limits is not None:
+        from oracle import resistance as orr
+        t = get_config("tiny2k")
+        ht = generate(t["n"], t["m"], t["lo"], t["hi"], t["alpha"], t["p_loc"],
+                      weights=t["weights"], seed=20251106 + t["index"])
+        Xs = start_block(7, 0, 0, ht.n + ht.m, t["b"])
+        Xc = start_block(7, 0, 1, ht.n, t["b"])
+        for label, lim in (("1thread", 1), ("all_threads", None)):
+            with threadpool_limits(limits=lim):
+                t0 = time.perf_counter()
+                orr.resistance(ht.n, ht.m, ht.eptr, ht.pins, ht.w, Xs, Xc, t["k"])
+                res[f"tiny2k_alg1_{label}_estimates_per_s"] = ht.m / (time.perf_counter() - t0)
+    return res
 
 
 def roofline_entry(bound, amount, ms_total, launches, peak, unit, kernels, traffic=None):
@@ -130,6 +182,168 @@ def roofline_entry(bound, amount, ms_total, launches, peak, unit, kernels, traff
     return {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
             "avg_launch_us": ms_total / max(launches, 1) * 1e3, "launches": launches,
             "kernels": kernels, "traffic": traffic}
+
+
+def timed(torch, hef, fn, reps, stages=False):
+    """Mean wall time of fn() over reps calls (after one untimed call) and,
+    with `stages`, the library's per-stage kernel times (ms, launches) over
+    those calls (the stage events add a few microseconds per launch, so
+    wall-clock figures are taken without them)."""
+    fn()
+    torch.cuda.synchronize()
+    hef.timing_read(reset=True)
+    hef.timing_enable(stages)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    hef.timing_enable(False)
+    return dt, hef.timing_read(reset=True), out
+
+
+def extras(args, torch, hef, cfg, h, dh, params, levels, B, k):
+    """Side measurements: Alg. 1 alone (FP32 and BF16 pool) with its SpMM
+    rate per level, the BF16 precision report, the node-reduction targets of
+    Section IV with their average conductance, the adjoint, and a measured
+    copy bandwidth."""
+    import numpy as np
+    from scipy.stats import spearmanr
+    from sklearn.metrics import adjusted_rand_score
+
+    extra = {"copy_GBps": measured_copy_GBps(torch)}
+    spmm_stages = ("spmm_prep", "spmm_csr", "spmm_csc")
+    # Alg. 1 alone at level 0 (the resistance estimate), FP32 and BF16 pool
+    R = {}
+    for basis in ("fp32", "bf16"):
+        p1 = hef.Params(k=cfg["k"], b=cfg["b"], basis=basis, assume_valid=True)
+        dt, _, out = timed(torch, hef, lambda: hef.resistance(dh, p1), 3)
+        R[basis] = out[0].cpu().numpy()
+        extra[f"alg1_{basis}_estimates_per_s"] = h.m / dt
+        extra[f"alg1_{basis}_ms"] = dt * 1e3
+        if basis == "fp32":
+            _, st1, _ = timed(torch, hef, lambda: hef.resistance(dh, p1), 3, stages=True)
+            ms_sp = sum(st1[x][0] for x in spmm_stages if x in st1) / 3
+            extra["alg1_spmm_GBps"] = spmm_step_bytes(h.n, h.m, h.nnz, B) * k / (ms_sp / 1e3) / 1e9
+    # SpMM rate per coarsening level: the level hypergraphs rebuilt from the
+    # recorded label maps, Alg. 1 on each
+    cl, nc, _, _, lv = hef.coarsen_levels(dh, params)
+    extra["rho_min_per_level"] = [float(x["rho"][x["rho"] > 0].min()) for x in lv]
+    per_level = []
+    g = dh
+    for i, x in enumerate(lv):
+        p1 = hef.Params(k=cfg["k"], b=cfg["b"], assume_valid=True)
+        dt, _, _ = timed(torch, hef, lambda: hef.resistance(g, p1), 2)
+        _, st1, _ = timed(torch, hef, lambda: hef.resistance(g, p1), 2, stages=True)
+        ms_sp = sum(st1[y][0] for y in spmm_stages if y in st1) / 2
+        gbps = spmm_step_bytes(g.n, g.m, g.nnz, B) * k / (ms_sp / 1e3) / 1e9
+        per_level.append({"n": g.n, "m": g.m, "nnz": g.nnz, "spmm_GBps": gbps,
+                          "spmm_frac": gbps / PEAK_HBM_GBS,
+                          "spmm_us_per_step": ms_sp / k * 1e3, "alg1_ms": dt * 1e3})
+        if i + 1 < len(lv):
+            g, _ = hef.rebuild(g, x["label"], lv[i + 1]["n"])
+    extra["spmm_per_level"] = per_level
+    del g
+    # BF16 pool: error against the float64 oracle's sample, rank correlation
+    # and cluster agreement against FP32
+    gold = os.path.join(ROOT, "tests", "golden", f"{args.config}_R_sample.npz")
+    if os.path.exists(gold):
+        d = np.load(gold)
+        for basis in ("fp32", "bf16"):
+            r = R[basis][d["idx"]].astype(np.float64)
+            extra[f"{basis}_vs_oracle_sample_norm_rel"] = float(
+                np.linalg.norm(r - d["R"]) / np.linalg.norm(d["R"]))
+    extra["bf16_vs_fp32_norm_rel"] = float(np.linalg.norm(R["bf16"].astype(np.float64) - R["fp32"])
+                                           / np.linalg.norm(R["fp32"].astype(np.float64)))
+    extra["bf16_vs_fp32_spearman"] = float(spearmanr(R["bf16"], R["fp32"]).statistic)
+    pc = hef.Params(k=cfg["k"], b=cfg["b"], levels=cfg["levels"], basis="bf16", assume_valid=True)
+    dt, _, out = timed(torch, hef, lambda: hef.coarsen(dh, pc), 1)
+    lvb = hef.last_coarsen_levels()
+    extra["coarsen_bf16_estimates_per_s"] = sum(x[1] for x in lvb) / dt
+    extra["coarsen_bf16_ms"] = dt * 1e3
+    a32, ab = cl.cpu().numpy(), out[0].cpu().numpy()
+    extra["bf16_vs_fp32_cluster_ari"] = float(adjusted_rand_score(a32, ab))
+    extra["bf16_vs_fp32_clusters"] = [int(nc), int(out[1])]
+    # context for the agreement: FP32 with another start-vector seed
+    p8 = hef.Params(k=cfg["k"], b=cfg["b"], levels=cfg["levels"], seed=8, assume_valid=True)
+    a8 = hef.coarsen(dh, p8)[0].cpu().numpy()
+    extra["fp32_seed8_vs_seed7_cluster_ari"] = float(adjusted_rand_score(a32, a8))
+    del a8
+
+    def decisions(r):
+        # level-0 threshold decision R_e < delta (delta: the lower median)
+        return r < np.sort(r)[max(1, int(np.ceil(0.5 * r.size))) - 1]
+
+    extra["bf16_vs_fp32_threshold_decisions_equal"] = float(
+        (decisions(R["fp32"]) == decisions(R["bf16"])).mean())
+    del R
+    # Section IV's node-reduction targets and the average conductance of
+    # Eq. (18) of the resulting clusters
+    for nr in (0.6, 0.8):
+        pn = hef.Params(k=cfg["k"], b=cfg["b"], levels=16, target_nr=nr, assume_valid=True)
+        dt, _, out = timed(torch, hef, lambda: hef.coarsen_levels(dh, pn), 1)
+        _, _, _, avg = hef.conductance(dh, out[0], out[1])
+        extra[f"nr{int(nr * 100)}"] = {"clusters": out[1], "node_reduction": 1 - out[1] / h.n,
+                                       "levels": len(out[4]), "ms": dt * 1e3,
+                                       "phi_avg": float(avg.item())}
+    # cluster quality (Eq. (3) per cluster, Eq. (18) average) of the FP32
+    # partition of the timed configuration
+    reps = 5
+    dt, _, out = timed(torch, hef, lambda: hef.conductance(dh, cl, nc), reps)
+    _, stq, _ = timed(torch, hef, lambda: hef.conductance(dh, cl, nc), reps, stages=True)
+    extra["conductance_clusters"] = nc
+    extra["conductance_phi_avg"] = float(out[3].item())
+    extra["conductance_kernels_ms"] = stq["quality"][0] / reps
+    extra["conductance_call_ms"] = dt * 1e3
+    del cl
+    torch.cuda.empty_cache()
+    # the 10M-node precision workload: BF16 against FP32 coarsening
+    if args.config == "large2m":
+        bcfg = get_config("bf16_10m")
+        hb = make_hypergraph("bf16_10m")
+        db = hef.DeviceHypergraph.from_arrays(hb.n, hb.m, hb.eptr, hb.pins, hb.w,
+                                              device=dh.device)
+        res = {}
+        for basis in ("bf16", "fp32"):
+            pb = hef.Params(k=bcfg["k"], b=bcfg["b"], levels=bcfg["levels"], basis=basis,
+                            assume_valid=True)
+            dt, _, out = timed(torch, hef, lambda: hef.coarsen(db, pb), 1)
+            lvx = hef.last_coarsen_levels()
+            res[basis] = (out[0].cpu().numpy(), out[1], out[2].cpu().numpy(), dt,
+                          sum(x[1] for x in lvx))
+            del out
+        (cb, ncb, Rb, tb, eb), (cf, ncf, Rf, tf, ef) = res["bf16"], res["fp32"]
+        extra["bf16_10m"] = {
+            "workload": f"bf16_10m: n={hb.n}, m={hb.m}, nnz={hb.nnz}, k={bcfg['k']}, "
+                        f"b={bcfg['b']}, {bcfg['levels']} levels",
+            "bf16_ms": tb * 1e3, "fp32_ms": tf * 1e3,
+            "bf16_estimates_per_s": eb / tb, "fp32_estimates_per_s": ef / tf,
+            "R0_norm_rel": float(np.linalg.norm(Rb.astype(np.float64) - Rf)
+                                 / np.linalg.norm(Rf.astype(np.float64))),
+            "R0_spearman": float(spearmanr(Rb, Rf).statistic),
+            "cluster_ari": float(adjusted_rand_score(cf, cb)), "clusters": [int(ncf), int(ncb)]}
+        del db, res
+        torch.cuda.empty_cache()
+    # forward + backward of Alg. 1 at the gradient workload
+    gname = "grad200k"
+    gc = get_config(gname)
+    gh = make_hypergraph(gname)
+    dg = hef.DeviceHypergraph.from_arrays(gh.n, gh.m, gh.eptr, gh.pins, gh.w, device=dh.device)
+    pg = hef.Params(k=gc["k"], b=gc["b"], assume_valid=True)
+    dR = torch.randn(gh.m, device=dh.device, generator=torch.Generator(dh.device).manual_seed(11))
+    tf, _, _ = timed(torch, hef, lambda: hef.resistance(dg, pg), 5)
+    w = dg.w.clone().requires_grad_(True)
+
+    def fwd_bwd():
+        w.grad = None
+        hef.HyperEFResistance.apply(w, dg, pg).backward(dR)
+
+    tfb, _, _ = timed(torch, hef, fwd_bwd, 5)
+    extra["adjoint_workload"] = f"{gname}: n={gh.n}, m={gh.m}, k={gc['k']}, b={gc['b']}"
+    extra["fwd_ms"] = tf * 1e3
+    extra["fwd_bwd_ms"] = tfb * 1e3
+    extra["fwd_bwd_over_fwd"] = tfb / tf
+    return extra
 
 
 def main():
@@ -155,7 +369,6 @@ def main():
     import torch
 
     import paper_2511_06600_amd as hef
-    from synth import get_config, make_hypergraph
 
     cfg = get_config(args.config)
     h = make_hypergraph(args.config)
@@ -209,6 +422,7 @@ def main():
     jg_f = sum(gram_flops(n, K) for (n, _, _) in levels) * S
     ja_f = sum(apply_flops(n, K) for (n, _, _) in levels) * S
     sc_b = sum(score_bytes(n, m, z, K) for (n, m, z) in levels) * S
+    sq_b = sum(score_qh_bytes(n, m, z, K) for (n, m, z) in levels) * S
     traffic = read_traffic()
     nfused = k * len(levels)  # fused SpMM launches per step
 
@@ -237,12 +451,16 @@ def main():
         "k_jgram": roofline_entry("mfma", jg_f, ms_of("orth_gram"), per.get("orth_gram", (0, 0))[1],
                                   PEAK_FP32_MFMA, "TFLOP/s", ["k_jgram"],
                                   traffic_of(["k_jgram"], len(levels))),
-        "k_japply": roofline_entry("mfma", ja_f, ms_of("orth_apply"), per.get("orth_apply", (0, 0))[1],
-                                   PEAK_FP32_MFMA, "TFLOP/s", ["k_japply"],
-                                   traffic_of(["k_japply"], len(levels))),
+        "k_japply_tri": roofline_entry("mfma", ja_f, ms_of("orth_apply"),
+                                       per.get("orth_apply", (0, 0))[1], PEAK_FP32_MFMA,
+                                       "TFLOP/s", ["k_japply_tri"],
+                                       traffic_of(["k_japply_tri"], len(levels))),
         "k_score_r": roofline_entry("hbm", sc_b, ms_of("score_r"), per.get("score_r", (0, 0))[1],
                                     PEAK_HBM_GBS, "GB/s", ["k_score_r"],
                                     traffic_of(["k_score_r"], len(levels))),
+        "k_score_qh": roofline_entry("hbm", sq_b, ms_of("score_qh"),
+                                     per.get("score_qh", (0, 0))[1], PEAK_HBM_GBS, "GB/s",
+                                     ["k_score_qh"], traffic_of(["k_score_qh"], len(levels))),
     }
     # the dominant kernel (by time) among those with an algorithmic count;
     # the local-clustering search (cluster_best) has none: its work is the
@@ -276,95 +494,12 @@ def main():
     }
 
     if not args.no_extras:
-        extra = {}
-        # Alg. 1 alone at level 0 (the resistance estimate), FP32 and BF16 pool
-        for basis in ("fp32", "bf16"):
-            p1 = hef.Params(k=cfg["k"], b=cfg["b"], basis=basis, assume_valid=True)
-            hef.resistance(dh, p1)
-            torch.cuda.synchronize()
-            hef.timing_read(reset=True)
-            hef.timing_enable(True)
-            ta = time.perf_counter()
-            reps = 3
-            for _ in range(reps):
-                hef.resistance(dh, p1)
-            torch.cuda.synchronize()
-            dt = (time.perf_counter() - ta) / reps
-            hef.timing_enable(False)
-            st1 = hef.timing_read(reset=True)
-            extra[f"alg1_{basis}_estimates_per_s"] = h.m / dt
-            extra[f"alg1_{basis}_ms"] = dt * 1e3
-            if basis == "fp32":
-                ms_sp = sum(st1[x][0] for x in spmm_stages if x in st1) / reps
-                extra["alg1_spmm_GBps"] = spmm_step_bytes(h.n, h.m, h.nnz, B) * k / (ms_sp / 1e3) / 1e9
-        pc = hef.Params(k=cfg["k"], b=cfg["b"], levels=cfg["levels"], basis="bf16",
-                        assume_valid=True)
-        hef.coarsen(dh, pc)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        hef.coarsen(dh, pc)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - ta
-        lv = hef.last_coarsen_levels()
-        extra["coarsen_bf16_estimates_per_s"] = sum(x[1] for x in lv) / dt
-        extra["coarsen_bf16_ms"] = dt * 1e3
-        # cluster quality (Eq. (3) per cluster, Eq. (18) average) of the FP32
-        # partition of the timed configuration
-        cl, ncl, _, _ = hef.coarsen(dh, params)
-        hef.conductance(dh, cl, ncl)
-        torch.cuda.synchronize()
-        hef.timing_read(reset=True)
-        hef.timing_enable(True)
-        reps = 5
-        ta = time.perf_counter()
-        for _ in range(reps):
-            _, _, _, avg = hef.conductance(dh, cl, ncl)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - ta) / reps
-        hef.timing_enable(False)
-        stq = hef.timing_read(reset=True)
-        ms_q = stq["quality"][0] / reps
-        extra["conductance_clusters"] = ncl
-        extra["conductance_phi_avg"] = float(avg.item())
-        extra["conductance_kernels_ms"] = ms_q
-        extra["conductance_pins_per_s"] = h.nnz / (ms_q / 1e3)
-        extra["conductance_call_ms"] = dt * 1e3
-        del dh, cl
-        torch.cuda.empty_cache()
-        # forward + backward of Alg. 1 at the gradient workload
-        gname = "grad200k"
-        gc = get_config(gname)
-        g = make_hypergraph(gname)
-        dg = hef.DeviceHypergraph.from_arrays(g.n, g.m, g.eptr, g.pins, g.w, device=dev)
-        pg = hef.Params(k=gc["k"], b=gc["b"], assume_valid=True)
-        dR = torch.randn(g.m, device=dev, generator=torch.Generator(dev).manual_seed(11))
-        hef.resistance(dg, pg)
-        hef.resistance_backward(dg, pg, dR)
-        torch.cuda.synchronize()
-        reps = 5
-        ta = time.perf_counter()
-        for _ in range(reps):
-            hef.resistance(dg, pg)
-        torch.cuda.synchronize()
-        tf = (time.perf_counter() - ta) / reps
-        # the autograd path: the forward keeps the Krylov tape, the backward
-        # runs the reverse sweep only
-        w = dg.w.clone().requires_grad_(True)
-        for _ in range(2):
-            hef.HyperEFResistance.apply(w, dg, pg).backward(dR)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        for _ in range(reps):
-            w.grad = None
-            R = hef.HyperEFResistance.apply(w, dg, pg)
-            R.backward(dR)
-        torch.cuda.synchronize()
-        tfb = (time.perf_counter() - ta) / reps
-        extra["adjoint_workload"] = f"{gname}: n={g.n}, m={g.m}, k={gc['k']}, b={gc['b']}"
-        extra["fwd_ms"] = tf * 1e3
-        extra["fwd_bwd_ms"] = tfb * 1e3
-        extra["fwd_bwd_over_fwd"] = tfb / tf
-        result["extras"] = extra
+        result["extras"] = extras(args, torch, hef, cfg, h, dh, params, levels, B, k)
+        result["alg1_level0_estimates_per_s"] = result["extras"]["alg1_fp32_estimates_per_s"]
+        peak = result["extras"]["copy_GBps"]
+        for r in result["rooflines"].values():
+            if r["bound"] == "hbm":
+                r["frac_of_measured_copy"] = r["achieved"] / peak
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(args.config)
