@@ -303,24 +303,62 @@ __device__ __forceinline__ void load8oct(const void *pool, int pool_type, int64_
     if (rb + q >= rows) v[q] = 0.0f;
 }
 
-// 32 rows of a 128-column super block into registers: row-major
-// input (thread -> row, 8 columns) or row-octet input (thread -> octet of
-// rows, 1 column); the store puts it column-major in LDS (column c at
-// S + c * kSLd, rows contiguous), where an octet is two 16-byte stores.
-__device__ __forceinline__ void slab_load(const void *pool, int pool_type, bool oct, int64_t r,
-                                          int64_t r1, int cbase, int K, int tid, float (&v)[8]) {
-  if (oct) load8oct(pool, pool_type, r + 8 * (tid >> 7), r1, cbase + (tid & 127), K, v);
-  else load8(pool, pool_type, r + (tid >> 4), r1, cbase + (tid & 15) * 8, K, v);
+// 32 rows of a 128-column super block of an FP32 pool into registers:
+// row-octet input (thread -> octet of rows, 1 column) or row-major input
+// (thread -> row, 8 columns).  The loads are unconditional (addresses
+// clamped into the chunk and the row), so nothing waits on them until the
+// values go to LDS; slab_put applies the row and column masks there and
+// stores the block column-major (column c at S + c * kSLd, rows
+// contiguous), an octet as two 16-byte stores.  Row-major input takes
+// 16-byte loads when K % 8 == 0 and single floats otherwise.
+template <bool OCT>
+__device__ __forceinline__ void slab_get(const float *pool, int64_t r, int64_t r1, int cbase,
+                                         int K, int tid, float (&v)[8]) {
+  if (OCT) {
+    const int64_t rb = r + 8 * (tid >> 7);
+    const int64_t rr = rb < r1 ? rb : ((r1 - 1) & ~int64_t(7));
+    const int c = cbase + (tid & 127);
+    const float *p = pool + ((rr >> 3) * K + (c < K ? c : K - 1)) * 8;
+    const float4 a = *reinterpret_cast<const float4 *>(p);
+    const float4 b = *reinterpret_cast<const float4 *>(p + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+    const int64_t row = r + (tid >> 4);
+    const float *p = pool + (row < r1 ? row : r1 - 1) * int64_t(K);
+    const int c = cbase + (tid & 15) * 8;
+    if ((K & 7) == 0) {
+      const float *q = p + (c < K ? c : K - 8);
+      const float4 a = *reinterpret_cast<const float4 *>(q);
+      const float4 b = *reinterpret_cast<const float4 *>(q + 4);
+      v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+      v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = p[c + q < K ? c + q : K - 1];
+    }
+  }
 }
 
-__device__ __forceinline__ void slab_store(float *S, bool oct, int tid, const float (&v)[8]) {
-  if (oct) {
-    float *d = S + (tid & 127) * kSLd + 8 * (tid >> 7);
-    *reinterpret_cast<float4 *>(d) = make_float4(v[0], v[1], v[2], v[3]);
-    *reinterpret_cast<float4 *>(d + 4) = make_float4(v[4], v[5], v[6], v[7]);
-  } else {
+template <bool OCT>
+__device__ __forceinline__ void slab_put(float *S, int64_t r, int64_t r1, int cbase, int K, int tid,
+                                         const float (&v)[8]) {
+  float m[8];
+  if (OCT) {
+    const int64_t rb = r + 8 * (tid >> 7);
+    const bool cok = cbase + (tid & 127) < K;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) S[((tid & 15) * 8 + q) * kSLd + (tid >> 4)] = v[q];
+    for (int q = 0; q < 8; ++q) m[q] = (cok && rb + q < r1) ? v[q] : 0.0f;
+    float *d = S + (tid & 127) * kSLd + 8 * (tid >> 7);
+    *reinterpret_cast<float4 *>(d) = make_float4(m[0], m[1], m[2], m[3]);
+    *reinterpret_cast<float4 *>(d + 4) = make_float4(m[4], m[5], m[6], m[7]);
+  } else {
+    const bool rok = r + (tid >> 4) < r1;
+    const int c = cbase + (tid & 15) * 8;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) m[q] = (rok && c + q < K) ? v[q] : 0.0f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) S[((tid & 15) * 8 + q) * kSLd + (tid >> 4)] = m[q];
   }
 }
 
@@ -342,10 +380,10 @@ __device__ __forceinline__ void gram_tile(const float *A, const float *Bm, int l
   }
 }
 
+template <bool OCT>
 __global__ void __launch_bounds__(kGT32)
-k_jgram(const void *__restrict__ pool, const void *__restrict__ poolB, int pool_type, int oct,
-        int64_t n, int K, int nsb, int npairs, int64_t rows_per_chunk,
-        double *__restrict__ partial) {
+k_jgram(const float *__restrict__ pool, const float *__restrict__ poolB, int64_t n, int K, int nsb,
+        int npairs, int64_t rows_per_chunk, double *__restrict__ partial) {
   __shared__ __attribute__((aligned(16))) float As[2][kSB * kSLd];
   __shared__ __attribute__((aligned(16))) float Bs[2][kSB * kSLd];
   const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
@@ -377,7 +415,7 @@ k_jgram(const void *__restrict__ pool, const void *__restrict__ poolB, int pool_
   // the first half of the block stages super block a, the second half b
   // (a diagonal pair stages one super block)
   const bool loader = !diag || tid < kGT32 / 2;
-  const void *src = tid < kGT32 / 2 ? pool : (cross ? poolB : pool);
+  const float *src = tid < kGT32 / 2 ? pool : (cross ? poolB : pool);
   const int cb = (tid < kGT32 / 2 ? ab.x : ab.y) * kSB;
   const int lt = tid & (kGT32 / 2 - 1);
   const int64_t r0 = chunk * rows_per_chunk;
@@ -386,26 +424,33 @@ k_jgram(const void *__restrict__ pool, const void *__restrict__ poolB, int pool_
   double d[16];
 #pragma unroll
   for (int v = 0; v < 16; ++v) { acc[v] = 0.0f; d[v] = 0.0; }
-  // a slab is staged as 32-row halves
+  // a slab is staged as 32-row halves.  Slab t + 1 goes to LDS at the start
+  // of iteration t (its loads were issued one iteration earlier), then the
+  // loads of slab t + 2 are issued, then slab t's products run: the LDS
+  // writes overlap other waves' products and the loads have a whole
+  // iteration to arrive.
   float rv[kSlab / 32][8];
   auto fetch = [&](int64_t r) __attribute__((always_inline)) {
 #pragma unroll
-    for (int h = 0; h < kSlab / 32; ++h) slab_load(src, pool_type, oct, r + 32 * h, r1, cb, K, lt, rv[h]);
+    for (int h = 0; h < kSlab / 32; ++h) slab_get<OCT>(src, r + 32 * h, r1, cb, K, lt, rv[h]);
   };
-  auto stash = [&](int b) __attribute__((always_inline)) {
+  auto stash = [&](int b, int64_t r) __attribute__((always_inline)) {
     float *S = tid < kGT32 / 2 ? As[b] : Bs[b];
 #pragma unroll
-    for (int h = 0; h < kSlab / 32; ++h) slab_store(S + 32 * h, oct, lt, rv[h]);
+    for (int h = 0; h < kSlab / 32; ++h) slab_put<OCT>(S + 32 * h, r + 32 * h, r1, cb, K, lt, rv[h]);
   };
-  if (loader) {
+  if (loader && r0 < r1) {  // (an empty chunk has nothing to stage)
     fetch(r0);
-    stash(0);
+    stash(0, r0);
+    if (r0 + kSlab < r1) fetch(r0 + kSlab);
   }
   __syncthreads();
   int buf = 0, slabs = 0;
   for (int64_t r = r0; r < r1; r += kSlab) {
-    const bool more = r + kSlab < r1;
-    if (more && loader) fetch(r + kSlab);
+    if (loader && r + kSlab < r1) {
+      stash(buf ^ 1, r + kSlab);
+      if (r + 2 * kSlab < r1) fetch(r + 2 * kSlab);
+    }
     const float *A = As[buf];
     const float *Bm = diag ? As[buf] : Bs[buf];
     if (on) gram_tile(A, Bm, lane, ti, tj, acc);
@@ -414,7 +459,6 @@ k_jgram(const void *__restrict__ pool, const void *__restrict__ poolB, int pool_
 #pragma unroll
       for (int v = 0; v < 16; ++v) { d[v] += double(acc[v]); acc[v] = 0.0f; }
     }
-    if (more && loader) stash(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
@@ -596,13 +640,19 @@ constexpr int kA2G = 4;  // k steps per register group (4 groups per 32-wide chu
 template <bool OCT, int NA>
 __device__ __forceinline__ void tri_chunks(const float *__restrict__ Vw,
                                            const float *__restrict__ RT, uint32_t vo,
-                                           uint32_t vo1, const bool (&vrow)[2], int K, int Kp,
+                                           uint32_t vo1, int K, int Kp,
                                            const uint32_t (&rb)[4], int h, int kc0, int kc1,
                                            floatx16 (&acc)[2][4]) {
   constexpr int GPC = 16 / kA2G;  // register groups per 32-wide chunk
   const int g0 = kc0 * GPC, g1 = kc1 * GPC;
   if (g0 >= g1) return;
+  // The loads are unconditional (k clamped into the row, rows clamped in the
+  // caller) and their values are masked only where the products use them,
+  // so the next group's loads stay in flight during the current products.
+  // A clamped row's products land in output rows that are never stored; a
+  // clamped k is zeroed here.
   float a[2][kA2G][2];
+  bool kin[2][kA2G];
   float4 b[2][NA];
   const char *vb = reinterpret_cast<const char *>(Vw);
   const char *rt = reinterpret_cast<const char *>(RT);
@@ -611,20 +661,17 @@ __device__ __forceinline__ void tri_chunks(const float *__restrict__ Vw,
 #pragma unroll
     for (int s = 0; s < kA2G; ++s) {
       const int k = kb + s;
-      const bool kin = k < K;
-      const uint32_t kk = kin ? uint32_t(k) : 0u;
-      float x0, x1;
+      kin[buf][s] = k < K;
+      const uint32_t kk = k < K ? uint32_t(k) : 0u;
       if constexpr (OCT) {
         // rows 2i and 2i + 1 sit side by side in their octet
         const float2 t = *reinterpret_cast<const float2 *>(vb + 4u * (vo + 8u * kk));
-        x0 = t.x;
-        x1 = t.y;
+        a[buf][s][0] = t.x;
+        a[buf][s][1] = t.y;
       } else {
-        x0 = *reinterpret_cast<const float *>(vb + 4u * (vo + kk));
-        x1 = *reinterpret_cast<const float *>(vb + 4u * (vo1 + kk));
+        a[buf][s][0] = *reinterpret_cast<const float *>(vb + 4u * (vo + kk));
+        a[buf][s][1] = *reinterpret_cast<const float *>(vb + 4u * (vo1 + kk));
       }
-      a[buf][s][0] = (kin && vrow[0]) ? x0 : 0.0f;
-      a[buf][s][1] = (kin && vrow[1]) ? x1 : 0.0f;
     }
 #pragma unroll
     for (int j = 0; j < NA; ++j)
@@ -639,7 +686,8 @@ __device__ __forceinline__ void tri_chunks(const float *__restrict__ Vw,
                                                                               : b[buf][j].w;
 #pragma unroll
         for (int r = 0; r < 2; ++r)
-          acc[r][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[buf][s][r], bv, acc[r][j], 0, 0, 0);
+          acc[r][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(kin[buf][s] ? a[buf][s][r] : 0.0f, bv,
+                                                           acc[r][j], 0, 0, 0);
       }
   };
   // two register groups in flight: the next group's loads are issued before
@@ -679,7 +727,6 @@ k_japply_tri(const float *__restrict__ V, float *__restrict__ Q, int64_t n, int 
   // the workgroup's rows of V from a uniform base (row0 is a multiple of 8)
   const float *Vw = OCT ? V + (row0 >> 3) * int64_t(K) * 8 : V + row0 * int64_t(K);
   const int64_t last = n - 1 - row0;  // the last valid local row
-  const bool vrow[2] = {2 * li <= last, 2 * li + 1 <= last};
   // a valid row pair to read (masked out above when past the end)
   const uint32_t r0 = uint32_t(2 * li <= last ? 2 * li : (last & ~int64_t(1)));
   const uint32_t r1 = uint32_t(2 * li + 1 <= last ? 2 * li + 1 : last);
@@ -701,10 +748,10 @@ k_japply_tri(const float *__restrict__ V, float *__restrict__ Q, int64_t n, int 
   const int e2 = nt >= 3 ? ct[2] + 1 : 0;
   const int e1 = nt >= 2 ? ct[1] + 1 : 0;
   const int e0 = ct[0] + 1;
-  if (nt >= 4) tri_chunks<OCT, 4>(Vw, RT, vo, vo1, vrow, K, Kp, rb, h, 0, e3, acc);
-  if (nt >= 3) tri_chunks<OCT, 3>(Vw, RT, vo, vo1, vrow, K, Kp, rb, h, e3, e2, acc);
-  if (nt >= 2) tri_chunks<OCT, 2>(Vw, RT, vo, vo1, vrow, K, Kp, rb, h, e2, e1, acc);
-  tri_chunks<OCT, 1>(Vw, RT, vo, vo1, vrow, K, Kp, rb, h, e1, e0, acc);
+  if (nt >= 4) tri_chunks<OCT, 4>(Vw, RT, vo, vo1, K, Kp, rb, h, 0, e3, acc);
+  if (nt >= 3) tri_chunks<OCT, 3>(Vw, RT, vo, vo1, K, Kp, rb, h, e3, e2, acc);
+  if (nt >= 2) tri_chunks<OCT, 2>(Vw, RT, vo, vo1, K, Kp, rb, h, e2, e1, acc);
+  tri_chunks<OCT, 1>(Vw, RT, vo, vo1, K, Kp, rb, h, e1, e0, acc);
   float *Qw = Q + row0 * int64_t(K);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -789,32 +836,58 @@ k_jgram_bf16(const uint16_t *__restrict__ pool, int oct, int64_t n, int K, int n
     const int ca = ab.x * kSB + 32 * ti + (lane & 31);
     const int cb0 = ab.y * kSB + 32 * tj0 + (lane & 31);
     const int cb1 = cb0 + 32;
-    auto ld = [&](int64_t rb, int c) -> bf16x8 {
-      uint4 u = make_uint4(0u, 0u, 0u, 0u);
-      if (rb < r1 && c < K) u = *reinterpret_cast<const uint4 *>(pool + ((rb >> 3) * K + c) * 8);
-      return *reinterpret_cast<const bf16x8 *>(&u);
+    // loads at addresses clamped into the chunk and the row, masked where
+    // the products use them; the next 64 rows are loaded during the
+    // current rows' products
+    const int64_t rlast = r1 > r0 ? ((r1 - 1) & ~int64_t(7)) : 0;
+    auto ld = [&](int64_t rb, int c) -> uint4 {
+      return *reinterpret_cast<const uint4 *>(
+          pool + (((rb < r1 ? rb : rlast) >> 3) * K + (c < K ? c : K - 1)) * 8);
     };
-    for (int64_t r = r0; r < r1; r += 64) {
-      bf16x8 av[4], bv0[4], bv1[4];
+    auto use = [&](const uint4 &u, int64_t rb, int c) -> bf16x8 {
+      const uint32_t m = uint32_t(rb < r1) & uint32_t(c < K) ? 0xFFFFFFFFu : 0u;
+      const uint4 z = make_uint4(u.x & m, u.y & m, u.z & m, u.w & m);
+      return *reinterpret_cast<const bf16x8 *>(&z);
+    };
+    uint4 ua[2][4], ub0[2][4], ub1[2][4];
+    auto fetch = [&](int64_t r, int q) __attribute__((always_inline)) {
 #pragma unroll
       for (int st = 0; st < 4; ++st) {
         const int64_t rb = r + 16 * st + 8 * (lane >> 5);
-        av[st] = ld(rb, ca);
-        bv0[st] = on0 ? ld(rb, cb0) : av[st];
-        bv1[st] = on1 ? ld(rb, cb1) : av[st];
+        ua[q][st] = ld(rb, ca);  // (unconditional, also where a tile is off)
+        ub0[q][st] = ld(rb, cb0);
+        ub1[q][st] = ld(rb, cb1);
       }
+    };
+    auto mul = [&](int64_t r, int q) __attribute__((always_inline)) {
 #pragma unroll
       for (int st = 0; st < 4; ++st) {
-        if (on0) acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[st], bv0[st], acc0, 0, 0, 0);
-        if (on1) acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[st], bv1[st], acc1, 0, 0, 0);
+        const int64_t rb = r + 16 * st + 8 * (lane >> 5);
+        const bf16x8 av = use(ua[q][st], rb, ca);
+        if (on0)
+          acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, use(ub0[q][st], rb, cb0), acc0, 0, 0, 0);
+        if (on1)
+          acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, use(ub1[q][st], rb, cb1), acc1, 0, 0, 0);
       }
-      if (++slabs == 2) {  // float32 sums over 128 rows, then float64
-        slabs = 0;
+    };
+    // two 64-row steps per trip (register buffers 0 and 1 by name), each
+    // buffer refilled as soon as its products are issued, so the loads of
+    // one step are in flight during the other's products; float32 sums
+    // over the trip's 128 rows, then float64
+    // (loads past the chunk read clamped addresses and are never used)
+    if (r0 < r1) {
+      fetch(r0, 0);
+      fetch(r0 + 64, 1);
+    }
+    for (int64_t r = r0; r < r1; r += 128) {
+      mul(r, 0);
+      fetch(r + 128, 0);
+      if (r + 64 < r1) mul(r + 64, 1);
+      fetch(r + 192, 1);
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          d0[v] += double(acc0[v]); acc0[v] = 0.0f;
-          d1[v] += double(acc1[v]); acc1[v] = 0.0f;
-        }
+      for (int v = 0; v < 16; ++v) {
+        d0[v] += double(acc0[v]); acc0[v] = 0.0f;
+        d1[v] += double(acc1[v]); acc1[v] = 0.0f;
       }
     }
   }
@@ -1024,9 +1097,17 @@ hef_status gram_run(const void *pool, const void *poolB, int pool_type, int64_t 
     k_jgram_bf16<<<int64_t(p.npairs) * p.nchunks, kGT, 0, s>>>(
         reinterpret_cast<const uint16_t *>(pool), oct, n, K, p.nsb, p.npairs, p.rows_per_chunk,
         partial);
+  else if (pool_type != kPoolF32) {
+    set_error("cross Gram of a BF16 pool is not supported");
+    return HEF_ERR_UNSUPPORTED;
+  } else if (oct)
+    k_jgram<true><<<int64_t(p.npairs) * p.nchunks, kGT32, 0, s>>>(
+        reinterpret_cast<const float *>(pool), reinterpret_cast<const float *>(poolB), n, K, p.nsb,
+        p.npairs, p.rows_per_chunk, partial);
   else
-    k_jgram<<<int64_t(p.npairs) * p.nchunks, kGT32, 0, s>>>(pool, poolB, pool_type, oct, n, K, p.nsb,
-                                                          p.npairs, p.rows_per_chunk, partial);
+    k_jgram<false><<<int64_t(p.npairs) * p.nchunks, kGT32, 0, s>>>(
+        reinterpret_cast<const float *>(pool), reinterpret_cast<const float *>(poolB), n, K, p.nsb,
+        p.npairs, p.rows_per_chunk, partial);
   HEF_LAUNCH_CHECK();
   }
   TimedScope ts(kStOrthReduce, s);
