@@ -451,10 +451,10 @@ def main():
         "k_jgram": roofline_entry("mfma", jg_f, ms_of("orth_gram"), per.get("orth_gram", (0, 0))[1],
                                   PEAK_FP32_MFMA, "TFLOP/s", ["k_jgram"],
                                   traffic_of(["k_jgram"], len(levels))),
-        "k_japply_tri": roofline_entry("mfma", ja_f, ms_of("orth_apply"),
+        "k_japply_dma": roofline_entry("mfma", ja_f, ms_of("orth_apply"),
                                        per.get("orth_apply", (0, 0))[1], PEAK_FP32_MFMA,
-                                       "TFLOP/s", ["k_japply_tri"],
-                                       traffic_of(["k_japply_tri"], len(levels))),
+                                       "TFLOP/s", ["k_japply_dma"],
+                                       traffic_of(["k_japply_dma"], len(levels))),
         "k_score_r": roofline_entry("hbm", sc_b, ms_of("score_r"), per.get("score_r", (0, 0))[1],
                                     PEAK_HBM_GBS, "GB/s", ["k_score_r"],
                                     traffic_of(["k_score_r"], len(levels))),

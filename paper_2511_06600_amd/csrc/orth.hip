@@ -767,6 +767,141 @@ k_japply_tri(const float *__restrict__ V, float *__restrict__ Q, int64_t n, int 
   }
 }
 
+// Q = V R^-1 for an FP32 pool in the row-octet layout, operands staged in
+// LDS by direct global-to-LDS loads (global_load_lds_dwordx4).  A workgroup
+// of 16 waves takes a panel of 256 rows and one of two column sets: set g
+// holds the 32-column tiles j with (nct - 1 - j) % 2 == g, in descending
+// order (at most 8 slots), which gives the two sets nearly equal triangular
+// work (tile j takes the k chunks 0..j, R^-1 being upper triangular).  Wave
+// w owns rows 32 (w % 8) .. 32 (w % 8) + 31 of the panel and the slots
+// w / 8, w / 8 + 2, w / 8 + 4, w / 8 + 6 (one 32x32 FP32 accumulator each;
+// alternate slots keep the two halves' triangular work even).  Per 32-wide
+// k chunk, two LDS buffers:
+//   A [k][256 rows]: one wave load is one k of the panel (lane i: rows
+//     4i..4i+3, a half octet); the k rows 16..31 sit 32 floats further
+//     on, so that the two lane halves (k and k + 16) read distinct banks;
+//   B [slot][32 columns][32 k] from the transposed copy RT[col][k], the
+//     16-byte k group x of column c stored at slot x ^ ((c >> 1) & 7), so
+//     that the operand reads of 16 consecutive columns hit distinct banks.
+// Chunk c + 1 is loaded into the other buffer during chunk c's products;
+// one barrier per chunk.  MFMA k-step s of lane half h is k = 16h + s of the
+// chunk, in A and B alike.  Tiles past their last chunk drop out (loads and
+// products).  Rows past n and k past K read clamped addresses: such rows
+// are never stored and R^-1 is zero in rows k >= K.
+constexpr int kDR = 256;   // rows per panel
+constexpr int kDT = 1024;  // threads: 16 waves
+constexpr int kPMaxTiles = 8;
+constexpr int kWT = 4;     // slots per wave
+typedef float f32x4 __attribute__((ext_vector_type(4)));  // (register-friendly float4)
+
+__global__ void __launch_bounds__(kDT)
+k_japply_dma(const float *__restrict__ V, float *__restrict__ Q, int64_t n, int K, int Kp,
+             const float *__restrict__ RT) {
+  // two buffers as four separate LDS objects, so that the compiler sees
+  // the loads into one buffer as disjoint from the reads of the other
+  __shared__ __attribute__((aligned(1024))) float As0[32 * kDR + 32];
+  __shared__ __attribute__((aligned(1024))) float As1[32 * kDR + 32];
+  __shared__ __attribute__((aligned(1024))) float Bs0[kPMaxTiles * 32 * 32];
+  __shared__ __attribute__((aligned(1024))) float Bs1[kPMaxTiles * 32 * 32];
+  const auto aoff = [](int kk) { return kk * kDR + ((kk >> 4) << 5); };
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t r0 = (lb >> 1) * kDR;
+  const int set = int(lb & 1);
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int rt = w & 7, tg = w >> 3;
+  const int lane = threadIdx.x & 63, li = lane & 31, h = lane >> 5;
+  const int nct = Kp / 32;
+  const int top = nct - 1 - set;  // this set's tiles: slot ts is tile top - 2 ts
+  const int ntile = top >= 0 ? top / 2 + 1 : 0;
+  if (ntile == 0) return;
+  const int nch = top + 1;  // chunks 0..top
+  const int64_t olast = (n - 1) >> 3;
+  int64_t og = (r0 >> 3) + (lane >> 1);
+  og = og <= olast ? og : olast;
+  const float *va = V + og * int64_t(K) * 8 + 4 * (lane & 1);
+  // each wave loads k rows 2w, 2w + 1 of A and the (slot, 8-column) pieces
+  // 2w, 2w + 1 of B
+  auto dma = [&](int c, float *A, float *B) __attribute__((always_inline)) {
+    const int k0 = 32 * c;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int kk = 2 * w + u;
+      const int k = k0 + kk < K ? k0 + kk : K - 1;
+      __builtin_amdgcn_global_load_lds(va + int64_t(k) * 8, A + aoff(kk), 16, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int piece = 2 * w + u;
+      const int ts = piece >> 2, t8 = piece & 3;
+      if (ts < ntile && top - 2 * ts >= c) {
+        const int cl = 8 * t8 + (lane >> 3);  // column within the tile
+        const int col = 32 * (top - 2 * ts) + cl;
+        const int x = (lane & 7) ^ ((cl >> 1) & 7);
+        __builtin_amdgcn_global_load_lds(RT + int64_t(col) * Kp + k0 + 4 * x,
+                                         B + (32 * ts + 8 * t8) * 32, 16, 0, 0);
+      }
+    }
+  };
+  floatx16 acc[kWT];
+#pragma unroll
+  for (int u = 0; u < kWT; ++u)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[u][v] = 0.0f;
+  auto mul = [&](int c, const float *A, const float *B) __attribute__((always_inline)) {
+    const int na = ntile < (top - c) / 2 + 1 ? ntile : (top - c) / 2 + 1;  // active slots
+    const float *pa = A + aoff(16 * h) + 32 * rt + li;
+    const float *pb = B + li * 32;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float a[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) a[t] = pa[(4 * q + t) * kDR];
+      const int xo = 4 * ((4 * h + q) ^ ((li >> 1) & 7));
+      f32x4 bv[kWT];
+#pragma unroll
+      for (int u = 0; u < kWT; ++u)
+        bv[u] = *reinterpret_cast<const f32x4 *>(pb + (tg + 2 * u) * 32 * 32 + xo);
+#pragma unroll
+      for (int u = 0; u < kWT; ++u) {
+        if (tg + 2 * u < na) {
+          acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0], bv[u].x, acc[u], 0, 0, 0);
+          acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1], bv[u].y, acc[u], 0, 0, 0);
+          acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[2], bv[u].z, acc[u], 0, 0, 0);
+          acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[3], bv[u].w, acc[u], 0, 0, 0);
+        }
+      }
+    }
+  };
+  dma(0, As0, Bs0);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's loads are in LDS
+  __syncthreads();
+  // chunk c in buffer c % 2 while chunk c + 1 loads into the other; after
+  // each chunk every wave waits for its loads, then the barrier
+  for (int c = 0; c < nch; c += 2) {
+    if (c + 1 < nch) dma(c + 1, As1, Bs1);
+    mul(c, As0, Bs0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    if (c + 1 >= nch) break;
+    if (c + 2 < nch) dma(c + 2, As0, Bs0);
+    mul(c + 1, As1, Bs1);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+  }
+  // D[i][j] of a 32x32 tile: lane holds column li, rows 8 (v >> 2) + 4 h + (v & 3)
+#pragma unroll
+  for (int u = 0; u < kWT; ++u) {
+    const int ts = tg + 2 * u;
+    if (ts >= ntile) continue;
+    const int col = 32 * (top - 2 * ts) + li;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t row = r0 + 32 * rt + 8 * (v >> 2) + 4 * h + (v & 3);
+      if (row < n && col < K) Q[row * K + col] = acc[u][v];
+    }
+  }
+}
+
 // ---------------------------------------------------------------- bf16 pool
 // With the pool stored as bfloat16 its values are exact bf16 numbers, so the
 // Gram runs on bf16 matrix cores (v_mfma_f32_32x32x16_bf16: exact products,
@@ -1124,13 +1259,13 @@ hef_status apply_run(const void *V, void *Q, int pool_type, int64_t n, int K, in
   if (n == 0) return HEF_OK;
   TimedScope ts(kStOrthApply, s);
   if (!full && !accumulate && pool_type == kPoolF32 && RinvT32) {
-    const int64_t nb = cdiv(n, kA2Rows);
-    if (oct)
-      k_japply_tri<true><<<nb, kA2T, 0, s>>>(reinterpret_cast<const float *>(V),
-                                             reinterpret_cast<float *>(Q), n, K, Kp, RinvT32);
+    if (oct)  // (Kp <= 512: at most 8 tiles per column set)
+      k_japply_dma<<<2 * cdiv(n, kDR), kDT, 0, s>>>(reinterpret_cast<const float *>(V),
+                                                   reinterpret_cast<float *>(Q), n, K, Kp,
+                                                   RinvT32);
     else
-      k_japply_tri<false><<<nb, kA2T, 0, s>>>(reinterpret_cast<const float *>(V),
-                                              reinterpret_cast<float *>(Q), n, K, Kp, RinvT32);
+      k_japply_tri<false><<<cdiv(n, kA2Rows), kA2T, 0, s>>>(
+          reinterpret_cast<const float *>(V), reinterpret_cast<float *>(Q), n, K, Kp, RinvT32);
     HEF_LAUNCH_CHECK();
     return HEF_OK;
   }
