@@ -471,6 +471,138 @@ k_jgram(const float *__restrict__ pool, const float *__restrict__ poolB, int64_t
   }
 }
 
+// The symmetric Gram of an FP32 pool in the row-octet layout, with the slabs
+// staged by direct global-to-LDS loads (global_load_lds_dwordx4): block,
+// wave and output layout as k_jgram.  A slab of a super block is kept as
+// [octet (8)][column (128)][8 rows], i.e. the pool's own layout; one wave
+// load fills 32 columns of one octet.  The 16-byte halves of column c sit
+// swapped when bit 3 of c is set, so that the operand reads of 16
+// consecutive columns hit distinct banks.  Slab t + 1 loads into the other
+// buffer during slab t's products; one barrier per slab.  Octets past the
+// last row are written as zeros instead (the pool's padding rows inside the
+// last octet are zero).
+constexpr int kGO = 8 * kSB * 8;  // floats of one staged slab of a super block
+
+__device__ __forceinline__ void gram_tile_oct(const float *A, const float *Bm, int lane, int ti,
+                                              int tj, floatx16 &acc) {
+  const int li = lane & 31, h = lane >> 5;
+  const int sw = (li >> 3) & 1;
+  const float *pa = A + (32 * ti + li) * 8;
+  const float *pb = Bm + (32 * tj + li) * 8;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int off = (4 * h + (q >> 1)) * (kSB * 8) + 4 * ((q & 1) ^ sw);
+    const float4 a = *reinterpret_cast<const float4 *>(pa + off);
+    const float4 b = *reinterpret_cast<const float4 *>(pb + off);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, acc, 0, 0, 0);
+  }
+}
+
+__global__ void __launch_bounds__(kGT32)
+k_jgram_dma(const float *__restrict__ pool, int64_t n, int K, int nsb, int npairs,
+            int64_t rows_per_chunk, double *__restrict__ partial) {
+  // buffers 0 and 1 of both super blocks as separate LDS objects (the loads
+  // into one buffer are then disjoint from the reads of the other)
+  __shared__ __attribute__((aligned(1024))) float A0[kGO];
+  __shared__ __attribute__((aligned(1024))) float A1[kGO];
+  __shared__ __attribute__((aligned(1024))) float B0[kGO];
+  __shared__ __attribute__((aligned(1024))) float B1[kGO];
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int pair = int(lb % npairs);
+  const int64_t chunk = lb / npairs;
+  const int2 ab = pair_of(pair, nsb);
+  const bool diag = ab.x == ab.y;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  int ti = w >> 2, tj = w & 3;
+  bool on = true;
+  if (diag) {
+    const int t = w < 10 ? w : w - 10;
+    const int r = w < 10 ? (t < 4 ? 0 : t < 7 ? 1 : t < 9 ? 2 : 3)
+                         : (t < 1 ? 1 : t < 3 ? 2 : 3);
+    const int first = w < 10 ? (r == 0 ? 0 : r == 1 ? 4 : r == 2 ? 7 : 9)
+                             : (r == 1 ? 0 : r == 2 ? 1 : 3);
+    ti = r;
+    tj = w < 10 ? r + (t - first) : t - first;
+    on = w < 10;
+  }
+  const int64_t r0 = chunk * rows_per_chunk;
+  const int64_t r1 = r0 + rows_per_chunk < n ? r0 + rows_per_chunk : n;
+  const int64_t olast = (n - 1) >> 3;
+  // wave w stages the pieces 4w..4w+3 of a slab: piece = (super block,
+  // octet, 32-column group); a diagonal pair stages one super block
+  // (waves 0..7 fill super block a, waves 8..15 super block b: each branch
+  // writes one known LDS object)
+  auto piece_load = [&](int64_t r, float *S, int cb, int piece) __attribute__((always_inline)) {
+    const int o = (piece >> 2) & 7, cg = piece & 3;
+    float *dst = S + o * (kSB * 8) + cg * 256;
+    const int64_t og = (r >> 3) + o;
+    if (og <= olast) {
+      const int cl = 32 * cg + (lane >> 1);  // column within the super block
+      const int hf = (lane & 1) ^ ((cl >> 3) & 1);
+      const int col = cb + cl < K ? cb + cl : K - 1;
+      __builtin_amdgcn_global_load_lds(pool + (og * K + col) * 8 + 4 * hf, dst, 16, 0, 0);
+    } else {
+      *reinterpret_cast<float4 *>(dst + 4 * lane) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+  };
+  auto dma = [&](int64_t r, float *SA, float *SB) __attribute__((always_inline)) {
+    if (w < 8) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) piece_load(r, SA, ab.x * kSB, 4 * w + u);
+    } else if (!diag) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) piece_load(r, SB, ab.y * kSB, 4 * (w - 8) + u);
+    }
+  };
+  floatx16 acc;
+  double d[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) { acc[v] = 0.0f; d[v] = 0.0; }
+  auto mul = [&](const float *SA, const float *SB) __attribute__((always_inline)) {
+    // (two copies, so that each reads known LDS objects)
+    if (!on) return;
+    if (diag) gram_tile_oct(SA, SA, lane, ti, tj, acc);
+    else gram_tile_oct(SA, SB, lane, ti, tj, acc);
+  };
+  if (r0 < r1) {
+    dma(r0, A0, B0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  }
+  __syncthreads();
+  int slabs = 0;
+  auto flush = [&]() __attribute__((always_inline)) {
+    if (++slabs == 2) {  // float32 sums over 128 rows, then float64
+      slabs = 0;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) { d[v] += double(acc[v]); acc[v] = 0.0f; }
+    }
+  };
+  for (int64_t r = r0; r < r1; r += 128) {
+    if (r + 64 < r1) dma(r + 64, A1, B1);
+    mul(A0, B0);
+    flush();
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    if (r + 64 >= r1) break;
+    if (r + 128 < r1) dma(r + 128, A0, B0);
+    mul(A1, B1);
+    flush();
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+  }
+  double *out = partial + (chunk * npairs + pair) * (16 * 1024);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int i = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    const int j = lane & 31;
+    out[(ti * 4 + tj) * 1024 + i * 32 + j] = on ? d[v] + double(acc[v]) : 0.0;
+  }
+}
+
 // G[gi][gj] from the chunk-summed tiles (mirrored unless `cross`).
 __global__ void k_jgram_scatter(const double *__restrict__ sums, int nsb, int npairs, int K,
                                 int cross, double *__restrict__ G) {
@@ -1235,7 +1367,10 @@ hef_status gram_run(const void *pool, const void *poolB, int pool_type, int64_t 
   else if (pool_type != kPoolF32) {
     set_error("cross Gram of a BF16 pool is not supported");
     return HEF_ERR_UNSUPPORTED;
-  } else if (oct)
+  } else if (oct && !poolB)
+    k_jgram_dma<<<int64_t(p.npairs) * p.nchunks, kGT32, 0, s>>>(
+        reinterpret_cast<const float *>(pool), n, K, p.nsb, p.npairs, p.rows_per_chunk, partial);
+  else if (oct)
     k_jgram<true><<<int64_t(p.npairs) * p.nchunks, kGT32, 0, s>>>(
         reinterpret_cast<const float *>(pool), reinterpret_cast<const float *>(poolB), n, K, p.nsb,
         p.npairs, p.rows_per_chunk, partial);
