@@ -63,11 +63,10 @@ def lanczos_bytes(n, m, b, k, s=4):
 
 
 def gram_flops(n, K):
-    """Matrix-core flops of one joint Gram (upper 128x128 super tiles; the
-    diagonal ones computed on and above their 32x32 diagonal)."""
-    nsb = (K + 127) // 128
-    tiles = sum(10 if a == b else 16 for a in range(nsb) for b in range(a, nsb))
-    return 2.0 * n * 32 * 32 * tiles
+    """Matrix-core flops of one joint Gram: the 32x32 tiles on and above the
+    diagonal of the K x K Gram (T(T+1)/2 of them, T = ceil(K / 32))."""
+    T = (K + 31) // 32
+    return 2.0 * n * 32 * 32 * (T * (T + 1) // 2)
 
 
 def apply_flops(n, K):
@@ -448,9 +447,9 @@ def main():
         "k_lapply": roofline_entry("hbm", la_b, ms_of("lanczos_apply"), per.get("lanczos_apply", (0, 0))[1],
                                    PEAK_HBM_GBS, "GB/s", ["k_lapply"],
                                    traffic_of(["k_lapply"], (k + 1) * len(levels))),
-        "k_jgram": roofline_entry("mfma", jg_f, ms_of("orth_gram"), per.get("orth_gram", (0, 0))[1],
-                                  PEAK_FP32_MFMA, "TFLOP/s", ["k_jgram"],
-                                  traffic_of(["k_jgram"], len(levels))),
+        "k_jgram_dma": roofline_entry("mfma", jg_f, ms_of("orth_gram"),
+                                      per.get("orth_gram", (0, 0))[1], PEAK_FP32_MFMA, "TFLOP/s",
+                                      ["k_jgram_dma"], traffic_of(["k_jgram_dma"], len(levels))),
         "k_japply_dma": roofline_entry("mfma", ja_f, ms_of("orth_apply"),
                                        per.get("orth_apply", (0, 0))[1], PEAK_FP32_MFMA,
                                        "TFLOP/s", ["k_japply_dma"],

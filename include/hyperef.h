@@ -99,7 +99,11 @@ typedef struct {
   float drop_tol;        /* tau: relative Gram-Schmidt residual below which
                             a pool column is dropped (1e-3)                 */
   int32_t orth_passes;   /* joint Cholesky-QR passes, 1 or 2                */
-  int32_t ckpt_every;    /* Krylov checkpoint interval of the adjoint (5)   */
+  int32_t ckpt_every;    /* adjoint tape: 0 (default) or >= k keeps every
+                            Krylov step of the forward, so the reverse sweep
+                            recomputes nothing (about 8 (k-1)(2n+m)b bytes of
+                            workspace); 1..k-1 keeps checkpoints every
+                            ckpt_every steps and recomputes each segment    */
   uint32_t flags;        /* HEF_FLAG_*                                      */
   float target_nr;       /* node-reduction target of the level loop (Section
                             IV: NR = 60 % is a 2.5x reduction): with
@@ -111,7 +115,7 @@ typedef struct {
 
 /* Fills *p with the defaults: k=10, b=1, levels=1, percentile=0.5,
  * local_clustering=1, basis=FP32, seed=7, drop_tol=1e-3, orth_passes=1,
- * ckpt_every=5, flags=0, target_nr=0. */
+ * ckpt_every=0, flags=0, target_nr=0. */
 void hef_params_default(hef_params *p);
 
 /* Pool width K = 2*b*k (b*k with a single-expansion flag). */
@@ -319,8 +323,8 @@ hef_status hef_conductance(const hef_hypergraph *hg, const int32_t *label, int32
  * Section I): given dR = dL/dR (DEVICE [m] float32), writes dw = dL/dw
  * (DEVICE [m] float32).  Unless p->flags has HEF_FLAG_TAPED it first
  * recomputes the forward pass with the same start blocks (which must be the
- * ones the forward used; NULL = counter generator), keeping Krylov
- * checkpoints every p->ckpt_every steps; with HEF_FLAG_TAPED it uses the
+ * ones the forward used; NULL = counter generator), keeping the Krylov
+ * tape p->ckpt_every asks for; with HEF_FLAG_TAPED it uses the
  * tape that hef_resistance_taped left in `ws` (same hypergraph, params and
  * workspace, untouched in between).  Ties in a maximum take the lowest
  * column index and the lowest CSR position.  The derivative is that of the

@@ -33,7 +33,7 @@ class Params:
     seed: int = 7
     drop_tol: float = 1e-3
     orth_passes: int = 1
-    ckpt_every: int = 5
+    ckpt_every: int = 0           # 0: the adjoint tape keeps every Krylov step
     assume_valid: bool = False
     star_only: bool = False
     clique_only: bool = False

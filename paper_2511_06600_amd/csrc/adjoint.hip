@@ -713,6 +713,15 @@ void carve(Arena &a, int64_t n, int64_t m, int64_t nnz, const hef_params &p, Bwd
   w.yseg_s = a.take<float>(int64_t(seg) * Ns * B);
   w.yseg_c = a.take<float>(int64_t(seg) * n * B);
   w.tseg = a.take<float>(int64_t(seg) * spmm_scratch_floats(n, m, B));
+  if (seg == k) {
+    // one segment: the taped forward fills the step buffers itself (Y_j,
+    // its clique sums, V_j), so the reverse sweep recomputes nothing
+    w.tape.v_s = w.vseg_s;
+    w.tape.v_c = w.vseg_c;
+    w.tape.y_s = w.yseg_s;
+    w.tape.y_c = w.yseg_c;
+    w.tape.t = w.tseg;
+  }
   w.abar_s = a.take<float>(3 * Ns * B);
   w.abar_c = a.take<float>(3 * n * B);
   w.vb_s = a.take<float>(Ns * B);
@@ -973,7 +982,8 @@ hef_status reverse_sweep(const Level &L, const hef_params &p, const float *dR, f
       return w.vseg_c + size_t(j - j0 - 1) * n * B;
     };
     // recompute: Y_j = A V_{j-1} (with the clique sums T) and V_j, j < j1
-    for (int j = j0 + 1; j <= j1; ++j) {
+    // (nothing to do when the taped forward kept every step)
+    for (int j = j0 + 1; j <= j1 && !w.tape.y_s; ++j) {
       const int t = j - j0 - 1;
       float *ysj = w.yseg_s + size_t(t) * Ns * B;
       float *ycj = w.yseg_c + size_t(t) * n * B;

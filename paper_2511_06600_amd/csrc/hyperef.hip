@@ -277,7 +277,7 @@ void hef_params_default(hef_params *p) {
   p->seed = 7;
   p->drop_tol = 1e-3f;
   p->orth_passes = 1;
-  p->ckpt_every = 5;
+  p->ckpt_every = 0;
   p->flags = 0;
   p->target_nr = 0.0f;
 }

@@ -682,58 +682,66 @@ hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double
     return HEF_OK;
   };
 
-  // indices into the rolling buffers: prev, cur, y, next
-  int ip = 0, ic = 1, iy = 2, in = 3;
+  // the rolling buffers: prev, cur, y, next (as pointers: with a full tape
+  // Y_j and V_j live in the tape's step buffers instead)
+  const bool full = tape && seg == k && tape->y_s;
+  const size_t scr = spmm_scratch_floats(n, m, B);
   const int K = out.K;
   const int64_t bk = int64_t(B) * k;
   // V_0 = X R^-1 (no pool write)
   if (use_star)
-    HEF_HIP(hipMemcpyAsync(sb[iy], start_star, Ns * B * sizeof(float), hipMemcpyDeviceToDevice, s));
+    HEF_HIP(hipMemcpyAsync(sb[2], start_star, Ns * B * sizeof(float), hipMemcpyDeviceToDevice, s));
   if (use_clique)
-    HEF_HIP(hipMemcpyAsync(cb[iy], start_clique, n * B * sizeof(float), hipMemcpyDeviceToDevice, s));
-  HEF_TRY(lgram2(B, nullptr, nullptr, use_star ? sb[iy] : nullptr, Ns, ps, Gs, nullptr, nullptr,
-                 use_clique ? cb[iy] : nullptr, n, pc, Gc, s));
+    HEF_HIP(hipMemcpyAsync(cb[2], start_clique, n * B * sizeof(float), hipMemcpyDeviceToDevice, s));
+  HEF_TRY(lgram2(B, nullptr, nullptr, use_star ? sb[2] : nullptr, Ns, ps, Gs, nullptr, nullptr,
+                 use_clique ? cb[2] : nullptr, n, pc, Gc, s));
   {
     TimedScope ts(kStLanczosSolve, s);
     HEF_TRY(lsolve_launch(G, B, tau, t_of(0), drops, r_of(0), s));
   }
   {
-    const ApplySide as{nullptr, nullptr, sb[iy], t_of(0), sb[in], use_star ? Ns : 0, 0};
-    const ApplySide ac{nullptr, nullptr, cb[iy], t_of(0) + C * B, cb[in], use_clique ? n : 0, 0};
+    const ApplySide as{nullptr, nullptr, sb[2], t_of(0), sb[3], use_star ? Ns : 0, 0};
+    const ApplySide ac{nullptr, nullptr, cb[2], t_of(0) + C * B, cb[3], use_clique ? n : 0, 0};
     HEF_TRY(lapply2(B, as, ac, nullptr, 0, 0, K, s));
   }
-  HEF_TRY(checkpoint(0, nullptr, sb[in], nullptr, cb[in]));
-  // rotate: cur <- next; prev stays "absent" for step 1
-  std::swap(ic, in);
-  bool have_prev = false;
-
+  HEF_TRY(checkpoint(0, nullptr, sb[3], nullptr, cb[3]));
+  float *sp = nullptr, *sc = sb[3], *cp = nullptr, *cc = cb[3];  // prev (absent), cur
+  // the rolling buffer that is neither prev, cur nor y (non-full runs)
+  auto spare = [&](float *const *buf, const float *p, const float *c, const float *y) {
+    for (int i = 0; i < 4; ++i)
+      if (buf[i] != p && buf[i] != c && buf[i] != y) return buf[i];
+    return buf[0];
+  };
   for (int j = 1; j <= k; ++j) {
-    HEF_TRY(spmm_apply(L, st, B, use_star ? sb[ic] : nullptr, use_star ? sb[iy] : nullptr,
-                       use_clique ? cb[ic] : nullptr, use_clique ? cb[iy] : nullptr, tb, s));
-    HEF_TRY(lgram2(B, have_prev ? sb[ip] : nullptr, sb[ic], use_star ? sb[iy] : nullptr, Ns, ps,
-                   Gs, have_prev ? cb[ip] : nullptr, cb[ic], use_clique ? cb[iy] : nullptr, n, pc,
-                   Gc, s));
+    float *sy = full ? tape->y_s + size_t(j - 1) * Ns * B : sb[2];
+    float *cy = full ? tape->y_c + size_t(j - 1) * n * B : cb[2];
+    float *tj = full ? tape->t + size_t(j - 1) * scr : tb;
+    HEF_TRY(spmm_apply(L, st, B, use_star ? sc : nullptr, use_star ? sy : nullptr,
+                       use_clique ? cc : nullptr, use_clique ? cy : nullptr, tj, s));
+    HEF_TRY(lgram2(B, sp, sc, use_star ? sy : nullptr, Ns, ps, Gs, cp, cc,
+                   use_clique ? cy : nullptr, n, pc, Gc, s));
     double *Tj = t_of(j);
     {
       TimedScope ts(kStLanczosSolve, s);
       HEF_TRY(lsolve_launch(G, B, tau, Tj, drops, r_of(j), s));
     }
+    // V_j: a tape step buffer (j < k, full tape) or the spare rolling buffer
+    float *sn = (full && j < k) ? tape->v_s + size_t(j - 1) * Ns * B
+                                : spare(sb, sp, sc, full ? sb[2] : sy);
+    float *cn = (full && j < k) ? tape->v_c + size_t(j - 1) * n * B
+                                : spare(cb, cp, cc, full ? cb[2] : cy);
     const int64_t col_s = (j - 1) * int64_t(B);
     const int64_t col_c = (use_star ? bk : 0) + (j - 1) * int64_t(B);
     {
-      const ApplySide as{have_prev ? sb[ip] : nullptr, sb[ic], sb[iy], Tj, sb[in],
-                         use_star ? Ns : 0, int(col_s)};
-      const ApplySide ac{have_prev ? cb[ip] : nullptr, cb[ic], cb[iy], Tj + C * B, cb[in],
-                         use_clique ? n : 0, int(col_c)};
+      const ApplySide as{sp, sc, sy, Tj, sn, use_star ? Ns : 0, int(col_s)};
+      const ApplySide ac{cp, cc, cy, Tj + C * B, cn, use_clique ? n : 0, int(col_c)};
       HEF_TRY(lapply2(B, as, ac, out.pool, out.pool_type, n, K, s));
     }
-    HEF_TRY(checkpoint(j, sb[ic], sb[in], cb[ic], cb[in]));
-    // rotate prev <- cur <- next, next <- old prev
-    const int old_prev = ip;
-    ip = ic;
-    ic = in;
-    in = old_prev;
-    have_prev = true;
+    HEF_TRY(checkpoint(j, sc, sn, cc, cn));
+    sp = sc;
+    sc = sn;
+    cp = cc;
+    cc = cn;
   }
   ws.reset(mk);
   return HEF_OK;

@@ -45,13 +45,19 @@ size_t krylov_ws_bytes(int64_t n, int64_t m, int B);
 //  * Rinv[j] (j = 0..k): the two whole C x C matrices R^-1, float64;
 //  * ck_star / ck_clique: checkpoint pairs (V_{sc-1}, V_{sc}) for segments
 //    s = 0..nseg-1 of `seg` steps (nseg = ceil(k/seg)); slot s holds
-//    2 blocks of (n+m) x B (star) or n x B (clique); V_{-1} is zero.
+//    2 blocks of (n+m) x B (star) or n x B (clique); V_{-1} is zero;
+//  * with one segment (seg = k) and the five step buffers set, every step
+//    itself: y_s / y_c[j-1] = Y_j = A V_{j-1} (steps 1..k), t[j-1] its SpMM
+//    scratch (the clique sums), v_s / v_c[j-1] = V_j (steps 1..k-1).  The
+//    forward then writes its blocks there and the reverse sweep recomputes
+//    nothing.
 struct KrylovTape {
   int seg = 0;
   double *T = nullptr;
   double *Rinv = nullptr;
   float *ck_star = nullptr;
   float *ck_clique = nullptr;
+  float *v_s = nullptr, *v_c = nullptr, *y_s = nullptr, *y_c = nullptr, *t = nullptr;
 };
 
 // k steps of block Lanczos per expansion (three-term recurrence; each new

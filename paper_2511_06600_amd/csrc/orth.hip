@@ -397,10 +397,13 @@ k_jgram(const float *__restrict__ pool, const float *__restrict__ poolB, int64_t
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = tid >> 6;
-  // Off-diagonal pairs: wave w owns tile (w / 4, w % 4).  Diagonal pairs:
-  // waves 0..9 own the ten tiles on or above the diagonal, row by row, and
-  // waves 10..15 only write zeros for the six tiles below it.
-  int ti = w >> 2, tj = w & 3;
+  // Off-diagonal and cross pairs: wave w owns tile (w / 4, (w - w / 4) % 4),
+  // so that the tiles of one row or one column of the super tile sit on the
+  // four SIMDs (wave w runs on SIMD w % 4) and tiles past column K, which are
+  // skipped, leave every SIMD the same share.  Diagonal pairs: waves 0..9
+  // own the ten tiles on or above the diagonal, row by row, and waves 10..15
+  // only write zeros for the six tiles below it.
+  int ti = w >> 2, tj = ((w & 3) - (w >> 2)) & 3;
   bool on = true;
   if (diag) {
     const int t = w < 10 ? w : w - 10;
@@ -412,6 +415,7 @@ k_jgram(const float *__restrict__ pool, const float *__restrict__ poolB, int64_t
     tj = w < 10 ? r + (t - first) : t - first;
     on = w < 10;
   }
+  on = on && ab.x * kSB + 32 * ti < K && ab.y * kSB + 32 * tj < K;
   // the first half of the block stages super block a, the second half b
   // (a diagonal pair stages one super block)
   const bool loader = !diag || tid < kGT32 / 2;
@@ -517,7 +521,7 @@ k_jgram_dma(const float *__restrict__ pool, int64_t n, int K, int nsb, int npair
   const bool diag = ab.x == ab.y;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-  int ti = w >> 2, tj = w & 3;
+  int ti = w >> 2, tj = ((w & 3) - (w >> 2)) & 3;  // (tiles of a row or column on 4 SIMDs)
   bool on = true;
   if (diag) {
     const int t = w < 10 ? w : w - 10;
@@ -529,6 +533,7 @@ k_jgram_dma(const float *__restrict__ pool, int64_t n, int K, int nsb, int npair
     tj = w < 10 ? r + (t - first) : t - first;
     on = w < 10;
   }
+  on = on && ab.x * kSB + 32 * ti < K && ab.y * kSB + 32 * tj < K;  // tiles past K skipped
   const int64_t r0 = chunk * rows_per_chunk;
   const int64_t r1 = r0 + rows_per_chunk < n ? r0 + rows_per_chunk : n;
   const int64_t olast = (n - 1) >> 3;
@@ -635,6 +640,7 @@ constexpr int kAM = 128, kAN = 128, kAK = 32;
 constexpr int kALDA = kAK + 1;   // A chunk [128][33]
 constexpr int kALDB = kAN + 1;   // B chunk [32][129]
 
+template <bool RAW>
 __global__ void __launch_bounds__(kAT32)
 k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oct, int64_t n,
          int K, int Kp, const float *__restrict__ Rinv32, int ncb, int full, int accumulate) {
@@ -651,6 +657,7 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oc
   // the column quarter of wave w rotates with the block, so that the waves
   // which stop early (below) fall on every SIMD in turn
   const int wr = (w >> 2) * 64, wc = int(((w & 3) + lb) & 3) * 32;
+  const bool won = col0 + wc < K;  // a wave whose columns are all past K idles
   floatx16 acc[2][1];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -667,11 +674,22 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oc
   // thread), B = 32 rows x 128 columns of Rinv32 (4 float4 per thread)
   float ra[1][8];
   float4 rb[2];
+  // RAW (an FP32 row-major V, K % 8 == 0): loads at clamped addresses,
+  // masked in stash, which keeps them in flight during the products
   auto fetch = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int h = 0; h < 1; ++h) {
       const int g = tid + kAT32 * h;
-      if (oct) {
+      if (RAW) {
+        const int r = g / (kAK / 8), c8 = (g % (kAK / 8)) * 8;
+        const int64_t row = row0 + r < n ? row0 + r : n - 1;
+        const int c = k0 + c8 < K ? k0 + c8 : K - 8;
+        const float *p = reinterpret_cast<const float *>(V) + row * K + c;
+        const float4 x = *reinterpret_cast<const float4 *>(p);
+        const float4 y = *reinterpret_cast<const float4 *>(p + 4);
+        ra[h][0] = x.x; ra[h][1] = x.y; ra[h][2] = x.z; ra[h][3] = x.w;
+        ra[h][4] = y.x; ra[h][5] = y.y; ra[h][6] = y.z; ra[h][7] = y.w;
+      } else if (oct) {
         const int o = g / kAK, c = g % kAK;
         load8oct(V, pool_type, row0 + 8 * o, n, k0 + c, K, ra[h]);
       } else {
@@ -683,9 +701,8 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oc
     for (int h = 0; h < 2; ++h) {
       const int g = tid + kAT32 * h;
       const int r = g / (kAN / 4), c4 = (g % (kAN / 4)) * 4;
-      const int kk = k0 + r, cc = col0 + c4;
-      rb[h] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (kk < kend && cc < Kp) rb[h] = *reinterpret_cast<const float4 *>(Rinv32 + int64_t(kk) * Kp + cc);
+      const int kk = k0 + r < kend ? k0 + r : kend - 1, cc = col0 + c4 < Kp ? col0 + c4 : Kp - 4;
+      rb[h] = *reinterpret_cast<const float4 *>(Rinv32 + int64_t(kk) * Kp + cc);
     }
   };
   auto stash = [&](int k0) __attribute__((always_inline)) {
@@ -706,8 +723,10 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oc
     for (int h = 0; h < 2; ++h) {
       const int g = tid + kAT32 * h;
       const int r = g / (kAN / 4), c4 = (g % (kAN / 4)) * 4;
+      const bool ok = k0 + r < kend && col0 + c4 < Kp;
       float *d = Bs + r * kALDB + c4;
-      d[0] = rb[h].x; d[1] = rb[h].y; d[2] = rb[h].z; d[3] = rb[h].w;
+      d[0] = ok ? rb[h].x : 0.0f; d[1] = ok ? rb[h].y : 0.0f;
+      d[2] = ok ? rb[h].z : 0.0f; d[3] = ok ? rb[h].w : 0.0f;
     }
   };
   fetch(0);
@@ -716,7 +735,7 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oc
     stash(k0);
     __syncthreads();
     if (k0 + kAK < kend) fetch(k0 + kAK);
-    if (k0 >= kw) continue;
+    if (k0 >= kw || !won) continue;
 #pragma unroll 4
     for (int s = 0; s < kAK / 2; ++s) {
       const int kk = 2 * s + (lane >> 5);
@@ -732,6 +751,26 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oc
           acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[a], b_op[b], acc[a][b], 0, 0, 0);
     }
   }
+  if (accumulate) {  // float32 only: the tile's old values are read first, all at once
+    float *Qf = reinterpret_cast<float *>(Q);
+    const int col = col0 + wc + (lane & 31);
+    const int cc = col < K ? col : K - 1;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      float old[16];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = row0 + wr + 32 * a + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        old[v] = Qf[(row < n ? row : n - 1) * K + cc];
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = row0 + wr + 32 * a + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        if (row < n && col < K) Qf[row * K + col] = old[v] + acc[a][0][v];
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -741,9 +780,7 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oc
         const int64_t row = row0 + wr + 32 * a + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         const int col = col0 + wc + 32 * b + (lane & 31);
         if (row < n && col < K) {
-          if (accumulate)  // float32 only
-            reinterpret_cast<float *>(Q)[row * K + col] += acc[a][b][v];
-          else if (pool_type == kPoolF32)
+          if (pool_type == kPoolF32)
             reinterpret_cast<float *>(Q)[row * K + col] = acc[a][b][v];
           else
             reinterpret_cast<uint16_t *>(Q)[row * K + col] = f2bf(acc[a][b][v]);
@@ -1405,8 +1442,12 @@ hef_status apply_run(const void *V, void *Q, int pool_type, int64_t n, int K, in
     return HEF_OK;
   }
   const int ncb = (K + kAN - 1) / kAN;
-  k_japply<<<cdiv(n, kAM) * ncb, kAT32, 0, s>>>(V, Q, pool_type, oct, n, K, Kp, Rinv32, ncb, full,
-                                              accumulate);
+  if (!oct && pool_type == kPoolF32 && (K & 7) == 0)
+    k_japply<true><<<cdiv(n, kAM) * ncb, kAT32, 0, s>>>(V, Q, pool_type, oct, n, K, Kp, Rinv32,
+                                                      ncb, full, accumulate);
+  else
+    k_japply<false><<<cdiv(n, kAM) * ncb, kAT32, 0, s>>>(V, Q, pool_type, oct, n, K, Kp, Rinv32,
+                                                       ncb, full, accumulate);
   HEF_LAUNCH_CHECK();
   return HEF_OK;
 }

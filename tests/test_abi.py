@@ -33,7 +33,7 @@ def test_params_default_and_pool_width():
     lib = _lib.load()
     p = _lib.HefParams()
     lib.hef_params_default(C.byref(p))
-    assert (p.k, p.b, p.levels, p.orth_passes, p.ckpt_every, p.seed) == (10, 1, 1, 1, 5, 7)
+    assert (p.k, p.b, p.levels, p.orth_passes, p.ckpt_every, p.seed) == (10, 1, 1, 1, 0, 7)
     assert abs(p.percentile - 0.5) < 1e-7 and abs(p.drop_tol - 1e-3) < 1e-9
     assert lib.hef_pool_width(C.byref(p)) == 20
     p.b, p.k = 8, 30
