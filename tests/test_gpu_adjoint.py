@@ -152,6 +152,20 @@ def test_full_size_gradient_matches_oracle():
     say(f"  L gpu {L:.9e} oracle {float(ref['L']):.9e}; dw norm-rel err vs oracle {err:.2e}")
     assert abs(L - float(ref["L"])) <= 1e-4 * abs(float(ref["L"]))
     assert err < 1e-3
+    # central differences of the float64 forward on 64 weights (written by
+    # tests/golden/make_grad200k_fd.py, oracle only): the same statistics
+    # as the oracle gradient meets, with the FP32 path's own error on top
+    fd = np.load(os.path.join(os.path.dirname(__file__), "golden", "grad200k_fd.npz"))
+    idx, q, cs = fd["idx"], fd["fd"], fd["column_switches"]
+    g_idx = dw[idx]
+    rel = np.abs(q - g_idx) / np.abs(g_idx)
+    quiet = cs == 0
+    say(f"  vs FD on {len(idx)} weights: median rel {np.median(rel):.2e}, "
+        f"within 2e-2 {(rel <= 2e-2).mean():.2f}, quiet {quiet.sum()}")
+    assert np.linalg.norm((q - g_idx)[quiet]) <= 2e-3 * np.linalg.norm(g_idx[quiet])
+    assert np.median(rel) <= 2e-3
+    assert (rel <= 2e-2).mean() >= 0.9
+    assert np.corrcoef(q, g_idx)[0, 1] >= 0.999
 
 
 def test_wide_pool_with_more_than_2_31_score_entries():
