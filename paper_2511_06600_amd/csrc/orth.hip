@@ -39,59 +39,110 @@ constexpr int kPS = kPW + 1;  // LDS row stride of a panel
 constexpr int kMaxPB = 16;    // 32-column blocks of the widest pool (K <= 512)
 
 // Right-looking: A holds G minus the contributions of the finished panels
-// (lower triangle).  Panel [c0, c0+w) is factored by one workgroup in LDS
-// (32 column steps); k_chol_update then subtracts its columns from the
-// trailing matrix, tile by tile, so every entry sees its subtractions in
-// ascending column order.
-__global__ void __launch_bounds__(1024)
+// (lower triangle).  Panel [c0, c0+w) is factored by k_chol_panel;
+// k_chol_update then subtracts its columns from the trailing matrix, tile
+// by tile, so every entry sees its subtractions in ascending column order.
+//
+// k_chol_panel: the first wave of every workgroup factors the w x w
+// diagonal block in registers (lane r holds row r; the pivot and the
+// normalised column entries reach the other lanes by readlane, so the 32
+// column steps need no barrier), which fixes the drop decisions and
+// pivots; then each thread carries one panel row below the block through
+// the same column steps (divide by the pivot, subtract the row's multiple of
+// every later column), so each entry of L sees the same operations in the
+// same order as a column-by-column factorisation of the whole panel.
+// Workgroup 0 also writes the diagonal block, keep and rho.
+constexpr int kCT = 256;  // panel threads: one row below the diagonal block each
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(u), l);
+  const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(u >> 32), l);
+  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+
+__global__ void __launch_bounds__(kCT)
 k_chol_panel(const double *__restrict__ A, const double *__restrict__ G, int K, int c0,
              double tau, double *__restrict__ LT, int32_t *__restrict__ keep,
              const int32_t *__restrict__ force_keep, double *__restrict__ rho) {
-  extern __shared__ double pan[];  // [K - c0][kPS]
-  __shared__ int s_keep;
-  __shared__ double s_ref[kPW];     // G_jj of the panel's columns
-  __shared__ int s_force[kPW];
+  __shared__ double Ln[kPW][kPS];  // the block's L (pivot on the diagonal)
+  __shared__ double s_piv[kPW];
+  __shared__ int s_kp[kPW];
   const int t = threadIdx.x;
   const int w = K - c0 < kPW ? K - c0 : kPW;
   const int nr = K - c0;
-  // thread t works on panel column t % 32 and rows t / 32 + 32 k
-  const int tc = t & (kPW - 1), tr = t >> 5;
-  if (tc < w)
-    for (int i = tr; i < nr; i += 1024 / kPW)
-      pan[i * kPS + tc] = i >= tc ? A[int64_t(c0 + i) * K + c0 + tc] : 0.0;
-  if (t < w) {
-    s_ref[t] = G[int64_t(c0 + t) * K + c0 + t];
-    s_force[t] = force_keep ? force_keep[c0 + t] : 1;
+  if (t < 64) {
+    const int r = t & (kPW - 1);
+    double x[kPW];
+#pragma unroll
+    for (int j = 0; j < kPW; ++j)
+      x[j] = (r < w && j <= r) ? A[int64_t(c0 + r) * K + c0 + j] : 0.0;
+    const double ref = r < w ? G[int64_t(c0 + r) * K + c0 + r] : 0.0;
+    const int frc = r < w ? (force_keep ? force_keep[c0 + r] : 1) : 0;
+    double dkeep = 0.0, pkeep = 0.0;  // lane r: column r's Schur pivot and L_rr
+    int kkeep = 0;
+#pragma unroll
+    for (int jj = 0; jj < kPW; ++jj) {
+      if (jj < w) {
+        const double d = readlane_f64(x[jj], jj);
+        const double rf = readlane_f64(ref, jj);
+        int kp = (rf > 0.0 && d > tau * tau * rf) ? 1 : 0;
+        if (!__builtin_amdgcn_readlane(frc, jj)) kp = 0;
+        const double piv = kp ? sqrt(d) : 0.0;
+        const double lv = (kp && r > jj && r < w) ? x[jj] / piv : 0.0;
+        if (r == jj) {
+          dkeep = d;
+          pkeep = piv;
+          kkeep = kp;
+        }
+        // column jj of L below the pivot (entries above the diagonal of the
+        // block are never read)
+        x[jj] = r == jj ? piv : lv;
+        if (kp) {
+#pragma unroll
+          for (int tc = jj + 1; tc < kPW; ++tc)
+            if (tc < w) x[tc] = __builtin_fma(-lv, readlane_f64(lv, tc), x[tc]);
+        }
+      }
+    }
+    if (t < kPW) {
+#pragma unroll
+      for (int j = 0; j < kPW; ++j) Ln[t][j] = j <= t ? x[j] : 0.0;
+      s_piv[t] = pkeep;
+      s_kp[t] = kkeep;
+      if (blockIdx.x == 0 && t < w) {
+#pragma unroll
+        for (int j = 0; j < kPW; ++j)
+          if (j <= t) LT[int64_t(c0 + j) * K + c0 + t] = x[j];
+        keep[c0 + t] = kkeep;
+        // relative Gram-Schmidt residual |R_jj| / ||V_j|| of a kept column
+        if (rho) rho[c0 + t] = kkeep ? sqrt(dkeep / ref) : 0.0;
+      }
+    }
   }
   __syncthreads();
-  for (int jj = 0; jj < w; ++jj) {
-    if (t == 0) {
-      const double d = pan[jj * kPS + jj];
-      const double ref = s_ref[jj];
-      int kp = (ref > 0.0 && d > tau * tau * ref) ? 1 : 0;
-      if (!s_force[jj]) kp = 0;
-      keep[c0 + jj] = kp;
-      // relative Gram-Schmidt residual |R_jj| / ||V_j|| of a kept column
-      if (rho) rho[c0 + jj] = kp ? sqrt(d / ref) : 0.0;
-      s_keep = kp;
-      pan[jj * kPS + jj] = kp ? sqrt(d) : 0.0;
+  // rows below the diagonal block
+  const int i = w + int(blockIdx.x) * kCT + t;
+  if (i >= nr) return;
+  double x[kPW];
+  const double *ar = A + int64_t(c0 + i) * K + c0;
+#pragma unroll
+  for (int j = 0; j < kPW; ++j) x[j] = j < w ? ar[j] : 0.0;
+#pragma unroll
+  for (int jj = 0; jj < kPW; ++jj) {
+    if (jj < w) {
+      const int kp = s_kp[jj];
+      x[jj] = kp ? x[jj] / s_piv[jj] : 0.0;
+      if (kp) {
+#pragma unroll
+        for (int tc = jj + 1; tc < kPW; ++tc)
+          if (tc < w) x[tc] = __builtin_fma(-x[jj], Ln[tc][jj], x[tc]);
+      }
     }
-    __syncthreads();
-    const int kp = s_keep;
-    const double piv = pan[jj * kPS + jj];
-    for (int i = jj + 1 + t; i < nr; i += 1024)
-      pan[i * kPS + jj] = kp ? pan[i * kPS + jj] / piv : 0.0;
-    __syncthreads();
-    if (kp && tc > jj && tc < w) {
-      const double lq = pan[tc * kPS + jj];
-      for (int i = tr; i < nr; i += 1024 / kPW)
-        if (i >= tc) pan[i * kPS + tc] -= pan[i * kPS + jj] * lq;
-    }
-    __syncthreads();
   }
-  if (tc < w)
-    for (int i = tr; i < nr; i += 1024 / kPW)
-      if (i >= tc) LT[int64_t(c0 + tc) * K + c0 + i] = pan[i * kPS + tc];
+#pragma unroll
+  for (int j = 0; j < kPW; ++j)
+    if (j < w) LT[int64_t(c0 + j) * K + c0 + i] = x[j];
 }
 
 // A[i][q] -= sum_{l in [c0, c0+w)} L[i][l] L[q][l] for c0+w <= q <= i < K:
@@ -1544,15 +1595,13 @@ hef_status orthonormalize_pool(void *P, void *out, int pool_type, int64_t n, int
       HEF_HIP(hipMemsetAsync(Rinv, 0, sizeof(double) * Kp * Kp, s));
       HEF_HIP(hipMemsetAsync(Rinv32, 0, sizeof(float) * Kp * Kp, s));
       HEF_HIP(hipMemsetAsync(RinvT32, 0, sizeof(float) * Kp * Kp, s));
-      HEF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_chol_panel),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_c)));
       HEF_HIP(hipMemcpyAsync(A, G, sizeof(double) * K * K, hipMemcpyDeviceToDevice, s));
       HEF_HIP(hipMemsetAsync(LT, 0, sizeof(double) * K * K, s));
       for (int c0 = 0; c0 < K; c0 += kPW) {
         const int w = K - c0 < kPW ? K - c0 : kPW;
-        k_chol_panel<<<1, 1024, size_t(K - c0) * kPS * sizeof(double), s>>>(
-            A, G, K, c0, tau, LT, keep, pass == 0 ? nullptr : keep,
-            pass == 0 ? rho_out : nullptr);
+        const int nb = K - c0 - w > 0 ? int(cdiv(K - c0 - w, kCT)) : 1;
+        k_chol_panel<<<nb, kCT, 0, s>>>(A, G, K, c0, tau, LT, keep, pass == 0 ? nullptr : keep,
+                                        pass == 0 ? rho_out : nullptr);
         const int nt = (K - c0 - w + kPW - 1) / kPW;
         if (nt > 0) k_chol_update<<<nt * (nt + 1) / 2, 256, 0, s>>>(A, LT, K, c0, w);
       }
