@@ -180,75 +180,107 @@ k_chol_update(double *__restrict__ A, const double *__restrict__ LT, int K, int 
 // X_JJ = L_JJ^-1, then X_IJ = -L_II^-1 sum_{M=J}^{I-1} L_IM X_MJ for I > J.
 // Rows and columns of dropped pivots are zero.  Writes Rinv = X^T
 // (row-major, Kp x Kp, float64 and float32; entries outside stay as set).
+//
+// The block sum runs on the float64 matrix cores: wave w takes the 16 x 16
+// tile w & 3 of the 32 x 32 sum over the k quarter w >> 2 of [j0, i0) (A
+// operands straight from L in global memory, 16 at a time ahead of their
+// products; B operands from the finished rows of X in LDS), and the four
+// quarters are added in a fixed order.  The solve with L_II is a forward
+// substitution: thread (i, j) keeps row i of column j (a column's 32 rows in
+// half a wave); at step l the lane of row l scales its entry by the pivot's
+// reciprocal and the other lanes take it by readlane.
+constexpr int kTK = 16;  // k steps (of 4) whose A operands are loaded together
+
+__device__ __forceinline__ double half_readlane_f64(double v, int l, int lane) {
+  return lane < 32 ? readlane_f64(v, l) : readlane_f64(v, l + 32);
+}
+
 __global__ void __launch_bounds__(1024)
 k_jtrinv(const double *__restrict__ LT, const int32_t *__restrict__ keep, int K, int Kp,
          double *__restrict__ Rinv, float *__restrict__ Rinv32, float *__restrict__ RinvT32) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
   extern __shared__ double X[];  // [K][kPS]: rows of the column block J
   __shared__ double T[kPW * kPS];
   __shared__ double Lb[kPW * kPS];
   __shared__ int kr[kPW], kc[kPW];
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int J = blockIdx.x;
   const int j0 = J * kPW;
   const int wj = K - j0 < kPW ? K - j0 : kPW;
   const int nb = (K + kPW - 1) / kPW;
   for (int e = t; e < K * kPS; e += 1024) X[e] = 0.0;
-  __syncthreads();
+  if (t < kPW) kc[t] = t < wj ? keep[j0 + t] : 0;
   for (int I = J; I < nb; ++I) {
     const int i0 = I * kPW;
     const int wi = K - i0 < kPW ? K - i0 : kPW;
-    // T = -sum_{m in [j0, i0)} L[i0+i][m] X[m][j]   (zero for I == J), the
-    // rows of L staged in LDS one 32 x 32 block at a time; every block of
-    // the row is loaded into registers up front (K <= 512: at most 16)
+    // L_II and the keep flags are loaded here and stored to LDS after the
+    // block sum, so their latency overlaps that of the A operands
+    const int lmm = t / kPW, lii = t % kPW;
+    const int lcl = lii < wi && lmm < wi;
+    const double lbv = LT[int64_t(i0 + (lcl ? lmm : 0)) * K + i0 + (lcl ? lii : 0)];
+    const int krv = t < kPW ? keep[i0 + (t < wi ? t : 0)] : 0;
+    // S = sum_{m in [j0, i0)} L[i0+i][m] X[m][j]; T = delta_IJ - S
+    const int tile = wv & 3, ks = wv >> 2;
+    const int ti = tile >> 1, tj = tile & 1;
+    const int r16 = lane & 15, k4 = lane >> 4;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
     {
-      const int j = t / kPW, i = t % kPW;
-      const int mm = t / kPW, ii = t % kPW;
-      double acc = (I == J && i == j) ? 1.0 : 0.0;
-      double lreg[kMaxPB];
+      const int S = (i0 - j0) / 4;  // k steps of 4
+      const int s0 = S * ks / 4, s1 = S * (ks + 1) / 4;
+      const int gi = i0 + 16 * ti + r16;
+      const int gc = gi < K ? gi : K - 1;  // rows past K: clamped load, zero operand
+      const bool rok = gi < K;
+      for (int sb = s0; sb < s1; sb += kTK) {
+        double a[kTK];
 #pragma unroll
-      for (int bb = 0; bb < kMaxPB; ++bb)
-        if (bb < I - J) lreg[bb] = ii < wi ? LT[int64_t(j0 + bb * kPW + mm) * K + i0 + ii] : 0.0;
+        for (int u = 0; u < kTK; ++u) {
+          const int ss = sb + u < s1 ? sb + u : s1 - 1;
+          a[u] = LT[int64_t(j0 + 4 * ss + k4) * K + gc];
+        }
 #pragma unroll
-      for (int bb = 0; bb < kMaxPB; ++bb) {
-        if (bb < I - J) {
-          const int M0 = j0 + bb * kPW;
-          __syncthreads();
-          Lb[ii * kPS + mm] = lreg[bb];
-          __syncthreads();
-          if (i < wi && j < wj) {
-            for (int m2 = 0; m2 < kPW; ++m2) acc -= Lb[i * kPS + m2] * X[(M0 + m2) * kPS + j];
+        for (int u = 0; u < kTK; ++u) {
+          if (sb + u < s1) {
+            const double b = X[(j0 + 4 * (sb + u) + k4) * kPS + 16 * tj + r16];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(rok ? a[u] : 0.0, b, acc, 0, 0, 0);
           }
         }
       }
-      T[i * kPS + j] = acc;
     }
-    __syncthreads();
-    // solve L_II X_IJ = T by forward substitution: L_II staged in LDS,
-    // thread (i, j) keeps row i of column j, a column's 32 rows in one wave;
-    // step l fixes x_l and removes it from the rows below (the same
-    // products, subtracted in the same ascending order as a row-by-row
-    // substitution)
-    {
-      const int mm = t / kPW, ii = t % kPW;
-      Lb[ii * kPS + mm] = (ii < wi && mm < wi) ? LT[int64_t(i0 + mm) * K + i0 + ii] : 0.0;
-      if (t < kPW) {
-        kr[t] = t < wi ? keep[i0 + t] : 0;
-        kc[t] = t < wj ? keep[j0 + t] : 0;
+    // quarters added in order ks = 0, 1, 2, 3 (accumulator r of a lane is
+    // tile row 4 r + (lane >> 4), column lane & 15)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      __syncthreads();
+      if (q == 0) {
+        Lb[lii * kPS + lmm] = lcl ? lbv : 0.0;
+        if (t < kPW) kr[t] = t < wi ? krv : 0;
+      }
+      if (ks == q) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * ti + 4 * r + k4, j = 16 * tj + r16;
+          const double v = q == 0 ? acc[r] : T[i * kPS + j] + acc[r];
+          T[i * kPS + j] = q < 3 ? v : (I == J && i == j ? 1.0 : 0.0) - v;
+        }
       }
     }
     __syncthreads();
+    // solve L_II X_IJ = T
     {
       const int j = t / kPW, i = t % kPW;
-      double acc = T[i * kPS + j];
-      for (int l = 0; l < wi; ++l) {
-        if (i == l) {
-          const double x = (kc[j] && kr[l]) ? acc / Lb[l * kPS + l] : 0.0;
-          if (j < wj) X[(i0 + l) * kPS + j] = x;
-          T[l * kPS + j] = x;
+      double a = T[i * kPS + j];
+      const double dinv = (kc[j] && kr[i]) ? 1.0 / Lb[i * kPS + i] : 0.0;
+      double xi = 0.0;
+#pragma unroll
+      for (int l = 0; l < kPW; ++l) {
+        if (l < wi) {
+          const double own = a * dinv;  // x_l on the lane of row l
+          if (i == l) xi = own;
+          const double xl = half_readlane_f64(own, l, lane);
+          if (i > l) a = __builtin_fma(-Lb[i * kPS + l], xl, a);
         }
-        wave_sync();
-        if (i > l) acc -= Lb[i * kPS + l] * T[l * kPS + j];
       }
+      if (j < wj && i < wi) X[(i0 + i) * kPS + j] = xi;
     }
     __syncthreads();
   }
