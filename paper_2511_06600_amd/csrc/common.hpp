@@ -86,6 +86,15 @@ __device__ __forceinline__ void wave_sync() {
 // Map a launched block index to a logical one so that each of the 8 XCDs of
 // an MI355X (which receive blocks round-robin) walks a contiguous range of
 // logical blocks; neighbouring work then shares its XCD's L2.
+// Lane l's value of v on every lane (l the same on all lanes: a scalar
+// broadcast, no LDS round trip).
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(u), l);
+  const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(u >> 32), l);
+  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
+}
+
 __device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblocks) {
   constexpr int64_t kXcd = 8;
   int64_t per = nblocks / kXcd;

@@ -230,7 +230,7 @@ k_gram_reduce(const double *__restrict__ in0, int64_t nrows0, double *__restrict
 // Cholesky of G with column dropping, then the Y-block columns of R^-1.
 // One wave per expansion; lane t holds row t of the C x C Gram (registers),
 // so the factorisation needs no barriers: column k's pivot and the entries
-// L_jk come from lane shuffles.  Column c is dropped when its reference
+// L_jk reach the other lanes by readlane.  Column c is dropped when its reference
 // length is 0 or its Schur pivot d_c <= tau^2 * G_cc.  L goes to LDS; lane c
 // then forms column c of R^-1 = L^-T by back substitution.
 template <int C>
@@ -254,8 +254,8 @@ k_lsolve(const double *__restrict__ Gall, int B, double tau, double *__restrict_
   uint64_t keep = 0;
 #pragma unroll
   for (int k = 0; k < C; ++k) {
-    const double d = __shfl(a[k], k, 64);
-    const double ref = __shfl(gref, k, 64);
+    const double d = readlane_f64(a[k], k);
+    const double ref = readlane_f64(gref, k);
     if (ref > 0.0 && d > tau * tau * ref) {
       keep |= uint64_t(1) << k;
       const double lkk = sqrt(d);
@@ -263,7 +263,7 @@ k_lsolve(const double *__restrict__ Gall, int B, double tau, double *__restrict_
       l[k] = lk;
 #pragma unroll
       for (int j = k + 1; j < C; ++j) {
-        const double ljk = __shfl(lk, j, 64);
+        const double ljk = readlane_f64(lk, j);
         if (j <= t) a[j] -= lk * ljk;
       }
     }

@@ -54,13 +54,6 @@ constexpr int kMaxPB = 16;    // 32-column blocks of the widest pool (K <= 512)
 // Workgroup 0 also writes the diagonal block, keep and rho.
 constexpr int kCT = 256;  // panel threads: one row below the diagonal block each
 
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-  const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(u), l);
-  const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(u >> 32), l);
-  return __builtin_bit_cast(double, (uint64_t(hi) << 32) | lo);
-}
-
 __global__ void __launch_bounds__(kCT)
 k_chol_panel(const double *__restrict__ A, const double *__restrict__ G, int K, int c0,
              double tau, double *__restrict__ LT, int32_t *__restrict__ keep,
