@@ -59,7 +59,13 @@ typedef enum {
 } hef_status;
 
 /* Storage type of the Krylov pool chi^(1..K). */
-typedef enum { HEF_BASIS_FP32 = 0, HEF_BASIS_BF16 = 1 } hef_basis;
+/* Pool storage.  HEF_BASIS_FP64 is a debug basis of hef_resistance and
+ * hef_resistance_static only: the Krylov pool is stored in float64 (the
+ * float32 Krylov blocks widened exactly), the joint Gram, R^-1 apply and the
+ * resistance ratios run in float64, and chi is returned as float64; every
+ * other entry point rejects it with HEF_ERR_UNSUPPORTED, and it takes
+ * orth_passes = 1. */
+typedef enum { HEF_BASIS_FP32 = 0, HEF_BASIS_BF16 = 1, HEF_BASIS_FP64 = 2 } hef_basis;
 
 /* Which operation a workspace is sized for. */
 typedef enum {
@@ -146,8 +152,9 @@ hef_status hef_validate_host(int32_t n, int32_t m, const int32_t *eptr,
  *   R            DEVICE [m] float32 output;
  *   qh           DEVICE [K] float64 output Q_H(chi^(i)), or NULL; a dropped
  *                column reports 0;
- *   chi          DEVICE [n x K] row-major output pool (float32, or bfloat16
- *                when basis = BF16), or NULL; dropped columns are zero.
+ *   chi          DEVICE [n x K] row-major output pool (float32, bfloat16 when
+ *                basis = BF16, float64 when basis = FP64), or NULL; dropped
+ *                columns are zero.
  * Unless HEF_FLAG_ASSUME_VALID is set, the results are checked on the device
  * (one more stream synchronisation) and HEF_ERR_NUMERICAL is returned if
  * every Q_H vanished or a value is not finite.  With HEF_FLAG_ASSUME_VALID

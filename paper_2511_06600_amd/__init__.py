@@ -29,7 +29,7 @@ class Params:
     levels: int = 1
     percentile: float = 0.5
     local_clustering: bool = True
-    basis: str = "fp32"           # "fp32" or "bf16" pool storage
+    basis: str = "fp32"           # "fp32" or "bf16" pool storage ("fp64": debug, resistance only)
     seed: int = 7
     drop_tol: float = 1e-3
     orth_passes: int = 1
@@ -44,7 +44,8 @@ class Params:
         p.k, p.b, p.levels = self.k, self.b, self.levels
         p.percentile = self.percentile
         p.local_clustering = int(self.local_clustering)
-        p.basis = {"fp32": _lib.BASIS_FP32, "bf16": _lib.BASIS_BF16}[self.basis]
+        p.basis = {"fp32": _lib.BASIS_FP32, "bf16": _lib.BASIS_BF16,
+                   "fp64": _lib.BASIS_FP64}[self.basis]
         p.seed = self.seed
         p.drop_tol = self.drop_tol
         p.orth_passes = self.orth_passes
@@ -104,6 +105,9 @@ def _workspace(hg, params, op):
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=hg.device)
 
 
+_POOL_DTYPE = {"fp32": torch.float32, "bf16": torch.bfloat16, "fp64": torch.float64}
+
+
 def resistance(hg: DeviceHypergraph, params: Params, start_star: torch.Tensor | None = None,
                start_clique: torch.Tensor | None = None, return_pool: bool = False):
     """Alg. 1: returns (R [m] float32, qh [K] float64, chi [n, K] or None)."""
@@ -113,8 +117,7 @@ def resistance(hg: DeviceHypergraph, params: Params, start_star: torch.Tensor | 
     qh = torch.empty(K, dtype=torch.float64, device=hg.device)
     chi = None
     if return_pool:
-        dt = torch.bfloat16 if params.basis == "bf16" else torch.float32
-        chi = torch.empty((hg.n, K), dtype=dt, device=hg.device)
+        chi = torch.empty((hg.n, K), dtype=_POOL_DTYPE[params.basis], device=hg.device)
     ws = _workspace(hg, params, _lib.OP_RESISTANCE)
     for t, rows in ((start_star, hg.n + hg.m), (start_clique, hg.n)):
         if t is not None:
@@ -136,8 +139,7 @@ def resistance_static(hg: DeviceHypergraph, params: Params,
     qh = torch.empty(K, dtype=torch.float64, device=hg.device)
     chi = None
     if return_pool:
-        dt = torch.bfloat16 if params.basis == "bf16" else torch.float32
-        chi = torch.empty((hg.n, K), dtype=dt, device=hg.device)
+        chi = torch.empty((hg.n, K), dtype=_POOL_DTYPE[params.basis], device=hg.device)
     for t, rows in ((start_star, hg.n + hg.m), (start_clique, hg.n)):
         if t is not None:
             assert t.dtype == torch.float32 and t.is_contiguous() and t.shape == (rows, params.b)

@@ -15,7 +15,7 @@ STATUS = {
 }
 (OP_RESISTANCE, OP_COARSEN, OP_CLUSTER_LEVEL, OP_BACKWARD, OP_APPLY, OP_CONDUCTANCE,
  OP_REBUILD, OP_RATING) = range(8)
-BASIS_FP32, BASIS_BF16 = 0, 1
+BASIS_FP32, BASIS_BF16, BASIS_FP64 = 0, 1, 2
 STATIC_SCRATCH_BYTES = 64 << 20  # HEF_STATIC_SCRATCH_BYTES
 FLAG_ASSUME_VALID, FLAG_STAR_ONLY, FLAG_CLIQUE_ONLY, FLAG_TAPED = 1, 2, 4, 8
 

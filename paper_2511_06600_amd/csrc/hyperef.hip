@@ -78,7 +78,7 @@ hef_status check_hg(const hef_hypergraph *hg) {
   return HEF_OK;
 }
 
-hef_status check_params(const hef_params *p, bool need_levels) {
+hef_status check_params(const hef_params *p, bool need_levels, bool allow_fp64 = false) {
   if (!p) { set_error("params is NULL"); return HEF_ERR_INVALID_ARGUMENT; }
   if (p->k < 1 || p->k > 1024) { set_error("k=%d out of range", p->k); return HEF_ERR_INVALID_ARGUMENT; }
   if (!pow2_block(p->b)) {
@@ -89,9 +89,17 @@ hef_status check_params(const hef_params *p, bool need_levels) {
     set_error("pool width %d exceeds 512", pool_width(*p));
     return HEF_ERR_UNSUPPORTED;
   }
-  if (p->basis != HEF_BASIS_FP32 && p->basis != HEF_BASIS_BF16) {
+  if (p->basis != HEF_BASIS_FP32 && p->basis != HEF_BASIS_BF16 && p->basis != HEF_BASIS_FP64) {
     set_error("unknown basis %d", p->basis);
     return HEF_ERR_INVALID_ARGUMENT;
+  }
+  if (p->basis == HEF_BASIS_FP64 && !allow_fp64) {
+    set_error("the float64 basis is a debug basis of hef_resistance only");
+    return HEF_ERR_UNSUPPORTED;
+  }
+  if (p->basis == HEF_BASIS_FP64 && p->orth_passes != 1) {
+    set_error("the float64 basis takes orth_passes = 1");
+    return HEF_ERR_UNSUPPORTED;
   }
   if (!(p->drop_tol >= 0.0f && p->drop_tol < 1.0f)) {
     set_error("drop_tol must lie in [0, 1)");
@@ -131,7 +139,7 @@ Level level_of(const hef_hypergraph *hg) {
 }
 
 size_t pool_bytes(int64_t n, int K, int basis) {
-  return size_t(n) * K * (basis == HEF_BASIS_BF16 ? 2 : 4);
+  return size_t(n) * K * (basis == HEF_BASIS_BF16 ? 2 : basis == HEF_BASIS_FP64 ? 8 : 4);
 }
 
 // Scratch needed by one resistance estimate at these sizes (beyond the
@@ -204,7 +212,8 @@ hef_status estimate_level(const Level &L, const hef_params &p, uint64_t seed, in
   KrylovOut ko;
   ko.pool = pool2;
   ko.K = K;
-  ko.pool_type = p.basis == HEF_BASIS_BF16 ? kPoolBF16 : kPoolF32;
+  ko.pool_type = p.basis == HEF_BASIS_BF16 ? kPoolBF16
+                 : p.basis == HEF_BASIS_FP64 ? kPoolF64 : kPoolF32;
   HEF_TRY(krylov_pool(L, st, B, p.k, double(p.drop_tol), start_star, start_clique, use_star,
                       use_clique, ko, ws, s));
   ws.reset(mk);
@@ -291,7 +300,7 @@ hef_status hef_workspace_size(const hef_hypergraph *hg, const hef_params *p, int
   const int64_t n = hg->n, m = hg->m, nnz = hg->nnz;
   switch (op) {
     case HEF_OP_RESISTANCE:
-      HEF_TRY(check_params(p, false));
+      HEF_TRY(check_params(p, false, true));
       *bytes = resistance_bytes(n, m, nnz, *p, true);
       return HEF_OK;
     case HEF_OP_COARSEN:
@@ -363,7 +372,7 @@ hef_status hef_resistance_static(const hef_hypergraph *hg, const hef_params *p,
                                  const float *start_star, const float *start_clique, float *R,
                                  double *qh, void *chi, hipStream_t stream) {
   HEF_TRY(check_hg(hg));
-  HEF_TRY(check_params(p, false));
+  HEF_TRY(check_params(p, false, true));
   const size_t need = resistance_bytes(hg->n, hg->m, hg->nnz, *p, chi == nullptr);
   if (need > HEF_STATIC_SCRATCH_BYTES) {
     set_error("this hypergraph needs %zu bytes of scratch; the static scratch holds %zu "
@@ -384,7 +393,7 @@ hef_status resistance_call(const hef_hypergraph *hg, const hef_params *p, const 
                            const float *start_clique, float *R, double *qh, void *chi, void *ws,
                            size_t ws_bytes, hipStream_t stream) {
   HEF_TRY(check_hg(hg));
-  HEF_TRY(check_params(p, false));
+  HEF_TRY(check_params(p, false, true));
   if (!R && hg->m > 0) { set_error("R is NULL"); return HEF_ERR_INVALID_ARGUMENT; }
   if (!ws) { set_error("workspace is NULL"); return HEF_ERR_INVALID_ARGUMENT; }
   const int64_t n = hg->n, m = hg->m, nnz = hg->nnz;

@@ -325,7 +325,8 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 // rows of the three inputs in LDS with coalesced float4 loads, one thread per
 // row (two for B = 16) forms the outputs, which leave through LDS as
 // coalesced stores.  The first pool_rows rows also go to the pool (row-octet
-// layout, float32 or bfloat16) at column col0.
+// layout, float32, bfloat16 or, for the float64 debug basis, float64) at
+// column col0.
 template <int CH>
 __device__ __forceinline__ void ld(const float *p, float (&v)[CH]) {
   if constexpr (CH == 4) {
@@ -466,6 +467,10 @@ k_lapply(const ApplyPair P, void *__restrict__ pool, int pool_type, int64_t pool
         float4 *pp = reinterpret_cast<float4 *>(reinterpret_cast<float *>(pool) + off);
         pp[0] = make_float4(v[0], v[1], v[2], v[3]);
         pp[1] = make_float4(v[4], v[5], v[6], v[7]);
+      } else if (pool_type == kPoolF64) {
+        double2 *pp = reinterpret_cast<double2 *>(reinterpret_cast<double *>(pool) + off);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pp[q] = make_double2(double(v[2 * q]), double(v[2 * q + 1]));
       } else {
         uint32_t wv[4];
 #pragma unroll

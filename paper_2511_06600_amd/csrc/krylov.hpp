@@ -29,7 +29,7 @@ hef_status spmm_apply(const Level &L, const Structure &st, int B, const float *x
                       float *ys, const float *xc, float *yc, float *scratch, hipStream_t s);
 
 // Pool column storage.
-enum PoolType { kPoolF32 = 0, kPoolBF16 = 1 };
+enum PoolType { kPoolF32 = 0, kPoolBF16 = 1, kPoolF64 = 2 };
 
 struct KrylovOut {
   void *pool = nullptr;  // oct_rows(n) x K, row-octet layout (fp32 or bf16)

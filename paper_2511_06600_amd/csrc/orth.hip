@@ -703,6 +703,116 @@ __global__ void k_jgram_scatter(const double *__restrict__ sums, int nsb, int np
   if (!cross) G[int64_t(gj) * K + gi] = s;
 }
 
+// The Gram of a float64 pool in the row-octet layout (the float64 debug
+// basis): workgroup = (row chunk, super-block pair a <= b), its partial in
+// the layout k_jgram_scatter reads (16 tiles of 32 x 32 per pair).  Thread
+// (ty, tx) accumulates rows 8 ty .. 8 ty + 7 of block a against columns
+// 8 tx .. 8 tx + 7 of block b in float64, over the chunk's rows staged 16 at
+// a time in LDS.
+constexpr int kG64Rows = 16;
+
+__global__ void __launch_bounds__(256)
+k_jgram_f64(const double *__restrict__ P, int64_t n, int K, int nsb, int npairs, int64_t rpc,
+            double *__restrict__ partial) {
+  __shared__ double As[kG64Rows][kSB + 1];
+  __shared__ double Bs[kG64Rows][kSB + 1];
+  const int pair = int(blockIdx.x % npairs);
+  const int64_t chunk = int64_t(blockIdx.x) / npairs;
+  const int2 ab = pair_of(pair, nsb);
+  const int64_t r0 = chunk * rpc;
+  const int64_t r1 = r0 + rpc < n ? r0 + rpc : n;
+  const int t = threadIdx.x, ty = t / 16, tx = t % 16;
+  double acc[8][8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+#pragma unroll
+    for (int v = 0; v < 8; ++v) acc[u][v] = 0.0;
+  for (int64_t r = r0; r < r1; r += kG64Rows) {
+    for (int e = t; e < kG64Rows * kSB; e += 256) {
+      const int rr = e % kG64Rows, cc = e / kG64Rows;
+      const int64_t row = r + rr;
+      const int ca = ab.x * kSB + cc, cb = ab.y * kSB + cc;
+      As[rr][cc] = (row < r1 && ca < K) ? P[((row >> 3) * K + ca) * 8 + (row & 7)] : 0.0;
+      Bs[rr][cc] = (row < r1 && cb < K) ? P[((row >> 3) * K + cb) * 8 + (row & 7)] : 0.0;
+    }
+    __syncthreads();
+    for (int rr = 0; rr < kG64Rows; ++rr) {
+      double av[8], bv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        av[u] = As[rr][8 * ty + u];
+        bv[u] = Bs[rr][8 * tx + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+  double *out = partial + int64_t(blockIdx.x) * 16 * 1024;
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int i = 8 * ty + u, j = 8 * tx + v;
+      out[((i / 32) * 4 + j / 32) * 1024 + (i % 32) * 32 + (j % 32)] = acc[u][v];
+    }
+}
+
+// Q = V Rinv in float64 for the float64 debug basis: V in the row-octet
+// layout, Rinv upper triangular (Kp x Kp, row-major), Q row-major n x K.
+// Workgroup = 64 x 64 output tile, thread (ty, tx) = 4 x 4 outputs; the k
+// loop stops at the tile's last column, 16 k at a time staged in LDS.
+__global__ void __launch_bounds__(256)
+k_japply_f64(const double *__restrict__ V, double *__restrict__ Q, int64_t n, int K, int Kp,
+             const double *__restrict__ Rinv) {
+  __shared__ double Vs[16][65];
+  __shared__ double Rs[16][65];
+  const int ncb = (K + 63) / 64;
+  const int64_t r0 = int64_t(blockIdx.x / ncb) * 64;
+  const int c0 = int(blockIdx.x % ncb) * 64;
+  const int t = threadIdx.x, ty = t / 16, tx = t % 16;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  const int kend = K < c0 + 64 ? K : c0 + 64;
+  for (int k0 = 0; k0 < kend; k0 += 16) {
+    for (int e = t; e < 16 * 64; e += 256) {
+      const int kk = e / 64, rr = e % 64;
+      const int64_t row = r0 + rr;
+      const int k = k0 + kk;
+      Vs[kk][rr] = (row < n && k < K) ? V[((row >> 3) * K + k) * 8 + (row & 7)] : 0.0;
+      Rs[kk][rr] = (k < K && c0 + rr < K) ? Rinv[int64_t(k) * Kp + c0 + rr] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = Vs[kk][4 * ty + u];
+        b[u] = Rs[kk][4 * tx + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = r0 + 4 * ty + u;
+      const int col = c0 + 4 * tx + v;
+      if (row < n && col < K) Q[row * K + col] = acc[u][v];
+    }
+}
+
 // ---------------------------------------------------------------- apply
 // Q = V Rinv (n x K times upper-triangular K x K), out of place.  Block =
 // 128 x 128 output tile; 8 waves of 64 x 32 (2 x 1 MFMA tiles) for the FP32
@@ -1473,7 +1583,14 @@ hef_status gram_run(const void *pool, const void *poolB, int pool_type, int64_t 
   HEF_HIP(hipMemsetAsync(G, 0, sizeof(double) * K * K, s));
   {
   TimedScope ts(kStOrthGram, s);
-  if (pool_type == kPoolBF16 && !poolB)
+  if (pool_type == kPoolF64) {
+    if (poolB || !oct) {
+      set_error("the float64 pool takes the row-octet Gram only");
+      return HEF_ERR_UNSUPPORTED;
+    }
+    k_jgram_f64<<<int64_t(p.npairs) * p.nchunks, 256, 0, s>>>(
+        reinterpret_cast<const double *>(pool), n, K, p.nsb, p.npairs, p.rows_per_chunk, partial);
+  } else if (pool_type == kPoolBF16 && !poolB)
     k_jgram_bf16<<<int64_t(p.npairs) * p.nchunks, kGT, 0, s>>>(
         reinterpret_cast<const uint16_t *>(pool), oct, n, K, p.nsb, p.npairs, p.rows_per_chunk,
         partial);
@@ -1503,9 +1620,20 @@ hef_status gram_run(const void *pool, const void *poolB, int pool_type, int64_t 
 
 hef_status apply_run(const void *V, void *Q, int pool_type, int64_t n, int K, int Kp,
                      const float *Rinv32, hipStream_t s, bool full = false,
-                     bool accumulate = false, bool oct = false, const float *RinvT32 = nullptr) {
+                     bool accumulate = false, bool oct = false, const float *RinvT32 = nullptr,
+                     const double *Rinv64 = nullptr) {
   if (n == 0) return HEF_OK;
   TimedScope ts(kStOrthApply, s);
+  if (pool_type == kPoolF64) {
+    if (!oct || full || accumulate || !Rinv64) {
+      set_error("the float64 pool takes the row-octet apply only");
+      return HEF_ERR_UNSUPPORTED;
+    }
+    k_japply_f64<<<cdiv(n, 64) * ((K + 63) / 64), 256, 0, s>>>(
+        reinterpret_cast<const double *>(V), reinterpret_cast<double *>(Q), n, K, Kp, Rinv64);
+    HEF_LAUNCH_CHECK();
+    return HEF_OK;
+  }
   if (!full && !accumulate && pool_type == kPoolF32 && RinvT32) {
     if (oct)  // (Kp <= 512: at most 8 tiles per column set)
       k_japply_dma<<<2 * cdiv(n, kDR), kDT, 0, s>>>(reinterpret_cast<const float *>(V),
@@ -1646,10 +1774,12 @@ hef_status orthonormalize_pool(void *P, void *out, int pool_type, int64_t n, int
             Kp, RhT, RlT, ncb);
       HEF_LAUNCH_CHECK();
     } else {
-      HEF_TRY(apply_run(src, dst, pool_type, n, K, Kp, Rinv32, s, false, false, oct, RinvT32));
+      HEF_TRY(apply_run(src, dst, pool_type, n, K, Kp, Rinv32, s, false, false, oct, RinvT32,
+                        Rinv));
     }
     if (pass == 1)
-      HEF_HIP(hipMemcpyAsync(out, P, size_t(n) * K * (pool_type == kPoolBF16 ? 2 : 4),
+      HEF_HIP(hipMemcpyAsync(out, P,
+                             size_t(n) * K * (pool_type == kPoolBF16 ? 2 : pool_type == kPoolF64 ? 8 : 4),
                              hipMemcpyDeviceToDevice, s));
   }
   if (keep_out) HEF_HIP(hipMemcpyAsync(keep_out, keep, K * sizeof(int32_t), hipMemcpyDeviceToDevice, s));

@@ -14,6 +14,7 @@
 // hyperedges (XCD-contiguous), so neighbouring hyperedges share pool rows
 // in L2.  Sums are float64 in a fixed order.
 #include <cfloat>
+#include <type_traits>
 
 #include "krylov.hpp"
 #include "prims.hpp"
@@ -25,10 +26,27 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kEdgesPerBlk = 128;
 
+// Pool values of one type: float64 for the float64 debug basis, else float
+// (bfloat16 widens exactly).
+template <int PT>
+using PoolVal = typename std::conditional<PT == kPoolF64, double, float>::type;
+
 template <int CPL, int PT>
 __device__ __forceinline__ void load_cols(const void *pool, int64_t p, int K, int c0,
-                                          float (&v)[CPL]) {
-  if (PT == kPoolF32) {
+                                          PoolVal<PT> (&v)[CPL]) {
+  if constexpr (PT == kPoolF64) {
+    const double *row = reinterpret_cast<const double *>(pool) + p * K + c0;
+    if ((K & 1) == 0 && c0 + CPL <= K) {
+#pragma unroll
+      for (int q = 0; q < CPL; q += 2) {
+        const double2 t = *reinterpret_cast<const double2 *>(row + q);
+        v[q] = t.x; v[q + 1] = t.y;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) v[q] = (c0 + q < K) ? row[q] : 0.0;
+    }
+  } else if (PT == kPoolF32) {
     const float *row = reinterpret_cast<const float *>(pool) + p * K + c0;
     if ((K & 3) == 0 && c0 + CPL <= K) {
 #pragma unroll
@@ -62,24 +80,31 @@ __device__ __forceinline__ void load_cols(const void *pool, int64_t p, int K, in
 // Spread of hyperedge [a, b) of pins over this lane's columns.  Pins go in
 // chunks of 4 (ids first, then rows, so the loads overlap); a chunk past the
 // end repeats the last pin, which leaves max and min unchanged.
+__device__ __forceinline__ float vmax(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ float vmin(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ double vmax(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ double vmin(double a, double b) { return fmin(a, b); }
+
 template <int CPL, int PT>
 __device__ __forceinline__ void edge_spread(const int32_t *__restrict__ pins, const void *pool,
                                             int K, int c0, int32_t a, int32_t b,
                                             double (&s)[CPL]) {
-  float mx[CPL], mn[CPL];
+  using T = PoolVal<PT>;
+  constexpr T kBig = PT == kPoolF64 ? T(DBL_MAX) : T(FLT_MAX);
+  T mx[CPL], mn[CPL];
 #pragma unroll
-  for (int q = 0; q < CPL; ++q) { mx[q] = -FLT_MAX; mn[q] = FLT_MAX; }
+  for (int q = 0; q < CPL; ++q) { mx[q] = -kBig; mn[q] = kBig; }
   for (int32_t j0 = a; j0 < b; j0 += 4) {
     int32_t pp[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) pp[u] = pins[j0 + u < b ? j0 + u : b - 1];
-    float v[4][CPL];
+    T v[4][CPL];
 #pragma unroll
     for (int u = 0; u < 4; ++u) load_cols<CPL, PT>(pool, pp[u], K, c0, v[u]);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int q = 0; q < CPL; ++q) { mx[q] = fmaxf(mx[q], v[u][q]); mn[q] = fminf(mn[q], v[u][q]); }
+      for (int q = 0; q < CPL; ++q) { mx[q] = vmax(mx[q], v[u][q]); mn[q] = vmin(mn[q], v[u][q]); }
   }
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
@@ -245,6 +270,9 @@ hef_status score_pool(const Level &L, const void *pool, int pool_type, int K, do
   if (pool_type == kPoolF32)
     st = wide ? score_t<8, kPoolF32>(L, pool, K, qh, R, partial, sbuf, nblk, s)
               : score_t<4, kPoolF32>(L, pool, K, qh, R, partial, sbuf, nblk, s);
+  else if (pool_type == kPoolF64)
+    st = wide ? score_t<8, kPoolF64>(L, pool, K, qh, R, partial, sbuf, nblk, s)
+              : score_t<4, kPoolF64>(L, pool, K, qh, R, partial, sbuf, nblk, s);
   else
     st = wide ? score_t<8, kPoolBF16>(L, pool, K, qh, R, partial, sbuf, nblk, s)
               : score_t<4, kPoolBF16>(L, pool, K, qh, R, partial, sbuf, nblk, s);

@@ -98,6 +98,14 @@ int main() {
       c.set(q);
       expect(c.what, hef_workspace_size(&big, &q, HEF_OP_COARSEN, &b), c.want);
     }
+    // the float64 basis: Alg. 1 only, one orthonormalisation pass
+    hef_params f = p;
+    f.basis = HEF_BASIS_FP64;
+    expect("params: fp64 basis (resistance)", hef_workspace_size(&big, &f, HEF_OP_RESISTANCE, &b), HEF_OK);
+    expect("params: fp64 basis (coarsen)", hef_workspace_size(&big, &f, HEF_OP_COARSEN, &b), HEF_ERR_UNSUPPORTED);
+    expect("params: fp64 basis (backward)", hef_workspace_size(&big, &f, HEF_OP_BACKWARD, &b), HEF_ERR_UNSUPPORTED);
+    f.orth_passes = 2;
+    expect("params: fp64 basis, two passes", hef_workspace_size(&big, &f, HEF_OP_RESISTANCE, &b), HEF_ERR_UNSUPPORTED);
   }
   // ---- argument errors returned before any device work
   float R[2];

@@ -79,6 +79,19 @@ def test_invalid_parameters_are_rejected_on_the_host():
     assert lib.hef_workspace_size(C.byref(_hg()), C.byref(p), 0, C.byref(out)) == 1
     assert b"orth_passes" in lib.hef_last_error()
     p.orth_passes = 1
+    # the float64 basis: Alg. 1 only, one orthonormalisation pass; basis 3 is unknown
+    p.basis = _lib.BASIS_FP64
+    assert lib.hef_workspace_size(C.byref(_hg()), C.byref(p), _lib.OP_RESISTANCE,
+                                  C.byref(out)) == 0
+    for op in (_lib.OP_COARSEN, _lib.OP_CLUSTER_LEVEL, _lib.OP_BACKWARD):
+        assert lib.hef_workspace_size(C.byref(_hg()), C.byref(p), op, C.byref(out)) == 6
+        assert b"float64 basis" in lib.hef_last_error()
+    p.orth_passes = 2
+    assert lib.hef_workspace_size(C.byref(_hg()), C.byref(p), _lib.OP_RESISTANCE,
+                                  C.byref(out)) == 6
+    p.orth_passes, p.basis = 1, 3
+    assert lib.hef_workspace_size(C.byref(_hg()), C.byref(p), 0, C.byref(out)) == 1
+    p.basis = _lib.BASIS_FP32
     assert lib.hef_workspace_size(None, C.byref(p), 0, C.byref(out)) == 1
     # hef_resistance fails its argument checks before touching the device
     assert lib.hef_resistance(None, C.byref(p), None, None, None, None, None, None, 0, None) == 1

@@ -125,6 +125,38 @@ def test_bf16_pool_within_1e2():
     _parity(h, 30, 8, basis="bf16", tol_norm=1e-2, tol_p999=1.0, tol_qh=1e-2)
 
 
+@pytest.mark.parametrize("name,k,b", [("tiny2k", 10, 1), ("netlist20k", 30, 8)])
+def test_fp64_debug_basis(name, k, b):
+    # the float64 basis: the pool, the joint orthonormalisation and the
+    # ratios in float64 from the float32 Krylov blocks, so the float32
+    # recurrence bounds R's error (same 1e-4 bar) while the pool is
+    # orthonormal to 1e-10 (one Cholesky QR loses kappa^2 u, kappa <= 1/drop_tol)
+    # and sum_e w_e r_e = 1 (Eqs. (9), (13)) holds to 1e-12
+    if name == "tiny2k":
+        h = make_hypergraph("tiny2k")
+    else:
+        h = generate(20000, 21000, 2, 2000, 2.7828, p_loc=0.7, weights="lognormal", seed=5)
+    say(f"case: resistance {name} k={k} b={b} basis=fp64")
+    R, qh, chi, est = _parity(h, k, b, basis="fp64")
+    assert chi.dtype == torch.float64
+    chi = chi.cpu().numpy()
+    kept = qh > 0
+    G = chi[:, kept].T @ chi[:, kept]
+    orth = np.abs(G - np.eye(G.shape[0])).max()
+    s = orr.edge_spread(h.eptr, h.pins, chi[:, kept])
+    tot = (h.w.astype(np.float64)[:, None] * s / qh[None, kept]).sum(0)
+    say(f"  pool orthogonality {orth:.1e}, max |sum w r - 1| {np.abs(tot - 1).max():.1e}")
+    assert orth < 1e-10
+    assert np.abs(tot - 1).max() < 1e-12
+    assert not chi[:, ~kept].any()
+    # the static-scratch entry point gives the same bits
+    if name == "tiny2k":
+        _, _, xs, xc = starts(h, b)
+        R2, qh2, _ = hef.resistance_static(to_device(h), hef.Params(k=k, b=b, basis="fp64"),
+                                           xs, xc)
+        assert np.array_equal(R2.cpu().numpy(), R) and np.array_equal(qh2.cpu().numpy(), qh)
+
+
 def test_counter_generator_start_matches_explicit_start():
     h = make_hypergraph("tiny2k")
     say("case: resistance tiny2k with NULL start blocks")
