@@ -173,6 +173,14 @@ def cpu_baseline(cfg_name):
     return res
 
 
+def best_bytes(work):
+    """The best-neighbour search (k_best) per coarsen step: each screened
+    (isolated node, candidate cluster) pair reads the first 128 columns of the
+    candidate's float16 centroid copy, 256 bytes (the pairs per level come
+    from hef_last_coarsen_work)."""
+    return 256 * sum(work)
+
+
 def roofline_entry(bound, amount, ms_total, launches, peak, unit, kernels, traffic=None):
     if bound == "hbm":
         ach = amount / (ms_total / 1e3) / 1e9
@@ -405,6 +413,7 @@ def main():
     hef.timing_enable(False)
     stages = hef.timing_read(reset=True)
     levels = hef.last_coarsen_levels()
+    work = hef.last_coarsen_work()
     ms_step = (t1 - t0) / args.steps * 1e3
     est_per_step = sum(lv[1] for lv in levels)
     value = est_per_step / (ms_step / 1e3)
@@ -460,10 +469,14 @@ def main():
         "k_score_qh": roofline_entry("hbm", sq_b, ms_of("score_qh"),
                                      per.get("score_qh", (0, 0))[1], PEAK_HBM_GBS, "GB/s",
                                      ["k_score_qh"], traffic_of(["k_score_qh"], len(levels))),
+        # the best-neighbour search: every screened (node, candidate) pair
+        # reads the first 128 columns of the candidate's float16 centroid
+        # copy (256 bytes); the pairs are counted on the device per level
+        "k_best": roofline_entry("hbm", best_bytes(work) * S, ms_of("cluster_best"),
+                                 per.get("cluster_best", (0, 0))[1], PEAK_HBM_GBS, "GB/s",
+                                 ["k_best"], traffic_of(["k_best"], len(levels))),
     }
-    # the dominant kernel (by time) among those with an algorithmic count;
-    # the local-clustering search (cluster_best) has none: its work is the
-    # candidate screening that its bounds prune, see its stage time
+    # the dominant kernel (by time) among those with an algorithmic count
     dom = max(rooflines, key=lambda kk: rooflines[kk]["avg_launch_us"] * rooflines[kk]["launches"])
     r = rooflines[dom]
     roof = {"bound": r["bound"], "achieved": r["achieved"], "peak": r["peak"], "unit": r["unit"],

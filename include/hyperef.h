@@ -242,6 +242,15 @@ hef_status hef_coarsen_levels(const hef_hypergraph *hg, const hef_params *p, int
  * estimated; returns the number of such levels. */
 int32_t hef_last_coarsen_levels(int32_t *n, int32_t *m, int64_t *nnz, int32_t cap);
 
+/* Work of the local clustering's best-neighbour search (Section III-B,
+ * Eq. (16)) in the calling thread's last hef_coarsen call, per level (HOST
+ * array of `cap` entries, may be NULL): the number of (isolated node,
+ * candidate cluster) pairs it screened, one per co-pin occurrence of every
+ * isolated node, i.e. sum over isolated p of sum_{e ∋ p} (|e| - 1); 0 for a
+ * level without local clustering.  Counted on the device with integer sums;
+ * returns the number of levels. */
+int32_t hef_last_coarsen_work(int64_t *best_candidates, int32_t cap);
+
 /* One level of Alg. 2 (steps 4-10) from GIVEN inputs, so that a caller can
  * feed the same resistances to two implementations:
  *   R        DEVICE [m] float32 resistances of this level;

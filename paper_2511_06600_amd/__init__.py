@@ -378,6 +378,16 @@ def last_coarsen_levels() -> list:
     return [(n[i], m[i], z[i]) for i in range(min(k, cap))]
 
 
+def last_coarsen_work() -> list:
+    """Per level of the calling thread's last coarsen: the (isolated node,
+    candidate cluster) pairs its best-neighbour search screened."""
+    lib = load()
+    cap = 64
+    w = (C.c_int64 * cap)()
+    k = lib.hef_last_coarsen_work(C.cast(w, C.c_void_p), cap)
+    return [w[i] for i in range(min(k, cap))]
+
+
 def timing_enable(on: bool = True) -> None:
     """Per-stage HIP-event timing inside the library (profiling aid)."""
     load().hef_timing_enable(1 if on else 0)

@@ -27,6 +27,7 @@ EXPORTS = [
     "hef_debug_apply", "hef_debug_gram", "hef_debug_gram_ws", "hef_start_block",
     "hef_status_string", "hef_last_error", "hef_timing_enable", "hef_timing_stage_count",
     "hef_timing_stage_name", "hef_timing_read", "hef_last_coarsen_levels",
+    "hef_last_coarsen_work",
 ]
 
 
@@ -98,6 +99,7 @@ def load() -> C.CDLL:
         "hef_timing_stage_name": (C.c_char_p, [i32]),
         "hef_timing_read": (i32, [vp, vp, i32, i32]),
         "hef_last_coarsen_levels": (i32, [vp, vp, vp, i32]),
+        "hef_last_coarsen_work": (i32, [vp, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -750,6 +750,33 @@ k_best(const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
   }
 }
 
+// *out += the (isolated node, candidate cluster) pairs k_best screens: one
+// per co-pin occurrence of every listed node p, sum_{e ∋ p} (|e| - 1).  A
+// thread per listed node, a block sum, one integer atomic per workgroup.
+__global__ void __launch_bounds__(256)
+k_count_candidates(const int32_t *__restrict__ list, const int32_t *__restrict__ count,
+                   const int32_t *__restrict__ vptr, const int32_t *__restrict__ eids,
+                   const int32_t *__restrict__ eptr, unsigned long long *__restrict__ out) {
+  __shared__ unsigned long long part[256];
+  const int64_t cnt = *count;
+  unsigned long long acc = 0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < cnt;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t p = list[i];
+    for (int32_t j = vptr[p]; j < vptr[p + 1]; ++j) {
+      const int32_t e = eids[j];
+      acc += unsigned(eptr[e + 1] - eptr[e] - 1);
+    }
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (int(threadIdx.x) < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && part[0]) atomicAdd(out, part[0]);
+}
+
 // ---- union-find over the attach pairs (roots end as component minima) ------
 __device__ __forceinline__ int32_t find_root(const int32_t *parent, int32_t x) {
   int32_t p = parent[x];
@@ -1200,7 +1227,8 @@ hef_status read_i32(const int32_t *dev, int32_t *host, hipStream_t s) {
 hef_status cluster_one_level(const Level &L, const Structure &st, const float *R, const float *eta,
                              const void *pool, int pool_type, int K, const double *qh,
                              float percentile, bool local, int32_t *label_out,
-                             int32_t *n_groups_out, float *eta_out, Arena &ws, hipStream_t s) {
+                             int32_t *n_groups_out, float *eta_out, Arena &ws, hipStream_t s,
+                             unsigned long long *work) {
   const int64_t n = L.n, m = L.m, nnz = L.nnz;
   const size_t mk = ws.mark();
   LevelWs w;
@@ -1298,6 +1326,9 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
                                                      w.small + 7, w.best_label, w.best_d);
         }
       }
+      if (work)
+        k_count_candidates<<<1024, 256, 0, s>>>(slist, w.small + 7, st.vptr, st.eids, L.eptr,
+                                                work);
       HEF_LAUNCH_CHECK();
     }
     // union-find over {p, best(p)}
@@ -1484,6 +1515,7 @@ thread_local int32_t g_levels_run = 0;
 thread_local int32_t g_level_n[kMaxLevelLog];
 thread_local int32_t g_level_m[kMaxLevelLog];
 thread_local int64_t g_level_nnz[kMaxLevelLog];
+thread_local int64_t g_level_work[kMaxLevelLog];
 
 // Persistent part of the coarsening workspace (sized at level 0, which
 // bounds every level).
@@ -1497,6 +1529,7 @@ struct CoarsenWs {
   float *w[2];
   float *eta[2];
   int32_t *label;
+  unsigned long long *work;  // [kMaxLevelLog] candidates screened per level
 };
 
 void carve_coarsen(Arena &a, int64_t n, int64_t m, int64_t nnz, const hef_params &p, CoarsenWs &c) {
@@ -1514,6 +1547,7 @@ void carve_coarsen(Arena &a, int64_t n, int64_t m, int64_t nnz, const hef_params
     c.eta[i] = a.take<float>(n + 1);
   }
   c.label = a.take<int32_t>(n + 1);
+  c.work = a.take<unsigned long long>(kMaxLevelLog);
 }
 
 }  // namespace
@@ -1580,7 +1614,7 @@ hef_status hef_cluster_level(const hef_hypergraph *hg, const hef_params *p, cons
   HEF_TRY(structure_build(L, st, a, stream));
   int32_t ng = 0;
   HEF_TRY(cluster_one_level(L, st, R, eta_in, chi, pt, K, qh, p->percentile,
-                            p->local_clustering != 0, cluster, &ng, eta_out, a, stream));
+                            p->local_clustering != 0, cluster, &ng, eta_out, a, stream, nullptr));
   HEF_HIP(hipStreamSynchronize(stream));
   *n_clusters = ng;
   return HEF_OK;
@@ -1680,6 +1714,8 @@ hef_status hef_coarsen_levels(const hef_hypergraph *hg, const hef_params *p, int
   const float *eta_cur = nullptr;
   int cur = 0;
   g_levels_run = 0;
+  k_zero_u64<<<1, kT, 0, stream>>>(c.work, kMaxLevelLog);
+  HEF_LAUNCH_CHECK();
   if (trace) trace->levels_run = 0;
   // node-reduction target: stop once n_l <= (1 - target_nr) n_0 (0 = off)
   const double n_goal = (1.0 - double(p->target_nr)) * double(n0);
@@ -1712,7 +1748,8 @@ hef_status hef_coarsen_levels(const hef_hypergraph *hg, const hef_params *p, int
     int32_t ng = 0;
     float *eta_next = c.eta[cur];
     HEF_TRY(cluster_one_level(L, c.st, c.R, eta_cur, c.pool, pt, K, c.qh, p->percentile,
-                              p->local_clustering != 0, c.label, &ng, eta_next, a, stream));
+                              p->local_clustering != 0, c.label, &ng, eta_next, a, stream,
+                              lev < kMaxLevelLog ? c.work + lev : nullptr));
     if (tr && trace->label && L.n > 0)
       HEF_HIP(hipMemcpyAsync(trace->label + int64_t(lev) * n0, c.label, sizeof(int32_t) * L.n,
                              hipMemcpyDeviceToDevice, stream));
@@ -1744,9 +1781,23 @@ hef_status hef_coarsen_levels(const hef_hypergraph *hg, const hef_params *p, int
     else
       HEF_HIP(hipMemsetAsync(eta, 0, sizeof(float) * L.n, stream));
   }
+  if (g_levels_run > 0) {
+    unsigned long long wk[kMaxLevelLog];
+    HEF_HIP(hipMemcpyAsync(wk, c.work, sizeof(unsigned long long) * g_levels_run,
+                           hipMemcpyDeviceToHost, stream));
+    HEF_HIP(hipStreamSynchronize(stream));
+    for (int i = 0; i < g_levels_run; ++i) g_level_work[i] = int64_t(wk[i]);
+  }
   HEF_HIP(hipStreamSynchronize(stream));
   *n_clusters = L.n;
   return HEF_OK;
+}
+
+int32_t hef_last_coarsen_work(int64_t *best_candidates, int32_t cap) {
+  const int32_t k = g_levels_run < cap ? g_levels_run : cap;
+  for (int32_t i = 0; i < k; ++i)
+    if (best_candidates) best_candidates[i] = g_level_work[i];
+  return g_levels_run;
 }
 
 int32_t hef_last_coarsen_levels(int32_t *n, int32_t *m, int64_t *nnz, int32_t cap) {

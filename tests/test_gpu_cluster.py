@@ -181,3 +181,25 @@ def test_rebuild_matches_oracle_counts(giant):
     lev = hef.last_coarsen_levels()
     say(f"  level 1: gpu {lev[1]} oracle {(nc1, m1, int(eptr1[-1]))}")
     assert tuple(lev[1]) == (nc1, m1, int(eptr1[-1]))
+
+
+def test_best_search_work_count():
+    # with no contraction (delta is the smallest updated resistance and a
+    # hyperedge contracts only strictly below it) every node with a
+    # hyperedge is isolated, so the best-neighbour search screens one
+    # candidate per co-pin occurrence: sum_e |e| (|e| - 1) at level 0
+    h = make_hypergraph("tiny2k")
+    dh = to_device(h)
+    say("case: work count of the best-neighbour search, tiny2k")
+    hef.coarsen(dh, hef.Params(k=10, b=1, levels=1, percentile=1e-9))
+    w = hef.last_coarsen_work()
+    sz = h.sizes().astype(np.int64)
+    assert w == [int((sz * (sz - 1)).sum())]
+    # the default threshold contracts part of the hyperedges: fewer, not none
+    hef.coarsen(dh, hef.Params(k=10, b=1, levels=2))
+    w2 = hef.last_coarsen_work()
+    say(f"  counts {w} and {w2}")
+    assert len(w2) == 2 and 0 < w2[0] < w[0]
+    # without local clustering nothing is screened
+    hef.coarsen(dh, hef.Params(k=10, b=1, levels=1, local_clustering=False))
+    assert hef.last_coarsen_work() == [0]
