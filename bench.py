@@ -210,8 +210,8 @@ def timed(torch, hef, fn, reps, stages=False):
 
 
 def extras(args, torch, hef, cfg, h, dh, params, levels, B, k):
-    """Side measurements: Alg. 1 alone (FP32 and BF16 pool) with its SpMM
-    rate per level, the BF16 precision report, the node-reduction targets of
+    """Side measurements: Alg. 1 alone (FP32, BF16 and the float64 debug
+    pool) with its SpMM rate per level, the precision report, the node-reduction targets of
     Section IV with their average conductance, the adjoint, and a measured
     copy bandwidth."""
     import numpy as np
@@ -222,7 +222,7 @@ def extras(args, torch, hef, cfg, h, dh, params, levels, B, k):
     spmm_stages = ("spmm_prep", "spmm_csr", "spmm_csc")
     # Alg. 1 alone at level 0 (the resistance estimate), FP32 and BF16 pool
     R = {}
-    for basis in ("fp32", "bf16"):
+    for basis in ("fp32", "bf16", "fp64"):
         p1 = hef.Params(k=cfg["k"], b=cfg["b"], basis=basis, assume_valid=True)
         dt, _, out = timed(torch, hef, lambda: hef.resistance(dh, p1), 3)
         R[basis] = out[0].cpu().numpy()
@@ -256,7 +256,7 @@ def extras(args, torch, hef, cfg, h, dh, params, levels, B, k):
     gold = os.path.join(ROOT, "tests", "golden", f"{args.config}_R_sample.npz")
     if os.path.exists(gold):
         d = np.load(gold)
-        for basis in ("fp32", "bf16"):
+        for basis in ("fp32", "bf16", "fp64"):
             r = R[basis][d["idx"]].astype(np.float64)
             extra[f"{basis}_vs_oracle_sample_norm_rel"] = float(
                 np.linalg.norm(r - d["R"]) / np.linalg.norm(d["R"]))
