@@ -157,6 +157,30 @@ def test_fp64_debug_basis(name, k, b):
         assert np.array_equal(R2.cpu().numpy(), R) and np.array_equal(qh2.cpu().numpy(), qh)
 
 
+@pytest.mark.parametrize("k,b,basis", [(29, 4, "fp32"), (29, 8, "fp32"), (29, 8, "fp64")])
+def test_pool_width_off_the_tile_grid(k, b, basis):
+    # K = 2 k b = 232 = 7 x 32 + 8 or 464 = 14 x 32 + 16: the last Cholesky
+    # panel, the last block column of R^-1 and the last Gram / apply tiles
+    # are partial
+    h = generate(20000, 21000, 2, 2000, 2.7828, p_loc=0.7, weights="lognormal", seed=5)
+    say(f"case: resistance netlist20k k={k} b={b} (K={2 * k * b}) basis={basis}")
+    _parity(h, k, b, basis=basis)
+
+
+def test_long_recurrence_two_passes():
+    # k = 61 steps: the pool is ill-conditioned enough that one FP32 Cholesky
+    # QR loses orthogonality (3e-4); the second pass restores it, and R then
+    # sits at the float64-basis level of the same FP32 recurrence (p99.9
+    # 8.5e-5 there, hence the 2e-4 bar; Q_H 1e-5, hence 2e-5)
+    h = generate(20000, 21000, 2, 2000, 2.7828, p_loc=0.7, weights="lognormal", seed=5)
+    say("case: resistance netlist20k k=61 b=4 (K=488) orth_passes=2")
+    R, qh, chi, est = _parity(h, 61, 4, orth_passes=2, tol_p999=2e-4, tol_qh=2e-5)
+    c = chi.cpu().numpy().astype(np.float64)[:, qh > 0]
+    orth = np.abs(c.T @ c - np.eye(c.shape[1])).max()
+    say(f"  pool orthogonality {orth:.1e}")
+    assert orth < 1e-6
+
+
 def test_counter_generator_start_matches_explicit_start():
     h = make_hypergraph("tiny2k")
     say("case: resistance tiny2k with NULL start blocks")
