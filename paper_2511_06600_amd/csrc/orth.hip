@@ -384,9 +384,13 @@ __device__ __forceinline__ void load8oct(const void *pool, int pool_type, int64_
 // (thread -> row, 8 columns).  The loads are unconditional (addresses
 // clamped into the chunk and the row), so nothing waits on them until the
 // values go to LDS; slab_put applies the row and column masks there and
-// stores the block column-major (column c at S + c * kSLd, rows
-// contiguous), an octet as two 16-byte stores.  Row-major input takes
-// 16-byte loads when K % 8 == 0 and single floats otherwise.
+// stores the block column-major (column c at S + c * kSLd), an octet as two
+// 16-byte stores.  Within column c the groups of 4 rows are permuted: slab
+// row r sits at r ^ slab_swz(c).  The transposed stores of row-major input
+// (16 columns 8 apart, whose starts share a bank since 8 kSLd is a multiple
+// of 32) then spread over all banks, while each 4-row group stays
+// contiguous for the 16-byte operand reads.  Row-major input takes 16-byte
+// loads when K % 8 == 0 and single floats otherwise.
 template <bool OCT>
 __device__ __forceinline__ void slab_get(const float *pool, int64_t r, int64_t r1, int cbase,
                                          int K, int tid, float (&v)[8]) {
@@ -416,25 +420,34 @@ __device__ __forceinline__ void slab_get(const float *pool, int64_t r, int64_t r
   }
 }
 
+// the row permutation of slab column c (c < kSB): an XOR of whole 4-row groups
+__device__ __forceinline__ int slab_swz(int c) { return ((c >> 3) & 15) << 2; }
+
+// Stores the 32 rows h * 32 ... of a slab (r is the first of them).
 template <bool OCT>
-__device__ __forceinline__ void slab_put(float *S, int64_t r, int64_t r1, int cbase, int K, int tid,
-                                         const float (&v)[8]) {
+__device__ __forceinline__ void slab_put(float *S, int h, int64_t r, int64_t r1, int cbase, int K,
+                                         int tid, const float (&v)[8]) {
   float m[8];
   if (OCT) {
     const int64_t rb = r + 8 * (tid >> 7);
-    const bool cok = cbase + (tid & 127) < K;
+    const int c = tid & 127;
+    const bool cok = cbase + c < K;
 #pragma unroll
     for (int q = 0; q < 8; ++q) m[q] = (cok && rb + q < r1) ? v[q] : 0.0f;
-    float *d = S + (tid & 127) * kSLd + 8 * (tid >> 7);
-    *reinterpret_cast<float4 *>(d) = make_float4(m[0], m[1], m[2], m[3]);
-    *reinterpret_cast<float4 *>(d + 4) = make_float4(m[4], m[5], m[6], m[7]);
+    const int row = 32 * h + 8 * (tid >> 7);
+    float *d = S + c * kSLd;
+    *reinterpret_cast<float4 *>(d + (row ^ slab_swz(c))) = make_float4(m[0], m[1], m[2], m[3]);
+    *reinterpret_cast<float4 *>(d + ((row + 4) ^ slab_swz(c))) =
+        make_float4(m[4], m[5], m[6], m[7]);
   } else {
     const bool rok = r + (tid >> 4) < r1;
-    const int c = cbase + (tid & 15) * 8;
+    const int c0 = (tid & 15) * 8;
+    const int c = cbase + c0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) m[q] = (rok && c + q < K) ? v[q] : 0.0f;
+    const int row = (32 * h + (tid >> 4)) ^ slab_swz(c0);  // (the 8 columns share slab_swz)
 #pragma unroll
-    for (int q = 0; q < 8; ++q) S[((tid & 15) * 8 + q) * kSLd + (tid >> 4)] = m[q];
+    for (int q = 0; q < 8; ++q) S[(c0 + q) * kSLd + row] = m[q];
   }
 }
 
@@ -443,12 +456,15 @@ __device__ __forceinline__ void slab_put(float *S, int64_t r, int64_t r1, int cb
 // that each lane reads four consecutive rows of its column at once.
 __device__ __forceinline__ void gram_tile(const float *A, const float *Bm, int lane, int ti, int tj,
                                           floatx16 &acc) {
-  const float *pa = A + (32 * ti + (lane & 31)) * kSLd + (lane >> 5) * (kSlab / 2);
-  const float *pb = Bm + (32 * tj + (lane & 31)) * kSLd + (lane >> 5) * (kSlab / 2);
+  const int ca = 32 * ti + (lane & 31), cb = 32 * tj + (lane & 31);
+  const int h = (lane >> 5) * (kSlab / 2);
+  const float *pa = A + ca * kSLd;
+  const float *pb = Bm + cb * kSLd;
+  const int sa = slab_swz(ca), sb = slab_swz(cb);
 #pragma unroll
   for (int s = 0; s < kSlab / 2; s += 4) {
-    const float4 a = *reinterpret_cast<const float4 *>(pa + s);
-    const float4 b = *reinterpret_cast<const float4 *>(pb + s);
+    const float4 a = *reinterpret_cast<const float4 *>(pa + ((h + s) ^ sa));
+    const float4 b = *reinterpret_cast<const float4 *>(pb + ((h + s) ^ sb));
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, acc, 0, 0, 0);
@@ -517,7 +533,7 @@ k_jgram(const float *__restrict__ pool, const float *__restrict__ poolB, int64_t
   auto stash = [&](int b, int64_t r) __attribute__((always_inline)) {
     float *S = tid < kGT32 / 2 ? As[b] : Bs[b];
 #pragma unroll
-    for (int h = 0; h < kSlab / 32; ++h) slab_put<OCT>(S + 32 * h, r + 32 * h, r1, cb, K, lt, rv[h]);
+    for (int h = 0; h < kSlab / 32; ++h) slab_put<OCT>(S, h, r + 32 * h, r1, cb, K, lt, rv[h]);
   };
   if (loader && r0 < r1) {  // (an empty chunk has nothing to stage)
     fetch(r0);
@@ -987,12 +1003,15 @@ k_japply(const void *__restrict__ V, void *__restrict__ Q, int pool_type, int oc
 //    kA2G consecutive entries of one row of RT (one 16-byte load);
 //  * the wave's two row tiles interleave: lane i of row tile r holds local
 //    row 2i + r, so in the row-octet layout one 8-byte load gives a lane its
-//    A values of both row tiles.
+//    A values of both row tiles;
+//  * a row-major pool with K % 4 == 0 (VEC) gives a lane its kA2G k values
+//    of one row as one 16-byte load (a group's first k is a multiple of 4,
+//    so the group lies wholly inside or wholly past column K).
 constexpr int kA2T = 256;
 constexpr int kA2Rows = 64;
 constexpr int kA2G = 4;  // k steps per register group (4 groups per 32-wide chunk)
 
-template <bool OCT, int NA>
+template <bool OCT, bool VEC, int NA>
 __device__ __forceinline__ void tri_chunks(const float *__restrict__ Vw,
                                            const float *__restrict__ RT, uint32_t vo,
                                            uint32_t vo1, int K, int Kp,
@@ -1013,19 +1032,30 @@ __device__ __forceinline__ void tri_chunks(const float *__restrict__ Vw,
   const char *rt = reinterpret_cast<const char *>(RT);
   auto load = [&](int g, int buf) __attribute__((always_inline)) {
     const int kb = 32 * (g / GPC) + 16 * h + kA2G * (g % GPC);  // first k of the group
+    if constexpr (VEC) {
+      const bool in = kb < K;
+      const uint32_t kk = in ? uint32_t(kb) : 0u;
+      const float4 t0 = *reinterpret_cast<const float4 *>(vb + 4u * (vo + kk));
+      const float4 t1 = *reinterpret_cast<const float4 *>(vb + 4u * (vo1 + kk));
+      a[buf][0][0] = t0.x; a[buf][1][0] = t0.y; a[buf][2][0] = t0.z; a[buf][3][0] = t0.w;
+      a[buf][0][1] = t1.x; a[buf][1][1] = t1.y; a[buf][2][1] = t1.z; a[buf][3][1] = t1.w;
 #pragma unroll
-    for (int s = 0; s < kA2G; ++s) {
-      const int k = kb + s;
-      kin[buf][s] = k < K;
-      const uint32_t kk = k < K ? uint32_t(k) : 0u;
-      if constexpr (OCT) {
-        // rows 2i and 2i + 1 sit side by side in their octet
-        const float2 t = *reinterpret_cast<const float2 *>(vb + 4u * (vo + 8u * kk));
-        a[buf][s][0] = t.x;
-        a[buf][s][1] = t.y;
-      } else {
-        a[buf][s][0] = *reinterpret_cast<const float *>(vb + 4u * (vo + kk));
-        a[buf][s][1] = *reinterpret_cast<const float *>(vb + 4u * (vo1 + kk));
+      for (int s = 0; s < kA2G; ++s) kin[buf][s] = in;
+    } else {
+#pragma unroll
+      for (int s = 0; s < kA2G; ++s) {
+        const int k = kb + s;
+        kin[buf][s] = k < K;
+        const uint32_t kk = k < K ? uint32_t(k) : 0u;
+        if constexpr (OCT) {
+          // rows 2i and 2i + 1 sit side by side in their octet
+          const float2 t = *reinterpret_cast<const float2 *>(vb + 4u * (vo + 8u * kk));
+          a[buf][s][0] = t.x;
+          a[buf][s][1] = t.y;
+        } else {
+          a[buf][s][0] = *reinterpret_cast<const float *>(vb + 4u * (vo + kk));
+          a[buf][s][1] = *reinterpret_cast<const float *>(vb + 4u * (vo1 + kk));
+        }
       }
     }
 #pragma unroll
@@ -1058,11 +1088,12 @@ __device__ __forceinline__ void tri_chunks(const float *__restrict__ Vw,
   if (g < g1) mul(0);
 }
 
-template <bool OCT>
+template <bool OCT, bool VEC>
 __global__ void __launch_bounds__(kA2T) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_japply_tri(const float *__restrict__ V, float *__restrict__ Q, int64_t n, int K, int Kp,
              const float *__restrict__ RT) {
-  static_assert(kA2G == 4, "a group's B values are one float4");
+  static_assert(kA2G == 4, "a group's B values (and VEC's A values) are one float4");
+  static_assert(!(OCT && VEC), "VEC is the row-major layout");
   const int64_t row0 = int64_t(xcd_block(blockIdx.x, gridDim.x)) * kA2Rows;
   // the wave index and everything derived from it are wave-uniform (scalar)
   const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
@@ -1103,10 +1134,10 @@ k_japply_tri(const float *__restrict__ V, float *__restrict__ Q, int64_t n, int 
   const int e2 = nt >= 3 ? ct[2] + 1 : 0;
   const int e1 = nt >= 2 ? ct[1] + 1 : 0;
   const int e0 = ct[0] + 1;
-  if (nt >= 4) tri_chunks<OCT, 4>(Vw, RT, vo, vo1, K, Kp, rb, h, 0, e3, acc);
-  if (nt >= 3) tri_chunks<OCT, 3>(Vw, RT, vo, vo1, K, Kp, rb, h, e3, e2, acc);
-  if (nt >= 2) tri_chunks<OCT, 2>(Vw, RT, vo, vo1, K, Kp, rb, h, e2, e1, acc);
-  tri_chunks<OCT, 1>(Vw, RT, vo, vo1, K, Kp, rb, h, e1, e0, acc);
+  if (nt >= 4) tri_chunks<OCT, VEC, 4>(Vw, RT, vo, vo1, K, Kp, rb, h, 0, e3, acc);
+  if (nt >= 3) tri_chunks<OCT, VEC, 3>(Vw, RT, vo, vo1, K, Kp, rb, h, e3, e2, acc);
+  if (nt >= 2) tri_chunks<OCT, VEC, 2>(Vw, RT, vo, vo1, K, Kp, rb, h, e2, e1, acc);
+  tri_chunks<OCT, VEC, 1>(Vw, RT, vo, vo1, K, Kp, rb, h, e1, e0, acc);
   float *Qw = Q + row0 * int64_t(K);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -1639,8 +1670,11 @@ hef_status apply_run(const void *V, void *Q, int pool_type, int64_t n, int K, in
       k_japply_dma<<<2 * cdiv(n, kDR), kDT, 0, s>>>(reinterpret_cast<const float *>(V),
                                                    reinterpret_cast<float *>(Q), n, K, Kp,
                                                    RinvT32);
+    else if ((K & 3) == 0)
+      k_japply_tri<false, true><<<cdiv(n, kA2Rows), kA2T, 0, s>>>(
+          reinterpret_cast<const float *>(V), reinterpret_cast<float *>(Q), n, K, Kp, RinvT32);
     else
-      k_japply_tri<false><<<cdiv(n, kA2Rows), kA2T, 0, s>>>(
+      k_japply_tri<false, false><<<cdiv(n, kA2Rows), kA2T, 0, s>>>(
           reinterpret_cast<const float *>(V), reinterpret_cast<float *>(Q), n, K, Kp, RinvT32);
     HEF_LAUNCH_CHECK();
     return HEF_OK;
