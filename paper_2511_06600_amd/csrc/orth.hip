@@ -1586,6 +1586,13 @@ k_japply_bf16(const uint16_t *__restrict__ V, uint16_t *__restrict__ Q, int oct,
       }
 }
 
+// Workgroups a Gram launch aims for.  The FP32 kernels hold 128 KB of LDS,
+// one workgroup per CU, and super-tile pairs differ in work (a diagonal pair
+// has 10 of the 16 tiles, and tiles past K are skipped); about eight
+// workgroups per CU even that out, where two left the CUs that drew two
+// large pairs running alone at the end.
+constexpr int kGramWG = 2048;
+
 struct GramPlan {
   int nsb = 0, npairs = 0, nchunks = 0;
   int64_t rows_per_chunk = 0;
@@ -1595,7 +1602,7 @@ GramPlan gram_plan(int64_t n, int K, bool cross = false) {
   GramPlan p;
   p.nsb = (K + kSB - 1) / kSB;
   p.npairs = cross ? p.nsb * p.nsb : p.nsb * (p.nsb + 1) / 2;
-  int64_t want = std::max<int64_t>(1, 512 / p.npairs);
+  int64_t want = std::max<int64_t>(1, kGramWG / p.npairs);
   int64_t per = cdiv(std::max<int64_t>(n, 1), want);
   per = std::max<int64_t>(128, cdiv(per, 128) * 128);  // whole slabs of both kernels
   p.rows_per_chunk = per;
@@ -1698,7 +1705,7 @@ hef_status apply_run(const void *V, void *Q, int pool_type, int64_t n, int K, in
 // need more partials than the finest.
 int64_t gram_max_chunks(int64_t n, int K, bool cross) {
   const GramPlan p = gram_plan(n, K, cross);
-  const int64_t want = std::max<int64_t>(1, 512 / p.npairs);
+  const int64_t want = std::max<int64_t>(1, kGramWG / p.npairs);
   return std::max<int64_t>(1, std::min<int64_t>(want, cdiv(std::max<int64_t>(n, 1), 128)));
 }
 
