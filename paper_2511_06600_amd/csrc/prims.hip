@@ -74,6 +74,35 @@ k_scan_add(int32_t *out, const int32_t *tile_off, int64_t n) {
   }
 }
 
+// Adds to every item of tile t the sum of the tiles before it, a block
+// reduction over tile_sums[0, t) (integer sums, so the order does not
+// matter); the last tile's block also writes the total to out[n].  Up to
+// kFinishTiles tiles this replaces the two kernels above: re-reading the
+// earlier sums (at most kFinishTiles^2 / 2 reads, from L2) costs less than a
+// launch.
+constexpr int64_t kFinishTiles = 2048;
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_finish(int32_t *out, const int32_t *tile_sums, int64_t n, int64_t ntiles) {
+  __shared__ int32_t red[kScanThreads / 64];
+  const int tid = threadIdx.x;
+  const int64_t t = blockIdx.x;
+  int32_t acc = 0;
+  for (int64_t j = tid; j < t; j += kScanThreads) acc += tile_sums[j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
+  if ((tid & 63) == 0) red[tid >> 6] = acc;
+  __syncthreads();
+  int32_t add = 0;
+#pragma unroll
+  for (int w = 0; w < kScanThreads / 64; ++w) add += red[w];
+  const int64_t base = t * kScanTile;
+  for (int i = tid; i < kScanTile; i += kScanThreads) {
+    const int64_t q = base + i;
+    if (q < n) out[q] += add;
+  }
+  if (t == ntiles - 1 && tid == 0) out[n] = add + tile_sums[t];
+}
+
 constexpr int kRadixBits = 8;
 constexpr int kBins = 1 << kRadixBits;
 constexpr int kRadixThreads = 256;
@@ -95,17 +124,56 @@ k_radix_hist(const uint32_t *keys, int64_t n, int shift, int32_t *hist, int nblo
   hist[int64_t(tid) * nblocks + blockIdx.x] = cnt[tid];
 }
 
+// The histogram scan folded into the scatter: when the histogram has at most
+// kRadixScanTiles scan tiles, it is scanned within tiles only (k_scan_tiles)
+// and each scatter block adds the tile prefixes itself, from an exclusive
+// scan of the tile sums in LDS (each thread takes a run of kTileRun sums).
+constexpr int kTileRun = 8;
+constexpr int kRadixScanTiles = kRadixThreads * kTileRun;
+
 // Each block re-reads its tile and places every item at
 // offset[digit][block] + (items of the same digit earlier in the tile).
+// offs holds the exclusive scan of the histogram (digit-major), or with
+// tile_sums given its scan within scan tiles, to which the block adds the
+// sum of the scan tiles before each entry's.
 __global__ void __launch_bounds__(kRadixThreads)
 k_radix_scatter(const uint32_t *kin, const uint32_t *vin, uint32_t *kout,
-                uint32_t *vout, int64_t n, int shift, const int32_t *offs, int nblocks) {
+                uint32_t *vout, int64_t n, int shift, const int32_t *offs, int nblocks,
+                const int32_t *tile_sums, int ntiles) {
   __shared__ int32_t base_cnt[kBins];
   __shared__ int32_t wcnt[kRadixThreads / 64][kBins];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
-  base_cnt[tid] = offs[int64_t(tid) * nblocks + blockIdx.x];
+  const int64_t hidx = int64_t(tid) * nblocks + blockIdx.x;
+  base_cnt[tid] = offs[hidx];
+  if (tile_sums) {
+    // exclusive prefix of the tile sums: a run of kTileRun per thread, a
+    // scan of the run totals (in wcnt[0], free until the rounds below),
+    // then each run's prefixes
+    __shared__ int32_t tpre[kRadixScanTiles];
+    int32_t run[kTileRun];
+    int32_t tot = 0;
+#pragma unroll
+    for (int q = 0; q < kTileRun; ++q) {
+      const int t = tid * kTileRun + q;
+      run[q] = tot;
+      tot += t < ntiles ? tile_sums[t] : 0;
+    }
+    wcnt[0][tid] = tot;
+    __syncthreads();
+    for (int off = 1; off < kRadixThreads; off <<= 1) {
+      const int32_t x = tid >= off ? wcnt[0][tid - off] : 0;
+      __syncthreads();
+      wcnt[0][tid] += x;
+      __syncthreads();
+    }
+    const int32_t before = wcnt[0][tid] - tot;
+#pragma unroll
+    for (int q = 0; q < kTileRun; ++q) tpre[tid * kTileRun + q] = before + run[q];
+    __syncthreads();
+    base_cnt[tid] += tpre[hidx / kScanTile];
+  }
   const int64_t base = int64_t(blockIdx.x) * kRadixTile;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int r = 0; r < kRadixRounds; ++r) {
@@ -229,8 +297,12 @@ hef_status exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, Arena 
     return HEF_OK;
   }
   k_scan_tiles<<<ntiles, kScanThreads, 0, s>>>(in, out, sums, n);
-  k_scan_sums<<<1, 1024, 0, s>>>(sums, ntiles, out + n);
-  k_scan_add<<<ntiles, kScanThreads, 0, s>>>(out, sums, n);
+  if (ntiles <= kFinishTiles) {
+    k_scan_finish<<<ntiles, kScanThreads, 0, s>>>(out, sums, n, ntiles);
+  } else {
+    k_scan_sums<<<1, 1024, 0, s>>>(sums, ntiles, out + n);
+    k_scan_add<<<ntiles, kScanThreads, 0, s>>>(out, sums, n);
+  }
   HEF_LAUNCH_CHECK();
   ws.reset(mk);
   return HEF_OK;
@@ -253,11 +325,21 @@ hef_status radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_out,
   HEF_WS_CHECK(ws);
   const int passes = (bits + kRadixBits - 1) / kRadixBits;
   uint32_t *ka = keys, *va = vals, *kb = keys_out, *vb = vals_out;
+  // the histogram's scan tiles: when there are at most kRadixScanTiles
+  // (n up to 64M keys) the scatter adds their prefixes itself
+  const int64_t htiles = cdiv(nb * kBins, kScanTile);
+  int32_t *tsum = htiles <= kRadixScanTiles ? ws.take<int32_t>(htiles) : nullptr;
+  HEF_WS_CHECK(ws);
   for (int p = 0; p < passes; ++p) {
     const int shift = p * kRadixBits;
     k_radix_hist<<<nb, kRadixThreads, 0, s>>>(ka, n, shift, hist, int(nb));
-    HEF_TRY(exclusive_scan_i32(hist, hist, nb * kBins, ws, s));
-    k_radix_scatter<<<nb, kRadixThreads, 0, s>>>(ka, va, kb, vb, n, shift, hist, int(nb));
+    if (tsum) {
+      k_scan_tiles<<<htiles, kScanThreads, 0, s>>>(hist, hist, tsum, nb * kBins);
+    } else {
+      HEF_TRY(exclusive_scan_i32(hist, hist, nb * kBins, ws, s));
+    }
+    k_radix_scatter<<<nb, kRadixThreads, 0, s>>>(ka, va, kb, vb, n, shift, hist, int(nb), tsum,
+                                                 int(htiles));
     HEF_LAUNCH_CHECK();
     std::swap(ka, kb);
     std::swap(va, vb);
