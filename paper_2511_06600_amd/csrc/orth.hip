@@ -54,6 +54,9 @@ constexpr int kMaxPB = 16;    // 32-column blocks of the widest pool (K <= 512)
 // Workgroup 0 also writes the diagonal block, keep and rho.
 constexpr int kCT = 256;  // panel threads: one row below the diagonal block each
 
+// FULL: the panel has kPW columns (every panel but a narrower last one), so
+// the column bounds are compile-time and the unrolled steps carry no tests.
+template <bool FULL>
 __global__ void __launch_bounds__(kCT)
 k_chol_panel(const double *__restrict__ A, const double *__restrict__ G, int K, int c0,
              double tau, double *__restrict__ LT, int32_t *__restrict__ keep,
@@ -62,7 +65,7 @@ k_chol_panel(const double *__restrict__ A, const double *__restrict__ G, int K, 
   __shared__ double s_piv[kPW];
   __shared__ int s_kp[kPW];
   const int t = threadIdx.x;
-  const int w = K - c0 < kPW ? K - c0 : kPW;
+  const int w = FULL ? kPW : (K - c0 < kPW ? K - c0 : kPW);
   const int nr = K - c0;
   if (t < 64) {
     const int r = t & (kPW - 1);
@@ -1794,8 +1797,14 @@ hef_status orthonormalize_pool(void *P, void *out, int pool_type, int64_t n, int
       for (int c0 = 0; c0 < K; c0 += kPW) {
         const int w = K - c0 < kPW ? K - c0 : kPW;
         const int nb = K - c0 - w > 0 ? int(cdiv(K - c0 - w, kCT)) : 1;
-        k_chol_panel<<<nb, kCT, 0, s>>>(A, G, K, c0, tau, LT, keep, pass == 0 ? nullptr : keep,
-                                        pass == 0 ? rho_out : nullptr);
+        if (w == kPW)
+          k_chol_panel<true><<<nb, kCT, 0, s>>>(A, G, K, c0, tau, LT, keep,
+                                                pass == 0 ? nullptr : keep,
+                                                pass == 0 ? rho_out : nullptr);
+        else
+          k_chol_panel<false><<<nb, kCT, 0, s>>>(A, G, K, c0, tau, LT, keep,
+                                                 pass == 0 ? nullptr : keep,
+                                                 pass == 0 ? rho_out : nullptr);
         const int nt = (K - c0 - w + kPW - 1) / kPW;
         if (nt > 0) k_chol_update<<<nt * (nt + 1) / 2, 256, 0, s>>>(A, LT, K, c0, w);
       }
