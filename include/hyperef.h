@@ -178,7 +178,12 @@ hef_status hef_resistance(const hef_hypergraph *hg, const hef_params *p,
  * HEF_ERR_WORKSPACE_TOO_SMALL with nothing written.  All calls on one device
  * share that device's scratch, which keeps the last call's contents (every
  * call initialises what it reads): calls that overlap on one device -- on
- * two streams or from two threads -- race and give undefined results. */
+ * two streams or from two threads -- race and give undefined results.  With
+ * HEF_FLAG_ASSUME_VALID the call synchronises nothing and enqueues only
+ * kernels and device-to-device copies (buffers are cleared by kernels, not
+ * hipMemsetAsync), so it can be captured into a HIP graph; every replay
+ * recomputes the result.  Make one call before capturing: the first call on
+ * a device looks up the scratch array's address. */
 #define HEF_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
 hef_status hef_resistance_static(const hef_hypergraph *hg, const hef_params *p,
                                  const float *start_star, const float *start_clique, float *R,

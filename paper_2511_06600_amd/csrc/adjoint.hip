@@ -954,12 +954,12 @@ hef_status reverse_sweep(const Level &L, const hef_params &p, const float *dR, f
   HEF_TRY(gemm_f32(w.chi, n, K, w.W2, Kp, pbar, true, s));
 
   // ---- 3. Lanczos steps in reverse, segment by segment
-  HEF_HIP(hipMemsetAsync(w.abar_s, 0, sizeof(float) * 3 * Ns * B, s));
-  HEF_HIP(hipMemsetAsync(w.abar_c, 0, sizeof(float) * 3 * n * B, s));
-  HEF_HIP(hipMemsetAsync(w.znode, 0, sizeof(double) * n, s));
-  HEF_HIP(hipMemsetAsync(w.hnode, 0, sizeof(double) * n, s));
-  HEF_HIP(hipMemsetAsync(w.eacc, 0, sizeof(double) * m, s));
-  HEF_HIP(hipMemsetAsync(w.X3, 0, sizeof(double) * 2 * C * B, s));
+  HEF_TRY(zero_async(w.abar_s, sizeof(float) * 3 * Ns * B, s));
+  HEF_TRY(zero_async(w.abar_c, sizeof(float) * 3 * n * B, s));
+  HEF_TRY(zero_async(w.znode, sizeof(double) * n, s));
+  HEF_TRY(zero_async(w.hnode, sizeof(double) * n, s));
+  HEF_TRY(zero_async(w.eacc, sizeof(double) * m, s));
+  HEF_TRY(zero_async(w.X3, sizeof(double) * 2 * C * B, s));
   const int seg = w.tape.seg;
   const int nseg = (k + seg - 1) / seg;
   const int mask = (use_star ? 1 : 0) | (use_clique ? 2 : 0);
@@ -1083,7 +1083,7 @@ hef_status hef_resistance_backward(const hef_hypergraph *hg, const hef_params *p
   }
   if (L.m == 0) return HEF_OK;
   if (L.n == 0) {
-    HEF_HIP(hipMemsetAsync(dw, 0, sizeof(float) * L.m, stream));
+    HEF_TRY(zero_async(dw, sizeof(float) * L.m, stream));
     return HEF_OK;
   }
   BwdWs w;
@@ -1126,7 +1126,7 @@ hef_status hef_resistance_taped(const hef_hypergraph *hg, const hef_params *p,
   }
   if (L.m == 0) return HEF_OK;
   if (L.n == 0) {
-    HEF_HIP(hipMemsetAsync(R, 0, sizeof(float) * L.m, stream));
+    HEF_TRY(zero_async(R, sizeof(float) * L.m, stream));
     return HEF_OK;
   }
   BwdWs w;

@@ -1265,7 +1265,7 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
         return HEF_ERR_NUMERICAL;
       }
       for (int r = 0; r < kRoundsPerSync; ++r, ++round) {
-        HEF_HIP(hipMemsetAsync(w.small, 0, sizeof(int32_t), s));
+        HEF_TRY(zero_async(w.small, sizeof(int32_t), s));
         k_round_propose<<<g1(m), kT, 0, s>>>(L.eptr, L.pins, w.rank, w.state, w.owner, w.packed,
                                             round, int32_t(m), w.small);
         k_round_select<<<g1(m), kT, 0, s>>>(L.eptr, L.pins, w.rank, w.state, w.owner, w.packed,
@@ -1338,10 +1338,10 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
       // two hook + compress rounds per host check (a settled forest is
       // left unchanged by further rounds)
       for (int it = 0; it < 64; it += 2) {
-        HEF_HIP(hipMemsetAsync(w.small + 2, 0, sizeof(int32_t), s));
+        HEF_TRY(zero_async(w.small + 2, sizeof(int32_t), s));
         k_uf_hook<<<g1(n), kT, 0, s>>>(w.best_label, w.parent, int32_t(n), w.small + 2);
         k_uf_compress<<<g1(n), kT, 0, s>>>(w.parent, int32_t(n));
-        HEF_HIP(hipMemsetAsync(w.small + 2, 0, sizeof(int32_t), s));
+        HEF_TRY(zero_async(w.small + 2, sizeof(int32_t), s));
         k_uf_hook<<<g1(n), kT, 0, s>>>(w.best_label, w.parent, int32_t(n), w.small + 2);
         k_uf_compress<<<g1(n), kT, 0, s>>>(w.parent, int32_t(n));
         HEF_LAUNCH_CHECK();
@@ -1433,7 +1433,7 @@ hef_status rebuild_level(const Level &L, const Structure &st, const int32_t *lab
   *m2_host = 0;
   *nnz2_host = 0;
   if (m == 0 || nnz == 0) {
-    HEF_HIP(hipMemsetAsync(eptr2, 0, sizeof(int32_t), s));
+    HEF_TRY(zero_async(eptr2, sizeof(int32_t), s));
     ws.reset(mk);
     return HEF_OK;
   }
@@ -1455,7 +1455,7 @@ hef_status rebuild_level(const Level &L, const Structure &st, const int32_t *lab
     return t3[2] ? HEF_ERR_UNSUPPORTED : HEF_OK;
   };
   // per-hyperedge sorts
-  HEF_HIP(hipMemsetAsync(misc, 0, sizeof(int32_t), s));
+  HEF_TRY(zero_async(misc, sizeof(int32_t), s));
   k_elab_small<<<g1(m), kT, 0, s>>>(L.eptr, L.pins, label, int32_t(m), k0, cnt);
   k_elab_big<<<1024, kT, 0, s>>>(st.big_e, st.n_big, L.eptr, L.pins, label, k0, cnt, misc);
   HEF_LAUNCH_CHECK();
@@ -1598,7 +1598,7 @@ hef_status hef_cluster_level(const hef_hypergraph *hg, const hef_params *p, cons
   }
   const int pt = p->basis == HEF_BASIS_BF16 ? kPoolBF16 : kPoolF32;
   if (p->local_clustering && hg->n > 0 && K > 0) {
-    HEF_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t), stream));
+    HEF_TRY(zero_async(flags, sizeof(int32_t), stream));
     const int64_t cnt = int64_t(hg->n) * K;
     const unsigned nb = unsigned(std::min<int64_t>(cdiv(cnt, kT), 4096));
     if (pt == kPoolF32) k_pool_range<kPoolF32><<<nb, kT, 0, stream>>>(chi, cnt, flags);
@@ -1653,7 +1653,7 @@ hef_status hef_rebuild(const hef_hypergraph *hg, const int32_t *label, int32_t n
   HEF_TRY(validate_device(L, flags, &bad, stream));
   if (bad) { set_error("invalid hypergraph (code %d)", bad); return HEF_ERR_INVALID_HYPERGRAPH; }
   if (hg->n > 0 && hg->nnz > 0) {
-    HEF_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t), stream));
+    HEF_TRY(zero_async(flags, sizeof(int32_t), stream));
     k_label_range<<<g1(hg->nnz), kT, 0, stream>>>(hg->pins, label, hg->nnz, n_clusters, flags);
     HEF_LAUNCH_CHECK();
     int32_t f = 0;
@@ -1779,7 +1779,7 @@ hef_status hef_coarsen_levels(const hef_hypergraph *hg, const hef_params *p, int
     if (eta_cur)
       HEF_HIP(hipMemcpyAsync(eta, eta_cur, sizeof(float) * L.n, hipMemcpyDeviceToDevice, stream));
     else
-      HEF_HIP(hipMemsetAsync(eta, 0, sizeof(float) * L.n, stream));
+      HEF_TRY(zero_async(eta, sizeof(float) * L.n, stream));
   }
   if (g_levels_run > 0) {
     unsigned long long wk[kMaxLevelLog];

@@ -425,13 +425,13 @@ hef_status resistance_call(const hef_hypergraph *hg, const hef_params *p, const 
     }
   }
   if (n == 0 || m == 0) {
-    if (qh && K) HEF_HIP(hipMemsetAsync(qh, 0, K * sizeof(double), stream));
+    if (qh && K) HEF_TRY(zero_async(qh, K * sizeof(double), stream));
     return HEF_OK;
   }
   HEF_TRY(estimate_level(L, *p, p->seed, 0, start_star, start_clique, st, pool, pool2, qh_ws,
                          R_ws, a, stream));
   if (check) {
-    HEF_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t), stream));
+    HEF_TRY(zero_async(flags, sizeof(int32_t), stream));
     k_check_finite<<<cdiv(std::max<int64_t>(m, K), 256), 256, 0, stream>>>(R_ws, m, qh_ws, K, flags);
     HEF_LAUNCH_CHECK();
     int32_t f = 0;

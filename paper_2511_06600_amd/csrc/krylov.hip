@@ -669,8 +669,8 @@ hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double
   const int C = 3 * B;
   double *Gs = G, *Gc = G + C * C;
   double *ps = partial, *pc = partial + size_t(kGramBlocks) * 9 * B * B;
-  HEF_HIP(hipMemsetAsync(drops, 0, 2 * sizeof(int32_t), s));
-  HEF_HIP(hipMemsetAsync(G, 0, 2 * 48 * 48 * sizeof(double), s));
+  HEF_TRY(zero_async(drops, 2 * sizeof(int32_t), s));
+  HEF_TRY(zero_async(G, 2 * 48 * 48 * sizeof(double), s));
   // per-step T (and R^-1 for the adjoint)
   auto t_of = [&](int j) { return tape ? tape->T + size_t(j) * 2 * C * B : Tm; };
   auto r_of = [&](int j) { return tape ? tape->Rinv + size_t(j) * 2 * C * C : nullptr; };
@@ -683,13 +683,13 @@ hef_status krylov_pool(const Level &L, const Structure &st, int B, int k, double
     if (use_star) {
       float *d = tape->ck_star + slot * 2 * Ns * B;
       if (vs_prev) HEF_HIP(hipMemcpyAsync(d, vs_prev, Ns * B * sizeof(float), hipMemcpyDeviceToDevice, s));
-      else HEF_HIP(hipMemsetAsync(d, 0, Ns * B * sizeof(float), s));
+      else HEF_TRY(zero_async(d, Ns * B * sizeof(float), s));
       HEF_HIP(hipMemcpyAsync(d + Ns * B, vs, Ns * B * sizeof(float), hipMemcpyDeviceToDevice, s));
     }
     if (use_clique) {
       float *d = tape->ck_clique + slot * 2 * n * B;
       if (vc_prev) HEF_HIP(hipMemcpyAsync(d, vc_prev, n * B * sizeof(float), hipMemcpyDeviceToDevice, s));
-      else HEF_HIP(hipMemsetAsync(d, 0, n * B * sizeof(float), s));
+      else HEF_TRY(zero_async(d, n * B * sizeof(float), s));
       HEF_HIP(hipMemcpyAsync(d + n * B, vc, n * B * sizeof(float), hipMemcpyDeviceToDevice, s));
     }
     return HEF_OK;

@@ -1621,7 +1621,7 @@ hef_status gram_run(const void *pool, const void *poolB, int pool_type, int64_t 
   const int64_t tot = int64_t(p.npairs) * 16 * 1024;
   double *sums = ws.take<double>(tot);
   HEF_WS_CHECK(ws);
-  HEF_HIP(hipMemsetAsync(G, 0, sizeof(double) * K * K, s));
+  HEF_TRY(zero_async(G, sizeof(double) * K * K, s));
   {
   TimedScope ts(kStOrthGram, s);
   if (pool_type == kPoolF64) {
@@ -1789,11 +1789,11 @@ hef_status orthonormalize_pool(void *P, void *out, int pool_type, int64_t n, int
       const size_t lds_c = size_t(K) * kPS * sizeof(double);
       HEF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_jtrinv),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_c)));
-      HEF_HIP(hipMemsetAsync(Rinv, 0, sizeof(double) * Kp * Kp, s));
-      HEF_HIP(hipMemsetAsync(Rinv32, 0, sizeof(float) * Kp * Kp, s));
-      HEF_HIP(hipMemsetAsync(RinvT32, 0, sizeof(float) * Kp * Kp, s));
+      HEF_TRY(zero_async(Rinv, sizeof(double) * Kp * Kp, s));
+      HEF_TRY(zero_async(Rinv32, sizeof(float) * Kp * Kp, s));
+      HEF_TRY(zero_async(RinvT32, sizeof(float) * Kp * Kp, s));
       HEF_HIP(hipMemcpyAsync(A, G, sizeof(double) * K * K, hipMemcpyDeviceToDevice, s));
-      HEF_HIP(hipMemsetAsync(LT, 0, sizeof(double) * K * K, s));
+      HEF_TRY(zero_async(LT, sizeof(double) * K * K, s));
       for (int c0 = 0; c0 < K; c0 += kPW) {
         const int w = K - c0 < kPW ? K - c0 : kPW;
         const int nb = K - c0 - w > 0 ? int(cdiv(K - c0 - w, kCT)) : 1;

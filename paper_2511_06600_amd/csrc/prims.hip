@@ -253,12 +253,38 @@ k_reduce_cols(const double *__restrict__ in0, int64_t nrows0, double *__restrict
   if (rl == 0 && c < ncols) out[c] = red[0][cl];
 }
 
+// 4-byte words when the pointer and the size allow it, else bytes.
+__global__ void k_zero_words(uint32_t *p, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = 0u;
+}
+
+__global__ void k_zero_bytes(uint8_t *p, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = 0u;
+}
+
 __global__ void k_flag_copy(const int32_t *flag, int32_t *out, int64_t n) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) out[i] = flag[i] ? 1 : 0;
 }
 
 }  // namespace
+
+hef_status zero_async(void *p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return HEF_OK;
+  const bool words = ((reinterpret_cast<uintptr_t>(p) | bytes) & 3) == 0;
+  const int64_t n = int64_t(words ? bytes / 4 : bytes);
+  const int64_t nb = std::min<int64_t>(cdiv(n, 256), 4096);
+  if (words)
+    k_zero_words<<<nb, 256, 0, s>>>(static_cast<uint32_t *>(p), n);
+  else
+    k_zero_bytes<<<nb, 256, 0, s>>>(static_cast<uint8_t *>(p), n);
+  HEF_LAUNCH_CHECK();
+  return HEF_OK;
+}
 
 hef_status reduce_cols_f64(const double *in, int64_t nrows, int64_t ncols, double *out,
                            hipStream_t s) {
@@ -292,7 +318,7 @@ hef_status exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, Arena 
   int32_t *sums = ws.take<int32_t>(ntiles + 1);
   HEF_WS_CHECK(ws);
   if (n == 0) {
-    HEF_HIP(hipMemsetAsync(out, 0, sizeof(int32_t), s));
+    HEF_TRY(zero_async(out, sizeof(int32_t), s));
     ws.reset(mk);
     return HEF_OK;
   }
@@ -355,7 +381,7 @@ hef_status radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_out,
 hef_status compact_flags(const int32_t *flag, int32_t *scratch, int32_t *idx_out,
                          int32_t *count_dev, int64_t n, Arena &ws, hipStream_t s) {
   if (n == 0) {
-    HEF_HIP(hipMemsetAsync(count_dev, 0, sizeof(int32_t), s));
+    HEF_TRY(zero_async(count_dev, sizeof(int32_t), s));
     return HEF_OK;
   }
   k_flag_copy<<<cdiv(n, 256), 256, 0, s>>>(flag, scratch, n);

@@ -37,6 +37,11 @@ hef_status reduce_cols_f64_pair(const double *in0, int64_t nrows0, double *out0,
                                 const double *in1, int64_t nrows1, double *out1, int64_t ncols,
                                 hipStream_t s);
 
+// Zeroes `bytes` bytes at p on stream s with a fill kernel rather than
+// hipMemsetAsync, so that a caller capturing the stream into a HIP graph
+// records kernel nodes only.
+hef_status zero_async(void *p, size_t bytes, hipStream_t s);
+
 inline int bits_for(int64_t maxval) {
   int b = 1;
   while (b < 32 && (int64_t(1) << b) <= maxval) ++b;

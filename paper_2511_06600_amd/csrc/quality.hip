@@ -274,8 +274,8 @@ extern "C" hef_status hef_conductance(const hef_hypergraph *hg, const int32_t *l
     HEF_HIP(hipStreamSynchronize(stream));
     return HEF_OK;
   }
-  HEF_HIP(hipMemsetAsync(q.bad, 0, sizeof(int32_t), stream));
-  HEF_HIP(hipMemsetAsync(q.split, 0, m * sizeof(int32_t), stream));
+  HEF_TRY(zero_async(q.bad, sizeof(int32_t), stream));
+  HEF_TRY(zero_async(q.split, m * sizeof(int32_t), stream));
   k_qual_emit<<<cdiv(nnz, kQT), kQT, 0, stream>>>(L.eptr, L.pins, label, int32_t(m), nnz, nc,
                                                    q.k0, q.v0, q.split, q.bad);
   HEF_LAUNCH_CHECK();

@@ -174,7 +174,7 @@ hef_status rating_run(const Level &L, const float *R, float shift, int32_t *best
     return HEF_ERR_INVALID_HYPERGRAPH;
   }
   if (m > 0) {
-    HEF_HIP(hipMemsetAsync(flags, 0, sizeof(int32_t), s));
+    HEF_TRY(zero_async(flags, sizeof(int32_t), s));
     k_rate_check<<<gr(m), kRT, 0, s>>>(R, m, flags);
     HEF_LAUNCH_CHECK();
     int32_t f = 0;

@@ -147,7 +147,7 @@ size_t structure_build_ws(int64_t n, int64_t m, int64_t nnz) {
 
 hef_status validate_device(const Level &L, int32_t *flag_dev, int32_t *bad_host,
                            hipStream_t s) {
-  HEF_HIP(hipMemsetAsync(flag_dev, 0, sizeof(int32_t), s));
+  HEF_TRY(zero_async(flag_dev, sizeof(int32_t), s));
   if (L.m > 0)
     k_validate<<<cdiv(L.m, 256), 256, 0, s>>>(L.eptr, L.pins, L.w, L.n, L.m, L.nnz, flag_dev);
   HEF_LAUNCH_CHECK();
@@ -180,7 +180,7 @@ hef_status structure_build(const Level &L, Structure &st, Arena &ws, hipStream_t
     k_seg_bounds<<<cdiv(nnz + 1, 256), 256, 0, s>>>(keys_out, nnz, int32_t(n), st.vptr);
     HEF_LAUNCH_CHECK();
   } else {
-    HEF_HIP(hipMemsetAsync(st.vptr, 0, (n + 1) * sizeof(int32_t), s));
+    HEF_TRY(zero_async(st.vptr, (n + 1) * sizeof(int32_t), s));
   }
 
   // scales and big-segment lists
