@@ -269,10 +269,12 @@ k_lsolve(const double *__restrict__ Gall, int B, double tau, double *__restrict_
       const double lkk = sqrt(d);
       const double lk = t == k ? lkk : (t > k ? a[k] / lkk : 0.0);
       l[k] = lk;
+      // (also the entries right of lane t's diagonal, which are never read:
+      // an unpredicated update; lk is zero on the rows above the pivot)
 #pragma unroll
       for (int j = k + 1; j < C; ++j) {
         const double ljk = readlane_f64(lk, j);
-        if (j <= t) a[j] -= lk * ljk;
+        a[j] -= lk * ljk;
       }
     }
   }
