@@ -182,7 +182,9 @@ def best_bytes(work):
 
 
 def roofline_entry(bound, amount, ms_total, launches, peak, unit, kernels, traffic=None):
-    if bound == "hbm":
+    if ms_total <= 0:  # (not timed: --stage-steps 0)
+        ach = 0.0
+    elif bound == "hbm":
         ach = amount / (ms_total / 1e3) / 1e9
     else:
         ach = amount / (ms_total / 1e3) / 1e12
@@ -359,6 +361,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="large2m")
+    ap.add_argument("--stage-steps", type=int, default=2,
+                    help="steps after the timed ones with an event pair around every stage, "
+                         "for the per-stage times and the rooflines of the other kernels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the Alg. 1-only, BF16 and adjoint side measurements")
@@ -403,6 +408,10 @@ def main():
         hef.coarsen(dh, params)
     torch.cuda.synchronize()
     hef.timing_read(reset=True)
+    # the timed steps carry HIP events only around each fused SpMM (the
+    # dominant kernel): an event pair per stage of every call would add
+    # about 5 % to the step
+    hef.timing_stages(["spmm_step"])
     hef.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -411,26 +420,39 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     hef.timing_enable(False)
-    stages = hef.timing_read(reset=True)
+    span = hef.timing_read(reset=True)
+    hef.timing_stages(None)
     levels = hef.last_coarsen_levels()
     work = hef.last_coarsen_work()
     ms_step = (t1 - t0) / args.steps * 1e3
     est_per_step = sum(lv[1] for lv in levels)
     value = est_per_step / (ms_step / 1e3)
     print(f"# step {ms_step:.2f} ms, levels {levels}", file=sys.stderr, flush=True)
+    # the other kernels' times: further steps, after the timed ones, with an
+    # event pair around every stage
+    SR = args.stage_steps
+    stages = {}
+    if SR > 0:
+        hef.timing_enable(True)
+        for _ in range(SR):
+            hef.coarsen(dh, params)
+        torch.cuda.synchronize()
+        hef.timing_enable(False)
+        stages = hef.timing_read(reset=True)
 
-    # ---- rooflines over the timed region
+    # ---- rooflines: the fused SpMM over the timed steps, the rest over the
+    # stage-timed steps
     per = {k: v for k, v in stages.items() if v[1]}
-    stage_ms = {k: round(v[0] / args.steps, 3)
+    stage_ms = {k: round(v[0] / SR, 3)
                 for k, v in sorted(per.items(), key=lambda kv: -kv[1][0])}
     S, B, k, K = args.steps, params.b, params.k, params.K
     spmm_b = sum(spmm_step_bytes(n, m, z, B) for (n, m, z) in levels) * k * S
-    lg_b = sum(lanczos_bytes(n, m, B, k)[0] for (n, m, _) in levels) * S
-    la_b = sum(lanczos_bytes(n, m, B, k)[1] for (n, m, _) in levels) * S
-    jg_f = sum(gram_flops(n, K) for (n, _, _) in levels) * S
-    ja_f = sum(apply_flops(n, K) for (n, _, _) in levels) * S
-    sc_b = sum(score_bytes(n, m, z, K) for (n, m, z) in levels) * S
-    sq_b = sum(score_qh_bytes(n, m, z, K) for (n, m, z) in levels) * S
+    lg_b = sum(lanczos_bytes(n, m, B, k)[0] for (n, m, _) in levels) * SR
+    la_b = sum(lanczos_bytes(n, m, B, k)[1] for (n, m, _) in levels) * SR
+    jg_f = sum(gram_flops(n, K) for (n, _, _) in levels) * SR
+    ja_f = sum(apply_flops(n, K) for (n, _, _) in levels) * SR
+    sc_b = sum(score_bytes(n, m, z, K) for (n, m, z) in levels) * SR
+    sq_b = sum(score_qh_bytes(n, m, z, K) for (n, m, z) in levels) * SR
     traffic = read_traffic()
     nfused = k * len(levels)  # fused SpMM launches per step
 
@@ -443,10 +465,10 @@ def main():
         tot = sum(traffic[kk][0] + traffic[kk][1] for kk in kernels)
         return tot / launches
 
-    spmm_stages = ("spmm_prep", "spmm_csr", "spmm_csc")
+    spmm_ms = span.get("spmm_step", (0.0, 0))[0]
     rooflines = {
         "a2_spmm": roofline_entry(
-            "hbm", spmm_b, ms_of(*spmm_stages), nfused * S, PEAK_HBM_GBS, "GB/s",
+            "hbm", spmm_b, spmm_ms, nfused * S, PEAK_HBM_GBS, "GB/s",
             ["k_prep", "k_csr", "k_csc"],
             traffic_of(["k_prep", "k_csr", "k_csc"],
                        nfused)),
@@ -472,7 +494,7 @@ def main():
         # the best-neighbour search: every screened (node, candidate) pair
         # reads the first 128 columns of the candidate's float16 centroid
         # copy (256 bytes); the pairs are counted on the device per level
-        "k_best": roofline_entry("hbm", best_bytes(work) * S, ms_of("cluster_best"),
+        "k_best": roofline_entry("hbm", best_bytes(work) * SR, ms_of("cluster_best"),
                                  per.get("cluster_best", (0, 0))[1], PEAK_HBM_GBS, "GB/s",
                                  ["k_best"], traffic_of(["k_best"], len(levels))),
     }

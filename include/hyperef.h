@@ -395,8 +395,14 @@ const char *hef_last_error(void);
  * elapsed times to per-stage totals, copies the totals (milliseconds) and
  * launch counts of the first `nstages` stages to the HOST arrays `ms` and
  * `counts` (either may be NULL), and clears them if `reset` is non-zero.
- * Stage names come from hef_timing_stage_name(0 .. count-1). */
+ * Stage names come from hef_timing_stage_name(0 .. count-1).
+ * hef_timing_stages(mask) limits the event pairs to the stages whose bit is
+ * set (bit i for stage i), so that a timed run pays for the events of the
+ * stages it measures only.  Until it is called every stage is timed except
+ * "spmm_step", one span over the fused SpMM's three kernels (which the
+ * stages spmm_prep, spmm_csr and spmm_csc also cover). */
 void hef_timing_enable(int32_t on);
+void hef_timing_stages(uint32_t mask);
 int32_t hef_timing_stage_count(void);
 const char *hef_timing_stage_name(int32_t stage);
 hef_status hef_timing_read(double *ms, int64_t *counts, int32_t nstages, int32_t reset);

@@ -393,6 +393,19 @@ def timing_enable(on: bool = True) -> None:
     load().hef_timing_enable(1 if on else 0)
 
 
+def timing_stages(names=None) -> None:
+    """Limit the timing events to the named stages (None: the default, every
+    stage but the spmm_step span)."""
+    lib = load()
+    idx = {lib.hef_timing_stage_name(i).decode(): i for i in range(lib.hef_timing_stage_count())}
+    if names is None:
+        names = [nm for nm in idx if nm != "spmm_step"]
+    mask = 0
+    for nm in names:
+        mask |= 1 << idx[nm]
+    lib.hef_timing_stages(mask)
+
+
 def timing_read(reset: bool = True) -> dict:
     """{stage: (total ms, launches)} of the stages timed since the last reset."""
     lib = load()

@@ -25,7 +25,8 @@ EXPORTS = [
     "hef_resistance_taped", "hef_conductance", "hef_coarsen_levels", "hef_rebuild",
     "hef_rating",
     "hef_debug_apply", "hef_debug_gram", "hef_debug_gram_ws", "hef_start_block",
-    "hef_status_string", "hef_last_error", "hef_timing_enable", "hef_timing_stage_count",
+    "hef_status_string", "hef_last_error", "hef_timing_enable", "hef_timing_stages",
+    "hef_timing_stage_count",
     "hef_timing_stage_name", "hef_timing_read", "hef_last_coarsen_levels",
     "hef_last_coarsen_work",
 ]
@@ -95,6 +96,7 @@ def load() -> C.CDLL:
         "hef_status_string": (C.c_char_p, [i32]),
         "hef_last_error": (C.c_char_p, []),
         "hef_timing_enable": (None, [i32]),
+        "hef_timing_stages": (None, [C.c_uint32]),
         "hef_timing_stage_count": (i32, []),
         "hef_timing_stage_name": (C.c_char_p, [i32]),
         "hef_timing_read": (i32, [vp, vp, i32, i32]),

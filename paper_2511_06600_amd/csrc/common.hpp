@@ -149,10 +149,11 @@ enum Stage : int {
   kStClusterBest,
   kStQuality,
   kStRating,
+  kStSpmmStep,  // the fused SpMM (prep, CSR and CSC) as one span; off unless selected
   kStageCount
 };
 
-bool timing_on();
+bool timing_on(int stage);
 void timing_push(int stage, hipEvent_t a, hipEvent_t b);
 
 struct TimedScope {
@@ -160,7 +161,7 @@ struct TimedScope {
   hipStream_t s;
   hipEvent_t a = nullptr, b = nullptr;
   TimedScope(int st, hipStream_t stream) : stage(st), s(stream) {
-    if (timing_on()) {
+    if (timing_on(st)) {
       if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
         (void)hipEventRecord(a, s);
       else

@@ -41,7 +41,13 @@ static std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> g_pending;
 static double g_ms[kStageCount];
 static int64_t g_cnt[kStageCount];
 
-bool timing_on() { return g_timing.load(std::memory_order_relaxed) != 0; }
+// every stage but the spmm_step span, which would count the SpMM twice
+static std::atomic<uint32_t> g_timing_mask{~(1u << kStSpmmStep)};
+static_assert(kStageCount <= 32, "the stage mask is 32 bits");
+bool timing_on(int stage) {
+  return g_timing.load(std::memory_order_relaxed) != 0 &&
+         ((g_timing_mask.load(std::memory_order_relaxed) >> stage) & 1u) != 0;
+}
 
 void timing_push(int stage, hipEvent_t a, hipEvent_t b) {
   std::lock_guard<std::mutex> lk(g_tmu);
@@ -53,7 +59,7 @@ static const char *kStageNames[kStageCount] = {
     "orth_gram", "orth_chol", "orth_apply", "score_qh", "score_r", "cluster_update",
     "cluster_contract", "cluster_local", "cluster_rebuild", "adjoint", "start_block",
     "spmm_prep", "lanczos_reduce", "orth_reduce",
-    "score_reduce", "cluster_best", "quality", "rating"};
+    "score_reduce", "cluster_best", "quality", "rating", "spmm_step"};
 
 namespace {
 
@@ -534,6 +540,7 @@ const char *hef_status_string(hef_status s) {
 const char *hef_last_error(void) { return hef::last_error(); }
 
 void hef_timing_enable(int32_t on) { hef::g_timing.store(on ? 1 : 0); }
+void hef_timing_stages(uint32_t mask) { hef::g_timing_mask.store(mask); }
 
 int32_t hef_timing_stage_count(void) { return kStageCount; }
 

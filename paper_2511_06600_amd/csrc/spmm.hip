@@ -408,6 +408,7 @@ hef_status spmm_t(const Level &L, const Structure &st, const float *xs, float *y
   float *W = scratch;
   float *U = scratch + m * G::RW;
   const int on = (xs ? 1 : 0) | (xc ? 2 : 0);
+  TimedScope step(kStSpmmStep, s);
   if (n > 0) {
     TimedScope ts(kStSpmmPrep, s);
     k_prep<B><<<cdiv(n * G::LPS, kThreads), kThreads, 0, s>>>(n, st.s, xs, xc, U);
