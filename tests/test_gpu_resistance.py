@@ -263,3 +263,36 @@ def test_long_node_segments(b):
         hub_err = np.abs(y[hubs] - ref[hubs]).max() / np.abs(ref[hubs]).max()
         say(f"  expansion {expansion}: rel err {err:.2e}, hub rows {hub_err:.2e}")
         assert err < 1e-6 and hub_err < 1e-6
+
+
+def test_stage_timing_mask():
+    # hef_timing_stages: with only the spmm_step span selected, one event pair
+    # per fused SpMM (k Krylov steps), and no other stage; by default every
+    # stage but that span
+    h = make_hypergraph("tiny2k")
+    dh = to_device(h)
+    p = hef.Params(k=10, b=1, assume_valid=True)
+    say("case: stage timing mask tiny2k k=10 b=1")
+    hef.resistance(dh, p)
+    torch.cuda.synchronize()
+    hef.timing_read(reset=True)
+    try:
+        hef.timing_stages(["spmm_step"])
+        hef.timing_enable(True)
+        hef.resistance(dh, p)
+        torch.cuda.synchronize()
+        hef.timing_enable(False)
+        only = {k: v for k, v in hef.timing_read(reset=True).items() if v[1]}
+        hef.timing_stages(None)
+        hef.timing_enable(True)
+        hef.resistance(dh, p)
+        torch.cuda.synchronize()
+        hef.timing_enable(False)
+        full = {k: v for k, v in hef.timing_read(reset=True).items() if v[1]}
+    finally:
+        hef.timing_enable(False)
+        hef.timing_stages(None)
+    assert set(only) == {"spmm_step"} and only["spmm_step"][1] == p.k
+    assert "spmm_step" not in full
+    assert full["spmm_csr"][1] == p.k and full["spmm_csc"][1] == p.k
+    assert only["spmm_step"][0] > 0.0
