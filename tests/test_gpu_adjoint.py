@@ -1,9 +1,9 @@
 """GPU parity of the adjoint (dL/dw for L = sum_e c_e R_e) through the C ABI.
 
 * against the float64 autograd gradient of the oracle (same seeded inputs):
-  within 1e-3 norm-relative (written here; derived in the design doc from the FP32
-  forward error of about 1e-5 amplified by the conditioning of the Krylov
-  recurrence), on hyperedges whose selected branch (largest ratio column,
+  within 1e-3 norm-relative (the FP32 forward error of about 1e-5,
+  amplified by the conditioning of the Krylov recurrence, with a margin), on
+  hyperedges whose selected branch (largest ratio column,
   largest / smallest pin) is the same on both sides;
 * Euler's identity: R is homogeneous of degree -1 in w, so w . dL/dw = -L;
 * at the full gradient workload (200k nodes, 210k hyperedges, lognormal

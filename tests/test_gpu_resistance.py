@@ -1,10 +1,11 @@
 """GPU parity of Alg. 1 (a1-a5): the HIP path against the FP64 oracle on the
 same seeded inputs, through the C ABI.
 
-Tolerances (written here, derived in the design doc): FP32 R within 1e-4
-norm-relative and 1e-4 at the 99.9th percentile of elementwise relative error
-over hyperedges with R >= 1e-3 max R; Q_H within 1e-5 relative; the BF16 pool
-within 1e-2 norm-relative.
+Tolerances: FP32 R within 1e-4 norm-relative and 1e-4 at the 99.9th
+percentile of elementwise relative error over hyperedges with R >= 1e-3 max R
+(FP32 rounding through k Krylov steps and the joint orthonormalisation,
+measured at about 1e-6 to 1e-5); Q_H within 1e-5 relative; the BF16 pool
+within 1e-2 norm-relative (bf16 rounding is 2^-9 relative per element).
 """
 import numpy as np
 import pytest
