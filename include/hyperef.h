@@ -99,7 +99,7 @@ typedef struct {
   int32_t b;             /* start vectors per expansion, 1..16              */
   int32_t levels;        /* coarsening levels for hef_coarsen (>= 1)        */
   float percentile;      /* merge threshold delta as a percentile of R, (0,1] */
-  int32_t local_clustering; /* 0/1: attach isolated nodes (Alg. 2 steps 7-10) */
+  int32_t local_clustering; /* 0/1: attach isolated nodes (Alg. 2's local clustering) */
   int32_t basis;         /* hef_basis of the pool                           */
   uint64_t seed;         /* counter-generator seed for start blocks         */
   float drop_tol;        /* tau: relative Gram-Schmidt residual below which
@@ -214,7 +214,7 @@ hef_status hef_coarsen(const hef_hypergraph *hg, const hef_params *p,
  *   qh         DEVICE [cap x K] float64: level l's Q_H per pool column;
  *   rho        DEVICE [cap x K] float64: level l's relative Gram-Schmidt
  *              residuals |R_jj| / ||V_j|| of the joint orthonormalisation
- *              (Alg. 1 step 4; 0 for a dropped column); min over j is the
+ *              (Alg. 1's orthonormalisation; 0 for a dropped column); min over j is the
  *              pool's conditioning margin;
  *   label      DEVICE [cap x n0] int32: level-l node -> level-(l+1) node at
  *              offset l*n0, first n_l entries;
@@ -277,7 +277,7 @@ hef_status hef_cluster_level(const hef_hypergraph *hg, const hef_params *p,
                              float *eta_out, void *ws, size_t ws_bytes,
                              hipStream_t stream);
 
-/* Alg. 2 step 6, the coarse hypergraph H' of a clustering: each pin p
+/* Alg. 2's coarse hypergraph H' of a clustering: each pin p
  * becomes label[p], the labels of a hyperedge are sorted and deduplicated,
  * hyperedges left with fewer than 2 pins are removed, and the kept ones keep
  * their order and weight (w' = w).
@@ -296,7 +296,7 @@ hef_status hef_rebuild(const hef_hypergraph *hg, const int32_t *label, int32_t n
                        hipStream_t stream);
 
 /* Resistance-based vertex-pair rating for multilevel partitioning
- * (Section III-E, Eq. (17); Alg. 3 step 3): for nodes p != q sharing
+ * (Section III-E, Eq. (17); Alg. 3): for nodes p != q sharing
  * hyperedges,  r(p, q) = sum over the hyperedges e holding both of
  * w(e) / (R_e - shift), summed in float64 in ascending hyperedge order; a
  * hyperedge with R_e - shift == 0 adds nothing.  Eq. (17) prints the

@@ -7,14 +7,13 @@ Passages followed (HyperEF 2.0):
   R_e < delta are contracted, each new supernode weighs the resistance of the
   hyperedge that formed it, and Eq. (15) adds the pins' weights eta(v) to R_e
   at the next level (eta = 0 on the original hypergraph);
-* Alg. 1 step 6 and Alg. 2 step 5: contraction starts from the lowest
-  resistances;
+* Alg. 1 and Alg. 2: contraction starts from the lowest resistances;
 * Section III-B: isolated nodes (those left ungrouped by the contraction)
   look at the clusters met through their hyperedges (Eq. (16)), measure the
   distance with the numerator of Eq. (13) against the mean chi-vector of each
   cluster, and merge with the nearest one; the merged cluster's resistance is
   updated in the manner of Eq. (15);
-* Alg. 2 steps 4-10.
+* Alg. 2, from the resistance update to the local clustering.
 
 Readings of silent points (all deterministic, so that a parallel
 implementation can reproduce them bit for bit):
@@ -133,7 +132,8 @@ def distance(chi_p: np.ndarray, cent: np.ndarray, qh: np.ndarray) -> np.ndarray:
 
 def cluster_level(n, m, eptr, pins, R, eta, chi, qh, percentile=0.5,
                   local_clustering=True) -> LevelResult:
-    """Alg. 2 steps 4-10 on one level H_l = (n, m, eptr, pins)."""
+    """One level of Alg. 2, resistance update to local clustering, on
+    H_l = (n, m, eptr, pins)."""
     eptr = np.asarray(eptr, dtype=np.int64)
     pins = np.asarray(pins, dtype=np.int64)
     eta = np.zeros(n, dtype=np.float32) if eta is None else np.asarray(eta, dtype=np.float32)
@@ -219,7 +219,7 @@ def cluster_level(n, m, eptr, pins, R, eta, chi, qh, percentile=0.5,
 
 
 def rebuild(m, eptr, pins, w, label):
-    """Alg. 2 step 6: coarse hypergraph over the labels (sorted unique pins,
+    """Alg. 2's coarse hypergraph over the labels (sorted unique pins,
     hyperedges with fewer than 2 labels removed, weights and order kept).
     Returns (m', eptr', pins', w', kept hyperedge ids)."""
     eptr = np.asarray(eptr, dtype=np.int64)

@@ -17,7 +17,7 @@ Hyperedge Effective Resistances", and Alg. 1):
   Gram-Schmidt in the expansion's own space, the random start block is left
   out of the pool, the star vectors lose their entries on star (hyperedge)
   nodes, and the joint list [star | clique] is orthonormalised again
-  (Alg. 1 steps 3-4);
+  (Alg. 1);
 * Eq. (13): r_e(chi) = (chi_p - chi_q)^2 / Q_H(chi) with p, q the most
   distant pins of e along chi, i.e. the numerator is (max - min)^2 over e;
 * Eq. (9): Q_H(chi) = sum_e w_e max_{u,v in e} (chi_u - chi_v)^2;
@@ -117,7 +117,7 @@ def clique_operator(n, m, eptr, pins, w):
 
 
 # --------------------------------------------------------------------------
-# Gram-Schmidt with column dropping (Alg. 1 step 4)
+# Gram-Schmidt with column dropping (Alg. 1)
 # --------------------------------------------------------------------------
 
 def orthonormalize(V: np.ndarray, ref: np.ndarray, tau: float):
@@ -178,7 +178,7 @@ class Pool:
 
 def unified_pool(n, m, eptr, pins, w, X_star, X_clique, k, tau=1e-3,
                  use_star=True, use_clique=True, keep_blocks=True) -> Pool:
-    """The pool chi^(1..2 rho) of Alg. 1 steps 1-4: per-expansion Krylov bases
+    """The pool chi^(1..2 rho) of Alg. 1: per-expansion Krylov bases
     without the start block, star vectors restricted to the hypergraph nodes,
     star columns first, then one joint Gram-Schmidt in R^n.  With
     keep_blocks=False the per-expansion blocks are released as soon as their
@@ -210,7 +210,7 @@ def unified_pool(n, m, eptr, pins, w, X_star, X_clique, k, tau=1e-3,
 
 
 # --------------------------------------------------------------------------
-# Resistance ratios (Eqs. (9), (13), (14); Alg. 1 steps 5-7)
+# Resistance ratios (Eqs. (9), (13), (14); Alg. 1)
 # --------------------------------------------------------------------------
 
 def edge_spread(eptr, pins, chi: np.ndarray) -> np.ndarray:

@@ -202,7 +202,7 @@ def coarsen_levels(hg: DeviceHypergraph, params: Params):
 
 
 def rebuild(hg: DeviceHypergraph, label: torch.Tensor, n_clusters: int):
-    """Alg. 2 step 6: the coarse hypergraph of a clustering, as
+    """Alg. 2's coarse hypergraph of a clustering, as
     (DeviceHypergraph over n_clusters nodes, kept [m'] int32 input ids)."""
     lib = load()
     assert label.dtype == torch.int32 and label.shape == (hg.n,) and label.is_contiguous()

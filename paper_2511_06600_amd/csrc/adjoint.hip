@@ -9,7 +9,7 @@
 //      smallest pin are taken at fixed positions (lowest column, lowest CSR
 //      position on ties), so R_e is smooth in chi on the branch they select;
 //      Q_H also depends on w directly;
-//   2. the joint Cholesky QR of the pool (Alg. 1 step 4): the adjoint of a
+//   2. the joint Cholesky QR of the pool (Alg. 1): the adjoint of a
 //      thin QR with positive diagonal, Vbar = (Qbar + Q sym(-Qbar^T Q)) R^-T,
 //      sym() copying the lower triangle onto the upper;
 //   3. every block-Lanczos step, a Cholesky QR of M = [V_{j-2} | V_{j-1} | Y]

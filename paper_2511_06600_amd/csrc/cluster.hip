@@ -1,7 +1,7 @@
 // One level of Alg. 2 (steps 4-10) and the level loop.
 //
 // Section III-A "Multilevel Effective Resistance Clustering" and Eq. (15);
-// Alg. 1 step 6 / Alg. 2 step 5 (contraction from the lowest resistance);
+// Alg. 1 and Alg. 2 (contraction from the lowest resistance);
 // Section III-B and Eq. (16) (resistance-based local clustering).  Readings
 // of the points the paper leaves open (all chosen so that the result is one
 // well-defined function of the inputs):
@@ -1222,7 +1222,7 @@ hef_status read_i32(const int32_t *dev, int32_t *host, hipStream_t s) {
 
 }  // namespace
 
-// Steps 4-10 of Alg. 2 on one level.  Outputs label[n] (canonical), the
+// One level of Alg. 2, resistance update to local clustering.  Outputs label[n] (canonical), the
 // group count (host) and eta_out[n_groups].  Needs the level's CSC (st).
 hef_status cluster_one_level(const Level &L, const Structure &st, const float *R, const float *eta,
                              const void *pool, int pool_type, int K, const double *qh,

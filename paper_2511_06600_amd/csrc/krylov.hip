@@ -1,4 +1,4 @@
-// Block Krylov bases of both expansions (Eq. (12), Alg. 1 steps 1-4).
+// Block Krylov bases of both expansions (Eq. (12), Alg. 1).
 //
 // Per expansion, b start vectors and k steps of the block three-term
 // recurrence: Y = A V_j, then V_{j+1} is the Gram-Schmidt of Y against

@@ -1,4 +1,4 @@
-// Joint orthonormalisation of the Krylov pool (Alg. 1 step 4: Gram-Schmidt
+// Joint orthonormalisation of the Krylov pool (Alg. 1: Gram-Schmidt
 // of the unified [star | clique] list), as Cholesky QR:
 //   G = V^T V      FP32 matrix-core tiles over 32-row LDS slabs, FP32
 //                  accumulation flushed to float64 every 128 rows, float64

@@ -7,7 +7,7 @@ namespace hef {
 
 size_t orth_ws_bytes(int64_t n, int K);
 
-// Orthonormalises the Krylov pool (Alg. 1 step 4, the joint Gram-Schmidt
+// Orthonormalises the Krylov pool (Alg. 1, the joint Gram-Schmidt
 // of [star | clique]): G = V^T V (matrix-core tiles, float64 across row
 // chunks), Cholesky G = R^T R in float64 with the drop rule (column j
 // dropped when its Schur pivot <= tau^2 G_jj), Q = V R^-1.  `P` holds V in

@@ -1,4 +1,4 @@
-// Resistance ratios (Eqs. (9), (13), (14); Alg. 1 steps 5-7).
+// Resistance ratios (Eqs. (9), (13), (14); Alg. 1).
 //
 // For every hyperedge e and pool column i the two most distant pins along
 // chi^(i) are its largest and smallest entries, so the numerator of Eq. (13)

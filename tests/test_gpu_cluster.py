@@ -165,7 +165,7 @@ def _with_giant_edge(h, size):
 
 @pytest.mark.parametrize("giant", [0, 17000], ids=["sorted_per_hyperedge", "global_sort"])
 def test_rebuild_matches_oracle_counts(giant):
-    """Alg. 2 step 6 on the GPU's own level-0 map: the coarse hypergraph the
+    """Alg. 2's coarse rebuild on the GPU's own level-0 map: the coarse hypergraph the
     library builds for level 1 has the node, hyperedge and pin counts of the
     oracle's rebuild of the same map.  Hyperedges up to 16384 pins are sorted
     one per workgroup; the 17000-pin one sends the level to the global
