@@ -230,22 +230,31 @@ __global__ void k_single_flag(const int32_t *__restrict__ owner, const int32_t *
 __global__ void __launch_bounds__(512)
 k_qh_order(const double *__restrict__ qh, int K, int32_t *__restrict__ perm,
            float *__restrict__ inv32, int32_t *__restrict__ nuse) {
+  // Q_H staged in LDS (columns past K and Q_H <= 0 as 0); the rank of
+  // column i counts the positive columns before it in (Q_H, index) order
+  __shared__ double q[512];
+  __shared__ int wpos[512 / 64];
   const int i = threadIdx.x;
-  if (i < K && qh[i] > 0.0) {
-    int r = 0;
-    for (int j = 0; j < K; ++j)
-      if (qh[j] > 0.0 && (qh[j] < qh[i] || (qh[j] == qh[i] && j < i))) ++r;
-    perm[r] = i;
-    inv32[r] = float(1.0 / qh[i]);
-  }
-  if (i == 0) {
-    int c = 0;
-    for (int j = 0; j < K; ++j) c += qh[j] > 0.0 ? 1 : 0;
-    *nuse = c;
-  }
+  const double qi = i < K ? qh[i] : 0.0;
+  q[i] = qi > 0.0 ? qi : 0.0;
+  const uint64_t pos = __ballot(qi > 0.0);
+  if ((i & 63) == 0) wpos[i >> 6] = __popcll(pos);
   __syncthreads();
-  for (int q = i; q < 512; q += 512)
-    if (q >= *nuse) { perm[q] = 0; inv32[q] = 0.0f; }
+  int nu = 0;
+#pragma unroll
+  for (int w = 0; w < 512 / 64; ++w) nu += wpos[w];
+  if (qi > 0.0) {
+    int r = 0;
+#pragma unroll 8
+    for (int j = 0; j < K; ++j) {
+      const double qj = q[j];
+      r += (qj > 0.0 && (qj < qi || (qj == qi && j < i))) ? 1 : 0;
+    }
+    perm[r] = i;
+    inv32[r] = float(1.0 / qi);
+  }
+  if (i == 0) *nuse = nu;
+  if (i >= nu) { perm[i] = 0; inv32[i] = 0.0f; }
 }
 
 // cperm[C][q] = float16 of cluster C's centroid in column perm[q] (zero for
@@ -763,9 +772,15 @@ k_count_candidates(const int32_t *__restrict__ list, const int32_t *__restrict__
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < cnt;
        i += int64_t(gridDim.x) * blockDim.x) {
     const int32_t p = list[i];
-    for (int32_t j = vptr[p]; j < vptr[p + 1]; ++j) {
-      const int32_t e = eids[j];
-      acc += unsigned(eptr[e + 1] - eptr[e] - 1);
+    const int32_t j1 = vptr[p + 1];
+    // four hyperedges' loads at a time (independent), then their sizes
+    for (int32_t j = vptr[p]; j < j1; j += 4) {
+      int32_t e[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) e[u] = j + u < j1 ? eids[j + u] : -1;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e[u] >= 0) acc += unsigned(eptr[e[u] + 1] - eptr[e[u]] - 1);
     }
   }
   part[threadIdx.x] = acc;
@@ -1326,9 +1341,9 @@ hef_status cluster_one_level(const Level &L, const Structure &st, const float *R
                                                      w.small + 7, w.best_label, w.best_d);
         }
       }
-      if (work)
-        k_count_candidates<<<1024, 256, 0, s>>>(slist, w.small + 7, st.vptr, st.eids, L.eptr,
-                                                work);
+      if (work)  // (about one listed node per thread at the finest level)
+        k_count_candidates<<<std::min<int64_t>(cdiv(n, 256), 4096), 256, 0, s>>>(
+            slist, w.small + 7, st.vptr, st.eids, L.eptr, work);
       HEF_LAUNCH_CHECK();
     }
     // union-find over {p, best(p)}
