@@ -45,14 +45,17 @@ constexpr int kMaxPB = 16;    // 32-column blocks of the widest pool (K <= 512)
 //
 // k_chol_panel: the first wave of every workgroup factors the w x w
 // diagonal block in registers (lane r holds row r; the pivot and the
-// normalised column entries reach the other lanes by readlane, so the 32
-// column steps need no barrier), which fixes the drop decisions and
-// pivots; then each thread carries one panel row below the block through
-// the same column steps (divide by the pivot, subtract the row's multiple of
-// every later column), so each entry of L sees the same operations in the
-// same order as a column-by-column factorisation of the whole panel.
-// Workgroup 0 also writes the diagonal block, keep and rho.
-constexpr int kCT = 256;  // panel threads: one row below the diagonal block each
+// normalised column entries reach the other lanes by readlane), which fixes
+// the drop decisions and pivots; the other three waves carry one panel row
+// below the block each through the same column steps (divide by the pivot,
+// subtract the row's multiple of every later column), so each entry of L
+// sees the same operations in the same order as a column-by-column
+// factorisation of the whole panel.  The two run as a pipeline: the first
+// wave publishes column j of the block (multiples, pivot, keep) in LDS while
+// the rows below take column j - 1, one barrier per column.  Workgroup 0
+// also writes the diagonal block, keep and rho.
+constexpr int kCT = 256;        // panel threads
+constexpr int kCR = kCT - 64;   // rows below the block per workgroup
 
 // FULL: the panel has kPW columns (every panel but a narrower last one), so
 // the column bounds are compile-time and the unrolled steps carry no tests.
@@ -67,78 +70,88 @@ k_chol_panel(const double *__restrict__ A, const double *__restrict__ G, int K, 
   const int t = threadIdx.x;
   const int w = FULL ? kPW : (K - c0 < kPW ? K - c0 : kPW);
   const int nr = K - c0;
-  if (t < 64) {
-    const int r = t & (kPW - 1);
-    double x[kPW];
+  const bool dw = t < 64;  // the diagonal block's wave (wave-uniform)
+  const int r = t & (kPW - 1);
+  // diagonal wave: lane r holds row r of the block; other waves: one row below
+  const int i = w + int(blockIdx.x) * kCR + (t - 64);
+  const bool row_ok = !dw && i < nr;
+  double x[kPW];
+  double ref = 0.0;
+  int frc = 0;
+  if (dw) {
 #pragma unroll
     for (int j = 0; j < kPW; ++j)
       x[j] = (r < w && j <= r) ? A[int64_t(c0 + r) * K + c0 + j] : 0.0;
-    const double ref = r < w ? G[int64_t(c0 + r) * K + c0 + r] : 0.0;
-    const int frc = r < w ? (force_keep ? force_keep[c0 + r] : 1) : 0;
-    double dkeep = 0.0, pkeep = 0.0;  // lane r: column r's Schur pivot and L_rr
-    int kkeep = 0;
+    ref = r < w ? G[int64_t(c0 + r) * K + c0 + r] : 0.0;
+    frc = r < w ? (force_keep ? force_keep[c0 + r] : 1) : 0;
+  } else if (row_ok) {
+    const double *ar = A + int64_t(c0 + i) * K + c0;
 #pragma unroll
-    for (int jj = 0; jj < kPW; ++jj) {
-      if (jj < w) {
-        const double d = readlane_f64(x[jj], jj);
-        const double rf = readlane_f64(ref, jj);
-        int kp = (rf > 0.0 && d > tau * tau * rf) ? 1 : 0;
-        if (!__builtin_amdgcn_readlane(frc, jj)) kp = 0;
-        const double piv = kp ? sqrt(d) : 0.0;
-        const double lv = (kp && r > jj && r < w) ? x[jj] / piv : 0.0;
-        if (r == jj) {
-          dkeep = d;
-          pkeep = piv;
-          kkeep = kp;
-        }
-        // column jj of L below the pivot (entries above the diagonal of the
-        // block are never read)
-        x[jj] = r == jj ? piv : lv;
-        if (kp) {
-#pragma unroll
-          for (int tc = jj + 1; tc < kPW; ++tc)
-            if (tc < w) x[tc] = __builtin_fma(-lv, readlane_f64(lv, tc), x[tc]);
-        }
-      }
+    for (int j = 0; j < kPW; ++j) x[j] = j < w ? ar[j] : 0.0;
+  }
+  double dkeep = 0.0, pkeep = 0.0;  // lane r: column r's Schur pivot and L_rr
+  int kkeep = 0;
+  // column jj of the diagonal block (first wave)
+  auto diag_step = [&](int jj) __attribute__((always_inline)) {
+    const double d = readlane_f64(x[jj], jj);
+    const double rf = readlane_f64(ref, jj);
+    int kp = (rf > 0.0 && d > tau * tau * rf) ? 1 : 0;
+    if (!__builtin_amdgcn_readlane(frc, jj)) kp = 0;
+    const double piv = kp ? sqrt(d) : 0.0;
+    const double lv = (kp && r > jj && r < w) ? x[jj] / piv : 0.0;
+    if (r == jj) {
+      dkeep = d;
+      pkeep = piv;
+      kkeep = kp;
     }
-    if (t < kPW) {
+    // column jj of L below the pivot (entries above the diagonal of the
+    // block are never read)
+    x[jj] = r == jj ? piv : lv;
+    if (t < kPW) Ln[t][jj] = t >= jj ? x[jj] : 0.0;
+    if (t == 0) {
+      s_piv[jj] = piv;
+      s_kp[jj] = kp;
+    }
+    if (kp) {
 #pragma unroll
-      for (int j = 0; j < kPW; ++j) Ln[t][j] = j <= t ? x[j] : 0.0;
-      s_piv[t] = pkeep;
-      s_kp[t] = kkeep;
-      if (blockIdx.x == 0 && t < w) {
+      for (int tc = jj + 1; tc < kPW; ++tc)
+        if (FULL || tc < w) x[tc] = __builtin_fma(-lv, readlane_f64(lv, tc), x[tc]);
+    }
+  };
+  // column jj for a row below the block (the other waves)
+  auto row_step = [&](int jj) __attribute__((always_inline)) {
+    const int kp = s_kp[jj];
+    x[jj] = kp ? x[jj] / s_piv[jj] : 0.0;
+    if (kp) {
 #pragma unroll
-        for (int j = 0; j < kPW; ++j)
-          if (j <= t) LT[int64_t(c0 + j) * K + c0 + t] = x[j];
-        keep[c0 + t] = kkeep;
-        // relative Gram-Schmidt residual |R_jj| / ||V_j|| of a kept column
-        if (rho) rho[c0 + t] = kkeep ? sqrt(dkeep / ref) : 0.0;
+      for (int tc = jj + 1; tc < kPW; ++tc)
+        if (FULL || tc < w) x[tc] = __builtin_fma(-x[jj], Ln[tc][jj], x[tc]);
+    }
+  };
+#pragma unroll
+  for (int jj = 0; jj <= kPW; ++jj) {
+    if (FULL || jj <= w) {
+      if (dw) {
+        if (jj < w) diag_step(jj);
+      } else if (row_ok && jj > 0) {
+        row_step(jj - 1);
       }
+      __syncthreads();
     }
   }
-  __syncthreads();
-  // rows below the diagonal block
-  const int i = w + int(blockIdx.x) * kCT + t;
-  if (i >= nr) return;
-  double x[kPW];
-  const double *ar = A + int64_t(c0 + i) * K + c0;
+  if (dw && t < kPW && blockIdx.x == 0 && t < w) {
 #pragma unroll
-  for (int j = 0; j < kPW; ++j) x[j] = j < w ? ar[j] : 0.0;
-#pragma unroll
-  for (int jj = 0; jj < kPW; ++jj) {
-    if (jj < w) {
-      const int kp = s_kp[jj];
-      x[jj] = kp ? x[jj] / s_piv[jj] : 0.0;
-      if (kp) {
-#pragma unroll
-        for (int tc = jj + 1; tc < kPW; ++tc)
-          if (tc < w) x[tc] = __builtin_fma(-x[jj], Ln[tc][jj], x[tc]);
-      }
-    }
+    for (int j = 0; j < kPW; ++j)
+      if (j <= t) LT[int64_t(c0 + j) * K + c0 + t] = x[j];
+    keep[c0 + t] = kkeep;
+    // relative Gram-Schmidt residual |R_jj| / ||V_j|| of a kept column
+    if (rho) rho[c0 + t] = kkeep ? sqrt(dkeep / ref) : 0.0;
   }
+  if (row_ok) {
 #pragma unroll
-  for (int j = 0; j < kPW; ++j)
-    if (j < w) LT[int64_t(c0 + j) * K + c0 + i] = x[j];
+    for (int j = 0; j < kPW; ++j)
+      if (j < w) LT[int64_t(c0 + j) * K + c0 + i] = x[j];
+  }
 }
 
 // A[i][q] -= sum_{l in [c0, c0+w)} L[i][l] L[q][l] for c0+w <= q <= i < K:
@@ -1796,7 +1809,7 @@ hef_status orthonormalize_pool(void *P, void *out, int pool_type, int64_t n, int
       HEF_TRY(zero_async(LT, sizeof(double) * K * K, s));
       for (int c0 = 0; c0 < K; c0 += kPW) {
         const int w = K - c0 < kPW ? K - c0 : kPW;
-        const int nb = K - c0 - w > 0 ? int(cdiv(K - c0 - w, kCT)) : 1;
+        const int nb = K - c0 - w > 0 ? int(cdiv(K - c0 - w, kCR)) : 1;
         if (w == kPW)
           k_chol_panel<true><<<nb, kCT, 0, s>>>(A, G, K, c0, tau, LT, keep,
                                                 pass == 0 ? nullptr : keep,
