@@ -361,9 +361,11 @@ csc_big(int bx, int nbx, const int32_t *__restrict__ list, const int32_t *__rest
 
 // One launch per pass: workgroups [0, kBigGrid) walk the long segments (one
 // wave each), the rest take the short ones (kBigGrid is a multiple of 8, so
-// a workgroup's XCD is the same in both numberings).
+// a workgroup's XCD is the same in both numberings).  Up to b = 8 the pass
+// is held to 64 VGPRs, i.e. 8 waves per SIMD for its gathers (one register
+// more would leave 7).
 template <int B>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(B <= 8 ? 8 : 1, 8)))
 k_csr(const int32_t *__restrict__ big_e, const int32_t *__restrict__ n_big,
       const int32_t *__restrict__ eptr, const int32_t *__restrict__ pins,
       const float *__restrict__ U, const float *__restrict__ alpha,
